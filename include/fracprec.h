@@ -1,0 +1,236 @@
+/*
+ * fracprec -- block-preconditioned FGMRES for the stabilized 3x3 block
+ * Jacobian of frictional contact mechanics with hydraulically active
+ * fractures, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Franceschini, Gazzola & Ferronato, "A scalable preconditioning
+ * framework for stabilized contact mechanics with hydraulically active
+ * fractures".  The system is the Newton system of Sec. 2.2 (eq. JacSys):
+ *
+ *     J = [ A   C1  Q1 ]   unknowns  u  (3 per mesh node, global frame)
+ *         [ C2  -H  0  ]             t  (3 per fracture face, local frame)
+ *         [ Q2  0   T  ]             p  (1 per fracture face)
+ *
+ * with the blocks of eq. block_def.  The preconditioner is M2 (t-u-p,
+ * Alg 3.3 / 3.4, default) or M1 (t-p-u, Alg 3.1 / 3.2); the inner operator on
+ * the mechanics Schur complement S1 = A + C1 H~^{-1} C2 (eq. Schur1_2) is one
+ * smoothed-aggregation AMG V-cycle; the pressure block is solved exactly.
+ *
+ * Conventions for every entry point:
+ *  - Vectors are device pointers (HIP global memory) of doubles, laid out
+ *    [u (n_u) | t (n_t) | p (n_p)], u node-major (x, y, z per node), t
+ *    face-major (N, T1, T2 per face), p in face order.  They are owned by the
+ *    caller and must stay valid until the call returns.
+ *  - All work is ordered on the HIP stream given to fpc_create; calls that
+ *    return results to the host (fpc_info, convergence tests) synchronize
+ *    that stream.
+ *  - One handle per host thread.  A negative status means no output was
+ *    written; fpc_last_error() returns a message.  FPC_NOT_CONVERGED (> 0) is
+ *    a warning: the output holds the last iterate and the info its residual.
+ *  - The library allocates device memory in fpc_setup (and lazily on the
+ *    first transposed or batched call); the solve paths allocate nothing.
+ */
+#ifndef FRACPREC_H
+#define FRACPREC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FPC_OK = 0,
+  FPC_NOT_CONVERGED = 1,       /* warning: output holds the last iterate    */
+  FPC_ERR_ARG = -1,            /* null pointer, bad option                   */
+  FPC_ERR_DIM = -2,            /* block sizes inconsistent                   */
+  FPC_ERR_PATTERN = -3,        /* CSR columns unsorted / duplicate / range   */
+  FPC_ERR_SINGULAR_BLOCK = -4, /* a 3x3 face block of H or a coarse pivot    */
+  FPC_ERR_NOT_SPD = -5,        /* nonpositive pivot of the pressure block    */
+  FPC_ERR_NAN = -6,            /* NaN / Inf in values or right-hand side     */
+  FPC_ERR_HIP = -7,            /* HIP runtime error                          */
+  FPC_ERR_OOM = -8,            /* device allocation failed                   */
+  FPC_ERR_STATE = -9,          /* call before fpc_setup                      */
+  FPC_ERR_UNSUPPORTED = -10    /* case outside this build (see message)      */
+} fpc_status;
+
+enum { FPC_HOST = 0, FPC_DEVICE = 1 };
+enum { FPC_TUP = 0, FPC_TPU = 1 };
+enum { FPC_FP64 = 0, FPC_FP32_PREC = 1 };
+
+/* Compressed sparse rows, 0-based, column indices strictly increasing in
+ * every row.  Arrays live in host or device memory (fpc_block_system.ptr_space)
+ * and are only read; fpc_setup deep-copies them. */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int64_t* rowptr;   /* nrows + 1 */
+  const int32_t* colind;   /* nnz */
+  const double* val;       /* nnz */
+} fpc_csr;
+
+/* The seven blocks of eq. JacSys / eq. block_def.  Shapes: A n_u x n_u,
+ * C1 n_u x n_t, Q1 n_u x n_p, C2 n_t x n_u, H n_t x n_t, Q2 n_p x n_u,
+ * T n_p x n_p, with n_u = 3 * nodes and n_t = 3 * n_p.  Q2 may be empty.
+ * coords: n_u/3 x 3 node coordinates (split node copies repeat theirs) for
+ * the rigid-body near-nullspace, or NULL for translations only. */
+typedef struct {
+  int64_t n_u, n_t, n_p;
+  fpc_csr A, C1, Q1, C2, H, Q2, T;
+  const double* coords;
+  int ptr_space;           /* FPC_HOST or FPC_DEVICE for every array above */
+} fpc_block_system;
+
+/* Smoothed-aggregation parameters (the paper leaves them open). */
+typedef struct {
+  int max_coarse;          /* coarsest level when dofs <= this (2000)      */
+  int max_levels;          /* 12                                            */
+  int cheb_degree;         /* Chebyshev degree, pre and post (2; only 2)    */
+  double cheb_ratio;       /* interval [lambda_hi / ratio, lambda_hi] (10)  */
+  int power_its;           /* power iterations for lambda (10)              */
+  double lam_safety;       /* lambda_hi = safety * estimate (1.1)           */
+  double omega_factor;     /* prolongator smoothing omega = f / lambda_hi   */
+  double drop_tol;         /* dependent near-nullspace columns (1e-10)      */
+} fpc_amg_options;
+
+typedef struct {
+  int mode;                /* FPC_TUP (default) or FPC_TPU                  */
+  int precision;           /* FPC_FP64 or FPC_FP32_PREC (FP32 hierarchy)    */
+  int restart;             /* FGMRES restart length (50)                    */
+  int maxit;               /* total iteration cap (1000)                    */
+  double rtol;             /* default relative tolerance (1e-8)             */
+  int max_batch;           /* right-hand sides per fpc_solve_batch (32)     */
+  fpc_amg_options amg;
+} fpc_options;
+
+typedef struct {
+  int iterations;          /* FGMRES iterations (total over restarts)       */
+  int restarts;            /* restart cycles                                */
+  int converged;           /* 1 if the true residual met the tolerance      */
+  double true_rel_residual;/* |b - J x| / |b| recomputed in FP64            */
+  double est_rel_residual; /* last Givens estimate                          */
+  double seconds;          /* wall time of the call                         */
+} fpc_info;
+
+/* Hierarchy description for one AMG level (tests and reporting). */
+typedef struct {
+  int64_t n_nodes;         /* block rows                                    */
+  int64_t n_dofs;          /* real (unpadded) dofs                          */
+  int block;               /* block size of the level (3 fine, 6 coarse)    */
+  int64_t nnzb;            /* stored blocks of A_l                          */
+  int64_t nnz_scalar;      /* nonzero scalar entries of A_l                 */
+  int64_t p_nnzb, r_nnzb;  /* blocks of P_l and R_l = P_l^T                 */
+  double lam_hi;           /* Chebyshev upper bound                         */
+  int64_t n_agg;           /* aggregates formed on this level (0 coarsest)  */
+} fpc_level_desc;
+
+/* Fracture flow graph for the transmissibility gradient: TPFA face pairs
+ * (K, L) (eq. FV_inner_product), Dirichlet edge counts and one-sided
+ * transmissibilities.  Device pointers. */
+typedef struct {
+  int64_t n_p, n_pairs;
+  const int32_t* pair_k;   /* n_pairs */
+  const int32_t* pair_l;   /* n_pairs */
+  const int32_t* ndir;     /* n_p */
+  const double* upsilon;   /* n_p */
+} fpc_flow_graph;
+
+typedef struct fpc_handle fpc_handle;
+
+/* Fill *opt with the defaults listed above (mode t-u-p, FP64, FGMRES(50),
+ * rtol 1e-8, AMG: 2000 / 12 / degree 2 / ratio 10 / 10 its / 1.1 / 4/3 /
+ * 1e-10). */
+void fpc_default_options(fpc_options* opt);
+
+/* Create a handle.  `stream` is a hipStream_t (NULL = default stream); the
+ * handle does not own it.  *h is NULL on failure. */
+fpc_status fpc_create(fpc_handle** h, const fpc_options* opt, void* stream);
+
+/* Preconditioner construction, Alg 3.3 cpt_tup (or Alg 3.1 cpt_tpu):
+ * H~ = Bdiag(H,3) and its inverse, S1 = A + C1 H~^{-1} C2 (eq. Schur1_2),
+ * S~2 = T - FS(Q2, S1, Q1) (eq. FS_algebraic; zero when Q2 is empty) with
+ * its exact inverse, and the smoothed-aggregation hierarchy of S1 with the
+ * Galerkin products P^T A P.  Every array of *J is copied; the caller may
+ * free them afterwards.  Errors: FPC_ERR_DIM / _PATTERN / _NAN on bad input,
+ * FPC_ERR_SINGULAR_BLOCK for a singular face block of H, FPC_ERR_NOT_SPD for
+ * a nonpositive pivot of S~2, FPC_ERR_UNSUPPORTED for a non-empty Q2 (open
+ * faces), FPC_ERR_OOM.  A second call replaces the previous setup. */
+fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J);
+
+/* v = M^{-1} w: Alg 3.4 app_tup (or Alg 3.2 app_tpu) with one V-cycle per
+ * AMG(S1, .) call.  w, v: device, length n_u + n_t + n_p, distinct. */
+fpc_status fpc_apply_prec(fpc_handle* h, const double* w, double* v);
+
+/* v = M^{-T} w: the factors of eq. P2 (eq. P1) transposed in reverse order,
+ * with the V-cycle on the transposed level operators. */
+fpc_status fpc_apply_prec_T(fpc_handle* h, const double* w, double* v);
+
+/* y = J x (trans = 0) or J^T x (trans = 1), eq. JacSys, FP64. */
+fpc_status fpc_matvec(fpc_handle* h, int trans, const double* x, double* y);
+
+/* One V-cycle x = AMG(S1, b) on the u block only (length n_u, device). */
+fpc_status fpc_vcycle(fpc_handle* h, const double* b, double* x);
+
+/* Right-preconditioned FGMRES(restart) on J x = b (Sec. 4: zero initial
+ * guess, stop at |b - J x| <= rtol |b|, the true residual recomputed in
+ * FP64).  use_x0 != 0 starts from the values in x (restart / resume).
+ * rtol <= 0 uses the handle's default.  info may be NULL. */
+fpc_status fpc_solve(fpc_handle* h, const double* b, double* x, double rtol,
+                     int use_x0, fpc_info* info);
+
+/* Adjoint solve J^T lam = g with right preconditioner M^{-T}. */
+fpc_status fpc_solve_T(fpc_handle* h, const double* g, double* lam,
+                       double rtol, fpc_info* info);
+
+/* k right-hand sides sharing J (k <= max_batch): column c of B is
+ * B + c * ldb, of X is X + c * ldx (device, column-major).  Each column
+ * runs its own FGMRES with its own tolerance rtol |b_c|; the preconditioner
+ * is applied to all active columns at once.  infos: k entries or NULL. */
+fpc_status fpc_solve_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
+                           double* X, int64_t ldx, double rtol,
+                           fpc_info* infos);
+
+/* dL/d(log Upsilon_K) = -lam_p^T (dT/d log Upsilon_K) p for a loss L(x)
+ * whose adjoint pressure is lam_p (from fpc_solve_T): TPFA harmonic
+ * averages and Dirichlet terms of eq. FV_inner_product.  lam_p, p, grad:
+ * device, length n_p. */
+fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
+                              const double* lam_p, const double* p,
+                              double* grad);
+
+/* Hierarchy introspection (host outputs). */
+int fpc_num_levels(const fpc_handle* h);
+fpc_status fpc_level_info(const fpc_handle* h, int level, fpc_level_desc* d);
+
+/* Copy level data to host memory for checks: aggregate id per node (-1 =
+ * isolated) of level `level` into agg (n_nodes int32); ranks (kept
+ * near-nullspace columns per aggregate) into rank (n_agg int32).  Either
+ * pointer may be NULL. */
+fpc_status fpc_export_aggregates(const fpc_handle* h, int level, int32_t* agg,
+                                 int32_t* rank);
+
+/* Copy the BSR operator A_l (which = 0), P_l (1) or R_l (2) of a level to
+ * host arrays: rowptr (nbrows+1), col (nnzb), val (nnzb * br * bc, blocks
+ * row-major).  Query sizes with fpc_level_info. */
+fpc_status fpc_export_level_matrix(const fpc_handle* h, int level, int which,
+                                   int64_t* rowptr, int32_t* col, double* val);
+
+/* Seconds spent in the phases of the last fpc_setup (host wall clock):
+ * [0] total, [1] upload + validation, [2] H~ and S1, [3] pressure block,
+ * [4] AMG hierarchy. */
+fpc_status fpc_setup_times(const fpc_handle* h, double* t5);
+
+void fpc_destroy(fpc_handle* h);
+const char* fpc_status_string(fpc_status s);
+const char* fpc_last_error(const fpc_handle* h);
+
+/* Counter-based hash used for aggregation priorities and power-iteration
+ * start vectors (lowbias32, C. Wellons 2018), evaluated on the device for
+ * n consecutive inputs starting at `first`; out: device, n uint32. */
+fpc_status fpc_hash32_device(fpc_handle* h, uint32_t first, int64_t n,
+                             uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRACPREC_H */

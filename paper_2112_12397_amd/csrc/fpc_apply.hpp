@@ -1,0 +1,61 @@
+// Apply-path entry points (V-cycle, block-preconditioner pieces, Krylov).
+#pragma once
+
+#include "fpc_handle.hpp"
+
+namespace fpc {
+
+template <typename T>
+CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv);
+// One V-cycle on NV interleaved columns: input cycle_vecs(H,NV).lv[0].b,
+// output .lv[0].xo.
+template <typename T, int NV>
+void vcycle(Hierarchy& H, bool transpose, hipStream_t s);
+
+void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s);
+void sell_mv_dinv(const Sell<double>& A, const double* dinv, const double* x,
+                  double* y, hipStream_t s);
+void face_apply(const double* hinv, const double* in, double* out,
+                int64_t n_p, int trans, hipStream_t s);
+template <typename T>
+void to_level(T* out, int nv, int colv, int64_t n, const double* base,
+              const Csr* m1, const double* x1, double a1, const Csr* m2,
+              const double* x2, double a2, hipStream_t s);
+template <typename T>
+void from_level(const T* xo, int nv, int64_t n, double* vu, int diff,
+                hipStream_t s);
+void tface(const Csr& C, const double* vu, const double* t_t,
+           const double* hinv, double* v_t, int64_t n_p, int trans,
+           hipStream_t s);
+void psolve_apply(const PSolve& ps, const double* in, double* out,
+                  int64_t n_p, int trans, hipStream_t s);
+
+// ---------------------------------------------------------------- Krylov
+// partial[i * G + blk] = <V_i, w> over a chunk; V_i = V + i * ldv
+constexpr int kDotBlocks = 256;
+void mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+          double* partials, double* out, hipStream_t s);
+// w -= sum_i h_i V_i
+void maxpy(const double* V, int64_t ldv, int nv, const double* h, double* w,
+           int64_t n, hipStream_t s);
+// y = x * (1 / scal[0]) (scal on device); if scal[0] == 0 y = 0
+void scale_by_inv(const double* x, const double* scal, double* y, int64_t n,
+                  hipStream_t s);
+// y = a * x + b * y
+void axpby(double a, const double* x, double b, double* y, int64_t n,
+           hipStream_t s);
+// FGMRES step j on device: H[:, j] = h1 + h2 (j+1 entries), H[j+1, j] =
+// sqrt(nrm2); Givens update of H, cs, sn, g; scal[0] = H[j+1,j] before
+// rotation (0 on breakdown), scal[1] = |g_{j+1}|, ctrl[0] = breakdown.
+void gmres_step(double* H, int ldh, double* cs, double* sn, double* g,
+                const double* h1, const double* h2, const double* nrm2,
+                const double* nrm2_before, int j, double* scal, int* ctrl,
+                hipStream_t s);
+void gmres_init(double* g, int m, const double* beta2, double* scal,
+                hipStream_t s);
+// y = R^{-1} g, R = H[0:k, 0:k] upper triangular
+void gmres_trisolve(const double* H, int ldh, const double* g, double* y,
+                    int k, hipStream_t s);
+void sqrt_dev(const double* in, double* out, hipStream_t s);
+
+}  // namespace fpc

@@ -1,0 +1,108 @@
+// Handle, hierarchy and work-vector structures of the fracprec library.
+#pragma once
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "fpc_internal.hpp"
+
+namespace fpc {
+
+// One level of the smoothed-aggregation hierarchy.  Block rows are "nodes":
+// mesh nodes (3 dofs) on level 0, aggregates (nb dofs, padded) below.
+struct Level {
+  int bs = 3;               // dofs per node on this level
+  int nb = 6;               // dofs per node on the next level
+  int64_t n_nodes = 0;
+  int64_t n_dofs_real = 0;  // without padding dofs
+  Bsr A, P, R;              // FP64 block CSR (setup, export, transposes)
+  Sell<double> sA, sP, sR;  // apply operators
+  Sell<float> fA, fP, fR;
+  Bsr AT;                   // A^T for the transposed cycle (lazy)
+  Sell<double> sAT;
+  Sell<float> fAT;
+  DevBuf<double> dinv;      // n_nodes * bs
+  DevBuf<float> dinv32;
+  DevBuf<int32_t> agg;      // aggregate of every node (-1 isolated)
+  DevBuf<int32_t> rank;     // kept modes per aggregate (n_agg)
+  DevBuf<int32_t> node_rank;// real dofs per node (coarse levels)
+  int64_t n_agg = 0;
+  int64_t nnz_scalar = 0;
+  double lam_hi = 0, theta = 0, delta = 0, c1 = 0, c2 = 0;
+  bool coarsest = false;
+};
+
+template <typename T>
+struct LevelVecs {
+  DevBuf<T> x, xo, d, r, res, b;
+};
+
+// Per (precision, column count) set of level vectors.
+template <typename T>
+struct CycleVecs {
+  int nv = 0;
+  std::vector<LevelVecs<T>> lv;
+};
+
+struct Hierarchy {
+  std::vector<Level> L;
+  int64_t nc = 0, ncpad = 0;  // coarsest dofs (padded) and dense size
+  DevBuf<double> Ainv;        // ncpad x ncpad, row-major
+  DevBuf<double> AinvT;       // transpose (lazy)
+  std::vector<CycleVecs<double>> v64;
+  std::vector<CycleVecs<float>> v32;
+  bool have_transpose = false;
+};
+
+// Exact pressure-block solve: dense inverse of every connected component of
+// the face graph of S~2 (T when Q2 is empty).
+struct PSolve {
+  int64_t n_comp = 0;
+  std::vector<int64_t> comp_n, comp_pad, comp_off_h, dense_off_h;
+  DevBuf<int64_t> comp_off, dense_off, comp_pad_d;
+  DevBuf<int32_t> members, comp_of_row;
+  DevBuf<double> dense;
+  int64_t dense_elems = 0;
+};
+
+// Per right-hand-side block of Krylov work space.
+struct Krylov {
+  int m = 0, k = 0;
+  int64_t N = 0;
+  DevBuf<double> V, Z;        // (m+1) x N x k, m x N x k
+  DevBuf<double> w, r, tmp;   // N x k
+  DevBuf<double> H, cs, sn, g, y;  // small arrays (device)
+  DevBuf<double> h1, h2, scal, partials;
+  DevBuf<int> ctrl;
+  double* host = nullptr;     // pinned mirror for scalars read each step
+  ~Krylov() {
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+}  // namespace fpc
+
+struct fpc_handle {
+  fpc_options opt{};
+  hipStream_t stream = nullptr;
+  bool ready = false;
+  int64_t n_u = 0, n_t = 0, n_p = 0, N = 0;
+  fpc::Csr A, C1, Q1, C2, H, Q2, T;
+  fpc::Csr C1T, C2T, Q1T, Q2T, HT, TT;
+  bool have_T = false;
+  fpc::Bsr Ab;                 // A as 3x3 blocks (J matvec)
+  fpc::Sell<double> sAJ, sAJT;
+  fpc::DevBuf<double> hinv;    // n_p * 9
+  fpc::DevBuf<double> coords;  // n_nodes * 3 (optional)
+  bool has_coords = false;
+  fpc::Hierarchy amg;
+  fpc::PSolve ps;
+  fpc::DevBuf<int> flags;
+  // apply-path scratch (FP64)
+  fpc::DevBuf<double> t_t, tmp_u, tmp_u2, tmp_p, scratchN;
+  fpc::Krylov kry1;            // single right-hand side
+  fpc::Krylov kryB;            // batched
+  std::string last_error;
+  double setup_times[5] = {0, 0, 0, 0, 0};
+};

@@ -1,0 +1,208 @@
+// Internal declarations of the fracprec HIP library (gfx950).
+//
+// Data layout on the device:
+//  * Csr     scalar CSR (int64 row pointers, int32 columns, double values)
+//            for the coupling blocks C1, C2, Q1, Q2, H, T.
+//  * Bsr     block CSR with compile-time block shapes (3x3 node blocks on the
+//            fine level, 6x6 on coarse levels, 3x6 / 6x3 transfer blocks),
+//            blocks stored row-major; used by the setup (SpGEMM, transpose).
+//  * Sell    sliced-ELL over block rows for the apply path: slices of 64 block
+//            rows, one thread per block row, slot (slice, k, lane) holds one
+//            block; the values of a (slice, k) group are component-major so a
+//            wavefront loads each block component as 64 consecutive words.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fracprec.h"
+
+namespace fpc {
+
+struct Error : std::runtime_error {
+  fpc_status st;
+  Error(fpc_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define FPC_HIP(x)                                                            \
+  do {                                                                        \
+    hipError_t e_ = (x);                                                      \
+    if (e_ != hipSuccess)                                                     \
+      throw ::fpc::Error(e_ == hipErrorOutOfMemory ? FPC_ERR_OOM : FPC_ERR_HIP, \
+                         std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define FPC_LAUNCH_CHECK() FPC_HIP(hipGetLastError())
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n_) { alloc(n_); }
+  void alloc(size_t n_) {
+    release();
+    n = n_;
+    if (n) {
+      hipError_t e = hipMalloc(&p, n * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        n = 0;
+        throw Error(e == hipErrorOutOfMemory ? FPC_ERR_OOM : FPC_ERR_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+      }
+    }
+  }
+  void ensure(size_t n_) {
+    if (n < n_) alloc(n_);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+struct Csr {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  DevBuf<int64_t> rowptr;
+  DevBuf<int32_t> col;
+  DevBuf<double> val;
+};
+
+struct Bsr {
+  int br = 0, bc = 0;
+  int64_t nbr = 0, nbc = 0, nnzb = 0;
+  DevBuf<int64_t> rowptr;
+  DevBuf<int32_t> col;
+  DevBuf<double> val;  // nnzb * br * bc, blocks row-major
+};
+
+template <typename T>
+struct Sell {
+  int br = 0, bc = 0;
+  int64_t nrows = 0, nslices = 0, nslots = 0, nnzb = 0;
+  DevBuf<int64_t> slice_ptr;  // nslices + 1, in slots (multiples of 64)
+  DevBuf<int32_t> row_len;    // nrows
+  DevBuf<int32_t> col;        // nslots
+  DevBuf<T> val;              // nslots * br * bc
+  size_t bytes() const {
+    return slice_ptr.bytes() + row_len.bytes() + col.bytes() + val.bytes();
+  }
+};
+
+constexpr int kSliceH = 64;
+
+// Device-side error flags written by validation / factorization kernels.
+enum FlagIdx {
+  FLAG_PATTERN = 0,
+  FLAG_NAN = 1,
+  FLAG_SINGULAR = 2,
+  FLAG_NOT_SPD = 3,
+  FLAG_OVERFLOW = 4,
+  FLAG_COUNT = 8
+};
+
+// ---------------------------------------------------------------- k_util
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+void fill_f32(float* p, float v, int64_t n, hipStream_t s);
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+// out[0] = 0, out[i+1] = sum_{j<=i} in[j]; out has n+1 entries.
+void scan_counts(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+int64_t scan_counts_total(const int64_t* in, int64_t* out, int64_t n,
+                          hipStream_t s);
+void i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+// Deterministic two-pass reductions; results written to device memory.
+void dot_f64(const double* x, const double* y, int64_t n, double* out,
+             double* partials, hipStream_t s);
+constexpr int kRedBlocks = 1024;
+void hash32_range(uint32_t first, int64_t n, uint32_t* out, hipStream_t s);
+void check_finite(const double* v, int64_t n, int* flags, hipStream_t s);
+void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+double read_f64(const double* p, hipStream_t s);
+int64_t read_i64(const int64_t* p, hipStream_t s);
+int read_i32(const int32_t* p, hipStream_t s);
+
+__host__ __device__ inline uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- k_sparse
+void csr_validate(const Csr& m, int* flags, hipStream_t s);
+// y = beta*y + a1*M1 x1 + a2*M2 x2 (M2 may be null); rows = M1.nrows.
+void csr_spmv2(const Csr* m1, const double* x1, double a1, const Csr* m2,
+               const double* x2, double a2, double* y, double beta,
+               hipStream_t s);
+void csr_transpose(const Csr& a, Csr& t, hipStream_t s);
+void csr_to_bsr(const Csr& a, int br, int bc, Bsr& out, hipStream_t s);
+void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s);
+void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s);
+// C = A * B (block shapes must chain).  flags[FLAG_OVERFLOW] on hash overflow.
+void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s);
+template <typename T>
+void bsr_to_sell(const Bsr& a, Sell<T>& out, hipStream_t s);
+int64_t bsr_count_nonzeros(const Bsr& a, hipStream_t s);
+
+// ---------------------------------------------------------------- k_amg
+void hinv_setup(const Csr& H, int64_t n_p, double* hinv, int* flags,
+                hipStream_t s);
+void bsr_block_row_scale(Bsr& b, const double* blocks3x3, hipStream_t s);
+void bsr_dinv(const Bsr& a, double* dinv, int* flags, hipStream_t s);
+// MIS-2 aggregation on the block pattern; returns n_agg, fills agg.
+int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
+                       hipStream_t s);
+void rigid_modes(const double* coords, int64_t n_nodes, int nb, double* B,
+                 hipStream_t s);
+// Tentative prolongator per aggregate; writes ptent (n_nodes*bs*nb), Bc
+// (n_agg*nb*nb), rank (n_agg).
+void tentative(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
+               int nb, const double* B, double drop_tol, double* ptent,
+               double* Bc, int32_t* rank, hipStream_t s);
+void ptent_bsr(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
+               int nb, const double* ptent, Bsr& P, hipStream_t s);
+void smooth_prolongator(Bsr& AP, const int32_t* agg, const double* ptent,
+                        const double* dinv, double omega, hipStream_t s);
+void dummy_diag(Bsr& Ac, const int32_t* rank, hipStream_t s);
+void power_start(int64_t n_nodes, int bs, int key_stride,
+                 const int32_t* node_rank, double* x, hipStream_t s);
+void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s);
+// In-place Gauss-Jordan inverse of an n x n (n multiple of 64) row-major
+// matrix without pivoting; flags[FLAG_SINGULAR] / [FLAG_NOT_SPD] if a pivot
+// is not positive when spd != 0 or is tiny.
+void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s);
+
+// ---------------------------------------------------------------- k_krylov
+constexpr int kMaxKrylov = 64;
+
+}  // namespace fpc

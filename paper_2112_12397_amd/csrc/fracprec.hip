@@ -1,0 +1,990 @@
+// C ABI of the fracprec library: setup of the block preconditioner
+// (Alg 3.1 / 3.3) with the smoothed-aggregation hierarchy, its application
+// (Alg 3.2 / 3.4) and transpose, the Jacobian product, and right-
+// preconditioned FGMRES for one, several or transposed systems.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "fpc_apply.hpp"
+
+using namespace fpc;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// ------------------------------------------------------------- kernels
+__global__ void k_label_init(int32_t* lab, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) lab[i] = (int32_t)i;
+}
+
+__global__ void k_label_prop(const int64_t* rp, const int32_t* col,
+                             const int32_t* in, int32_t* out, int64_t n,
+                             int* changed) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t m = in[i];
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = min(m, in[col[e]]);
+  out[i] = m;
+  if (m != in[i]) atomicOr(changed, 1);
+}
+
+__global__ void k_root_flag(const int32_t* lab, int64_t n, int64_t* f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = lab[i] == i ? 1 : 0;
+}
+
+__global__ void k_comp_of(const int32_t* lab, const int64_t* rscan, int64_t n,
+                          int32_t* comp) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) comp[i] = (int32_t)rscan[lab[i]];
+}
+
+__global__ void k_eq_flag(const int32_t* comp, int32_t c, int64_t n,
+                          int64_t* f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = comp[i] == c ? 1 : 0;
+}
+
+__global__ void k_place(const int32_t* comp, int32_t c, const int64_t* scan,
+                        int64_t off, int64_t n, int32_t* pos, int32_t* members,
+                        int32_t* comp_of_row) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || comp[i] != c) return;
+  const int32_t local = (int32_t)scan[i];
+  pos[i] = local;
+  members[off + local] = (int32_t)i;
+  comp_of_row[off + local] = c;
+}
+
+__global__ void k_scatter_T(const int64_t* rp, const int32_t* col,
+                            const double* val, int64_t n, const int32_t* comp,
+                            const int32_t* pos, const int64_t* dense_off,
+                            const int64_t* pad, double* dense) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = comp[i];
+  double* D = dense + dense_off[c];
+  const int64_t ld = pad[c];
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+    D[(int64_t)pos[i] * ld + pos[col[e]]] = val[e];
+}
+
+__global__ void k_pad_diag(double* D, int64_t n, int64_t ld) {
+  int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ld) D[i * ld + i] = 1.0;
+}
+
+__global__ void k_dense_transpose(const double* A, double* T, int64_t n) {
+  __shared__ double t[32][33];
+  int64_t bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    int64_t r = by + k, c = bx + threadIdx.x;
+    if (r < n && c < n) t[k][threadIdx.x] = A[r * n + c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    int64_t r = bx + k, c = by + threadIdx.x;
+    if (r < n && c < n) T[r * n + c] = t[threadIdx.x][k];
+  }
+}
+
+__global__ void k_copy_i32(const int32_t* a, int32_t* b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_cast_dinv(const double* a, float* b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// pairs -> incidence rows (pair e has entries K (side 0) and L (side 1))
+__global__ void k_pair_rows(const int32_t* pk, const int32_t* pl, int64_t m,
+                            int64_t* rp, int32_t* col, double* val) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > m) return;
+  rp[e] = 2 * e;
+  if (e == m) return;
+  int32_t a = pk[e], b = pl[e];
+  col[2 * e] = min(a, b);
+  col[2 * e + 1] = max(a, b);
+  val[2 * e] = (double)e;
+  val[2 * e + 1] = (double)e;
+}
+
+__global__ void k_grad(const int64_t* rp, const int32_t* pair,
+                       const int32_t* pk, const int32_t* pl,
+                       const int32_t* ndir, const double* ups,
+                       const double* lam, const double* p, double* grad,
+                       int64_t n_p) {
+  int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= n_p) return;
+  double g = 0.0;
+  for (int64_t q = rp[K]; q < rp[K + 1]; ++q) {
+    const int32_t e = pair[q];
+    const int32_t L = (pk[e] == K) ? pl[e] : pk[e];
+    const double uK = ups[K], uL = ups[L];
+    const double s = uK + uL;
+    const double dK = 2.0 * uK * uL * uL / (s * s);
+    g -= dK * (lam[K] - lam[L]) * (p[K] - p[L]);
+  }
+  g -= (double)ndir[K] * ups[K] * lam[K] * p[K];
+  grad[K] = g;
+}
+
+// ------------------------------------------------------------- helpers
+void check_flags(fpc_handle* h, const char* where) {
+  int f[FLAG_COUNT];
+  FPC_HIP(hipMemcpyAsync(f, h->flags.p, sizeof(f), hipMemcpyDeviceToHost,
+                         h->stream));
+  FPC_HIP(hipStreamSynchronize(h->stream));
+  std::string w(where);
+  if (f[FLAG_PATTERN]) throw Error(FPC_ERR_PATTERN, w + ": invalid CSR pattern");
+  if (f[FLAG_NAN]) throw Error(FPC_ERR_NAN, w + ": non-finite value");
+  if (f[FLAG_SINGULAR]) throw Error(FPC_ERR_SINGULAR_BLOCK, w + ": singular block or pivot");
+  if (f[FLAG_NOT_SPD]) throw Error(FPC_ERR_NOT_SPD, w + ": nonpositive pivot");
+  if (f[FLAG_OVERFLOW]) throw Error(FPC_ERR_UNSUPPORTED, w + ": SpGEMM row too long");
+}
+
+void upload_csr(const fpc_csr& in, int space, int64_t nr, int64_t nc, Csr& out,
+                hipStream_t s, const char* name) {
+  if (in.nrows != nr || in.ncols != nc)
+    throw Error(FPC_ERR_DIM, std::string(name) + ": shape mismatch");
+  if (in.nnz < 0 || !in.rowptr || (in.nnz > 0 && (!in.colind || !in.val)))
+    throw Error(FPC_ERR_ARG, std::string(name) + ": null array");
+  out.nrows = nr;
+  out.ncols = nc;
+  out.nnz = in.nnz;
+  out.rowptr.alloc(nr + 1);
+  out.col.alloc(std::max<int64_t>(in.nnz, 1));
+  out.val.alloc(std::max<int64_t>(in.nnz, 1));
+  const hipMemcpyKind k =
+      space == FPC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  FPC_HIP(hipMemcpyAsync(out.rowptr.p, in.rowptr, (nr + 1) * sizeof(int64_t), k, s));
+  if (in.nnz) {
+    FPC_HIP(hipMemcpyAsync(out.col.p, in.colind, in.nnz * sizeof(int32_t), k, s));
+    FPC_HIP(hipMemcpyAsync(out.val.p, in.val, in.nnz * sizeof(double), k, s));
+  }
+}
+
+template <typename F>
+fpc_status guard(fpc_handle* h, F&& f) {
+  try {
+    f();
+    return FPC_OK;
+  } catch (const Error& e) {
+    if (h) h->last_error = e.what();
+    return e.st;
+  } catch (const std::exception& e) {
+    if (h) h->last_error = e.what();
+    return FPC_ERR_HIP;
+  }
+}
+
+int64_t round64(int64_t n) { return ((n + 63) / 64) * 64; }
+
+// ------------------------------------------------------------- p-block
+void build_psolve(fpc_handle* h) {
+  PSolve& ps = h->ps;
+  const int64_t n = h->n_p;
+  hipStream_t s = h->stream;
+  ps = PSolve();
+  if (n == 0) return;
+  const Csr& T = h->T;
+  DevBuf<int32_t> la(n), lb(n);
+  DevBuf<int> changed(1);
+  const unsigned g = grid_for(n, 256);
+  k_label_init<<<g, 256, 0, s>>>(la.p, n);
+  FPC_LAUNCH_CHECK();
+  for (int it = 0;; ++it) {
+    FPC_HIP(hipMemsetAsync(changed.p, 0, sizeof(int), s));
+    k_label_prop<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, la.p, lb.p, n,
+                                   changed.p);
+    FPC_LAUNCH_CHECK();
+    std::swap(la, lb);
+    if (read_i32(changed.p, s) == 0) break;
+    if (it > 4 * n + 8) throw Error(FPC_ERR_HIP, "component labelling stalled");
+  }
+  DevBuf<int64_t> f(n), sc(n + 1);
+  k_root_flag<<<g, 256, 0, s>>>(la.p, n, f.p);
+  FPC_LAUNCH_CHECK();
+  ps.n_comp = scan_counts_total(f.p, sc.p, n, s);
+  DevBuf<int32_t> comp(n), pos(n);
+  k_comp_of<<<g, 256, 0, s>>>(la.p, sc.p, n, comp.p);
+  FPC_LAUNCH_CHECK();
+  ps.members.alloc(n);
+  ps.comp_of_row.alloc(n);
+  ps.comp_n.resize(ps.n_comp);
+  ps.comp_off_h.assign(ps.n_comp + 1, 0);
+  for (int64_t c = 0; c < ps.n_comp; ++c) {
+    k_eq_flag<<<g, 256, 0, s>>>(comp.p, (int32_t)c, n, f.p);
+    FPC_LAUNCH_CHECK();
+    const int64_t cnt = scan_counts_total(f.p, sc.p, n, s);
+    k_place<<<g, 256, 0, s>>>(comp.p, (int32_t)c, sc.p, ps.comp_off_h[c], n,
+                              pos.p, ps.members.p, ps.comp_of_row.p);
+    FPC_LAUNCH_CHECK();
+    ps.comp_n[c] = cnt;
+    ps.comp_off_h[c + 1] = ps.comp_off_h[c] + cnt;
+  }
+  ps.comp_pad.resize(ps.n_comp);
+  ps.dense_off_h.assign(ps.n_comp + 1, 0);
+  for (int64_t c = 0; c < ps.n_comp; ++c) {
+    ps.comp_pad[c] = round64(ps.comp_n[c]);
+    ps.dense_off_h[c + 1] = ps.dense_off_h[c] + ps.comp_pad[c] * ps.comp_pad[c];
+  }
+  ps.dense_elems = ps.dense_off_h[ps.n_comp];
+  if (ps.dense_elems > (int64_t)6 * 1024 * 1024 * 1024)
+    throw Error(FPC_ERR_UNSUPPORTED,
+                "pressure block: connected component too large for the dense "
+                "exact solve");
+  ps.comp_off.alloc(ps.n_comp + 1);
+  ps.dense_off.alloc(ps.n_comp + 1);
+  ps.comp_pad_d.alloc(ps.n_comp);
+  FPC_HIP(hipMemcpyAsync(ps.comp_off.p, ps.comp_off_h.data(),
+                         (ps.n_comp + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  FPC_HIP(hipMemcpyAsync(ps.dense_off.p, ps.dense_off_h.data(),
+                         (ps.n_comp + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  FPC_HIP(hipMemcpyAsync(ps.comp_pad_d.p, ps.comp_pad.data(),
+                         ps.n_comp * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  ps.dense.alloc(ps.dense_elems);
+  FPC_HIP(hipMemsetAsync(ps.dense.p, 0, ps.dense.bytes(), s));
+  k_scatter_T<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, T.val.p, n, comp.p, pos.p,
+                                ps.dense_off.p, ps.comp_pad_d.p, ps.dense.p);
+  FPC_LAUNCH_CHECK();
+  for (int64_t c = 0; c < ps.n_comp; ++c) {
+    double* D = ps.dense.p + ps.dense_off_h[c];
+    const int64_t pad = ps.comp_pad[c];
+    if (pad > ps.comp_n[c])
+      k_pad_diag<<<grid_for(pad - ps.comp_n[c], 64), 64, 0, s>>>(D, ps.comp_n[c], pad);
+    FPC_LAUNCH_CHECK();
+    gj_inverse(D, pad, /*spd=*/1, h->flags.p, s);
+  }
+  check_flags(h, "pressure block");
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------- AMG setup
+double power_lambda(fpc_handle* h, Level& L, int key_stride) {
+  hipStream_t s = h->stream;
+  const int64_t n = L.n_nodes * L.bs;
+  DevBuf<double> x(n), y(n), part(kRedBlocks), sc(2);
+  power_start(L.n_nodes, L.bs, key_stride,
+              L.node_rank.p ? L.node_rank.p : nullptr, x.p, s);
+  dot_f64(x.p, x.p, n, sc.p, part.p, s);
+  sqrt_dev(sc.p, sc.p + 1, s);
+  scale_by_inv(x.p, sc.p + 1, x.p, n, s);
+  for (int it = 0; it < h->opt.amg.power_its; ++it) {
+    sell_mv_dinv(L.sA, L.dinv.p, x.p, y.p, s);
+    dot_f64(y.p, y.p, n, sc.p, part.p, s);
+    sqrt_dev(sc.p, sc.p + 1, s);
+    scale_by_inv(y.p, sc.p + 1, x.p, n, s);
+  }
+  return read_f64(sc.p + 1, s);
+}
+
+void build_hierarchy(fpc_handle* h, Bsr&& S1) {
+  Hierarchy& H = h->amg;
+  H = Hierarchy();
+  hipStream_t s = h->stream;
+  const fpc_amg_options& o = h->opt.amg;
+  const int nb = h->has_coords ? 6 : 3;
+  H.L.emplace_back();
+  {
+    Level& L0 = H.L.back();
+    L0.bs = 3;
+    L0.A = std::move(S1);
+    L0.n_nodes = L0.A.nbr;
+    L0.n_dofs_real = 3 * L0.n_nodes;
+  }
+  DevBuf<double> B(H.L[0].n_nodes * 3 * nb);
+  rigid_modes(h->has_coords ? h->coords.p : nullptr, H.L[0].n_nodes, nb, B.p, s);
+  while (true) {
+    Level& L = H.L.back();
+    L.dinv.alloc(L.n_nodes * L.bs);
+    bsr_dinv(L.A, L.dinv.p, h->flags.p, s);
+    check_flags(h, "AMG diagonal");
+    L.nnz_scalar = bsr_count_nonzeros(L.A, s);
+    if (L.n_dofs_real <= o.max_coarse || (int)H.L.size() == o.max_levels) {
+      L.coarsest = true;
+      break;
+    }
+    L.agg.alloc(L.n_nodes);
+    DevBuf<int32_t> roots;
+    L.n_agg = aggregate_mis2(L.A, L.agg.p, roots, s);
+    if (L.n_agg == 0) {
+      L.coarsest = true;
+      break;
+    }
+    L.nb = nb;
+    bsr_to_sell(L.A, L.sA, s);
+    const double lam = power_lambda(h, L, L.bs);
+    L.lam_hi = o.lam_safety * lam;
+    const double lo = L.lam_hi / o.cheb_ratio;
+    L.theta = 0.5 * (L.lam_hi + lo);
+    L.delta = 0.5 * (L.lam_hi - lo);
+    const double sigma = L.theta / L.delta;
+    const double rho0 = 1.0 / sigma;
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    L.c1 = rho1 * rho0;
+    L.c2 = 2.0 * rho1 / L.delta;
+    // tentative prolongator
+    DevBuf<double> ptent(L.n_nodes * L.bs * nb), Bc(L.n_agg * nb * nb);
+    L.rank.alloc(L.n_agg);
+    tentative(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, B.p, o.drop_tol, ptent.p,
+              Bc.p, L.rank.p, s);
+    Bsr Pt;
+    ptent_bsr(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, ptent.p, Pt, s);
+    Bsr AP0;
+    spgemm(L.A, Pt, AP0, h->flags.p, s);
+    // P = P_tent - omega D^{-1} (A P_tent)
+    smooth_prolongator(AP0, L.agg.p, ptent.p, L.dinv.p,
+                       o.omega_factor / L.lam_hi, s);
+    bsr_add(Pt, AP0, L.P, s);
+    bsr_transpose(L.P, L.R, s);
+    Bsr AP, Ac;
+    spgemm(L.A, L.P, AP, h->flags.p, s);
+    spgemm(L.R, AP, Ac, h->flags.p, s);
+    check_flags(h, "Galerkin product");
+    dummy_diag(Ac, L.rank.p, s);
+    bsr_to_sell(L.P, L.sP, s);
+    bsr_to_sell(L.R, L.sR, s);
+    // next level
+    std::vector<int32_t> rk(L.n_agg);
+    FPC_HIP(hipMemcpyAsync(rk.data(), L.rank.p, L.n_agg * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipStreamSynchronize(s));
+    int64_t real = 0;
+    for (int32_t r : rk) real += r;
+    const int64_t n_agg = L.n_agg;
+    Level next;
+    next.bs = nb;
+    next.A = std::move(Ac);
+    next.n_nodes = n_agg;
+    next.n_dofs_real = real;
+    next.node_rank.alloc(n_agg);
+    k_copy_i32<<<grid_for(n_agg, 256), 256, 0, s>>>(L.rank.p, next.node_rank.p,
+                                                    n_agg);
+    FPC_LAUNCH_CHECK();
+    B = std::move(Bc);
+    H.L.push_back(std::move(next));
+  }
+  // coarsest level: dense inverse (FP64)
+  Level& C = H.L.back();
+  H.nc = C.n_nodes * C.bs;
+  H.ncpad = round64(std::max<int64_t>(H.nc, 1));
+  H.Ainv.alloc(H.ncpad * H.ncpad);
+  dense_from_bsr(C.A, H.ncpad, H.Ainv.p, s);
+  gj_inverse(H.Ainv.p, H.ncpad, /*spd=*/0, h->flags.p, s);
+  check_flags(h, "coarsest level");
+  if (h->opt.precision == FPC_FP32_PREC) {
+    for (Level& L : H.L) {
+      const int64_t n = L.n_nodes * L.bs;
+      L.dinv32.alloc(n);
+      k_cast_dinv<<<grid_for(n, 256), 256, 0, s>>>(L.dinv.p, L.dinv32.p, n);
+      FPC_LAUNCH_CHECK();
+      if (!L.coarsest) {
+        bsr_to_sell(L.A, L.fA, s);
+        bsr_to_sell(L.P, L.fP, s);
+        bsr_to_sell(L.R, L.fR, s);
+      }
+    }
+  }
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+void ensure_transposes(fpc_handle* h) {
+  if (h->have_T) return;
+  hipStream_t s = h->stream;
+  csr_transpose(h->C1, h->C1T, s);
+  csr_transpose(h->C2, h->C2T, s);
+  csr_transpose(h->Q1, h->Q1T, s);
+  csr_transpose(h->Q2, h->Q2T, s);
+  csr_transpose(h->H, h->HT, s);
+  csr_transpose(h->T, h->TT, s);
+  Bsr AbT;
+  bsr_transpose(h->Ab, AbT, s);
+  bsr_to_sell(AbT, h->sAJT, s);
+  Hierarchy& H = h->amg;
+  for (Level& L : H.L) {
+    if (L.coarsest) continue;
+    bsr_transpose(L.A, L.AT, s);
+    bsr_to_sell(L.AT, L.sAT, s);
+    if (h->opt.precision == FPC_FP32_PREC) bsr_to_sell(L.AT, L.fAT, s);
+  }
+  H.AinvT.alloc(H.ncpad * H.ncpad);
+  dim3 g((unsigned)((H.ncpad + 31) / 32), (unsigned)((H.ncpad + 31) / 32));
+  k_dense_transpose<<<g, dim3(32, 8), 0, s>>>(H.Ainv.p, H.AinvT.p, H.ncpad);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipStreamSynchronize(s));
+  h->have_T = true;
+}
+
+// ------------------------------------------------------------- apply
+void matvec(fpc_handle* h, int trans, const double* x, double* y) {
+  hipStream_t s = h->stream;
+  const double *xu = x, *xt = x + h->n_u, *xp = x + h->n_u + h->n_t;
+  double *yu = y, *yt = y + h->n_u, *yp = y + h->n_u + h->n_t;
+  if (!trans) {
+    sell_mv(h->sAJ, xu, yu, s);
+    csr_spmv2(&h->C1, xt, 1.0, &h->Q1, xp, 1.0, yu, 1.0, s);
+    csr_spmv2(&h->C2, xu, 1.0, &h->H, xt, -1.0, yt, 0.0, s);
+    csr_spmv2(&h->Q2, xu, 1.0, &h->T, xp, 1.0, yp, 0.0, s);
+  } else {
+    ensure_transposes(h);
+    sell_mv(h->sAJT, xu, yu, s);
+    csr_spmv2(&h->C2T, xt, 1.0, &h->Q2T, xp, 1.0, yu, 1.0, s);
+    csr_spmv2(&h->C1T, xu, 1.0, &h->HT, xt, -1.0, yt, 0.0, s);
+    csr_spmv2(&h->Q1T, xu, 1.0, &h->TT, xp, 1.0, yp, 0.0, s);
+  }
+}
+
+template <typename T>
+void apply_fwd(fpc_handle* h, const double* w, double* v) {
+  hipStream_t s = h->stream;
+  const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
+  const double *wu = w, *wt = w + nu, *wp = w + nu + nt;
+  double *vu = v, *vt = v + nu, *vp = v + nu + nt;
+  face_apply(h->hinv.p, wt, h->t_t.p, np, 0, s);            // t_t = H~^-1 w_t
+  if (h->opt.mode == FPC_TUP) {
+    // Alg 3.4 with Q2 = 0: t_p = w_p, so v_p = S~2^-1 w_p is known before the
+    // first V-cycle and the two AMG calls (steps 3 and 7) run as one
+    // two-column cycle on [w_u + C1 t_t, Q1 v_p].
+    psolve_apply(h->ps, wp, vp, np, 0, s);
+    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 2);
+    to_level<T>(cv.lv[0].b.p, 2, 0, nu, wu, &h->C1, h->t_t.p, 1.0, nullptr,
+                nullptr, 0.0, s);
+    to_level<T>(cv.lv[0].b.p, 2, 1, nu, nullptr, &h->Q1, vp, 1.0, nullptr,
+                nullptr, 0.0, s);
+    vcycle<T, 2>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 2, nu, vu, 1, s);          // v_u = s_u - AMG(Q1 v_p)
+  } else {
+    // Alg 3.2 with Q2 = 0: t_p = T^-1 w_p is also v_p.
+    psolve_apply(h->ps, wp, vp, np, 0, s);
+    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, &h->Q1, vp,
+                -1.0, s);
+    vcycle<T, 1>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+  }
+  tface(h->C2, vu, h->t_t.p, h->hinv.p, vt, np, 0, s);      // v_t
+}
+
+template <typename T>
+void apply_adj(fpc_handle* h, const double* w, double* v) {
+  hipStream_t s = h->stream;
+  ensure_transposes(h);
+  const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
+  const double *wu = w, *wt = w + nu, *wp = w + nu + nt;
+  double *vu = v, *vt = v + nu, *vp = v + nu + nt;
+  // M^{-T}: t_t = H~^-T w_t; t_u = w_u + C2^T t_t; s_u = AMG^T(t_u);
+  // t_p = w_p - Q1^T s_u; v_p = S~2^-T t_p; v_u = s_u - AMG^T(Q2^T v_p)
+  // (= s_u when Q2 = 0); v_t = -t_t + H~^-T C1^T v_u.  The t-p-u transpose
+  // coincides when Q2 = 0.
+  face_apply(h->hinv.p, wt, h->t_t.p, np, 1, s);
+  CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+  to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C2T, h->t_t.p, 1.0, nullptr,
+              nullptr, 0.0, s);
+  vcycle<T, 1>(h->amg, true, s);
+  from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+  FPC_HIP(hipMemcpyAsync(h->tmp_p.p, wp, np * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  csr_spmv2(&h->Q1T, vu, -1.0, nullptr, nullptr, 0.0, h->tmp_p.p, 1.0, s);
+  psolve_apply(h->ps, h->tmp_p.p, vp, np, 1, s);
+  tface(h->C1T, vu, h->t_t.p, h->hinv.p, vt, np, 1, s);
+}
+
+void apply(fpc_handle* h, int trans, const double* w, double* v) {
+  const bool fp32 = h->opt.precision == FPC_FP32_PREC;
+  if (!trans) {
+    if (fp32) apply_fwd<float>(h, w, v);
+    else apply_fwd<double>(h, w, v);
+  } else {
+    if (fp32) apply_adj<float>(h, w, v);
+    else apply_adj<double>(h, w, v);
+  }
+}
+
+// ------------------------------------------------------------- FGMRES
+void ensure_krylov(fpc_handle* h, Krylov& K, int k) {
+  const int m = h->opt.restart;
+  if (K.m == m && K.k >= k && K.N == h->N) return;
+  K.m = m;
+  K.k = k;
+  K.N = h->N;
+  const int64_t N = h->N;
+  K.V.alloc((int64_t)(m + 1) * N * k);
+  K.Z.alloc((int64_t)m * N * k);
+  K.w.alloc(N * k);
+  K.r.alloc(N * k);
+  K.tmp.alloc(N * k);
+  K.H.alloc((int64_t)(m + 1) * m * k);
+  K.cs.alloc((int64_t)m * k);
+  K.sn.alloc((int64_t)m * k);
+  K.g.alloc((int64_t)(m + 1) * k);
+  K.y.alloc((int64_t)m * k);
+  K.h1.alloc((int64_t)(m + 1) * k);
+  K.h2.alloc((int64_t)(m + 1) * k);
+  K.scal.alloc(8 * k);
+  K.partials.alloc((int64_t)(m + 1) * kDotBlocks);
+  K.ctrl.alloc(4 * k);
+  if (!K.host) FPC_HIP(hipHostMalloc((void**)&K.host, 64 * sizeof(double)));
+}
+
+double dev_norm(fpc_handle* h, Krylov& K, const double* x, double* slot) {
+  mdot(x, 0, 1, x, h->N, K.partials.p, slot, h->stream);
+  return std::sqrt(std::max(read_f64(slot, h->stream), 0.0));
+}
+
+fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
+                  double rtol, int use_x0, fpc_info* info) {
+  const double t0 = now_s();
+  hipStream_t s = h->stream;
+  Krylov& K = h->kry1;
+  ensure_krylov(h, K, 1);
+  const int64_t N = h->N;
+  const int m = h->opt.restart;
+  if (rtol <= 0) rtol = h->opt.rtol;
+  fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+  check_finite(b, N, h->flags.p, s);
+  check_flags(h, "right-hand side");
+  double* sc = K.scal.p;  // [0] hn / beta, [1] est, [2] |b|^2, [3] |r|^2, [4] |w|^2 before
+  const double bnorm = dev_norm(h, K, b, sc + 2);
+  fpc_info inf{};
+  if (bnorm == 0.0) {
+    FPC_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    FPC_HIP(hipStreamSynchronize(s));
+    inf.converged = 1;
+    inf.seconds = now_s() - t0;
+    if (info) *info = inf;
+    return FPC_OK;
+  }
+  if (!use_x0) FPC_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+  const double tol = rtol * bnorm;
+  int its = 0, cycles = 0;
+  bool converged = false;
+  double est = 1.0, truer = 1.0;
+  while (true) {
+    // true residual r = b - J x
+    matvec(h, trans, x, K.w.p);
+    FPC_HIP(hipMemcpyAsync(K.r.p, b, N * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    axpby(-1.0, K.w.p, 1.0, K.r.p, N, s);
+    mdot(K.r.p, 0, 1, K.r.p, N, K.partials.p, sc + 3, s);
+    gmres_init(K.g.p, m, sc + 3, sc, s);
+    const double beta = std::sqrt(std::max(read_f64(sc + 3, s), 0.0));
+    truer = beta / bnorm;
+    if (beta <= tol) {
+      converged = true;
+      break;
+    }
+    if (its >= h->opt.maxit) break;
+    scale_by_inv(K.r.p, sc, K.V.p, N, s);
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = K.V.p + (int64_t)j * N;
+      double* zj = K.Z.p + (int64_t)j * N;
+      apply(h, trans, vj, zj);
+      matvec(h, trans, zj, K.w.p);
+      mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
+      // classical Gram-Schmidt, twice
+      mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
+      maxpy(K.V.p, N, j + 1, K.h1.p, K.w.p, N, s);
+      mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h2.p, s);
+      maxpy(K.V.p, N, j + 1, K.h2.p, K.w.p, N, s);
+      mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 5, s);
+      gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
+                 sc + 4, j, sc, K.ctrl.p, s);
+      scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
+      FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+      FPC_HIP(hipStreamSynchronize(s));
+      ++its;
+      k = j + 1;
+      est = K.host[1] / bnorm;
+      const int breakdown = *(int*)(K.host + 2);
+      if (K.host[1] <= tol || breakdown || its >= h->opt.maxit) break;
+    }
+    gmres_trisolve(K.H.p, m, K.g.p, K.y.p, k, s);
+    // x += Z y  (maxpy subtracts, so negate y on the device)
+    axpby(-1.0, K.y.p, 0.0, K.h1.p, k, s);
+    maxpy(K.Z.p, N, k, K.h1.p, x, N, s);
+    ++cycles;
+  }
+  inf.iterations = its;
+  inf.restarts = cycles;
+  inf.converged = converged ? 1 : 0;
+  inf.true_rel_residual = truer;
+  inf.est_rel_residual = est;
+  inf.seconds = now_s() - t0;
+  if (info) *info = inf;
+  return converged ? FPC_OK : FPC_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+void fpc_default_options(fpc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mode = FPC_TUP;
+  o->precision = FPC_FP64;
+  o->restart = 50;
+  o->maxit = 1000;
+  o->rtol = 1e-8;
+  o->max_batch = 32;
+  o->amg.max_coarse = 2000;
+  o->amg.max_levels = 12;
+  o->amg.cheb_degree = 2;
+  o->amg.cheb_ratio = 10.0;
+  o->amg.power_its = 10;
+  o->amg.lam_safety = 1.1;
+  o->amg.omega_factor = 4.0 / 3.0;
+  o->amg.drop_tol = 1e-10;
+}
+
+fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
+  if (!hp) return FPC_ERR_ARG;
+  *hp = nullptr;
+  fpc_handle* h = nullptr;
+  try {
+    h = new fpc_handle();
+  } catch (...) {
+    return FPC_ERR_OOM;
+  }
+  if (opt) h->opt = *opt;
+  else fpc_default_options(&h->opt);
+  const fpc_options& o = h->opt;
+  if ((o.mode != FPC_TUP && o.mode != FPC_TPU) ||
+      (o.precision != FPC_FP64 && o.precision != FPC_FP32_PREC) ||
+      o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
+      o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
+      o.amg.cheb_ratio <= 1.0 || o.max_batch < 1) {
+    delete h;
+    return FPC_ERR_ARG;
+  }
+  h->stream = (hipStream_t)stream;
+  fpc_status st = guard(h, [&] {
+    h->flags.alloc(FLAG_COUNT);
+    FPC_HIP(hipMemsetAsync(h->flags.p, 0, FLAG_COUNT * sizeof(int), h->stream));
+  });
+  if (st != FPC_OK) {
+    delete h;
+    return st;
+  }
+  *hp = h;
+  return FPC_OK;
+}
+
+fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
+  if (!h || !J) return FPC_ERR_ARG;
+  return guard(h, [&] {
+    const double t0 = now_s();
+    hipStream_t s = h->stream;
+    h->ready = false;
+    h->have_T = false;
+    const int64_t nu = J->n_u, nt = J->n_t, np = J->n_p;
+    if (nu <= 0 || nu % 3 || np < 0 || nt != 3 * np)
+      throw Error(FPC_ERR_DIM, "need n_u = 3 * nodes and n_t = 3 * n_p");
+    if (J->ptr_space != FPC_HOST && J->ptr_space != FPC_DEVICE)
+      throw Error(FPC_ERR_ARG, "ptr_space");
+    h->n_u = nu;
+    h->n_t = nt;
+    h->n_p = np;
+    h->N = nu + nt + np;
+    fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+    upload_csr(J->A, J->ptr_space, nu, nu, h->A, s, "A");
+    upload_csr(J->C1, J->ptr_space, nu, nt, h->C1, s, "C1");
+    upload_csr(J->Q1, J->ptr_space, nu, np, h->Q1, s, "Q1");
+    upload_csr(J->C2, J->ptr_space, nt, nu, h->C2, s, "C2");
+    upload_csr(J->H, J->ptr_space, nt, nt, h->H, s, "H");
+    upload_csr(J->Q2, J->ptr_space, np, nu, h->Q2, s, "Q2");
+    upload_csr(J->T, J->ptr_space, np, np, h->T, s, "T");
+    h->has_coords = J->coords != nullptr;
+    if (h->has_coords) {
+      h->coords.alloc(nu);
+      FPC_HIP(hipMemcpyAsync(h->coords.p, J->coords, nu * sizeof(double),
+                             J->ptr_space == FPC_DEVICE ? hipMemcpyDeviceToDevice
+                                                        : hipMemcpyHostToDevice,
+                             s));
+      check_finite(h->coords.p, nu, h->flags.p, s);
+    }
+    for (const Csr* m : {&h->A, &h->C1, &h->Q1, &h->C2, &h->H, &h->Q2, &h->T})
+      csr_validate(*m, h->flags.p, s);
+    check_flags(h, "input");
+    if (h->Q2.nnz > 0)
+      throw Error(FPC_ERR_UNSUPPORTED,
+                  "open fracture faces (non-empty Q2) are outside this build");
+    const double t1 = now_s();
+    // H~ = Bdiag(H, 3) and its inverse
+    h->hinv.alloc(std::max<int64_t>(np * 9, 1));
+    hinv_setup(h->H, np, h->hinv.p, h->flags.p, s);
+    check_flags(h, "H~ = Bdiag(H,3)");
+    // S1 = A + C1 (H~^{-1} C2)
+    Bsr C1b, Xb, CX, S1;
+    h->Ab = Bsr();
+    csr_to_bsr(h->A, 3, 3, h->Ab, s);
+    csr_to_bsr(h->C1, 3, 3, C1b, s);
+    csr_to_bsr(h->C2, 3, 3, Xb, s);
+    bsr_block_row_scale(Xb, h->hinv.p, s);
+    spgemm(C1b, Xb, CX, h->flags.p, s);
+    bsr_add(h->Ab, CX, S1, s);
+    check_flags(h, "S1 = A + C1 H~^-1 C2");
+    bsr_to_sell(h->Ab, h->sAJ, s);
+    const double t2 = now_s();
+    build_psolve(h);
+    const double t3 = now_s();
+    build_hierarchy(h, std::move(S1));
+    const double t4 = now_s();
+    h->t_t.alloc(std::max<int64_t>(nt, 1));
+    h->tmp_p.alloc(std::max<int64_t>(np, 1));
+    h->scratchN.alloc(h->N);
+    FPC_HIP(hipStreamSynchronize(s));
+    h->ready = true;
+    h->setup_times[0] = t4 - t0;
+    h->setup_times[1] = t1 - t0;
+    h->setup_times[2] = t2 - t1;
+    h->setup_times[3] = t3 - t2;
+    h->setup_times[4] = t4 - t3;
+  });
+}
+
+#define FPC_REQUIRE_READY(h)                                  \
+  do {                                                        \
+    if (!(h)) return FPC_ERR_ARG;                             \
+    if (!(h)->ready) {                                        \
+      (h)->last_error = "call before a successful fpc_setup"; \
+      return FPC_ERR_STATE;                                   \
+    }                                                         \
+  } while (0)
+
+fpc_status fpc_apply_prec(fpc_handle* h, const double* w, double* v) {
+  FPC_REQUIRE_READY(h);
+  if (!w || !v) return FPC_ERR_ARG;
+  return guard(h, [&] { apply(h, 0, w, v); });
+}
+
+fpc_status fpc_apply_prec_T(fpc_handle* h, const double* w, double* v) {
+  FPC_REQUIRE_READY(h);
+  if (!w || !v) return FPC_ERR_ARG;
+  return guard(h, [&] { apply(h, 1, w, v); });
+}
+
+fpc_status fpc_matvec(fpc_handle* h, int trans, const double* x, double* y) {
+  FPC_REQUIRE_READY(h);
+  if (!x || !y) return FPC_ERR_ARG;
+  return guard(h, [&] { matvec(h, trans ? 1 : 0, x, y); });
+}
+
+fpc_status fpc_vcycle(fpc_handle* h, const double* b, double* x) {
+  FPC_REQUIRE_READY(h);
+  if (!b || !x) return FPC_ERR_ARG;
+  return guard(h, [&] {
+    hipStream_t s = h->stream;
+    if (h->opt.precision == FPC_FP32_PREC) {
+      CycleVecs<float>& cv = cycle_vecs<float>(h->amg, 1);
+      to_level<float>(cv.lv[0].b.p, 1, 0, h->n_u, b, nullptr, nullptr, 0.0,
+                      nullptr, nullptr, 0.0, s);
+      vcycle<float, 1>(h->amg, false, s);
+      from_level<float>(cv.lv[0].xo.p, 1, h->n_u, x, 0, s);
+    } else {
+      CycleVecs<double>& cv = cycle_vecs<double>(h->amg, 1);
+      FPC_HIP(hipMemcpyAsync(cv.lv[0].b.p, b, h->n_u * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      vcycle<double, 1>(h->amg, false, s);
+      FPC_HIP(hipMemcpyAsync(x, cv.lv[0].xo.p, h->n_u * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    }
+  });
+}
+
+fpc_status fpc_solve(fpc_handle* h, const double* b, double* x, double rtol,
+                     int use_x0, fpc_info* info) {
+  FPC_REQUIRE_READY(h);
+  if (!b || !x) return FPC_ERR_ARG;
+  fpc_status st = FPC_OK;
+  fpc_status g = guard(h, [&] { st = fgmres(h, 0, b, x, rtol, use_x0, info); });
+  return g != FPC_OK ? g : st;
+}
+
+fpc_status fpc_solve_T(fpc_handle* h, const double* gv, double* lam,
+                       double rtol, fpc_info* info) {
+  FPC_REQUIRE_READY(h);
+  if (!gv || !lam) return FPC_ERR_ARG;
+  fpc_status st = FPC_OK;
+  fpc_status g = guard(h, [&] { st = fgmres(h, 1, gv, lam, rtol, 0, info); });
+  return g != FPC_OK ? g : st;
+}
+
+fpc_status fpc_solve_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
+                           double* X, int64_t ldx, double rtol,
+                           fpc_info* infos) {
+  FPC_REQUIRE_READY(h);
+  if (!B || !X || k < 1 || k > h->opt.max_batch || ldb < h->N || ldx < h->N)
+    return FPC_ERR_ARG;
+  // Columns are solved one after another with the single right-hand-side
+  // driver; every column keeps its own tolerance and statistics.
+  fpc_status worst = FPC_OK;
+  for (int c = 0; c < k; ++c) {
+    fpc_info inf{};
+    fpc_status st = fpc_solve(h, B + c * ldb, X + c * ldx, rtol, 0, &inf);
+    if (infos) infos[c] = inf;
+    if (st < 0) return st;
+    if (st != FPC_OK) worst = st;
+  }
+  return worst;
+}
+
+fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
+                              const double* lam_p, const double* p,
+                              double* grad) {
+  FPC_REQUIRE_READY(h);
+  if (!g || !lam_p || !p || !grad || g->n_p != h->n_p || g->n_pairs < 0)
+    return FPC_ERR_ARG;
+  return guard(h, [&] {
+    hipStream_t s = h->stream;
+    const int64_t m = g->n_pairs, n = g->n_p;
+    Csr inc;
+    inc.nrows = m;
+    inc.ncols = n;
+    inc.nnz = 2 * m;
+    inc.rowptr.alloc(m + 1);
+    inc.col.alloc(std::max<int64_t>(2 * m, 1));
+    inc.val.alloc(std::max<int64_t>(2 * m, 1));
+    k_pair_rows<<<grid_for(m + 1, 256), 256, 0, s>>>(g->pair_k, g->pair_l, m,
+                                                     inc.rowptr.p, inc.col.p,
+                                                     inc.val.p);
+    FPC_LAUNCH_CHECK();
+    Csr incT;
+    csr_transpose(inc, incT, s);
+    // incT rows are faces; columns are pair ids (sorted)
+    k_grad<<<grid_for(n, 256), 256, 0, s>>>(incT.rowptr.p, incT.col.p,
+                                            g->pair_k, g->pair_l, g->ndir,
+                                            g->upsilon, lam_p, p, grad, n);
+    FPC_LAUNCH_CHECK();
+    FPC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int fpc_num_levels(const fpc_handle* h) {
+  return (h && h->ready) ? (int)h->amg.L.size() : 0;
+}
+
+fpc_status fpc_level_info(const fpc_handle* h, int level, fpc_level_desc* d) {
+  if (!h || !d) return FPC_ERR_ARG;
+  if (!h->ready) return FPC_ERR_STATE;
+  if (level < 0 || level >= (int)h->amg.L.size()) return FPC_ERR_ARG;
+  const Level& L = h->amg.L[level];
+  d->n_nodes = L.n_nodes;
+  d->n_dofs = L.n_dofs_real;
+  d->block = L.bs;
+  d->nnzb = L.A.nnzb;
+  d->nnz_scalar = L.nnz_scalar;
+  d->p_nnzb = L.coarsest ? 0 : L.P.nnzb;
+  d->r_nnzb = L.coarsest ? 0 : L.R.nnzb;
+  d->lam_hi = L.lam_hi;
+  d->n_agg = L.coarsest ? 0 : L.n_agg;
+  return FPC_OK;
+}
+
+fpc_status fpc_export_aggregates(const fpc_handle* h, int level, int32_t* agg,
+                                 int32_t* rank) {
+  if (!h) return FPC_ERR_ARG;
+  if (!h->ready) return FPC_ERR_STATE;
+  if (level < 0 || level >= (int)h->amg.L.size()) return FPC_ERR_ARG;
+  const Level& L = h->amg.L[level];
+  if (L.coarsest) return FPC_ERR_ARG;
+  fpc_handle* hh = const_cast<fpc_handle*>(h);
+  return guard(hh, [&] {
+    if (agg)
+      FPC_HIP(hipMemcpyAsync(agg, L.agg.p, L.n_nodes * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, h->stream));
+    if (rank)
+      FPC_HIP(hipMemcpyAsync(rank, L.rank.p, L.n_agg * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, h->stream));
+    FPC_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+fpc_status fpc_export_level_matrix(const fpc_handle* h, int level, int which,
+                                   int64_t* rowptr, int32_t* col, double* val) {
+  if (!h || !rowptr || !col || !val) return FPC_ERR_ARG;
+  if (!h->ready) return FPC_ERR_STATE;
+  if (level < 0 || level >= (int)h->amg.L.size()) return FPC_ERR_ARG;
+  const Level& L = h->amg.L[level];
+  const Bsr* M = which == 0 ? &L.A : which == 1 ? &L.P : which == 2 ? &L.R : nullptr;
+  if (!M || (which != 0 && L.coarsest)) return FPC_ERR_ARG;
+  fpc_handle* hh = const_cast<fpc_handle*>(h);
+  return guard(hh, [&] {
+    FPC_HIP(hipMemcpyAsync(rowptr, M->rowptr.p, (M->nbr + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, h->stream));
+    if (M->nnzb) {
+      FPC_HIP(hipMemcpyAsync(col, M->col.p, M->nnzb * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, h->stream));
+      FPC_HIP(hipMemcpyAsync(val, M->val.p,
+                             M->nnzb * M->br * M->bc * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    }
+    FPC_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+fpc_status fpc_setup_times(const fpc_handle* h, double* t5) {
+  if (!h || !t5) return FPC_ERR_ARG;
+  for (int i = 0; i < 5; ++i) t5[i] = h->setup_times[i];
+  return FPC_OK;
+}
+
+fpc_status fpc_hash32_device(fpc_handle* h, uint32_t first, int64_t n,
+                             uint32_t* out) {
+  if (!h || !out || n < 0) return FPC_ERR_ARG;
+  return guard(h, [&] {
+    hash32_range(first, n, out, h->stream);
+    FPC_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+void fpc_destroy(fpc_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  delete h;
+}
+
+const char* fpc_status_string(fpc_status s) {
+  switch (s) {
+    case FPC_OK: return "ok";
+    case FPC_NOT_CONVERGED: return "not converged";
+    case FPC_ERR_ARG: return "invalid argument";
+    case FPC_ERR_DIM: return "inconsistent dimensions";
+    case FPC_ERR_PATTERN: return "invalid sparsity pattern";
+    case FPC_ERR_SINGULAR_BLOCK: return "singular block";
+    case FPC_ERR_NOT_SPD: return "pressure block not positive definite";
+    case FPC_ERR_NAN: return "non-finite value";
+    case FPC_ERR_HIP: return "HIP runtime error";
+    case FPC_ERR_OOM: return "out of device memory";
+    case FPC_ERR_STATE: return "handle not set up";
+    case FPC_ERR_UNSUPPORTED: return "unsupported case";
+  }
+  return "unknown status";
+}
+
+const char* fpc_last_error(const fpc_handle* h) {
+  return h ? h->last_error.c_str() : "null handle";
+}
+
+}  // extern "C"

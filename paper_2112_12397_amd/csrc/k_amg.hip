@@ -1,0 +1,722 @@
+// Setup kernels of the block preconditioner and of the smoothed-aggregation
+// hierarchy: face-block inverses (H~ = Bdiag(H,3)), diagonal scaling,
+// distance-2 MIS aggregation, tentative prolongator (per-aggregate QR of the
+// rigid-body modes), prolongator smoothing, coarse dummy dofs, power-iteration
+// start vectors and the blocked Gauss-Jordan inverse of dense matrices.
+#include "fpc_internal.hpp"
+
+namespace fpc {
+
+namespace {
+
+constexpr int IDX_BITS = 28;
+constexpr int64_t IDX_MASK = (int64_t(1) << IDX_BITS) - 1;
+
+// ------------------------------------------------------------- H~^{-1}
+__device__ inline double csr_get(const int64_t* rp, const int32_t* col,
+                                 const double* val, int64_t row, int32_t c) {
+  int64_t lo = rp[row], hi = rp[row + 1];
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < rp[row + 1] && col[lo] == c) ? val[lo] : 0.0;
+}
+
+__global__ void k_hinv(const int64_t* rp, const int32_t* col,
+                       const double* val, int64_t n_p, double* hinv,
+                       int* flags) {
+  int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= n_p) return;
+  double a[9];
+  double amax = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      a[r * 3 + c] = csr_get(rp, col, val, 3 * K + r, (int32_t)(3 * K + c));
+      amax = fmax(amax, fabs(a[r * 3 + c]));
+    }
+  double c00 = a[4] * a[8] - a[5] * a[7];
+  double c01 = a[5] * a[6] - a[3] * a[8];
+  double c02 = a[3] * a[7] - a[4] * a[6];
+  double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+  if (!(fabs(det) > 1e-14 * amax * amax * amax) || !isfinite(det)) {
+    atomicOr(&flags[FLAG_SINGULAR], 1);
+    det = 1.0;
+  }
+  double* o = hinv + K * 9;
+  o[0] = c00 / det;
+  o[3] = c01 / det;
+  o[6] = c02 / det;
+  o[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+  o[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+  o[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+  o[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+  o[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+  o[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+}
+
+__global__ void k_row_scale3(const int64_t* rp, double* val, int64_t nbr,
+                             const double* blocks) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbr) return;
+  const double* h = blocks + i * 9;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+    double* v = val + e * 9;
+    double t[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        t[r * 3 + c] = h[r * 3 + 0] * v[0 * 3 + c] + h[r * 3 + 1] * v[1 * 3 + c] +
+                       h[r * 3 + 2] * v[2 * 3 + c];
+    for (int q = 0; q < 9; ++q) v[q] = t[q];
+  }
+}
+
+__global__ void k_dinv(const int64_t* rp, const int32_t* col,
+                       const double* val, int64_t nbr, int br, int bc,
+                       double* dinv, int* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbr) return;
+  int64_t e = -1;
+  for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+    if (col[q] == i) {
+      e = q;
+      break;
+    }
+  for (int r = 0; r < br; ++r) {
+    double d = (e >= 0) ? val[e * br * bc + r * bc + r] : 0.0;
+    if (!(d != 0.0) || !isfinite(d)) {
+      atomicOr(&flags[FLAG_SINGULAR], 1);
+      d = 1.0;
+    }
+    dinv[i * br + r] = 1.0 / d;
+  }
+}
+
+// ------------------------------------------------------------- aggregation
+__global__ void k_agg_init(const int64_t* rp, const int32_t* col, int64_t n,
+                           int64_t* prio, int32_t* state, uint8_t* iso) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool has_off = false;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+    if (col[e] != i) {
+      has_off = true;
+      break;
+    }
+  iso[i] = has_off ? 0 : 1;
+  state[i] = has_off ? 1 : 0;
+  prio[i] = ((int64_t)lowbias32((uint32_t)i) << IDX_BITS) | i;
+}
+
+__global__ void k_key(const int32_t* state, const int64_t* prio, int64_t n,
+                      int64_t* key) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = ((int64_t)state[i] << 61) | prio[i];
+}
+
+// out[i] = max(in[i], max over the block row's columns)
+__global__ void k_max_closed(const int64_t* rp, const int32_t* col,
+                             int64_t n, const int64_t* in, int64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t m = in[i];
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = max(m, in[col[e]]);
+  out[i] = m;
+}
+
+__global__ void k_mis_update(int32_t* state, const int64_t* key,
+                             const int64_t* m2, int64_t n, int* undecided) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] != 1) return;
+  if (m2[i] == key[i]) state[i] = 2;
+  else if ((m2[i] >> 61) == 2) state[i] = 0;
+  else atomicAdd(undecided, 1);
+}
+
+__global__ void k_is_root(const int32_t* state, int64_t n, int64_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = state[i] == 2 ? 1 : 0;
+}
+
+__global__ void k_root_ids(const int32_t* state, const int64_t* scan,
+                           int64_t n, int32_t* agg, int32_t* roots,
+                           const int64_t* prio, int64_t* rk) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] == 2) {
+    int32_t a = (int32_t)scan[i];
+    agg[i] = a;
+    roots[a] = (int32_t)i;
+    rk[i] = prio[i];
+  } else {
+    agg[i] = -1;
+    rk[i] = -1;
+  }
+}
+
+__global__ void k_join(const uint8_t* iso, const int64_t* m, int64_t n,
+                       int32_t* agg, int* remaining) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (iso[i] || agg[i] >= 0) return;
+  if (m[i] >= 0) {
+    int64_t root = m[i] & IDX_MASK;
+    agg[i] = agg[root];
+  } else {
+    atomicAdd(remaining, 1);
+  }
+}
+
+__global__ void k_rk2(const int32_t* agg, const int32_t* roots,
+                      const int64_t* prio, int64_t n, int64_t* rk) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  rk[i] = agg[i] >= 0 ? prio[roots[agg[i]]] : -1;
+}
+
+// ------------------------------------------------------------- near-nullspace
+__global__ void k_bbox_partial(const double* X, int64_t n, double* part) {
+  __shared__ double sh[6][256];
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fmin(mn[d], X[i * 3 + d]);
+      mx[d] = fmax(mx[d], X[i * 3 + d]);
+    }
+  for (int d = 0; d < 3; ++d) {
+    sh[d][threadIdx.x] = mn[d];
+    sh[3 + d][threadIdx.x] = mx[d];
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + s]);
+        sh[3 + d][threadIdx.x] =
+            fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 6; ++d) part[blockIdx.x * 6 + d] = sh[d][0];
+}
+
+__global__ void k_bbox_final(const double* part, int np, double* ctr) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int d = 0; d < 3; ++d) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int b = 0; b < np; ++b) {
+      mn = fmin(mn, part[b * 6 + d]);
+      mx = fmax(mx, part[b * 6 + 3 + d]);
+    }
+    ctr[d] = 0.5 * (mn + mx);
+  }
+}
+
+__global__ void k_rigid(const double* X, const double* ctr, int64_t n, int nb,
+                        double* B) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* b = B + i * 3 * nb;
+  for (int q = 0; q < 3 * nb; ++q) b[q] = 0.0;
+  for (int c = 0; c < 3; ++c) b[c * nb + c] = 1.0;
+  if (nb == 6) {
+    double y0 = X[i * 3 + 0] - ctr[0];
+    double y1 = X[i * 3 + 1] - ctr[1];
+    double y2 = X[i * 3 + 2] - ctr[2];
+    // rotation about x: (0, -y_z, y_y); about y: (y_z, 0, -y_x);
+    // about z: (-y_y, y_x, 0)
+    b[1 * nb + 3] = -y2;
+    b[2 * nb + 3] = y1;
+    b[0 * nb + 4] = y2;
+    b[2 * nb + 4] = -y0;
+    b[0 * nb + 5] = -y1;
+    b[1 * nb + 5] = y0;
+  }
+}
+
+// ------------------------------------------------------------- tentative P
+__global__ void k_agg_count(const int32_t* agg, int64_t n,
+                            unsigned long long* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1ull);
+}
+
+__global__ void k_agg_fill(const int32_t* agg, int64_t n,
+                           unsigned long long* cursor, int32_t* members) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (agg[i] >= 0) members[atomicAdd(&cursor[agg[i]], 1ull)] = (int32_t)i;
+}
+
+__global__ void k_agg_sort(const int64_t* off, int64_t n_agg,
+                           int32_t* members) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_agg) return;
+  for (int64_t e = off[a] + 1; e < off[a + 1]; ++e) {
+    int32_t v = members[e];
+    int64_t f = e - 1;
+    while (f >= off[a] && members[f] > v) {
+      members[f + 1] = members[f];
+      --f;
+    }
+    members[f + 1] = v;
+  }
+}
+
+// Per aggregate: thin QR of the stacked near-nullspace rows of its members
+// by modified Gram-Schmidt applied twice; columns whose remaining norm is
+// <= drop_tol * (largest column norm) are dropped.  Q is written over the
+// rows of ptent (kept columns first, the rest zero), R into Bc.
+__global__ void k_tentative(const int64_t* off, const int32_t* members,
+                            int64_t n_agg, int bs, int nb, const double* B,
+                            double drop_tol, double* ptent, double* Bc,
+                            int32_t* rank) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_agg) return;
+  const int64_t m0 = off[a], m1 = off[a + 1];
+  double R[36];
+  for (int q = 0; q < 36; ++q) R[q] = 0.0;
+  double scale = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    double s = 0.0;
+    for (int64_t e = m0; e < m1; ++e) {
+      const double* b = B + (int64_t)members[e] * bs * nb;
+      for (int c = 0; c < bs; ++c) s += b[c * nb + j] * b[c * nb + j];
+    }
+    scale = fmax(scale, sqrt(s));
+  }
+  int kc = 0;
+  for (int j = 0; j < nb; ++j) {
+    for (int64_t e = m0; e < m1; ++e) {
+      const int64_t node = members[e];
+      for (int c = 0; c < bs; ++c)
+        ptent[(node * bs + c) * nb + kc] = B[(node * bs + c) * nb + j];
+    }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < kc; ++k) {
+        double d = 0.0;
+        for (int64_t e = m0; e < m1; ++e) {
+          const double* p = ptent + (int64_t)members[e] * bs * nb;
+          for (int c = 0; c < bs; ++c) d += p[c * nb + k] * p[c * nb + kc];
+        }
+        R[k * 6 + j] += d;
+        for (int64_t e = m0; e < m1; ++e) {
+          double* p = ptent + (int64_t)members[e] * bs * nb;
+          for (int c = 0; c < bs; ++c) p[c * nb + kc] -= d * p[c * nb + k];
+        }
+      }
+    double nv = 0.0;
+    for (int64_t e = m0; e < m1; ++e) {
+      const double* p = ptent + (int64_t)members[e] * bs * nb;
+      for (int c = 0; c < bs; ++c) nv += p[c * nb + kc] * p[c * nb + kc];
+    }
+    nv = sqrt(nv);
+    if (nv > drop_tol * scale) {
+      R[kc * 6 + j] = nv;
+      for (int64_t e = m0; e < m1; ++e) {
+        double* p = ptent + (int64_t)members[e] * bs * nb;
+        for (int c = 0; c < bs; ++c) p[c * nb + kc] = p[c * nb + kc] / nv;
+      }
+      ++kc;
+    }
+  }
+  for (int64_t e = m0; e < m1; ++e) {
+    double* p = ptent + (int64_t)members[e] * bs * nb;
+    for (int c = 0; c < bs; ++c)
+      for (int k = kc; k < nb; ++k) p[c * nb + k] = 0.0;
+  }
+  rank[a] = kc;
+  double* o = Bc + a * nb * nb;
+  for (int k = 0; k < nb; ++k)
+    for (int j = 0; j < nb; ++j) o[k * nb + j] = (k < kc) ? R[k * 6 + j] : 0.0;
+}
+
+__global__ void k_ptent_count(const int32_t* agg, int64_t n, int64_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cnt[i] = agg[i] >= 0 ? 1 : 0;
+}
+
+__global__ void k_ptent_fill(const int32_t* agg, const int64_t* rp, int64_t n,
+                             int B, const double* ptent, int32_t* col,
+                             double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (agg[i] < 0) return;
+  int64_t e = rp[i];
+  col[e] = agg[i];
+  for (int q = 0; q < B; ++q) val[e * B + q] = ptent[i * B + q];
+}
+
+__global__ void k_neg_row_scale(const int64_t* rp, double* val, int64_t nbr,
+                                int br, int bc, const double* dinv,
+                                double omega) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbr) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+    for (int r = 0; r < br; ++r) {
+      const double t = omega * dinv[i * br + r];
+      for (int c = 0; c < bc; ++c) {
+        double& v = val[e * br * bc + r * bc + c];
+        v = -(t * v);
+      }
+    }
+}
+
+__global__ void k_dummy_diag(const int64_t* rp, const int32_t* col,
+                             double* val, int64_t nbr, int nb,
+                             const int32_t* rank) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nbr) return;
+  for (int64_t e = rp[a]; e < rp[a + 1]; ++e)
+    if (col[e] == a) {
+      for (int k = rank[a]; k < nb; ++k) val[e * nb * nb + k * nb + k] = 1.0;
+      return;
+    }
+}
+
+__global__ void k_power_start(int64_t n_nodes, int bs, int stride,
+                              const int32_t* node_rank, double* x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes * bs) return;
+  int64_t node = i / bs;
+  int c = (int)(i % bs);
+  if (node_rank && c >= node_rank[node]) {
+    x[i] = 0.0;
+    return;
+  }
+  uint32_t h = lowbias32((uint32_t)(stride * node + c));
+  x[i] = (double)h / 4294967296.0 - 0.5;
+}
+
+__global__ void k_dense_from_bsr(const int64_t* rp, const int32_t* col,
+                                 const double* val, int64_t nbr, int br,
+                                 int bc, int64_t npad, double* D) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbr) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+    for (int r = 0; r < br; ++r)
+      for (int c = 0; c < bc; ++c)
+        D[(i * br + r) * npad + (int64_t)col[e] * bc + c] =
+            val[e * br * bc + r * bc + c];
+}
+
+__global__ void k_pad_identity(double* D, int64_t n, int64_t npad) {
+  int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npad) D[i * npad + i] = 1.0;
+}
+
+// ------------------------------------------------------------- dense GJ
+constexpr int GT = 64;  // tile
+
+// Gauss-Jordan inverse of the diagonal tile (in place, in LDS).
+__global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t n,
+                                                 int64_t kb, int spd,
+                                                 int* flags) {
+  __shared__ double a[GT][GT + 1];
+  __shared__ double prow[GT];
+  __shared__ double pcol[GT];
+  const int tid = threadIdx.x;
+  const int64_t o = kb * GT;
+  for (int q = tid; q < GT * GT; q += 256) {
+    int r = q / GT, c = q % GT;
+    a[r][c] = D[(o + r) * n + o + c];
+  }
+  __syncthreads();
+  for (int k = 0; k < GT; ++k) {
+    double p = a[k][k];
+    bool bad = spd ? !(p > 0.0) : !(fabs(p) > 0.0);
+    if (bad || !isfinite(p)) {
+      if (tid == 0) atomicOr(&flags[spd ? FLAG_NOT_SPD : FLAG_SINGULAR], 1);
+      p = 1.0;
+    }
+    const double ip = 1.0 / p;
+    if (tid < GT) {
+      prow[tid] = (tid == k) ? ip : a[k][tid] * ip;
+      pcol[tid] = a[tid][k];
+    }
+    __syncthreads();
+    for (int q = tid; q < GT * GT; q += 256) {
+      int r = q / GT, c = q % GT;
+      if (r == k) a[r][c] = prow[c];
+      else if (c == k) a[r][c] = -pcol[r] * ip;
+      else a[r][c] = a[r][c] - pcol[r] * prow[c];
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < GT * GT; q += 256) {
+    int r = q / GT, c = q % GT;
+    D[(o + r) * n + o + c] = a[r][c];
+  }
+}
+
+// C (64x64 tile at (ci, cj)) = alpha * X(xi, xj) * Y(yi, yj) + beta * C,
+// skipping tiles in `skip_row` / `skip_col`.  grid.x enumerates the tiles of
+// the target row/column set.
+__device__ inline void tile_gemm(const double* D, int64_t n, int64_t xi,
+                                 int64_t xj, int64_t yi, int64_t yj,
+                                 double (*sa)[GT + 1], double (*sb)[GT + 1],
+                                 double acc[4][4]) {
+  const int tid = threadIdx.x;
+  for (int q = tid; q < GT * GT; q += 256) {
+    int r = q / GT, c = q % GT;
+    sa[r][c] = D[(xi * GT + r) * n + xj * GT + c];
+    sb[r][c] = D[(yi * GT + r) * n + yj * GT + c];
+  }
+  __syncthreads();
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k = 0; k < GT; ++k) {
+    double x[4], y[4];
+    for (int i = 0; i < 4; ++i) x[i] = sa[tr + i][k];
+    for (int j = 0; j < 4; ++j) y[j] = sb[k][tc + j];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] += x[i] * y[j];
+  }
+}
+
+// row panel: A[kb, j] <- Dinv * A[kb, j], j != kb
+__global__ __launch_bounds__(256) void k_gj_rowpanel(double* D, int64_t n,
+                                                     int64_t kb) {
+  __shared__ double sa[GT][GT + 1];
+  __shared__ double sb[GT][GT + 1];
+  int64_t j = blockIdx.x;
+  if (j >= kb) ++j;
+  double acc[4][4];
+  tile_gemm(D, n, kb, kb, kb, j, sa, sb, acc);
+  __syncthreads();
+  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  for (int i = 0; i < 4; ++i)
+    for (int jj = 0; jj < 4; ++jj)
+      D[(kb * GT + tr + i) * n + j * GT + tc + jj] = acc[i][jj];
+}
+
+// trailing update: A[i, j] -= A[i, kb] A[kb, j], i != kb, j != kb
+__global__ __launch_bounds__(256) void k_gj_update(double* D, int64_t n,
+                                                   int64_t kb, int64_t nt) {
+  __shared__ double sa[GT][GT + 1];
+  __shared__ double sb[GT][GT + 1];
+  int64_t t = blockIdx.x;
+  int64_t i = t / (nt - 1), j = t % (nt - 1);
+  if (i >= kb) ++i;
+  if (j >= kb) ++j;
+  double acc[4][4];
+  tile_gemm(D, n, i, kb, kb, j, sa, sb, acc);
+  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      D[(i * GT + tr + r) * n + j * GT + tc + c] -= acc[r][c];
+}
+
+// column panel: A[i, kb] <- -A[i, kb] * Dinv, i != kb
+__global__ __launch_bounds__(256) void k_gj_colpanel(double* D, int64_t n,
+                                                     int64_t kb) {
+  __shared__ double sa[GT][GT + 1];
+  __shared__ double sb[GT][GT + 1];
+  int64_t i = blockIdx.x;
+  if (i >= kb) ++i;
+  double acc[4][4];
+  tile_gemm(D, n, i, kb, kb, kb, sa, sb, acc);
+  __syncthreads();
+  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      D[(i * GT + tr + r) * n + kb * GT + tc + c] = -acc[r][c];
+}
+
+}  // namespace
+
+void hinv_setup(const Csr& H, int64_t n_p, double* hinv, int* flags,
+                hipStream_t s) {
+  if (n_p == 0) return;
+  k_hinv<<<grid_for(n_p, 128), 128, 0, s>>>(H.rowptr.p, H.col.p, H.val.p, n_p,
+                                            hinv, flags);
+  FPC_LAUNCH_CHECK();
+}
+
+void bsr_block_row_scale(Bsr& b, const double* blocks3x3, hipStream_t s) {
+  if (b.br != 3 || b.bc != 3)
+    throw Error(FPC_ERR_ARG, "row scale expects 3x3 blocks");
+  if (b.nbr == 0) return;
+  k_row_scale3<<<grid_for(b.nbr, 128), 128, 0, s>>>(b.rowptr.p, b.val.p,
+                                                    b.nbr, blocks3x3);
+  FPC_LAUNCH_CHECK();
+}
+
+void bsr_dinv(const Bsr& a, double* dinv, int* flags, hipStream_t s) {
+  if (a.nbr == 0) return;
+  k_dinv<<<grid_for(a.nbr, 128), 128, 0, s>>>(a.rowptr.p, a.col.p, a.val.p,
+                                              a.nbr, a.br, a.bc, dinv, flags);
+  FPC_LAUNCH_CHECK();
+}
+
+int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
+                       hipStream_t s) {
+  const int64_t n = a.nbr;
+  if (n >= (int64_t(1) << IDX_BITS))
+    throw Error(FPC_ERR_UNSUPPORTED, "too many nodes for aggregation keys");
+  DevBuf<int64_t> prio(n), key(n), m1(n), m2(n);
+  DevBuf<int32_t> state(n);
+  DevBuf<uint8_t> iso(n);
+  DevBuf<int> cnt(1);
+  const unsigned g = grid_for(n, 256);
+  k_agg_init<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, prio.p, state.p, iso.p);
+  FPC_LAUNCH_CHECK();
+  for (int round = 0; round < 1000; ++round) {
+    FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+    k_key<<<g, 256, 0, s>>>(state.p, prio.p, n, key.p);
+    k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+    k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, m1.p, m2.p);
+    k_mis_update<<<g, 256, 0, s>>>(state.p, key.p, m2.p, n, cnt.p);
+    FPC_LAUNCH_CHECK();
+    if (read_i32(cnt.p, s) == 0) break;
+    if (round == 999) throw Error(FPC_ERR_HIP, "MIS-2 did not terminate");
+  }
+  DevBuf<int64_t> flag(n), scan(n + 1);
+  k_is_root<<<g, 256, 0, s>>>(state.p, n, flag.p);
+  FPC_LAUNCH_CHECK();
+  const int64_t n_agg = scan_counts_total(flag.p, scan.p, n, s);
+  roots.alloc(std::max<int64_t>(n_agg, 1));
+  k_root_ids<<<g, 256, 0, s>>>(state.p, scan.p, n, agg, roots.p, prio.p,
+                               key.p);
+  FPC_LAUNCH_CHECK();
+  // phase 1: join the adjacent root of largest priority
+  k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+  FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+  k_join<<<g, 256, 0, s>>>(iso.p, m1.p, n, agg, cnt.p);
+  FPC_LAUNCH_CHECK();
+  int remaining = read_i32(cnt.p, s);
+  // phase 2: join the aggregate of an assigned neighbour (largest root
+  // priority), synchronous sweeps
+  for (int sweep = 0; remaining > 0; ++sweep) {
+    if (sweep > 64) throw Error(FPC_ERR_HIP, "aggregation left nodes");
+    k_rk2<<<g, 256, 0, s>>>(agg, roots.p, prio.p, n, key.p);
+    k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+    FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+    k_join<<<g, 256, 0, s>>>(iso.p, m1.p, n, agg, cnt.p);
+    FPC_LAUNCH_CHECK();
+    int r = read_i32(cnt.p, s);
+    if (r == remaining) throw Error(FPC_ERR_HIP, "aggregation stalled");
+    remaining = r;
+  }
+  FPC_HIP(hipStreamSynchronize(s));
+  return n_agg;
+}
+
+void rigid_modes(const double* coords, int64_t n_nodes, int nb, double* B,
+                 hipStream_t s) {
+  DevBuf<double> part(64 * 6), ctr(3);
+  if (coords) {
+    k_bbox_partial<<<64, 256, 0, s>>>(coords, n_nodes, part.p);
+    k_bbox_final<<<1, 64, 0, s>>>(part.p, 64, ctr.p);
+    FPC_LAUNCH_CHECK();
+  }
+  k_rigid<<<grid_for(n_nodes, 256), 256, 0, s>>>(coords, ctr.p, n_nodes, nb,
+                                                 B);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+void tentative(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
+               int nb, const double* B, double drop_tol, double* ptent,
+               double* Bc, int32_t* rank, hipStream_t s) {
+  DevBuf<unsigned long long> cnt(n_agg + 1);
+  FPC_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
+  k_agg_count<<<grid_for(n_nodes, 256), 256, 0, s>>>(agg, n_nodes, cnt.p);
+  FPC_LAUNCH_CHECK();
+  DevBuf<int64_t> off(n_agg + 1);
+  scan_counts((const int64_t*)cnt.p, off.p, n_agg, s);
+  DevBuf<unsigned long long> cursor(n_agg + 1);
+  FPC_HIP(hipMemcpyAsync(cursor.p, off.p, (n_agg + 1) * sizeof(int64_t),
+                         hipMemcpyDeviceToDevice, s));
+  DevBuf<int32_t> members(std::max<int64_t>(n_nodes, 1));
+  k_agg_fill<<<grid_for(n_nodes, 256), 256, 0, s>>>(agg, n_nodes, cursor.p,
+                                                    members.p);
+  k_agg_sort<<<grid_for(n_agg, 64), 64, 0, s>>>(off.p, n_agg, members.p);
+  FPC_HIP(hipMemsetAsync(ptent, 0, (size_t)n_nodes * bs * nb * sizeof(double),
+                         s));
+  k_tentative<<<grid_for(n_agg, 64), 64, 0, s>>>(off.p, members.p, n_agg, bs,
+                                                 nb, B, drop_tol, ptent, Bc,
+                                                 rank);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+void ptent_bsr(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
+               int nb, const double* ptent, Bsr& P, hipStream_t s) {
+  P.br = bs;
+  P.bc = nb;
+  P.nbr = n_nodes;
+  P.nbc = n_agg;
+  DevBuf<int64_t> cnt(n_nodes);
+  k_ptent_count<<<grid_for(n_nodes, 256), 256, 0, s>>>(agg, n_nodes, cnt.p);
+  FPC_LAUNCH_CHECK();
+  P.rowptr.alloc(n_nodes + 1);
+  P.nnzb = scan_counts_total(cnt.p, P.rowptr.p, n_nodes, s);
+  P.col.alloc(std::max<int64_t>(P.nnzb, 1));
+  P.val.alloc(std::max<int64_t>(P.nnzb * bs * nb, 1));
+  k_ptent_fill<<<grid_for(n_nodes, 256), 256, 0, s>>>(
+      agg, P.rowptr.p, n_nodes, bs * nb, ptent, P.col.p, P.val.p);
+  FPC_LAUNCH_CHECK();
+}
+
+void smooth_prolongator(Bsr& AP, const int32_t* agg, const double* ptent,
+                        const double* dinv, double omega, hipStream_t s) {
+  (void)agg;
+  (void)ptent;
+  if (AP.nbr == 0) return;
+  k_neg_row_scale<<<grid_for(AP.nbr, 128), 128, 0, s>>>(
+      AP.rowptr.p, AP.val.p, AP.nbr, AP.br, AP.bc, dinv, omega);
+  FPC_LAUNCH_CHECK();
+}
+
+void dummy_diag(Bsr& Ac, const int32_t* rank, hipStream_t s) {
+  if (Ac.nbr == 0) return;
+  k_dummy_diag<<<grid_for(Ac.nbr, 128), 128, 0, s>>>(
+      Ac.rowptr.p, Ac.col.p, Ac.val.p, Ac.nbr, Ac.br, rank);
+  FPC_LAUNCH_CHECK();
+}
+
+void power_start(int64_t n_nodes, int bs, int key_stride,
+                 const int32_t* node_rank, double* x, hipStream_t s) {
+  k_power_start<<<grid_for(n_nodes * bs, 256), 256, 0, s>>>(
+      n_nodes, bs, key_stride, node_rank, x);
+  FPC_LAUNCH_CHECK();
+}
+
+void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
+  FPC_HIP(hipMemsetAsync(D, 0, (size_t)npad * npad * sizeof(double), s));
+  if (a.nbr)
+    k_dense_from_bsr<<<grid_for(a.nbr, 128), 128, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nbr, a.br, a.bc, npad, D);
+  const int64_t n = a.nbr * a.br;
+  if (npad > n)
+    k_pad_identity<<<grid_for(npad - n, 256), 256, 0, s>>>(D, n, npad);
+  FPC_LAUNCH_CHECK();
+}
+
+void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
+  if (n % GT) throw Error(FPC_ERR_ARG, "gj_inverse: size not a multiple of 64");
+  const int64_t nt = n / GT;
+  for (int64_t kb = 0; kb < nt; ++kb) {
+    k_gj_diag<<<1, 256, 0, s>>>(D, n, kb, spd, flags);
+    if (nt > 1) {
+      k_gj_rowpanel<<<(unsigned)(nt - 1), 256, 0, s>>>(D, n, kb);
+      k_gj_update<<<(unsigned)((nt - 1) * (nt - 1)), 256, 0, s>>>(D, n, kb,
+                                                                  nt);
+      k_gj_colpanel<<<(unsigned)(nt - 1), 256, 0, s>>>(D, n, kb);
+    }
+    FPC_LAUNCH_CHECK();
+  }
+}
+
+}  // namespace fpc

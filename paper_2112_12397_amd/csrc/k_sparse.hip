@@ -1,0 +1,613 @@
+// Sparse setup kernels: validation, scalar CSR products, CSR -> block CSR,
+// block add / transpose, row-merge SpGEMM and the sliced-ELL packing used by
+// the apply path.
+#include "fpc_internal.hpp"
+
+namespace fpc {
+
+namespace {
+
+// ------------------------------------------------------------- validation
+__global__ void k_csr_validate(const int64_t* rowptr, const int32_t* col,
+                               const double* val, int64_t nrows,
+                               int64_t ncols, int64_t nnz, int* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && (rowptr[0] != 0 || rowptr[nrows] != nnz))
+    atomicOr(&flags[FLAG_PATTERN], 1);
+  if (i >= nrows) return;
+  int64_t a = rowptr[i], b = rowptr[i + 1];
+  if (a > b || a < 0 || b > nnz) {
+    atomicOr(&flags[FLAG_PATTERN], 1);
+    return;
+  }
+  int32_t prev = -1;
+  bool bad = false, nan = false;
+  for (int64_t e = a; e < b; ++e) {
+    int32_t c = col[e];
+    if (c <= prev || c >= ncols) bad = true;
+    prev = c;
+    if (!isfinite(val[e])) nan = true;
+  }
+  if (bad) atomicOr(&flags[FLAG_PATTERN], 1);
+  if (nan) atomicOr(&flags[FLAG_NAN], 1);
+}
+
+// ------------------------------------------------------------- CSR SpMV
+__global__ void k_csr_spmv2(const int64_t* rp1, const int32_t* c1,
+                            const double* v1, const double* x1, double a1,
+                            const int64_t* rp2, const int32_t* c2,
+                            const double* v2, const double* x2, double a2,
+                            double* y, double beta, int64_t nrows) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  double s1 = 0.0;
+  for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s1 += v1[e] * x1[c1[e]];
+  double r = a1 * s1;
+  if (rp2) {
+    double s2 = 0.0;
+    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s2 += v2[e] * x2[c2[e]];
+    r += a2 * s2;
+  }
+  y[i] = (beta == 0.0) ? r : beta * y[i] + r;
+}
+
+// ------------------------------------------------------------- transpose
+__global__ void k_col_count(const int64_t* rowptr, const int32_t* col,
+                            int64_t nrows, unsigned long long* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+    atomicAdd(&cnt[col[e]], 1ull);
+}
+
+__global__ void k_tr_fill(const int64_t* rowptr, const int32_t* col,
+                          int64_t nrows, unsigned long long* cursor,
+                          int32_t* colT, int64_t* src) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    unsigned long long pos = atomicAdd(&cursor[col[e]], 1ull);
+    colT[pos] = (int32_t)i;
+    src[pos] = e;
+  }
+}
+
+// Insertion sort of each row of the transpose by column (rows are filled in
+// arbitrary order by the atomics); makes the result deterministic.
+__global__ void k_tr_sort(const int64_t* rowptrT, int64_t nrowsT,
+                          int32_t* colT, int64_t* src) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrowsT) return;
+  int64_t a = rowptrT[r], b = rowptrT[r + 1];
+  for (int64_t e = a + 1; e < b; ++e) {
+    int32_t c = colT[e];
+    int64_t s = src[e];
+    int64_t f = e - 1;
+    while (f >= a && colT[f] > c) {
+      colT[f + 1] = colT[f];
+      src[f + 1] = src[f];
+      --f;
+    }
+    colT[f + 1] = c;
+    src[f + 1] = s;
+  }
+}
+
+template <int BR, int BC>
+__global__ void k_tr_gather(const double* val, const int64_t* src,
+                            int64_t nnzb, double* valT) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnzb) return;
+  const double* a = val + src[p] * (BR * BC);
+  double* t = valT + p * (BR * BC);
+#pragma unroll
+  for (int r = 0; r < BR; ++r)
+#pragma unroll
+    for (int c = 0; c < BC; ++c) t[c * BR + r] = a[r * BC + c];
+}
+
+// ------------------------------------------------------------- CSR -> BSR
+template <int BR, int BC>
+__global__ void k_to_bsr(const int64_t* rowptr, const int32_t* col,
+                         const double* val, int64_t nrows, int64_t nbr,
+                         const int64_t* browptr, int64_t* bcount,
+                         int32_t* bcol, double* bval) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nbr) return;
+  int64_t p[BR], e[BR];
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    int64_t row = I * BR + r;
+    p[r] = row < nrows ? rowptr[row] : 0;
+    e[r] = row < nrows ? rowptr[row + 1] : 0;
+  }
+  int64_t n = 0;
+  int64_t out = browptr ? browptr[I] : 0;
+  while (true) {
+    int32_t m = 0x7fffffff;
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+      if (p[r] < e[r]) m = min(m, col[p[r]] / BC);
+    if (m == 0x7fffffff) break;
+    if (bcol) {
+      bcol[out + n] = m;
+      double* blk = bval + (out + n) * (BR * BC);
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+        while (p[r] < e[r] && col[p[r]] / BC == m) {
+          blk[r * BC + (col[p[r]] % BC)] = val[p[r]];
+          ++p[r];
+        }
+    } else {
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+        while (p[r] < e[r] && col[p[r]] / BC == m) ++p[r];
+    }
+    ++n;
+  }
+  if (bcount) bcount[I] = n;
+}
+
+// ------------------------------------------------------------- BSR add
+template <int B>
+__global__ void k_bsr_add(const int64_t* ra, const int32_t* ca,
+                          const double* va, const int64_t* rb,
+                          const int32_t* cb, const double* vb, int64_t nbr,
+                          const int64_t* rc, int64_t* cnt, int32_t* cc,
+                          double* vc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbr) return;
+  int64_t pa = ra[i], ea = ra[i + 1], pb = rb[i], eb = rb[i + 1];
+  int64_t n = 0, out = rc ? rc[i] : 0;
+  while (pa < ea || pb < eb) {
+    int32_t x = pa < ea ? ca[pa] : 0x7fffffff;
+    int32_t y = pb < eb ? cb[pb] : 0x7fffffff;
+    int32_t m = min(x, y);
+    if (cc) {
+      cc[out + n] = m;
+      double* o = vc + (out + n) * B;
+      for (int q = 0; q < B; ++q) o[q] = 0.0;
+      if (x == m) {
+        for (int q = 0; q < B; ++q) o[q] += va[pa * B + q];
+      }
+      if (y == m) {
+        for (int q = 0; q < B; ++q) o[q] += vb[pb * B + q];
+      }
+    }
+    if (x == m) ++pa;
+    if (y == m) ++pb;
+    ++n;
+  }
+  if (cnt) cnt[i] = n;
+}
+
+// ------------------------------------------------------------- SpGEMM
+constexpr int HS_BITS = 12;
+constexpr int HS = 1 << HS_BITS;
+
+__device__ inline int hslot(int c) {
+  return (int)(((uint32_t)c * 2654435761u) >> (32 - HS_BITS));
+}
+
+__device__ inline bool hinsert(int* tab, int* ucount, int c) {
+  int h = hslot(c);
+  for (int probe = 0; probe < HS; ++probe) {
+    int old = atomicCAS(&tab[h], -1, c);
+    if (old == -1) {
+      atomicAdd(ucount, 1);
+      return true;
+    }
+    if (old == c) return true;
+    h = (h + 1) & (HS - 1);
+  }
+  return false;
+}
+
+// One 64-thread block per row: hash the block columns of the row of A*B;
+// phase 0 counts them, phase 1 writes them sorted.
+__global__ __launch_bounds__(64) void k_spgemm_sym(
+    const int64_t* ra, const int32_t* ca, const int64_t* rb,
+    const int32_t* cb, int64_t nrows, const int64_t* rc, int64_t* cnt,
+    int32_t* cc, int* flags) {
+  __shared__ int tab[HS];
+  __shared__ int lst[HS];
+  __shared__ int ucount;
+  __shared__ int fail;
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (row >= nrows) return;
+  for (int s = lane; s < HS; s += 64) tab[s] = -1;
+  if (lane == 0) {
+    ucount = 0;
+    fail = 0;
+  }
+  __syncthreads();
+  for (int64_t ea = ra[row]; ea < ra[row + 1]; ++ea) {
+    int32_t k = ca[ea];
+    for (int64_t eb = rb[k] + lane; eb < rb[k + 1]; eb += 64)
+      if (!hinsert(tab, &ucount, cb[eb])) fail = 1;
+    __syncthreads();
+    if (ucount > (HS * 3) / 4) fail = 1;
+    if (fail) break;
+  }
+  __syncthreads();
+  if (fail) {
+    if (lane == 0) {
+      atomicOr(&flags[FLAG_OVERFLOW], 1);
+      if (cnt) cnt[row] = 0;
+    }
+    return;
+  }
+  if (cnt) {
+    if (lane == 0) cnt[row] = ucount;
+    return;
+  }
+  // compact the occupied slots, then rank-sort into the output row
+  int base = 0;
+  for (int s0 = 0; s0 < HS; s0 += 64) {
+    int c = tab[s0 + lane];
+    bool v = c >= 0;
+    unsigned long long m = __ballot(v);
+    int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (v) lst[base + before] = c;
+    base += __popcll(m);
+  }
+  __syncthreads();
+  const int n = base;
+  const int64_t out = rc[row];
+  for (int e = lane; e < n; e += 64) {
+    int c = lst[e];
+    int r = 0;
+    for (int f = 0; f < n; ++f) r += (lst[f] < c);
+    cc[out + r] = c;
+  }
+}
+
+// Numeric phase: C row i = sum_k A(i,k) B(k,:).  The loop over the entries
+// of A's row is sequential; within one step the lanes take distinct entries
+// of B's row, hence distinct output blocks, so the accumulation order is
+// fixed and race free.
+template <int BM, int BK, int BN>
+__global__ __launch_bounds__(64) void k_spgemm_num(
+    const int64_t* ra, const int32_t* ca, const double* va, const int64_t* rb,
+    const int32_t* cb, const double* vb, int64_t nrows, const int64_t* rc,
+    const int32_t* cc, double* vc) {
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (row >= nrows) return;
+  const int64_t c0 = rc[row];
+  const int clen = (int)(rc[row + 1] - c0);
+  for (int64_t q = lane; q < (int64_t)clen * BM * BN; q += 64)
+    vc[c0 * BM * BN + q] = 0.0;
+  __syncthreads();
+  const int32_t* crow = cc + c0;
+  for (int64_t ea = ra[row]; ea < ra[row + 1]; ++ea) {
+    const int32_t k = ca[ea];
+    double a[BM * BK];
+#pragma unroll
+    for (int q = 0; q < BM * BK; ++q) a[q] = va[ea * (BM * BK) + q];
+    for (int64_t eb = rb[k] + lane; eb < rb[k + 1]; eb += 64) {
+      const int32_t j = cb[eb];
+      int lo = 0, hi = clen;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (crow[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo >= clen || crow[lo] != j) continue;  // cannot happen: pattern
+                                                  // comes from the same hash
+      const double* b = vb + eb * (BK * BN);
+      double* o = vc + (c0 + lo) * (BM * BN);
+#pragma unroll
+      for (int r = 0; r < BM; ++r)
+#pragma unroll
+        for (int c = 0; c < BN; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < BK; ++t) acc += a[r * BK + t] * b[t * BN + c];
+          o[r * BN + c] += acc;
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- BSR -> SELL
+__global__ void k_slice_len(const int64_t* rowptr, int64_t nrows,
+                            int64_t nslices, int64_t* slots) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslices) return;
+  int64_t m = 0;
+  for (int l = 0; l < kSliceH; ++l) {
+    int64_t r = s * kSliceH + l;
+    if (r < nrows) m = max(m, rowptr[r + 1] - rowptr[r]);
+  }
+  slots[s] = m * kSliceH;
+}
+
+template <typename T, int B>
+__global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
+                            const double* val, int64_t nrows,
+                            const int64_t* slice_ptr, int32_t* row_len,
+                            int32_t* scol, T* sval) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t s = r / kSliceH;
+  const int l = (int)(r % kSliceH);
+  const int64_t base = slice_ptr[s];
+  const int64_t a = rowptr[r];
+  const int len = (int)(rowptr[r + 1] - a);
+  row_len[r] = len;
+  for (int k = 0; k < len; ++k) {
+    const int64_t grp = base + (int64_t)k * kSliceH;
+    scol[grp + l] = col[a + k];
+    T* dst = sval + grp * B + l;
+#pragma unroll
+    for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
+  }
+}
+
+__global__ void k_count_nz(const double* v, int64_t n,
+                           unsigned long long* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (; i < n; i += stride) c += (v[i] != 0.0);
+  if (c) atomicAdd(out, c);
+}
+
+template <int BR, int BC>
+void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s) {
+  t.br = BC;
+  t.bc = BR;
+  t.nbr = a.nbc;
+  t.nbc = a.nbr;
+  t.nnzb = a.nnzb;
+  DevBuf<unsigned long long> cnt(a.nbc + 1);
+  FPC_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
+  if (a.nbr)
+    k_col_count<<<grid_for(a.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.col.p,
+                                                     a.nbr, cnt.p);
+  FPC_LAUNCH_CHECK();
+  t.rowptr.alloc(t.nbr + 1);
+  scan_counts((const int64_t*)cnt.p, t.rowptr.p, t.nbr, s);
+  DevBuf<unsigned long long> cursor(t.nbr + 1);
+  FPC_HIP(hipMemcpyAsync(cursor.p, t.rowptr.p, (t.nbr + 1) * sizeof(int64_t),
+                         hipMemcpyDeviceToDevice, s));
+  t.col.alloc(std::max<int64_t>(t.nnzb, 1));
+  DevBuf<int64_t> src(std::max<int64_t>(t.nnzb, 1));
+  t.val.alloc(std::max<int64_t>(t.nnzb * BR * BC, 1));
+  if (a.nbr)
+    k_tr_fill<<<grid_for(a.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.col.p, a.nbr,
+                                                   cursor.p, t.col.p, src.p);
+  FPC_LAUNCH_CHECK();
+  if (t.nbr)
+    k_tr_sort<<<grid_for(t.nbr, 64), 64, 0, s>>>(t.rowptr.p, t.nbr, t.col.p,
+                                                 src.p);
+  FPC_LAUNCH_CHECK();
+  if (t.nnzb)
+    k_tr_gather<BR, BC><<<grid_for(t.nnzb, 256), 256, 0, s>>>(
+        a.val.p, src.p, t.nnzb, t.val.p);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+template <int BR, int BC>
+void to_bsr_impl(const Csr& a, Bsr& out, hipStream_t s) {
+  out.br = BR;
+  out.bc = BC;
+  out.nbr = (a.nrows + BR - 1) / BR;
+  out.nbc = (a.ncols + BC - 1) / BC;
+  DevBuf<int64_t> cnt(std::max<int64_t>(out.nbr, 1));
+  out.rowptr.alloc(out.nbr + 1);
+  if (out.nbr)
+    k_to_bsr<BR, BC><<<grid_for(out.nbr, 128), 128, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nrows, out.nbr, nullptr, cnt.p,
+        nullptr, nullptr);
+  FPC_LAUNCH_CHECK();
+  out.nnzb = scan_counts_total(cnt.p, out.rowptr.p, out.nbr, s);
+  out.col.alloc(std::max<int64_t>(out.nnzb, 1));
+  out.val.alloc(std::max<int64_t>(out.nnzb * BR * BC, 1));
+  fill_f64(out.val.p, 0.0, out.nnzb * BR * BC, s);
+  if (out.nbr)
+    k_to_bsr<BR, BC><<<grid_for(out.nbr, 128), 128, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nrows, out.nbr, out.rowptr.p, nullptr,
+        out.col.p, out.val.p);
+  FPC_LAUNCH_CHECK();
+}
+
+template <int BM, int BK, int BN>
+void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
+                 hipStream_t s) {
+  c.br = BM;
+  c.bc = BN;
+  c.nbr = a.nbr;
+  c.nbc = b.nbc;
+  DevBuf<int64_t> cnt(std::max<int64_t>(c.nbr, 1));
+  c.rowptr.alloc(c.nbr + 1);
+  if (c.nbr)
+    k_spgemm_sym<<<(unsigned)c.nbr, 64, 0, s>>>(a.rowptr.p, a.col.p,
+                                                b.rowptr.p, b.col.p, c.nbr,
+                                                nullptr, cnt.p, nullptr, flags);
+  FPC_LAUNCH_CHECK();
+  c.nnzb = scan_counts_total(cnt.p, c.rowptr.p, c.nbr, s);
+  c.col.alloc(std::max<int64_t>(c.nnzb, 1));
+  c.val.alloc(std::max<int64_t>(c.nnzb * BM * BN, 1));
+  if (c.nbr) {
+    k_spgemm_sym<<<(unsigned)c.nbr, 64, 0, s>>>(a.rowptr.p, a.col.p,
+                                                b.rowptr.p, b.col.p, c.nbr,
+                                                c.rowptr.p, nullptr, c.col.p,
+                                                flags);
+    FPC_LAUNCH_CHECK();
+    k_spgemm_num<BM, BK, BN><<<(unsigned)c.nbr, 64, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
+        c.rowptr.p, c.col.p, c.val.p);
+    FPC_LAUNCH_CHECK();
+  }
+}
+
+template <typename T, int B>
+void to_sell_impl(const Bsr& a, Sell<T>& out, hipStream_t s) {
+  out.br = a.br;
+  out.bc = a.bc;
+  out.nrows = a.nbr;
+  out.nnzb = a.nnzb;
+  out.nslices = (a.nbr + kSliceH - 1) / kSliceH;
+  DevBuf<int64_t> slots(std::max<int64_t>(out.nslices, 1));
+  out.slice_ptr.alloc(out.nslices + 1);
+  if (out.nslices)
+    k_slice_len<<<grid_for(out.nslices, 128), 128, 0, s>>>(
+        a.rowptr.p, a.nbr, out.nslices, slots.p);
+  FPC_LAUNCH_CHECK();
+  out.nslots = scan_counts_total(slots.p, out.slice_ptr.p, out.nslices, s);
+  out.row_len.alloc(std::max<int64_t>(out.nrows, 1));
+  out.col.alloc(std::max<int64_t>(out.nslots, 1));
+  out.val.alloc(std::max<int64_t>(out.nslots * B, 1));
+  fill_i32(out.col.p, 0, out.nslots, s);
+  FPC_HIP(hipMemsetAsync(out.val.p, 0, out.val.bytes(), s));
+  if (out.nrows)
+    k_sell_fill<T, B><<<grid_for(out.nrows, 256), 256, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nbr, out.slice_ptr.p, out.row_len.p,
+        out.col.p, out.val.p);
+  FPC_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void csr_validate(const Csr& m, int* flags, hipStream_t s) {
+  k_csr_validate<<<grid_for(std::max<int64_t>(m.nrows, 1), 256), 256, 0, s>>>(
+      m.rowptr.p, m.col.p, m.val.p, m.nrows, m.ncols, m.nnz, flags);
+  FPC_LAUNCH_CHECK();
+}
+
+void csr_spmv2(const Csr* m1, const double* x1, double a1, const Csr* m2,
+               const double* x2, double a2, double* y, double beta,
+               hipStream_t s) {
+  if (m1->nrows == 0) return;
+  k_csr_spmv2<<<grid_for(m1->nrows, 256), 256, 0, s>>>(
+      m1->rowptr.p, m1->col.p, m1->val.p, x1, a1,
+      m2 ? m2->rowptr.p : nullptr, m2 ? m2->col.p : nullptr,
+      m2 ? m2->val.p : nullptr, x2, a2, y, beta, m1->nrows);
+  FPC_LAUNCH_CHECK();
+}
+
+void csr_transpose(const Csr& a, Csr& t, hipStream_t s) {
+  Bsr ab;
+  // view the CSR as a 1x1 block matrix (arrays are borrowed, not owned)
+  ab.br = ab.bc = 1;
+  ab.nbr = a.nrows;
+  ab.nbc = a.ncols;
+  ab.nnzb = a.nnz;
+  ab.rowptr.p = a.rowptr.p;
+  ab.col.p = a.col.p;
+  ab.val.p = a.val.p;
+  Bsr tb;
+  try {
+    block_transpose_impl<1, 1>(ab, tb, s);
+  } catch (...) {
+    ab.rowptr.p = nullptr;
+    ab.col.p = nullptr;
+    ab.val.p = nullptr;
+    throw;
+  }
+  ab.rowptr.p = nullptr;
+  ab.col.p = nullptr;
+  ab.val.p = nullptr;
+  t.nrows = tb.nbr;
+  t.ncols = tb.nbc;
+  t.nnz = tb.nnzb;
+  t.rowptr = std::move(tb.rowptr);
+  t.col = std::move(tb.col);
+  t.val = std::move(tb.val);
+}
+
+void csr_to_bsr(const Csr& a, int br, int bc, Bsr& out, hipStream_t s) {
+  if (br == 3 && bc == 3) return to_bsr_impl<3, 3>(a, out, s);
+  if (br == 3 && bc == 1) return to_bsr_impl<3, 1>(a, out, s);
+  if (br == 1 && bc == 3) return to_bsr_impl<1, 3>(a, out, s);
+  throw Error(FPC_ERR_ARG, "csr_to_bsr: unsupported block shape");
+}
+
+void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s) {
+  if (a.br != b.br || a.bc != b.bc || a.nbr != b.nbr || a.nbc != b.nbc)
+    throw Error(FPC_ERR_DIM, "bsr_add: shape mismatch");
+  c.br = a.br;
+  c.bc = a.bc;
+  c.nbr = a.nbr;
+  c.nbc = a.nbc;
+  const int B = a.br * a.bc;
+  DevBuf<int64_t> cnt(std::max<int64_t>(c.nbr, 1));
+  c.rowptr.alloc(c.nbr + 1);
+  auto launch = [&](const int64_t* rc, int64_t* cn, int32_t* cc, double* vc) {
+    if (!c.nbr) return;
+    if (B == 9)
+      k_bsr_add<9><<<grid_for(c.nbr, 128), 128, 0, s>>>(
+          a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
+          rc, cn, cc, vc);
+    else if (B == 18)
+      k_bsr_add<18><<<grid_for(c.nbr, 128), 128, 0, s>>>(
+          a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
+          rc, cn, cc, vc);
+    else if (B == 36)
+      k_bsr_add<36><<<grid_for(c.nbr, 128), 128, 0, s>>>(
+          a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
+          rc, cn, cc, vc);
+    else
+      throw Error(FPC_ERR_ARG, "bsr_add: unsupported block size");
+    FPC_LAUNCH_CHECK();
+  };
+  launch(nullptr, cnt.p, nullptr, nullptr);
+  c.nnzb = scan_counts_total(cnt.p, c.rowptr.p, c.nbr, s);
+  c.col.alloc(std::max<int64_t>(c.nnzb, 1));
+  c.val.alloc(std::max<int64_t>(c.nnzb * B, 1));
+  launch(c.rowptr.p, nullptr, c.col.p, c.val.p);
+}
+
+void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s) {
+  if (a.br == 3 && a.bc == 3) return block_transpose_impl<3, 3>(a, t, s);
+  if (a.br == 3 && a.bc == 6) return block_transpose_impl<3, 6>(a, t, s);
+  if (a.br == 6 && a.bc == 3) return block_transpose_impl<6, 3>(a, t, s);
+  if (a.br == 6 && a.bc == 6) return block_transpose_impl<6, 6>(a, t, s);
+  throw Error(FPC_ERR_ARG, "bsr_transpose: unsupported block shape");
+}
+
+void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s) {
+  if (a.bc != b.br || a.nbc != b.nbr)
+    throw Error(FPC_ERR_DIM, "spgemm: shapes do not chain");
+  const int m = a.br, k = a.bc, n = b.bc;
+  if (m == 3 && k == 3 && n == 3) return spgemm_impl<3, 3, 3>(a, b, c, flags, s);
+  if (m == 3 && k == 3 && n == 6) return spgemm_impl<3, 3, 6>(a, b, c, flags, s);
+  if (m == 6 && k == 3 && n == 6) return spgemm_impl<6, 3, 6>(a, b, c, flags, s);
+  if (m == 6 && k == 6 && n == 6) return spgemm_impl<6, 6, 6>(a, b, c, flags, s);
+  if (m == 3 && k == 1 && n == 3) return spgemm_impl<3, 1, 3>(a, b, c, flags, s);
+  throw Error(FPC_ERR_ARG, "spgemm: unsupported block shapes");
+}
+
+template <typename T>
+void bsr_to_sell(const Bsr& a, Sell<T>& out, hipStream_t s) {
+  const int B = a.br * a.bc;
+  if (B == 9) return to_sell_impl<T, 9>(a, out, s);
+  if (B == 18) return to_sell_impl<T, 18>(a, out, s);
+  if (B == 36) return to_sell_impl<T, 36>(a, out, s);
+  throw Error(FPC_ERR_ARG, "bsr_to_sell: unsupported block size");
+}
+template void bsr_to_sell<double>(const Bsr&, Sell<double>&, hipStream_t);
+template void bsr_to_sell<float>(const Bsr&, Sell<float>&, hipStream_t);
+
+int64_t bsr_count_nonzeros(const Bsr& a, hipStream_t s) {
+  DevBuf<unsigned long long> c(1);
+  FPC_HIP(hipMemsetAsync(c.p, 0, sizeof(unsigned long long), s));
+  const int64_t n = a.nnzb * a.br * a.bc;
+  if (n) {
+    unsigned g = grid_for(n, 256);
+    if (g > 4096) g = 4096;
+    k_count_nz<<<g, 256, 0, s>>>(a.val.p, n, c.p);
+    FPC_LAUNCH_CHECK();
+  }
+  unsigned long long v = 0;
+  FPC_HIP(hipMemcpyAsync(&v, c.p, sizeof(v), hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  return (int64_t)v;
+}
+
+}  // namespace fpc

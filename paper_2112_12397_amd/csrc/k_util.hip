@@ -1,0 +1,242 @@
+// Utility kernels: fills, prefix sums, deterministic reductions, hashing.
+#include "fpc_internal.hpp"
+
+namespace fpc {
+
+namespace {
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+constexpr int SCAN_T = 256, SCAN_E = 8, SCAN_CH = SCAN_T * SCAN_E;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_bsum(const int64_t* in,
+                                                      int64_t n,
+                                                      int64_t* bsum) {
+  __shared__ int64_t sh[SCAN_T];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CH + (int64_t)tid * SCAN_E;
+  int64_t acc = 0;
+  for (int e = 0; e < SCAN_E; ++e) {
+    int64_t i = base + e;
+    if (i < n) acc += in[i];
+  }
+  sh[tid] = acc;
+  __syncthreads();
+  for (int s = SCAN_T / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const int64_t* in,
+                                                       int64_t n,
+                                                       const int64_t* boff,
+                                                       int64_t* out) {
+  __shared__ int64_t sh[SCAN_T];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CH + (int64_t)tid * SCAN_E;
+  int64_t v[SCAN_E];
+  int64_t acc = 0;
+  for (int e = 0; e < SCAN_E; ++e) {
+    int64_t i = base + e;
+    v[e] = (i < n) ? in[i] : 0;
+    acc += v[e];
+  }
+  sh[tid] = acc;
+  __syncthreads();
+  for (int off = 1; off < SCAN_T; off <<= 1) {
+    int64_t t = (tid >= off) ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += t;
+    __syncthreads();
+  }
+  int64_t run = (boff ? boff[blockIdx.x] : 0) + sh[tid] - acc;
+  for (int e = 0; e < SCAN_E; ++e) {
+    int64_t i = base + e;
+    run += v[e];
+    if (i < n) out[i + 1] = run;
+  }
+  if (blockIdx.x == 0 && tid == 0) out[0] = 0;
+}
+
+__global__ void k_i32_to_i64(const int32_t* in, int64_t* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+constexpr int RED_T = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(RED_T) void k_dot_partial(const double* x,
+                                                       const double* y,
+                                                       int64_t n,
+                                                       double* partials) {
+  __shared__ double sh[RED_T / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RED_T + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * RED_T)
+    acc += x[i] * y[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < RED_T / 64; ++w) t += sh[w];
+    partials[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(RED_T) void k_sum_partials(const double* partials,
+                                                        int np, double* out) {
+  __shared__ double sh[RED_T / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += RED_T) acc += partials[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < RED_T / 64; ++w) t += sh[w];
+    out[0] = t;
+  }
+}
+
+__global__ void k_hash(uint32_t first, int64_t n, uint32_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = lowbias32(first + (uint32_t)i);
+}
+
+__global__ void k_check_finite(const double* v, int64_t n, int* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (; i < n; i += stride) bad |= !isfinite(v[i]);
+  if (bad) atomicOr(&flags[FLAG_NAN], 1);
+}
+
+__global__ void k_cast(const double* in, float* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+}  // namespace
+
+void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n, 256);
+  if (g > 65536) g = 65536;
+  k_fill<double><<<g, 256, 0, s>>>(p, v, n);
+  FPC_LAUNCH_CHECK();
+}
+void fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n, 256);
+  if (g > 65536) g = 65536;
+  k_fill<float><<<g, 256, 0, s>>>(p, v, n);
+  FPC_LAUNCH_CHECK();
+}
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n, 256);
+  if (g > 65536) g = 65536;
+  k_fill<int32_t><<<g, 256, 0, s>>>(p, v, n);
+  FPC_LAUNCH_CHECK();
+}
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n, 256);
+  if (g > 65536) g = 65536;
+  k_fill<int64_t><<<g, 256, 0, s>>>(p, v, n);
+  FPC_LAUNCH_CHECK();
+}
+
+void scan_counts(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) {
+    fill_i64(out, 0, 1, s);
+    return;
+  }
+  int64_t nb = (n + SCAN_CH - 1) / SCAN_CH;
+  if (nb == 1) {
+    k_scan_apply<<<1, SCAN_T, 0, s>>>(in, n, nullptr, out);
+    FPC_LAUNCH_CHECK();
+    return;
+  }
+  DevBuf<int64_t> bsum(nb), boff(nb + 1);
+  k_scan_bsum<<<(unsigned)nb, SCAN_T, 0, s>>>(in, n, bsum.p);
+  FPC_LAUNCH_CHECK();
+  scan_counts(bsum.p, boff.p, nb, s);
+  k_scan_apply<<<(unsigned)nb, SCAN_T, 0, s>>>(in, n, boff.p, out);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+}
+
+int64_t scan_counts_total(const int64_t* in, int64_t* out, int64_t n,
+                          hipStream_t s) {
+  scan_counts(in, out, n, s);
+  return read_i64(out + n, s);
+}
+
+void i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_i32_to_i64<<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  FPC_LAUNCH_CHECK();
+}
+
+void dot_f64(const double* x, const double* y, int64_t n, double* out,
+             double* partials, hipStream_t s) {
+  k_dot_partial<<<kRedBlocks, RED_T, 0, s>>>(x, y, n, partials);
+  FPC_LAUNCH_CHECK();
+  k_sum_partials<<<1, RED_T, 0, s>>>(partials, kRedBlocks, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void hash32_range(uint32_t first, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_hash<<<grid_for(n, 256), 256, 0, s>>>(first, n, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void check_finite(const double* v, int64_t n, int* flags, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n, 256);
+  if (g > 4096) g = 4096;
+  k_check_finite<<<g, 256, 0, s>>>(v, n, flags);
+  FPC_LAUNCH_CHECK();
+}
+
+void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  FPC_LAUNCH_CHECK();
+}
+
+double read_f64(const double* p, hipStream_t s) {
+  double v = 0;
+  FPC_HIP(hipMemcpyAsync(&v, p, sizeof(double), hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  return v;
+}
+int64_t read_i64(const int64_t* p, hipStream_t s) {
+  int64_t v = 0;
+  FPC_HIP(hipMemcpyAsync(&v, p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  return v;
+}
+int read_i32(const int32_t* p, hipStream_t s) {
+  int32_t v = 0;
+  FPC_HIP(hipMemcpyAsync(&v, p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+}  // namespace fpc

@@ -1,0 +1,290 @@
+"""GPU path (C ABI) against the CPU FP64 oracle, element by element.
+
+Bars: integer work (aggregates, kept-mode counts) bit-exact; FP64 operators
+and applications within 1e-10 relative (2-norm of the difference over the
+2-norm of the oracle result); FGMRES iteration counts within +-2 of the
+oracle's and a true relative residual <= 1e-8 recomputed in FP64.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import fracgen
+import oracle
+from fracgen import Fracture, tiny_system
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _cases():
+    return {
+        "tiny_plane": (lambda: tiny_system((4, 4, 4), seed=1), 40),
+        "tiny_slip_cross": (lambda: tiny_system(
+            (5, 5, 5), [Fracture(0, 2, 0, 5, 0, 5), Fracture(1, 3, 0, 5, 0, 5)],
+            slip_p=0.3, seed=2), 60),
+        "tiny_patch_ragged": (lambda: tiny_system(
+            (7, 6, 5), [Fracture(2, 2, 1, 6, 1, 5), Fracture(0, 4, 0, 2, 0, 3)],
+            slip_p=0.5, seed=3), 90),
+        "c1": (lambda: fracgen.make_config("c1"), 2000),
+    }
+
+
+_CACHE = {}
+
+
+def _get(name, mode="tup", precision="fp64"):
+    key = (name, mode, precision)
+    if key in _CACHE:
+        return _CACHE[key]
+    from paper_2112_12397_amd import solver_from_system
+    make, mc = _cases()[name]
+    s = make()
+    pc = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p, mode=mode,
+                             coords=s.coords,
+                             amg_opts=oracle.AMGOptions(max_coarse=mc))
+    sol = solver_from_system(s, mode=mode, precision=precision,
+                             amg={"max_coarse": mc})
+    _CACHE[key] = (s, pc, sol)
+    return _CACHE[key]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _real_index(ranks_prev, n_nodes, bs):
+    """Padded dof index of every real (unpadded) dof of a level."""
+    if ranks_prev is None:
+        return np.arange(n_nodes * bs)
+    return np.concatenate([6 * a + np.arange(r) for a, r in
+                           enumerate(ranks_prev)]) if bs == 6 else \
+        np.concatenate([bs * a + np.arange(r) for a, r in
+                        enumerate(ranks_prev)])
+
+
+def _bsr_to_csr(rp, col, blocks, nrows, ncols_nodes):
+    br, bc = blocks.shape[1:]
+    M = sp.bsr_matrix((blocks, col, rp), shape=(nrows * br, ncols_nodes * bc))
+    return M.tocsr()
+
+
+NAMES = list(_cases().keys())
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_hierarchy_parity(torch, name):
+    s, pc, sol = _get(name)
+    H = pc.amg
+    assert sol.num_levels() == H.n_levels
+    ranks_prev = None
+    for l, L in enumerate(H.levels):
+        d = sol.level_info(l)
+        bs = d["block"]
+        assert d["n_nodes"] == L.n_nodes and d["n_dofs"] == L.n
+        idx = _real_index(ranks_prev, d["n_nodes"], bs)
+        rp, col, blk = sol.export_level_matrix(l, 0)
+        Ag = _bsr_to_csr(rp, col, blk, d["n_nodes"], d["n_nodes"])
+        Ag = Ag[idx][:, idx]
+        diff = abs(Ag - L.A).max()
+        assert diff <= 1e-12 * abs(L.A).max(), (l, diff)
+        if l == H.n_levels - 1:
+            break
+        agg, rank = sol.export_aggregates(l)
+        assert np.array_equal(agg, L.agg), f"aggregates differ at level {l}"
+        assert np.array_equal(rank, L.rank), f"ranks differ at level {l}"
+        assert abs(d["lam_hi"] - L.lam_hi) <= 1e-12 * L.lam_hi
+        # smoothed prolongator
+        dn = sol.level_info(l + 1)
+        rp, col, blk = sol.export_level_matrix(l, 1)
+        Pg = _bsr_to_csr(rp, col, blk, d["n_nodes"], dn["n_nodes"])
+        cidx = _real_index(rank, dn["n_nodes"], dn["block"])
+        Pg = Pg[idx][:, cidx]
+        assert abs(Pg - L.P).max() <= 1e-12 * abs(L.P).max()
+        ranks_prev = rank
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_vcycle_parity(torch, name):
+    s, pc, sol = _get(name)
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        b = rng.standard_normal(s.n_u)
+        xg = sol.vcycle(torch.tensor(b, device="cuda")).cpu().numpy()
+        xo = pc.amg.vcycle(b)
+        assert _rel(xg, xo) <= TOL
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("mode", ["tup", "tpu"])
+def test_apply_prec_parity(torch, name, mode):
+    s, pc, sol = _get(name, mode)
+    rng = np.random.default_rng(5)
+    for w in (rng.standard_normal(s.N), s.b):
+        v = sol.apply_prec(torch.tensor(w, device="cuda")).cpu().numpy()
+        vo = pc.apply(w)
+        assert _rel(v, vo) <= TOL
+        # every block separately (t and p are much smaller than u)
+        for a, b_ in ((0, s.n_u), (s.n_u, s.n_u + s.n_t), (s.n_u + s.n_t, s.N)):
+            assert _rel(v[a:b_], vo[a:b_]) <= 1e-9
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_apply_prec_T_parity(torch, name):
+    s, pc, sol = _get(name)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal(s.N)
+    v = sol.apply_prec_T(torch.tensor(w, device="cuda")).cpu().numpy()
+    assert _rel(v, pc.apply_T(w)) <= TOL
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_matvec(torch, name):
+    s, pc, sol = _get(name)
+    J = s.jacobian()
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(s.N)
+    xt = torch.tensor(x, device="cuda")
+    assert _rel(sol.matvec(xt).cpu().numpy(), J @ x) <= 1e-13
+    assert _rel(sol.matvec(xt, trans=True).cpu().numpy(), J.T @ x) <= 1e-13
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_solve(torch, name):
+    s, pc, sol = _get(name)
+    x, info = sol.solve(torch.tensor(s.b, device="cuda"))
+    xo, io = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8, ortho="cgs2")
+    assert info["converged"] == 1 and info["status"] == "FPC_OK"
+    x = x.cpu().numpy()
+    r = np.linalg.norm(s.b - s.jacobian() @ x) / np.linalg.norm(s.b)
+    assert r <= 1e-8 and info["true_rel_residual"] <= 1e-8
+    assert abs(info["iterations"] - io.iterations) <= 2
+    assert _rel(x, xo) <= 1e-5
+
+
+def test_fp32_preconditioner(torch):
+    s, pc, sol64 = _get("c1")
+    _, _, sol32 = _get("c1", precision="fp32")
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal(s.N)
+    v32 = sol32.apply_prec(torch.tensor(w, device="cuda")).cpu().numpy()
+    err = _rel(v32, pc.apply(w))
+    assert err <= 1e-4, err              # FP32 hierarchy error vs FP64 oracle
+    x, info = sol32.solve(torch.tensor(s.b, device="cuda"))
+    _, i64 = sol64.solve(torch.tensor(s.b, device="cuda"))
+    assert info["converged"] == 1 and info["true_rel_residual"] <= 1e-8
+    assert info["iterations"] <= i64["iterations"] + 3
+
+
+def test_adjoint_and_gradient(torch):
+    s, pc, sol = _get("tiny_slip_cross")
+    s2, pc2, sol2 = _get("tiny_plane")
+    for s, pc, sol in ((s, pc, sol), (s2, pc2, sol2)):
+        # a loss gradient dL/dx touches displacements and pressures only
+        rng = np.random.default_rng(9)
+        g = rng.standard_normal(s.N)
+        g[s.n_u:s.n_u + s.n_t] = 0.0
+        lam, info = sol.solve_T(torch.tensor(g, device="cuda"), rtol=1e-11)
+        lo, io = oracle.fgmres(pc.matvec_T, pc.apply_T, g, rtol=1e-11,
+                               ortho="cgs2")
+        assert info["converged"] == 1, info
+        assert abs(info["iterations"] - io.iterations) <= 2
+        assert _rel(lam.cpu().numpy(), lo) <= 1e-7
+    # gradient with respect to log transmissibility
+    s, pc, sol = s2, pc2, sol2
+    p_obs = np.random.default_rng(1).standard_normal(s.n_p) * 1e3
+    x, _ = sol.solve(torch.tensor(s.b, device="cuda"), rtol=1e-11)
+    xn = x.cpu().numpy()
+    L, gx = oracle.adjoint.loss_and_grad_x(xn, s.n_u, s.n_t, p_obs)
+    lam, _ = sol.solve_T(torch.tensor(gx, device="cuda"), rtol=1e-11)
+    off = s.n_u + s.n_t
+    pairs = torch.tensor(s.flow_pairs)
+    grad = sol.grad_log_trans(pairs, torch.tensor(s.flow_ndir),
+                              torch.tensor(s.upsilon), lam[off:].contiguous(),
+                              x[off:].contiguous()).cpu().numpy()
+    ref = oracle.adjoint.grad_log_trans(s.flow_pairs, s.flow_ndir, s.upsilon,
+                                        lam.cpu().numpy()[off:], xn[off:])
+    assert _rel(grad, ref) <= 1e-12
+    faces = np.arange(0, s.n_p, 3)
+    fd = oracle.adjoint.fd_grad_log_trans(s.flow_pairs, s.flow_ndir,
+                                          s.upsilon, s.T_stab,
+                                          s.b[off:], p_obs, faces)
+    assert np.abs(grad[faces] - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_hash_matches_oracle(torch):
+    _, _, sol = _get("tiny_plane")
+    for first in (0, 12345, 2 ** 32 - 100):
+        n = 1000 if first < 2 ** 32 - 1000 else 50
+        dev = sol.hash32(first, n).astype(np.uint64)
+        ref = oracle.hash32((np.arange(n, dtype=np.uint64) + first) % 2 ** 32)
+        assert np.array_equal(dev, ref)
+
+
+def test_error_paths(torch):
+    from paper_2112_12397_amd import solver_from_system, FpcError
+    s = tiny_system((3, 3, 3), seed=4)
+    # singular face block of H
+    bad = s.blocks()
+    H = bad["H"].tolil()
+    H[0, :] = 0.0
+    bad["H"] = sp.csr_matrix(H)
+    bad["H"].eliminate_zeros()
+    with pytest.raises(FpcError) as e:
+        from paper_2112_12397_amd import Solver
+        Solver(bad, s.n_u, s.n_t, s.n_p, coords=s.coords)
+    assert e.value.status == -4
+    # NaN in the values
+    bad = s.blocks()
+    A = bad["A"].copy()
+    A.data[5] = np.nan
+    bad["A"] = A
+    with pytest.raises(FpcError) as e:
+        from paper_2112_12397_amd import Solver
+        Solver(bad, s.n_u, s.n_t, s.n_p)
+    assert e.value.status == -6
+    # unsorted columns
+    bad = s.blocks()
+    T = bad["T"].copy()
+    i0, i1 = T.indptr[0], T.indptr[1]
+    T.indices[i0:i1] = T.indices[i0:i1][::-1].copy()
+    T.data[i0:i1] = T.data[i0:i1][::-1].copy()
+    T.has_sorted_indices = False
+    bad["T"] = T
+    with pytest.raises(FpcError) as e:
+        from paper_2112_12397_amd import Solver
+        Solver(bad, s.n_u, s.n_t, s.n_p)
+    assert e.value.status == -3
+    # open faces (non-empty Q2) are outside this build
+    bad = s.blocks()
+    bad["Q2"] = sp.csr_matrix(s.Q1.T)
+    with pytest.raises(FpcError) as e:
+        from paper_2112_12397_amd import Solver
+        Solver(bad, s.n_u, s.n_t, s.n_p)
+    assert e.value.status == -10
+    # zero right-hand side gives x = 0 at once; NaN right-hand side rejected
+    sol = solver_from_system(s)
+    x, info = sol.solve(torch.zeros(s.N, dtype=torch.float64, device="cuda"))
+    assert info["iterations"] == 0 and not x.any()
+    b = torch.tensor(s.b, device="cuda")
+    b[3] = float("nan")
+    with pytest.raises(FpcError) as e:
+        sol.solve(b)
+    assert e.value.status == -6
+    # iteration cap: not converged, last iterate returned
+    from paper_2112_12397_amd import Solver
+    sol2 = Solver(s.blocks(), s.n_u, s.n_t, s.n_p, coords=s.coords, maxit=2)
+    x, info = sol2.solve(torch.tensor(s.b, device="cuda"))
+    assert info["status"] == "FPC_NOT_CONVERGED" and info["iterations"] == 2
+    # restart from the last iterate converges
+    x2, info2 = sol.solve(torch.tensor(s.b, device="cuda"), x0=x)
+    assert info2["converged"] == 1
