@@ -1,0 +1,259 @@
+#!/usr/bin/env python
+"""Benchmark of the block-preconditioned FGMRES solve on one MI355X.
+
+Workload (default): the 80^3 Q1 hex mesh with three orthogonal full
+fractures, 30% slip faces, one right-hand side (n_u 1,654,104, n_t 57,600,
+n_p 19,200).  One step is one pass of the whole path on device-resident
+inputs: preconditioner construction (H~, S1 = A + C1 H~^-1 C2, pressure
+block inverse, smoothed-aggregation hierarchy with its Galerkin products)
+followed by the FGMRES(50) solve to a true relative residual of 1e-8.
+
+Printed: one JSON line.  ``value`` is the FGMRES time-to-1e-8 in seconds of
+the plain FP64 path (mean over the timed steps); the FP32-preconditioned
+solve time and its speedup, the V-cycle bandwidth, the roofline of the
+dominant kernel (level-0 residual SpMV of the V-cycle, timed with HIP events
+inside the timed region) and the CPU oracle baseline are added as objects.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("FGMRES time-to-1e-8 residual (s), FP32-precond vs FP64; "
+          "V-cycle HBM GB/s")
+WORKLOADS = {
+    "c1": "10^3 Q1 hex, one full fracture plane (100 faces), all stick",
+    "c2": "80^3 Q1 hex, three orthogonal full fractures (19,200 faces), "
+          "Bernoulli(0.3) slip, single right-hand side",
+    "c3": "128x128x64 Q1 hex, 12 random fractures, layered modulus",
+    "c4": "64^3 Q1 hex, 6 random fractures",
+    "c5": "48^3 Q1 hex, 4 full x-normal fractures (9,216 faces)",
+}
+
+
+def spmv_bytes(nnz, nrows, ncols, sv=8, si=4, nv=1, extra_vec=0):
+    """Algorithmic bytes of y = M x: values + column indices of the true
+    nonzeros, row pointers, one read of x and one write of y per column,
+    plus ``extra_vec`` further row-length vector streams per column."""
+    return (nnz * (sv + si) + 4 * (nrows + 1)
+            + nv * (nrows + ncols + extra_vec * nrows) * sv)
+
+
+def vcycle_bytes(levels, nv=1, sv=8):
+    """Algorithmic bytes of one V-cycle: per level the four fused smoother /
+    residual products with A_l (their vector streams beyond one read and
+    one write: 3 + 1 + 4 + 3), restriction, prolongation; the coarsest level
+    reads its dense inverse once."""
+    total = 0
+    for i, d in enumerate(levels):
+        n = d["n_nodes"] * d["block"]
+        if d["n_agg"] == 0:                       # coarsest
+            total += n * n * 8 + 2 * nv * n * sv
+            break
+        nxt = levels[i + 1]
+        nc = nxt["n_nodes"] * nxt["block"]
+        nnzP = d["p_nnzb"] * d["block"] * nxt["block"]
+        total += 4 * spmv_bytes(d["nnz_scalar"], n, n, sv, nv=nv)
+        total += nv * 11 * n * sv
+        total += spmv_bytes(nnzP, nc, n, sv, nv=nv)          # R = P^T
+        total += spmv_bytes(nnzP, n, nc, sv, nv=nv)          # P
+    return total
+
+
+def device_blocks(torch, s):
+    out = {}
+    for k, M in s.blocks().items():
+        out[k] = (torch.tensor(M.indptr.astype(np.int64), device="cuda"),
+                  torch.tensor(M.indices.astype(np.int32), device="cuda"),
+                  torch.tensor(M.data.astype(np.float64), device="cuda"))
+    return out
+
+
+def cpu_baseline(s, gpu_iters, sample_its):
+    """The CPU oracle on the same workload, one thread: preconditioner setup
+    (untimed for the value), then ``sample_its`` FGMRES iterations, scaled to
+    the GPU's iteration count."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pc = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p,
+                                 coords=s.coords)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, info = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8,
+                                maxit=sample_its)
+        t_its = time.perf_counter() - t0
+    per_it = t_its / max(info.iterations, 1)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": per_it * gpu_iters, "unit": "s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"{info.iterations} FGMRES iterations of the NumPy/SciPy "
+                       f"FP64 oracle on this workload after its setup "
+                       f"({t_setup:.1f} s, not in value), scaled to the GPU "
+                       f"iteration count {gpu_iters}"),
+            "per_iteration_s": per_it, "setup_s": t_setup,
+            "cpu_model": cpu, "host": platform.node()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample-its", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; multi-GPU runs "
+              "are not supported (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fracgen
+    from paper_2112_12397_amd import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    s = fracgen.make_config(args.config)
+    blocks = device_blocks(torch, s)
+    coords = torch.tensor(s.coords, device="cuda")
+    b = torch.tensor(s.b, device="cuda")
+    x = torch.empty_like(b)
+
+    sol = Solver(blocks, s.n_u, s.n_t, s.n_p, coords=coords)
+    for _ in range(args.warmup):
+        sol.setup(blocks, coords)
+        sol.solve(b, out=x)
+    torch.cuda.synchronize()
+
+    sol.kernel_timer(enable=True, reset=True)
+    t_setup, t_solve, infos = 0.0, 0.0, []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        sol.setup(blocks, coords)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = sol.solve(b, out=x)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_setup += t1 - t0
+        t_solve += t2 - t1
+        infos.append(info)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all
+    launches, kernel_ms = sol.kernel_timer(enable=False, reset=True)
+    K = args.steps
+    iters = infos[-1]["iterations"]
+    for inf in infos:
+        if not inf["converged"] or inf["true_rel_residual"] > 1e-8:
+            raise SystemExit(f"solve did not converge: {inf}")
+
+    levels = [sol.level_info(l) for l in range(sol.num_levels())]
+    setup_parts = sol.setup_times()
+
+    # dominant kernel: level-0 residual SpMV of the two-column V-cycle
+    d0 = levels[0]
+    nv = 2
+    k_bytes = spmv_bytes(d0["nnz_scalar"], s.n_u, s.n_u, nv=nv, extra_vec=1)
+    k_avg_s = kernel_ms / max(launches, 1) / 1e3
+    achieved = k_bytes / k_avg_s / 1e9
+
+    # V-cycle bandwidth (one FP64 column), HIP events on the library stream
+    vb = torch.randn(s.n_u, dtype=torch.float64, device="cuda")
+    vx = torch.empty_like(vb)
+    for _ in range(3):
+        sol.vcycle(vb, out=vx)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+        enable_timing=True)
+    nrep = 20
+    ev0.record()
+    for _ in range(nrep):
+        sol.vcycle(vb, out=vx)
+    ev1.record()
+    torch.cuda.synchronize()
+    vc_s = ev0.elapsed_time(ev1) / nrep / 1e3
+    vc_bytes = vcycle_bytes(levels)
+
+    out = {
+        "metric": METRIC,
+        "value": t_solve / K,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_all / K,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
+                   "n_u": s.n_u, "n_t": s.n_t, "n_p": s.n_p, "N": s.N,
+                   "mode": "t-u-p", "restart": 50, "rtol": 1e-8,
+                   "seed": s.seed},
+        "iterations": iters,
+        "true_rel_residual": infos[-1]["true_rel_residual"],
+        "setup_s": t_setup / K,
+        "setup_parts_s": setup_parts,
+        "amg_levels": [{"dofs": d["n_dofs"], "nnz": d["nnz_scalar"]}
+                       for d in levels],
+        "vcycle": {"seconds": vc_s, "algorithmic_bytes": vc_bytes,
+                   "GBps": vc_bytes / vc_s / 1e9,
+                   "frac": vc_bytes / vc_s / 1e9 / HBM_PEAK_GBS,
+                   "columns": 1, "dtype": "f64"},
+        "roofline": {"bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "level-0 residual SpMV (sliced-ELL 3x3 blocks, "
+                               "2 columns, FP64)",
+                     "bytes_per_launch": k_bytes,
+                     "avg_launch_us": k_avg_s * 1e6,
+                     "launches": launches},
+    }
+
+    if not args.no_fp32:
+        sol32 = Solver(blocks, s.n_u, s.n_t, s.n_p, coords=coords,
+                       precision="fp32")
+        for _ in range(args.warmup):
+            sol32.solve(b, out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            x32, i32 = sol32.solve(b, out=x)
+        torch.cuda.synchronize()
+        t32 = (time.perf_counter() - t0) / K
+        out["fp32_prec"] = {"solve_s": t32, "iterations": i32["iterations"],
+                            "true_rel_residual": i32["true_rel_residual"],
+                            "converged": bool(i32["converged"]),
+                            "speedup_vs_fp64": (t_solve / K) / t32}
+        del sol32
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, iters, args.cpu_sample_its)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -27,8 +27,10 @@
  *  - One handle per host thread.  A negative status means no output was
  *    written; fpc_last_error() returns a message.  FPC_NOT_CONVERGED (> 0) is
  *    a warning: the output holds the last iterate and the info its residual.
- *  - The library allocates device memory in fpc_setup (and lazily on the
- *    first transposed or batched call); the solve paths allocate nothing.
+ *  - The library allocates device memory in fpc_setup (and once more on the
+ *    first transposed call, for the transposed operators, and on the first
+ *    single-column V-cycle of the t-u-p mode); fpc_apply_prec and fpc_solve
+ *    allocate nothing after setup.
  */
 #ifndef FRACPREC_H
 #define FRACPREC_H
@@ -218,6 +220,14 @@ fpc_status fpc_export_level_matrix(const fpc_handle* h, int level, int which,
  * [0] total, [1] upload + validation, [2] H~ and S1, [3] pressure block,
  * [4] AMG hierarchy. */
 fpc_status fpc_setup_times(const fpc_handle* h, double* t5);
+
+/* Reporting aid: when enable != 0, the level-0 residual SpMV of every
+ * V-cycle (the dominant kernel) is bracketed by HIP events on the handle's
+ * stream.  Returns the number of timed launches and their total device time
+ * (ms) accumulated since the last reset; reset != 0 clears the counters.
+ * Synchronizes the stream. */
+fpc_status fpc_kernel_timer(fpc_handle* h, int enable, int reset,
+                            int64_t* launches, double* total_ms);
 
 void fpc_destroy(fpc_handle* h);
 const char* fpc_status_string(fpc_status s);

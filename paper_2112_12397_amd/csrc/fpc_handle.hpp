@@ -45,7 +45,46 @@ struct CycleVecs {
   std::vector<LevelVecs<T>> lv;
 };
 
+// HIP-event timer around one kernel of the V-cycle (the level-0 residual
+// SpMV), used for reporting its achieved bandwidth.
+struct KTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  int64_t launches = 0;
+  double total_ms = 0.0;
+  void begin(hipStream_t s) {
+    if (!on) return;
+    if (ev.empty()) {
+      ev.resize(4096);
+      for (auto& e : ev) FPC_HIP(hipEventCreate(&e));
+    }
+    if (used + 2 > ev.size()) flush();
+    FPC_HIP(hipEventRecord(ev[used], s));
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    FPC_HIP(hipEventRecord(ev[used + 1], s));
+    used += 2;
+  }
+  void flush() {
+    if (used == 0) return;
+    FPC_HIP(hipEventSynchronize(ev[used - 1]));
+    for (size_t i = 0; i < used; i += 2) {
+      float ms = 0.f;
+      FPC_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      total_ms += ms;
+      ++launches;
+    }
+    used = 0;
+  }
+  ~KTimer() {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 struct Hierarchy {
+  KTimer* timer = nullptr;
   std::vector<Level> L;
   int64_t nc = 0, ncpad = 0;  // coarsest dofs (padded) and dense size
   DevBuf<double> Ainv;        // ncpad x ncpad, row-major
@@ -103,6 +142,7 @@ struct fpc_handle {
   fpc::DevBuf<double> t_t, tmp_u, tmp_u2, tmp_p, scratchN;
   fpc::Krylov kry1;            // single right-hand side
   fpc::Krylov kryB;            // batched
+  fpc::KTimer ktimer;
   std::string last_error;
   double setup_times[5] = {0, 0, 0, 0, 0};
 };

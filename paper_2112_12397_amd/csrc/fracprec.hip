@@ -296,6 +296,7 @@ double power_lambda(fpc_handle* h, Level& L, int key_stride) {
 void build_hierarchy(fpc_handle* h, Bsr&& S1) {
   Hierarchy& H = h->amg;
   H = Hierarchy();
+  H.timer = h->ktimer.on ? &h->ktimer : nullptr;
   hipStream_t s = h->stream;
   const fpc_amg_options& o = h->opt.amg;
   const int nb = h->has_coords ? 6 : 3;
@@ -753,6 +754,11 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     h->t_t.alloc(std::max<int64_t>(nt, 1));
     h->tmp_p.alloc(std::max<int64_t>(np, 1));
     h->scratchN.alloc(h->N);
+    // work vectors of the solve path, so that solves allocate nothing
+    ensure_krylov(h, h->kry1, 1);
+    const int nvf = h->opt.mode == FPC_TUP ? 2 : 1;
+    if (h->opt.precision == FPC_FP32_PREC) cycle_vecs<float>(h->amg, nvf);
+    else cycle_vecs<double>(h->amg, nvf);
     FPC_HIP(hipStreamSynchronize(s));
     h->ready = true;
     h->setup_times[0] = t4 - t0;
@@ -947,6 +953,23 @@ fpc_status fpc_setup_times(const fpc_handle* h, double* t5) {
   if (!h || !t5) return FPC_ERR_ARG;
   for (int i = 0; i < 5; ++i) t5[i] = h->setup_times[i];
   return FPC_OK;
+}
+
+fpc_status fpc_kernel_timer(fpc_handle* h, int enable, int reset,
+                            int64_t* launches, double* total_ms) {
+  if (!h) return FPC_ERR_ARG;
+  return guard(h, [&] {
+    KTimer& t = h->ktimer;
+    t.flush();
+    if (launches) *launches = t.launches;
+    if (total_ms) *total_ms = t.total_ms;
+    if (reset) {
+      t.launches = 0;
+      t.total_ms = 0.0;
+    }
+    t.on = enable != 0;
+    h->amg.timer = t.on ? &t : nullptr;
+  });
 }
 
 fpc_status fpc_hash32_device(fpc_handle* h, uint32_t first, int64_t n,

@@ -380,7 +380,7 @@ const float* seldinv<float>(const Level& L) { return L.dinv32.p; }
 
 template <typename T, int BS, int NV>
 void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
-                  int phase) {
+                  int phase, KTimer* timer) {
   const Sell<T>& A = selA<T>(L, tr);
   const T* dinv = seldinv<T>(L);
   const T it = T(1.0 / L.theta), c1 = T(L.c1), c2 = T(L.c2);
@@ -389,8 +389,10 @@ void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
                                EpiPre1<T, BS, NV>{v.b.p, dinv, v.x.p, v.d.p,
                                                   v.r.p, it, c1, c2},
                                s);
+    if (timer) timer->begin(s);
     launch_sell<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
                                EpiRes<T, BS, NV>{v.r.p, v.res.p}, s);
+    if (timer) timer->end(s);
   } else {
     launch_sell<T, BS, BS, NV>(A, LoadX<T, NV>{v.x.p},
                                EpiPost1<T, BS, NV>{v.b.p, dinv, v.x.p, v.xo.p,
@@ -419,9 +421,9 @@ void prolong_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
 
 template <typename T, int NV>
 void dispatch_smooth(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
-                     int phase) {
-  if (L.bs == 3) smooth_level<T, 3, NV>(L, v, tr, s, phase);
-  else smooth_level<T, 6, NV>(L, v, tr, s, phase);
+                     int phase, KTimer* timer) {
+  if (L.bs == 3) smooth_level<T, 3, NV>(L, v, tr, s, phase, timer);
+  else smooth_level<T, 6, NV>(L, v, tr, s, phase, timer);
 }
 
 template <typename T, int NV>
@@ -451,11 +453,12 @@ void vcycle_rec(Hierarchy& H, CycleVecs<T>& cv, size_t l, bool tr,
     FPC_LAUNCH_CHECK();
     return;
   }
-  dispatch_smooth<T, NV>(L, v, tr, s, 0);
+  KTimer* timer = (l == 0) ? H.timer : nullptr;
+  dispatch_smooth<T, NV>(L, v, tr, s, 0, timer);
   dispatch_transfer<T, NV>(L, v, cv.lv[l + 1], s, true);
   vcycle_rec<T, NV>(H, cv, l + 1, tr, s);
   dispatch_transfer<T, NV>(L, v, cv.lv[l + 1], s, false);
-  dispatch_smooth<T, NV>(L, v, tr, s, 1);
+  dispatch_smooth<T, NV>(L, v, tr, s, 1, nullptr);
 }
 
 template <typename T>

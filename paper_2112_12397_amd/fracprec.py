@@ -86,7 +86,8 @@ EXPORTS = ("fpc_default_options", "fpc_create", "fpc_setup", "fpc_apply_prec",
            "fpc_solve_T", "fpc_solve_batch", "fpc_grad_log_trans",
            "fpc_num_levels", "fpc_level_info", "fpc_export_aggregates",
            "fpc_export_level_matrix", "fpc_setup_times", "fpc_destroy",
-           "fpc_status_string", "fpc_last_error", "fpc_hash32_device")
+           "fpc_status_string", "fpc_last_error", "fpc_hash32_device",
+           "fpc_kernel_timer")
 
 _lib = None
 
@@ -125,6 +126,8 @@ def load_library(path: str = LIB_PATH):
         "fpc_status_string": (C.c_char_p, [i32]),
         "fpc_last_error": (C.c_char_p, [H]),
         "fpc_hash32_device": (i32, [H, C.c_uint32, i64, vp]),
+        "fpc_kernel_timer": (i32, [H, i32, i32, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -384,6 +387,14 @@ class Solver:
                     "setup_times")
         return dict(total=t[0], upload=t[1], schur=t[2], pressure=t[3],
                     amg=t[4])
+
+    def kernel_timer(self, enable=True, reset=True):
+        """(launches, total_ms) of the timed level-0 residual SpMV."""
+        n, ms = C.c_int64(), C.c_double()
+        self._check(self.lib.fpc_kernel_timer(self.h, int(enable), int(reset),
+                                              C.byref(n), C.byref(ms)),
+                    "kernel_timer")
+        return n.value, ms.value
 
     def hash32(self, first, n):
         out = self.torch.empty(n, dtype=self.torch.int32, device=self.device)
