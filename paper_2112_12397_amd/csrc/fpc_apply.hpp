@@ -12,6 +12,11 @@ CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv);
 template <typename T, int NV>
 void vcycle(Hierarchy& H, bool transpose, hipStream_t s);
 
+// Autotuned apply layout of one operator for `nv` columns; *choice = 1 for
+// sliced ELL, else the row-group width.
+template <typename T>
+void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice);
+
 void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s);
 void sell_mv_dinv(const Sell<double>& A, const double* dinv, const double* x,
                   double* y, hipStream_t s);

@@ -17,11 +17,13 @@ struct Level {
   int64_t n_nodes = 0;
   int64_t n_dofs_real = 0;  // without padding dofs
   Bsr A, P, R;              // FP64 block CSR (setup, export, transposes)
-  Sell<double> sA, sP, sR;  // apply operators
-  Sell<float> fA, fP, fR;
+  Sell<double> sA;          // FP64 A in sliced ELL (power iteration)
+  Op<double> oA, oP, oR;    // apply operators (layout chosen by the tuner)
+  Op<float> fA, fP, fR;
   Bsr AT;                   // A^T for the transposed cycle (lazy)
-  Sell<double> sAT;
-  Sell<float> fAT;
+  Op<double> oAT;
+  Op<float> fAT;
+  int layout[3] = {0, 0, 0};   // tuner choice for A, P, R (1 = sliced ELL)
   DevBuf<double> dinv;      // n_nodes * bs
   DevBuf<float> dinv32;
   DevBuf<int32_t> agg;      // aggregate of every node (-1 isolated)
@@ -102,6 +104,7 @@ struct PSolve {
   DevBuf<int64_t> comp_off, dense_off, comp_pad_d;
   DevBuf<int32_t> members, comp_of_row;
   DevBuf<double> dense;
+  DevBuf<float> dense32;      // FP32 copy (FP32 preconditioner); dense freed
   int64_t dense_elems = 0;
 };
 

@@ -112,6 +112,33 @@ struct Sell {
 
 constexpr int kSliceH = 64;
 
+// Row-group layout for operators with long rows: a group of G lanes owns one
+// block row and walks it in chunks of G blocks; the values of a chunk are
+// component-major (component q of the chunk's blocks is G consecutive words).
+template <typename T>
+struct Vrow {
+  int br = 0, bc = 0, G = 0;
+  int64_t nrows = 0, nchunks = 0, nnzb = 0;
+  DevBuf<int64_t> chunk_ptr;  // nrows + 1, in chunks
+  DevBuf<int32_t> row_len;    // nrows
+  DevBuf<int32_t> col;        // nchunks * G
+  DevBuf<T> val;              // nchunks * G * br * bc
+  size_t bytes() const {
+    return chunk_ptr.bytes() + row_len.bytes() + col.bytes() + val.bytes();
+  }
+};
+
+// An apply-path operator in the layout the setup autotuner chose:
+// fmt 0 = sliced ELL (one thread per block row), fmt 1 = row groups.
+template <typename T>
+struct Op {
+  int fmt = 0;
+  Sell<T> s;
+  Vrow<T> v;
+  int64_t rows() const { return fmt ? v.nrows : s.nrows; }
+  size_t bytes() const { return fmt ? v.bytes() : s.bytes(); }
+};
+
 // Device-side error flags written by validation / factorization kernels.
 enum FlagIdx {
   FLAG_PATTERN = 0,
@@ -172,6 +199,8 @@ void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s);
 void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s);
 template <typename T>
 void bsr_to_sell(const Bsr& a, Sell<T>& out, hipStream_t s);
+template <typename T>
+void bsr_to_vrow(const Bsr& a, int G, Vrow<T>& out, hipStream_t s);
 int64_t bsr_count_nonzeros(const Bsr& a, hipStream_t s);
 
 // ---------------------------------------------------------------- k_amg

@@ -271,6 +271,12 @@ void build_psolve(fpc_handle* h) {
     gj_inverse(D, pad, /*spd=*/1, h->flags.p, s);
   }
   check_flags(h, "pressure block");
+  if (h->opt.precision == FPC_FP32_PREC) {
+    ps.dense32.alloc(ps.dense_elems);
+    cast_f64_f32(ps.dense.p, ps.dense32.p, ps.dense_elems, s);
+    FPC_HIP(hipStreamSynchronize(s));
+    ps.dense.release();
+  }
   FPC_HIP(hipStreamSynchronize(s));
 }
 
@@ -358,8 +364,6 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
     spgemm(L.R, AP, Ac, h->flags.p, s);
     check_flags(h, "Galerkin product");
     dummy_diag(Ac, L.rank.p, s);
-    bsr_to_sell(L.P, L.sP, s);
-    bsr_to_sell(L.R, L.sR, s);
     // next level
     std::vector<int32_t> rk(L.n_agg);
     FPC_HIP(hipMemcpyAsync(rk.data(), L.rank.p, L.n_agg * sizeof(int32_t),
@@ -388,17 +392,23 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
   dense_from_bsr(C.A, H.ncpad, H.Ainv.p, s);
   gj_inverse(H.Ainv.p, H.ncpad, /*spd=*/0, h->flags.p, s);
   check_flags(h, "coarsest level");
-  if (h->opt.precision == FPC_FP32_PREC) {
-    for (Level& L : H.L) {
+  // apply layouts, tuned for the column count of the preconditioner
+  const int nv = h->opt.mode == FPC_TUP ? 2 : 1;
+  for (Level& L : H.L) {
+    if (L.coarsest) continue;
+    L.sA = Sell<double>();
+    if (h->opt.precision == FPC_FP32_PREC) {
       const int64_t n = L.n_nodes * L.bs;
       L.dinv32.alloc(n);
       k_cast_dinv<<<grid_for(n, 256), 256, 0, s>>>(L.dinv.p, L.dinv32.p, n);
       FPC_LAUNCH_CHECK();
-      if (!L.coarsest) {
-        bsr_to_sell(L.A, L.fA, s);
-        bsr_to_sell(L.P, L.fP, s);
-        bsr_to_sell(L.R, L.fR, s);
-      }
+      tune_op<float>(L.A, nv, L.fA, s, &L.layout[0]);
+      tune_op<float>(L.P, nv, L.fP, s, &L.layout[1]);
+      tune_op<float>(L.R, nv, L.fR, s, &L.layout[2]);
+    } else {
+      tune_op<double>(L.A, nv, L.oA, s, &L.layout[0]);
+      tune_op<double>(L.P, nv, L.oP, s, &L.layout[1]);
+      tune_op<double>(L.R, nv, L.oR, s, &L.layout[2]);
     }
   }
   FPC_HIP(hipStreamSynchronize(s));
@@ -420,8 +430,8 @@ void ensure_transposes(fpc_handle* h) {
   for (Level& L : H.L) {
     if (L.coarsest) continue;
     bsr_transpose(L.A, L.AT, s);
-    bsr_to_sell(L.AT, L.sAT, s);
-    if (h->opt.precision == FPC_FP32_PREC) bsr_to_sell(L.AT, L.fAT, s);
+    if (h->opt.precision == FPC_FP32_PREC) tune_op<float>(L.AT, 1, L.fAT, s, nullptr);
+    else tune_op<double>(L.AT, 1, L.oAT, s, nullptr);
   }
   H.AinvT.alloc(H.ncpad * H.ncpad);
   dim3 g((unsigned)((H.ncpad + 31) / 32), (unsigned)((H.ncpad + 31) / 32));

@@ -72,13 +72,41 @@ __global__ void k_tr_fill(const int64_t* rowptr, const int32_t* col,
   }
 }
 
-// Insertion sort of each row of the transpose by column (rows are filled in
-// arbitrary order by the atomics); makes the result deterministic.
-__global__ void k_tr_sort(const int64_t* rowptrT, int64_t nrowsT,
-                          int32_t* colT, int64_t* src) {
+// Rows of the transpose up to RS entries: one wavefront per row ranks its
+// entries in LDS (keys are distinct) and writes them in order.
+constexpr int RS = 4096;
+__global__ __launch_bounds__(64) void k_tr_sort_wave(const int64_t* rowptrT,
+                                                     int64_t nrowsT,
+                                                     int32_t* colT,
+                                                     int64_t* src) {
+  __shared__ int32_t kc[RS];
+  __shared__ int64_t ks[RS];
+  const int64_t r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (r >= nrowsT) return;
+  const int64_t a = rowptrT[r];
+  const int n = (int)(rowptrT[r + 1] - a);
+  if (n < 2 || n > RS) return;
+  for (int e = lane; e < n; e += 64) {
+    kc[e] = colT[a + e];
+    ks[e] = src[a + e];
+  }
+  __syncthreads();
+  for (int e = lane; e < n; e += 64) {
+    const int32_t key = kc[e];
+    int rank = 0;
+    for (int f = 0; f < n; ++f) rank += (kc[f] < key);
+    colT[a + rank] = key;
+    src[a + rank] = ks[e];
+  }
+}
+
+__global__ void k_tr_sort_long(const int64_t* rowptrT, int64_t nrowsT,
+                               int32_t* colT, int64_t* src) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrowsT) return;
   int64_t a = rowptrT[r], b = rowptrT[r + 1];
+  if (b - a <= RS) return;
   for (int64_t e = a + 1; e < b; ++e) {
     int32_t c = colT[e];
     int64_t s = src[e];
@@ -347,6 +375,35 @@ __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
   }
 }
 
+__global__ void k_vrow_count(const int64_t* rowptr, int64_t nrows, int G,
+                             int64_t* cnt) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t len = rowptr[r + 1] - rowptr[r];
+  cnt[r] = (len + G - 1) / G;
+}
+
+template <typename T, int B>
+__global__ void k_vrow_fill(const int64_t* rowptr, const int32_t* col,
+                            const double* val, int64_t nrows, int G,
+                            const int64_t* chunk_ptr, int32_t* row_len,
+                            int32_t* vcol, T* vval) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t a = rowptr[r];
+  const int len = (int)(rowptr[r + 1] - a);
+  row_len[r] = len;
+  const int64_t c0 = chunk_ptr[r];
+  for (int k = 0; k < len; ++k) {
+    const int64_t grp = (c0 + k / G) * G;
+    const int sl = k % G;
+    vcol[grp + sl] = col[a + k];
+    T* dst = vval + grp * B + sl;
+#pragma unroll
+    for (int q = 0; q < B; ++q) dst[(int64_t)q * G] = (T)val[(a + k) * B + q];
+  }
+}
+
 __global__ void k_count_nz(const double* v, int64_t n,
                            unsigned long long* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,9 +438,12 @@ void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s) {
     k_tr_fill<<<grid_for(a.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.col.p, a.nbr,
                                                    cursor.p, t.col.p, src.p);
   FPC_LAUNCH_CHECK();
-  if (t.nbr)
-    k_tr_sort<<<grid_for(t.nbr, 64), 64, 0, s>>>(t.rowptr.p, t.nbr, t.col.p,
-                                                 src.p);
+  if (t.nbr) {
+    k_tr_sort_wave<<<(unsigned)t.nbr, 64, 0, s>>>(t.rowptr.p, t.nbr, t.col.p,
+                                                  src.p);
+    k_tr_sort_long<<<grid_for(t.nbr, 64), 64, 0, s>>>(t.rowptr.p, t.nbr,
+                                                      t.col.p, src.p);
+  }
   FPC_LAUNCH_CHECK();
   if (t.nnzb)
     k_tr_gather<BR, BC><<<grid_for(t.nnzb, 256), 256, 0, s>>>(
@@ -582,6 +642,43 @@ void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s) {
   if (m == 3 && k == 1 && n == 3) return spgemm_impl<3, 1, 3>(a, b, c, flags, s);
   throw Error(FPC_ERR_ARG, "spgemm: unsupported block shapes");
 }
+
+template <typename T, int B>
+void to_vrow_impl(const Bsr& a, int G, Vrow<T>& out, hipStream_t s) {
+  out.br = a.br;
+  out.bc = a.bc;
+  out.G = G;
+  out.nrows = a.nbr;
+  out.nnzb = a.nnzb;
+  DevBuf<int64_t> cnt(std::max<int64_t>(a.nbr, 1));
+  out.chunk_ptr.alloc(a.nbr + 1);
+  if (a.nbr)
+    k_vrow_count<<<grid_for(a.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.nbr, G,
+                                                      cnt.p);
+  FPC_LAUNCH_CHECK();
+  out.nchunks = scan_counts_total(cnt.p, out.chunk_ptr.p, a.nbr, s);
+  out.row_len.alloc(std::max<int64_t>(a.nbr, 1));
+  out.col.alloc(std::max<int64_t>(out.nchunks * G, 1));
+  out.val.alloc(std::max<int64_t>(out.nchunks * G * B, 1));
+  fill_i32(out.col.p, 0, out.nchunks * G, s);
+  FPC_HIP(hipMemsetAsync(out.val.p, 0, out.val.bytes(), s));
+  if (a.nbr)
+    k_vrow_fill<T, B><<<grid_for(a.nbr, 256), 256, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nbr, G, out.chunk_ptr.p,
+        out.row_len.p, out.col.p, out.val.p);
+  FPC_LAUNCH_CHECK();
+}
+
+template <typename T>
+void bsr_to_vrow(const Bsr& a, int G, Vrow<T>& out, hipStream_t s) {
+  const int B = a.br * a.bc;
+  if (B == 9) return to_vrow_impl<T, 9>(a, G, out, s);
+  if (B == 18) return to_vrow_impl<T, 18>(a, G, out, s);
+  if (B == 36) return to_vrow_impl<T, 36>(a, G, out, s);
+  throw Error(FPC_ERR_ARG, "bsr_to_vrow: unsupported block size");
+}
+template void bsr_to_vrow<double>(const Bsr&, int, Vrow<double>&, hipStream_t);
+template void bsr_to_vrow<float>(const Bsr&, int, Vrow<float>&, hipStream_t);
 
 template <typename T>
 void bsr_to_sell(const Bsr& a, Sell<T>& out, hipStream_t s) {

@@ -50,32 +50,39 @@ struct LoadScaled {
 };
 
 // ---------------------------------------------------------------- epilogues
+// Every epilogue works element-wise on (block row, component i, column v):
+// `one` handles one element, operator() a whole block row of one column.
+#define FPC_EPI_ROW                                                   \
+  __device__ void operator()(int64_t row, int v, const T* acc) const { \
+    _Pragma("unroll") for (int i = 0; i < BR; ++i) one(row, i, v, acc[i]); \
+  }
+
 template <typename T, int BR, int NV>
 struct EpiStore {
   T* __restrict__ y;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) y[(row * BR + i) * NV + v] = acc[i];
+  __device__ void one(int64_t row, int i, int v, T a) const {
+    y[(row * BR + i) * NV + v] = a;
   }
+  FPC_EPI_ROW
 };
 
 template <typename T, int BR, int NV>
 struct EpiAdd {
   T* __restrict__ y;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) y[(row * BR + i) * NV + v] += acc[i];
+  __device__ void one(int64_t row, int i, int v, T a) const {
+    y[(row * BR + i) * NV + v] += a;
   }
+  FPC_EPI_ROW
 };
 
 template <typename T, int BR>
 struct EpiDinv {
   const T* __restrict__ dinv;
   T* __restrict__ y;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) y[row * BR + i] = dinv[row * BR + i] * acc[i];
+  __device__ void one(int64_t row, int i, int, T a) const {
+    y[row * BR + i] = dinv[row * BR + i] * a;
   }
+  FPC_EPI_ROW
 };
 
 // Pre-smoothing from x = 0, two Chebyshev steps fused around q = A d0:
@@ -88,20 +95,18 @@ struct EpiPre1 {
   T* __restrict__ d;
   T* __restrict__ R;
   T inv_theta, c1, c2;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t dof = row * BR + i, k = dof * NV + v;
-      const T bi = b[k], di = dinv[dof];
-      const T d0 = di * bi * inv_theta;
-      const T R1 = bi - acc[i];
-      const T r1 = di * R1;
-      const T d1 = c1 * d0 + c2 * r1;
-      x[k] = d0 + d1;
-      d[k] = d1;
-      R[k] = R1;
-    }
+  __device__ void one(int64_t row, int i, int v, T a) const {
+    const int64_t dof = row * BR + i, k = dof * NV + v;
+    const T bi = b[k], di = dinv[dof];
+    const T d0 = di * bi * inv_theta;
+    const T R1 = bi - a;
+    const T r1 = di * R1;
+    const T d1 = c1 * d0 + c2 * r1;
+    x[k] = d0 + d1;
+    d[k] = d1;
+    R[k] = R1;
   }
+  FPC_EPI_ROW
 };
 
 // residual after pre-smoothing: res = R1 - A d1 = b - A x
@@ -109,13 +114,11 @@ template <typename T, int BR, int NV>
 struct EpiRes {
   const T* __restrict__ R;
   T* __restrict__ res;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t k = (row * BR + i) * NV + v;
-      res[k] = R[k] - acc[i];
-    }
+  __device__ void one(int64_t row, int i, int v, T a) const {
+    const int64_t k = (row * BR + i) * NV + v;
+    res[k] = R[k] - a;
   }
+  FPC_EPI_ROW
 };
 
 // post-smoothing step 1 around q = A x: r0 = D^-1 (b - q), d0 = r0 / theta,
@@ -129,17 +132,15 @@ struct EpiPost1 {
   T* __restrict__ d;
   T* __restrict__ r;
   T inv_theta;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t dof = row * BR + i, k = dof * NV + v;
-      const T r0 = dinv[dof] * (b[k] - acc[i]);
-      const T d0 = r0 * inv_theta;
-      xo[k] = xin[k] + d0;
-      d[k] = d0;
-      r[k] = r0;
-    }
+  __device__ void one(int64_t row, int i, int v, T a) const {
+    const int64_t dof = row * BR + i, k = dof * NV + v;
+    const T r0 = dinv[dof] * (b[k] - a);
+    const T d0 = r0 * inv_theta;
+    xo[k] = xin[k] + d0;
+    d[k] = d0;
+    r[k] = r0;
   }
+  FPC_EPI_ROW
 };
 
 // post-smoothing step 2 around q = A d0: r1 = r0 - D^-1 q,
@@ -151,14 +152,12 @@ struct EpiPost2 {
   const T* __restrict__ din;
   T* __restrict__ xo;
   T c1, c2;
-  __device__ void operator()(int64_t row, int v, const T* acc) const {
-#pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t dof = row * BR + i, k = dof * NV + v;
-      const T r1 = r[k] - dinv[dof] * acc[i];
-      xo[k] += c1 * din[k] + c2 * r1;
-    }
+  __device__ void one(int64_t row, int i, int v, T a) const {
+    const int64_t dof = row * BR + i, k = dof * NV + v;
+    const T r1 = r[k] - dinv[dof] * a;
+    xo[k] += c1 * din[k] + c2 * r1;
   }
+  FPC_EPI_ROW
 };
 
 // ---------------------------------------------------------------- SpMV
@@ -207,6 +206,101 @@ void launch_sell(const Sell<T>& A, Load ld, Epi epi, hipStream_t s) {
   const unsigned grid = (unsigned)((waves + 3) / 4);
   k_sell<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   FPC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- row groups
+template <typename T>
+struct VrowView {
+  int64_t nrows;
+  const int64_t* __restrict__ chunk_ptr;
+  const int32_t* __restrict__ row_len;
+  const int32_t* __restrict__ col;
+  const T* __restrict__ val;
+};
+
+template <typename T>
+VrowView<T> vview(const Vrow<T>& a) {
+  return VrowView<T>{a.nrows, a.chunk_ptr.p, a.row_len.p, a.col.p, a.val.p};
+}
+
+// G lanes per block row: lane sl takes blocks sl, sl+G, ... of the row
+// (chunk-contiguous, component-major), then the G partial sums are combined
+// with cross-lane shuffles inside the aligned lane group.
+template <typename T, int BR, int BC, int NV, int G, class Load, class Epi>
+__global__ __launch_bounds__(256) void k_vrow(VrowView<T> A, Load ld, Epi epi) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t t = blk * 256 + threadIdx.x;
+  const int64_t row = t / G;
+  const int sl = (int)(t % G);
+  if (row >= A.nrows) return;
+  const int len = A.row_len[row];
+  const int64_t c0 = A.chunk_ptr[row];
+  T acc[NV][BR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[v][i] = T(0);
+  for (int k0 = 0; k0 < len; k0 += G) {
+    if (k0 + sl < len) {
+      const int64_t grp = (c0 + k0 / G) * (int64_t)G;
+      const int64_t c = A.col[grp + sl];
+      const T* __restrict__ vb = A.val + grp * (BR * BC) + sl;
+      T bv[BR * BC];
+#pragma unroll
+      for (int q = 0; q < BR * BC; ++q) bv[q] = vb[(int64_t)q * G];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T xv[BC];
+#pragma unroll
+        for (int j = 0; j < BC; ++j) xv[j] = ld(c * BC + j, v);
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+          for (int j = 0; j < BC; ++j) acc[v][i] += bv[i * BC + j] * xv[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int i = 0; i < BR; ++i) acc[v][i] += __shfl_xor(acc[v][i], off, 64);
+  // after the butterfly every lane of the group holds all BR*NV sums; lane
+  // sl writes elements sl, sl+G, ...
+#pragma unroll
+  for (int q0 = 0; q0 < BR * NV; q0 += G) {
+    const int q = q0 + sl;
+    if (q < BR * NV) {
+      T a = T(0);
+#pragma unroll
+      for (int vv = 0; vv < NV; ++vv)
+#pragma unroll
+        for (int ii = 0; ii < BR; ++ii)
+          if (ii * NV + vv == q) a = acc[vv][ii];
+      epi.one(row, q / NV, q % NV, a);
+    }
+  }
+}
+
+template <typename T, int BR, int BC, int NV, int G, class Load, class Epi>
+void launch_vrow(const Vrow<T>& A, Load ld, Epi epi, hipStream_t s) {
+  if (A.nrows == 0) return;
+  const int64_t threads = A.nrows * G;
+  const unsigned grid = (unsigned)((threads + 255) / 256);
+  k_vrow<T, BR, BC, NV, G, Load, Epi><<<grid, 256, 0, s>>>(vview(A), ld, epi);
+  FPC_LAUNCH_CHECK();
+}
+
+template <typename T, int BR, int BC, int NV, class Load, class Epi>
+void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
+  if (op.fmt == 0) return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
+  switch (op.v.G) {
+    case 4: return launch_vrow<T, BR, BC, NV, 4>(op.v, ld, epi, s);
+    case 16: return launch_vrow<T, BR, BC, NV, 16>(op.v, ld, epi, s);
+    case 64: return launch_vrow<T, BR, BC, NV, 64>(op.v, ld, epi, s);
+  }
+  throw Error(FPC_ERR_ARG, "launch_op: unsupported row-group width");
 }
 
 // ---------------------------------------------------------------- coarsest
@@ -317,9 +411,11 @@ __global__ void k_tface(const int64_t* __restrict__ rp,
   }
 }
 
-// exact pressure-block solve: one wavefront per (component, row)
+// exact pressure-block solve: one wavefront per (component, row); each lane
+// keeps four independent loads of the dense inverse row in flight.
+template <typename M>
 __global__ __launch_bounds__(256) void k_psolve(
-    const double* __restrict__ dense, const int64_t* __restrict__ dense_off,
+    const M* __restrict__ dense, const int64_t* __restrict__ dense_off,
     const int64_t* __restrict__ comp_off, const int64_t* __restrict__ comp_pad,
     const int32_t* __restrict__ comp_of_row, const int32_t* __restrict__ members,
     const double* __restrict__ in, double* __restrict__ out, int64_t n_p,
@@ -332,12 +428,23 @@ __global__ __launch_bounds__(256) void k_psolve(
   const int64_t n = comp_off[c + 1] - o;
   const int64_t ld = comp_pad[c];
   const int64_t r = g - o;
-  const double* M = dense + dense_off[c];
-  double acc = 0.0;
-  if (!trans)
-    for (int64_t k = lane; k < n; k += 64) acc += M[r * ld + k] * in[members[o + k]];
-  else
-    for (int64_t k = lane; k < n; k += 64) acc += M[k * ld + r] * in[members[o + k]];
+  const M* __restrict__ D = dense + dense_off[c];
+  const int32_t* __restrict__ mem = members + o;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t k = lane;
+  if (!trans) {
+    const M* __restrict__ row = D + r * ld;
+    for (; k + 192 < n; k += 256) {
+      a0 += (double)row[k] * in[mem[k]];
+      a1 += (double)row[k + 64] * in[mem[k + 64]];
+      a2 += (double)row[k + 128] * in[mem[k + 128]];
+      a3 += (double)row[k + 192] * in[mem[k + 192]];
+    }
+    for (; k < n; k += 64) a0 += (double)row[k] * in[mem[k]];
+  } else {
+    for (; k < n; k += 64) a0 += (double)D[k * ld + r] * in[mem[k]];
+  }
+  double acc = (a0 + a1) + (a2 + a3);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) out[members[g]] = acc;
 }
@@ -350,27 +457,27 @@ __global__ void k_zero(T* p, int64_t n) {
 
 // ---------------------------------------------------------------- V-cycle
 template <typename T>
-const Sell<T>& selA(const Level& L, bool tr);
+const Op<T>& selA(const Level& L, bool tr);
 template <>
-const Sell<double>& selA<double>(const Level& L, bool tr) {
-  return tr ? L.sAT : L.sA;
+const Op<double>& selA<double>(const Level& L, bool tr) {
+  return tr ? L.oAT : L.oA;
 }
 template <>
-const Sell<float>& selA<float>(const Level& L, bool tr) {
+const Op<float>& selA<float>(const Level& L, bool tr) {
   return tr ? L.fAT : L.fA;
 }
 template <typename T>
-const Sell<T>& selP(const Level& L);
+const Op<T>& selP(const Level& L);
 template <>
-const Sell<double>& selP<double>(const Level& L) { return L.sP; }
+const Op<double>& selP<double>(const Level& L) { return L.oP; }
 template <>
-const Sell<float>& selP<float>(const Level& L) { return L.fP; }
+const Op<float>& selP<float>(const Level& L) { return L.fP; }
 template <typename T>
-const Sell<T>& selR(const Level& L);
+const Op<T>& selR(const Level& L);
 template <>
-const Sell<double>& selR<double>(const Level& L) { return L.sR; }
+const Op<double>& selR<double>(const Level& L) { return L.oR; }
 template <>
-const Sell<float>& selR<float>(const Level& L) { return L.fR; }
+const Op<float>& selR<float>(const Level& L) { return L.fR; }
 template <typename T>
 const T* seldinv(const Level& L);
 template <>
@@ -381,24 +488,24 @@ const float* seldinv<float>(const Level& L) { return L.dinv32.p; }
 template <typename T, int BS, int NV>
 void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
                   int phase, KTimer* timer) {
-  const Sell<T>& A = selA<T>(L, tr);
+  const Op<T>& A = selA<T>(L, tr);
   const T* dinv = seldinv<T>(L);
   const T it = T(1.0 / L.theta), c1 = T(L.c1), c2 = T(L.c2);
   if (phase == 0) {
-    launch_sell<T, BS, BS, NV>(A, LoadScaled<T, NV>{v.b.p, dinv, it},
+    launch_op<T, BS, BS, NV>(A, LoadScaled<T, NV>{v.b.p, dinv, it},
                                EpiPre1<T, BS, NV>{v.b.p, dinv, v.x.p, v.d.p,
                                                   v.r.p, it, c1, c2},
                                s);
     if (timer) timer->begin(s);
-    launch_sell<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
+    launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
                                EpiRes<T, BS, NV>{v.r.p, v.res.p}, s);
     if (timer) timer->end(s);
   } else {
-    launch_sell<T, BS, BS, NV>(A, LoadX<T, NV>{v.x.p},
+    launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.x.p},
                                EpiPost1<T, BS, NV>{v.b.p, dinv, v.x.p, v.xo.p,
                                                    v.d.p, v.r.p, it},
                                s);
-    launch_sell<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
+    launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
                                EpiPost2<T, BS, NV>{dinv, v.r.p, v.d.p, v.xo.p,
                                                    c1, c2},
                                s);
@@ -408,14 +515,14 @@ void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
 template <typename T, int BS, int NB, int NV>
 void restrict_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
                     hipStream_t s) {
-  launch_sell<T, NB, BS, NV>(selR<T>(L), LoadX<T, NV>{v.res.p},
+  launch_op<T, NB, BS, NV>(selR<T>(L), LoadX<T, NV>{v.res.p},
                              EpiStore<T, NB, NV>{vc.b.p}, s);
 }
 
 template <typename T, int BS, int NB, int NV>
 void prolong_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
                    hipStream_t s) {
-  launch_sell<T, BS, NB, NV>(selP<T>(L), LoadX<T, NV>{vc.xo.p},
+  launch_op<T, BS, NB, NV>(selP<T>(L), LoadX<T, NV>{vc.xo.p},
                              EpiAdd<T, BS, NV>{v.x.p}, s);
 }
 
@@ -472,7 +579,80 @@ std::vector<CycleVecs<float>>& vec_sets<float>(Hierarchy& H) {
   return H.v32;
 }
 
+// ---------------------------------------------------------------- tuner
+template <typename T, int BR, int BC, int NV>
+double time_op(const Op<T>& op, const T* x, T* y, hipStream_t s, int reps) {
+  launch_op<T, BR, BC, NV>(op, LoadX<T, NV>{x}, EpiStore<T, BR, NV>{y}, s);
+  hipEvent_t e0, e1;
+  FPC_HIP(hipEventCreate(&e0));
+  FPC_HIP(hipEventCreate(&e1));
+  FPC_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r)
+    launch_op<T, BR, BC, NV>(op, LoadX<T, NV>{x}, EpiStore<T, BR, NV>{y}, s);
+  FPC_HIP(hipEventRecord(e1, s));
+  FPC_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  FPC_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+template <typename T, int NV>
+double time_any(const Op<T>& op, int br, int bc, const T* x, T* y,
+                hipStream_t s, int reps) {
+  if (br == 3 && bc == 3) return time_op<T, 3, 3, NV>(op, x, y, s, reps);
+  if (br == 3 && bc == 6) return time_op<T, 3, 6, NV>(op, x, y, s, reps);
+  if (br == 6 && bc == 3) return time_op<T, 6, 3, NV>(op, x, y, s, reps);
+  if (br == 6 && bc == 6) return time_op<T, 6, 6, NV>(op, x, y, s, reps);
+  throw Error(FPC_ERR_ARG, "tuner: unsupported block shape");
+}
+
 }  // namespace
+
+// Pick the apply layout of one operator: sliced ELL (one thread per block
+// row) or row groups of 4, 16 or 64 lanes, by timing `reps` products with
+// `nv` columns on the device; only the winner is kept.
+template <typename T>
+void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice) {
+  DevBuf<T> x(std::max<int64_t>(M.nbc * M.bc * nv, 1));
+  DevBuf<T> y(std::max<int64_t>(M.nbr * M.br * nv, 1));
+  FPC_HIP(hipMemsetAsync(x.p, 0, x.bytes(), s));
+  const int reps = 5;
+  auto timeit = [&](const Op<T>& op) {
+    return nv == 2 ? time_any<T, 2>(op, M.br, M.bc, x.p, y.p, s, reps)
+                   : time_any<T, 1>(op, M.br, M.bc, x.p, y.p, s, reps);
+  };
+  // candidates that cannot win are skipped: sliced ELL for very long rows,
+  // wide row groups for short rows
+  const double avg = M.nbr ? (double)M.nnzb / (double)M.nbr : 0.0;
+  Op<T> best;
+  double tbest = 1e300;
+  int cbest = 0;
+  if (avg <= 64.0) {
+    best.fmt = 0;
+    bsr_to_sell(M, best.s, s);
+    tbest = timeit(best);
+    cbest = 1;
+  }
+  for (int G : {4, 16, 64}) {
+    if (cbest != 0 && G > 4 * avg + 4) continue;
+    Op<T> cand;
+    cand.fmt = 1;
+    bsr_to_vrow(M, G, cand.v, s);
+    const double t = timeit(cand);
+    if (t < tbest) {
+      tbest = t;
+      best = std::move(cand);
+      cbest = G;
+    }
+  }
+  out = std::move(best);
+  if (choice) *choice = cbest;
+  FPC_HIP(hipStreamSynchronize(s));
+}
+template void tune_op<double>(const Bsr&, int, Op<double>&, hipStream_t, int*);
+template void tune_op<float>(const Bsr&, int, Op<float>&, hipStream_t, int*);
 
 template <typename T>
 CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv) {
@@ -583,9 +763,17 @@ void tface(const Csr& C, const double* vu, const double* t_t,
 void psolve_apply(const PSolve& ps, const double* in, double* out,
                   int64_t n_p, int trans, hipStream_t s) {
   if (n_p == 0) return;
-  k_psolve<<<(unsigned)((n_p + 3) / 4), 256, 0, s>>>(
-      ps.dense.p, ps.dense_off.p, ps.comp_off.p, ps.comp_pad_d.p,
-      ps.comp_of_row.p, ps.members.p, in, out, n_p, trans);
+  const unsigned g = (unsigned)((n_p + 3) / 4);
+  if (ps.dense32.p)
+    k_psolve<float><<<g, 256, 0, s>>>(ps.dense32.p, ps.dense_off.p,
+                                      ps.comp_off.p, ps.comp_pad_d.p,
+                                      ps.comp_of_row.p, ps.members.p, in, out,
+                                      n_p, trans);
+  else
+    k_psolve<double><<<g, 256, 0, s>>>(ps.dense.p, ps.dense_off.p,
+                                       ps.comp_off.p, ps.comp_pad_d.p,
+                                       ps.comp_of_row.p, ps.members.p, in,
+                                       out, n_p, trans);
   FPC_LAUNCH_CHECK();
 }
 
