@@ -35,6 +35,44 @@ void tface(const Csr& C, const double* vu, const double* t_t,
 void psolve_apply(const PSolve& ps, const double* in, double* out,
                   int64_t n_p, int trans, hipStream_t s);
 
+// ---------------------------------------------------------------- batches
+void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,
+               hipStream_t s);
+void pack_cols(const double* B, int64_t ldb, int64_t n, int k, int KB,
+               double* out, hipStream_t s);
+void unpack_cols(const double* Xi, int64_t n, int k, int KB, double* X,
+                 int64_t ldx, hipStream_t s);
+void face_apply_b(const double* hinv, const double* in, double* out,
+                  int64_t n_p, int KB, int trans, hipStream_t s);
+void csr_spmv2_b(const Csr* m1, const double* x1, double a1, const Csr* m2,
+                 const double* x2, double a2, double* y, double beta, int KB,
+                 hipStream_t s);
+template <typename T>
+void to_level_b(T* out, int sel, int KB, int64_t n, const double* base,
+                const Csr& M1, const double* x1, double a1, hipStream_t s);
+template <typename T>
+void from_level_b(const T* xo, int64_t n, int KB, double* vu, hipStream_t s);
+void tface_b(const Csr& C, const double* vu, const double* t_t,
+             const double* hinv, double* v_t, int64_t n_p, int KB,
+             hipStream_t s);
+void psolve_apply_b(const PSolve& ps, const double* in, double* out,
+                    int64_t n_p, int KB, hipStream_t s);
+void bmdot(const double* V, int64_t ldv, int nv, const double* W, int64_t n,
+           int KB, double* part, double* out, hipStream_t s);
+void bmaxpy(const double* V, int64_t ldv, int nv, const double* h, double* W,
+            int64_t n, int KB, hipStream_t s);
+void bscale(const double* x, const double* scal, double* y, int64_t n, int KB,
+            hipStream_t s);
+void bsub(const double* a, double* b, int64_t n, hipStream_t s);
+void bgmres_step(double* H, double* cs, double* sn, double* g,
+                 const double* h1, const double* h2, const double* nrm2,
+                 const double* nrm0, int j, int m, int KB, const int* active,
+                 double* scal, double* est, int* brk, hipStream_t s);
+void bgmres_init(double* g, int m, int KB, const double* beta2,
+                 const int* active, double* scal, hipStream_t s);
+void btrisolve(const double* H, const double* g, double* y, const int* kc,
+               int m, int KB, hipStream_t s);
+
 // ---------------------------------------------------------------- Krylov
 // partial[i * G + blk] = <V_i, w> over a chunk; V_i = V + i * ldv
 constexpr int kDotBlocks = 256;

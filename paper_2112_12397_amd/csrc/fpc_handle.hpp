@@ -24,6 +24,10 @@ struct Level {
   Op<double> oAT;
   Op<float> fAT;
   int layout[3] = {0, 0, 0};   // tuner choice for A, P, R (1 = sliced ELL)
+  // multi-right-hand-side operators (sliced ELL, one thread per row and
+  // column), built on the first batched solve
+  Op<double> bA, bP, bR;
+  Op<float> gA, gP, gR;
   DevBuf<double> dinv;      // n_nodes * bs
   DevBuf<float> dinv32;
   DevBuf<int32_t> agg;      // aggregate of every node (-1 isolated)
@@ -123,6 +127,16 @@ struct Krylov {
   }
 };
 
+// Work space of the batched solve (KB interleaved right-hand sides).
+struct BatchWork {
+  int KB = 0, m = 0;
+  int64_t N = 0;
+  DevBuf<double> V, Z, W, R, Bi, Xi, tt;
+  DevBuf<double> H, cs, sn, g, y, yneg, h1, h2, nrm0, nrm2, beta2, scal, est,
+      bnorm2, partials;
+  DevBuf<int> active, kc, brk;
+};
+
 }  // namespace fpc
 
 struct fpc_handle {
@@ -146,6 +160,7 @@ struct fpc_handle {
   fpc::Krylov kry1;            // single right-hand side
   fpc::Krylov kryB;            // batched
   fpc::KTimer ktimer;
+  fpc::BatchWork bw;
   std::string last_error;
   double setup_times[5] = {0, 0, 0, 0, 0};
 };

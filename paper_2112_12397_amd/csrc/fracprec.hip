@@ -644,6 +644,243 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
   return converged ? FPC_OK : FPC_NOT_CONVERGED;
 }
 
+// ------------------------------------------------------------- batches
+void ensure_batch_ops(fpc_handle* h) {
+  hipStream_t s = h->stream;
+  const bool fp32 = h->opt.precision == FPC_FP32_PREC;
+  for (Level& L : h->amg.L) {
+    if (L.coarsest) continue;
+    if (fp32 ? L.gA.s.nrows != 0 : L.bA.s.nrows != 0) continue;
+    if (fp32) {
+      L.gA.fmt = L.gP.fmt = L.gR.fmt = 0;
+      bsr_to_sell(L.A, L.gA.s, s);
+      bsr_to_sell(L.P, L.gP.s, s);
+      bsr_to_sell(L.R, L.gR.s, s);
+    } else {
+      L.bA.fmt = L.bP.fmt = L.bR.fmt = 0;
+      bsr_to_sell(L.A, L.bA.s, s);
+      bsr_to_sell(L.P, L.bP.s, s);
+      bsr_to_sell(L.R, L.bR.s, s);
+    }
+  }
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+BatchWork& batch_work(fpc_handle* h, int KB) {
+  BatchWork* w = &h->bw;
+  const int m = h->opt.restart;
+  if (w->KB == KB && w->m == m && w->N == h->N) return *w;
+  w->KB = KB;
+  w->m = m;
+  w->N = h->N;
+  const int64_t N = h->N;
+  w->V.alloc((int64_t)(m + 1) * N * KB);
+  w->Z.alloc((int64_t)m * N * KB);
+  w->W.alloc(N * KB);
+  w->R.alloc(N * KB);
+  w->Bi.alloc(N * KB);
+  w->Xi.alloc(N * KB);
+  w->tt.alloc(std::max<int64_t>(h->n_t, 1) * KB);
+  w->H.alloc((int64_t)KB * (m + 1) * m);
+  w->cs.alloc((int64_t)KB * m);
+  w->sn.alloc((int64_t)KB * m);
+  w->g.alloc((int64_t)KB * (m + 1));
+  w->y.alloc((int64_t)KB * m);
+  w->yneg.alloc((int64_t)KB * m);
+  w->h1.alloc((int64_t)KB * (m + 1));
+  w->h2.alloc((int64_t)KB * (m + 1));
+  w->nrm0.alloc(KB);
+  w->nrm2.alloc(KB);
+  w->beta2.alloc(KB);
+  w->scal.alloc(KB);
+  w->est.alloc(KB);
+  w->bnorm2.alloc(KB);
+  w->partials.alloc((int64_t)(m + 1) * kDotBlocks * KB);
+  w->active.alloc(KB);
+  w->kc.alloc(KB);
+  w->brk.alloc(KB);
+  return *w;
+}
+
+void matvec_b(fpc_handle* h, const double* X, double* Y, int KB) {
+  hipStream_t s = h->stream;
+  const int64_t nu = h->n_u, nt = h->n_t;
+  const double *Xu = X, *Xt = X + nu * KB, *Xp = X + (nu + nt) * KB;
+  double *Yu = Y, *Yt = Y + nu * KB, *Yp = Y + (nu + nt) * KB;
+  sell_mv_b(h->sAJ, Xu, Yu, KB, s);
+  csr_spmv2_b(&h->C1, Xt, 1.0, &h->Q1, Xp, 1.0, Yu, 1.0, KB, s);
+  csr_spmv2_b(&h->C2, Xu, 1.0, &h->H, Xt, -1.0, Yt, 0.0, KB, s);
+  csr_spmv2_b(&h->Q2, Xu, 1.0, &h->T, Xp, 1.0, Yp, 0.0, KB, s);
+}
+
+// Alg 3.4 on KB right-hand sides at once (Q2 = 0: the two AMG calls of every
+// column run in one V-cycle over 2 KB interleaved columns).
+template <typename T, int NV>
+void apply_fwd_b(fpc_handle* h, BatchWork& w, const double* W, double* V) {
+  hipStream_t s = h->stream;
+  const int KB = NV / 2;
+  const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
+  const double *Wu = W, *Wt = W + nu * KB, *Wp = W + (nu + nt) * KB;
+  double *Vu = V, *Vt = V + nu * KB, *Vp = V + (nu + nt) * KB;
+  face_apply_b(h->hinv.p, Wt, w.tt.p, np, KB, 0, s);
+  psolve_apply_b(h->ps, Wp, Vp, np, KB, s);
+  CycleVecs<T>& cv = cycle_vecs<T>(h->amg, NV);
+  to_level_b<T>(cv.lv[0].b.p, 0, KB, nu, Wu, h->C1, w.tt.p, 1.0, s);
+  to_level_b<T>(cv.lv[0].b.p, 1, KB, nu, nullptr, h->Q1, Vp, 1.0, s);
+  vcycle<T, NV>(h->amg, false, s);
+  from_level_b<T>(cv.lv[0].xo.p, nu, KB, Vu, s);
+  tface_b(h->C2, Vu, w.tt.p, h->hinv.p, Vt, np, KB, s);
+}
+
+void apply_b(fpc_handle* h, BatchWork& w, const double* W, double* V) {
+  const bool fp32 = h->opt.precision == FPC_FP32_PREC;
+  if (w.KB == 8) {
+    if (fp32) apply_fwd_b<float, 16>(h, w, W, V);
+    else apply_fwd_b<double, 16>(h, w, W, V);
+  } else {
+    if (fp32) apply_fwd_b<float, 64>(h, w, W, V);
+    else apply_fwd_b<double, 64>(h, w, W, V);
+  }
+}
+
+// Block of k right-hand sides: every column runs its own FGMRES(m) with its
+// own tolerance; the columns advance together so that the preconditioner and
+// the Jacobian are applied to all active columns in one pass.
+fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
+                        double* X, int64_t ldx, double rtol, fpc_info* infos) {
+  const double t0 = now_s();
+  hipStream_t s = h->stream;
+  if (h->opt.mode != FPC_TUP)
+    throw Error(FPC_ERR_UNSUPPORTED, "batched solve uses the t-u-p mode");
+  const int KB = k <= 8 ? 8 : 32;
+  ensure_batch_ops(h);
+  BatchWork& w = batch_work(h, KB);
+  const int m = h->opt.restart;
+  const int64_t N = h->N;
+  if (rtol <= 0) rtol = h->opt.rtol;
+  fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+  for (int c = 0; c < k; ++c) check_finite(B + c * ldb, N, h->flags.p, s);
+  check_flags(h, "right-hand sides");
+  pack_cols(B, ldb, N, k, KB, w.Bi.p, s);
+  bmdot(w.Bi.p, 0, 1, w.Bi.p, N, KB, w.partials.p, w.bnorm2.p, s);
+  std::vector<double> bn(KB), hbuf(KB);
+  std::vector<int> act(KB, 0), kc(KB, 0), brk(KB, 0), done(KB, 0),
+      conv(KB, 0), its(KB, 0), cycles(KB, 0);
+  std::vector<double> truer(KB, 0.0), estv(KB, 0.0);
+  FPC_HIP(hipMemcpyAsync(bn.data(), w.bnorm2.p, KB * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < KB; ++c) {
+    bn[c] = std::sqrt(std::max(bn[c], 0.0));
+    if (c >= k || bn[c] == 0.0) {
+      done[c] = 1;
+      conv[c] = 1;
+    }
+  }
+  FPC_HIP(hipMemsetAsync(w.Xi.p, 0, N * KB * sizeof(double), s));
+  int total = 0;
+  while (true) {
+    matvec_b(h, w.Xi.p, w.W.p, KB);
+    FPC_HIP(hipMemcpyAsync(w.R.p, w.Bi.p, N * KB * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    bsub(w.R.p, w.W.p, N * KB, s);  // W = R - W = B - J X
+    bmdot(w.W.p, 0, 1, w.W.p, N, KB, w.partials.p, w.beta2.p, s);
+    FPC_HIP(hipMemcpyAsync(hbuf.data(), w.beta2.p, KB * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int c = 0; c < KB; ++c) {
+      act[c] = 0;
+      kc[c] = 0;
+      if (done[c]) continue;
+      const double beta = std::sqrt(std::max(hbuf[c], 0.0));
+      truer[c] = beta / bn[c];
+      if (beta <= rtol * bn[c]) {
+        done[c] = 1;
+        conv[c] = 1;
+        continue;
+      }
+      act[c] = 1;
+      any = true;
+    }
+    if (!any || total >= h->opt.maxit) break;
+    FPC_HIP(hipMemcpyAsync(w.active.p, act.data(), KB * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    bgmres_init(w.g.p, m, KB, w.beta2.p, w.active.p, w.scal.p, s);
+    bscale(w.W.p, w.scal.p, w.V.p, N, KB, s);
+    for (int c = 0; c < KB; ++c)
+      if (act[c]) ++cycles[c];
+    int jlast = 0;
+    for (int j = 0; j < m; ++j) {
+      const int64_t stride = N * KB;
+      double* Vj = w.V.p + (int64_t)j * stride;
+      double* Zj = w.Z.p + (int64_t)j * stride;
+      apply_b(h, w, Vj, Zj);
+      matvec_b(h, Zj, w.W.p, KB);
+      bmdot(w.W.p, 0, 1, w.W.p, N, KB, w.partials.p, w.nrm0.p, s);
+      bmdot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h1.p, s);
+      bmaxpy(w.V.p, stride, j + 1, w.h1.p, w.W.p, N, KB, s);
+      bmdot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h2.p, s);
+      bmaxpy(w.V.p, stride, j + 1, w.h2.p, w.W.p, N, KB, s);
+      bmdot(w.W.p, 0, 1, w.W.p, N, KB, w.partials.p, w.nrm2.p, s);
+      bgmres_step(w.H.p, w.cs.p, w.sn.p, w.g.p, w.h1.p, w.h2.p, w.nrm2.p,
+                  w.nrm0.p, j, m, KB, w.active.p, w.scal.p, w.est.p, w.brk.p,
+                  s);
+      bscale(w.W.p, w.scal.p, w.V.p + (int64_t)(j + 1) * stride, N, KB, s);
+      FPC_HIP(hipMemcpyAsync(estv.data(), w.est.p, KB * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      FPC_HIP(hipMemcpyAsync(brk.data(), w.brk.p, KB * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+      FPC_HIP(hipStreamSynchronize(s));
+      ++total;
+      jlast = j;
+      bool changed = false, still = false;
+      for (int c = 0; c < KB; ++c) {
+        if (!act[c]) continue;
+        ++its[c];
+        if (estv[c] <= rtol * bn[c] || brk[c] || its[c] >= h->opt.maxit) {
+          act[c] = 0;
+          kc[c] = j + 1;
+          changed = true;
+        } else {
+          still = true;
+        }
+      }
+      if (!still || total >= h->opt.maxit) break;
+      if (changed)
+        FPC_HIP(hipMemcpyAsync(w.active.p, act.data(), KB * sizeof(int),
+                               hipMemcpyHostToDevice, s));
+    }
+    for (int c = 0; c < KB; ++c)
+      if (act[c]) kc[c] = jlast + 1;
+    int kmax = 0;
+    for (int c = 0; c < KB; ++c) kmax = std::max(kmax, kc[c]);
+    FPC_HIP(hipMemcpyAsync(w.kc.p, kc.data(), KB * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    btrisolve(w.H.p, w.g.p, w.y.p, w.kc.p, m, KB, s);
+    axpby(-1.0, w.y.p, 0.0, w.yneg.p, (int64_t)m * KB, s);
+    bmaxpy(w.Z.p, N * KB, kmax, w.yneg.p, w.Xi.p, N, KB, s);
+    for (int c = 0; c < KB; ++c)
+      if (!done[c] && its[c] >= h->opt.maxit) done[c] = 1;
+  }
+  unpack_cols(w.Xi.p, N, k, KB, X, ldx, s);
+  FPC_HIP(hipStreamSynchronize(s));
+  const double secs = now_s() - t0;
+  bool all = true;
+  for (int c = 0; c < k; ++c) {
+    all = all && conv[c];
+    if (infos) {
+      infos[c].iterations = its[c];
+      infos[c].restarts = cycles[c];
+      infos[c].converged = conv[c];
+      infos[c].true_rel_residual = bn[c] > 0 ? truer[c] : 0.0;
+      infos[c].est_rel_residual = bn[c] > 0 ? estv[c] / bn[c] : 0.0;
+      infos[c].seconds = secs;
+    }
+  }
+  return all ? FPC_OK : FPC_NOT_CONVERGED;
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -852,17 +1089,11 @@ fpc_status fpc_solve_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
   FPC_REQUIRE_READY(h);
   if (!B || !X || k < 1 || k > h->opt.max_batch || ldb < h->N || ldx < h->N)
     return FPC_ERR_ARG;
-  // Columns are solved one after another with the single right-hand-side
-  // driver; every column keeps its own tolerance and statistics.
-  fpc_status worst = FPC_OK;
-  for (int c = 0; c < k; ++c) {
-    fpc_info inf{};
-    fpc_status st = fpc_solve(h, B + c * ldb, X + c * ldx, rtol, 0, &inf);
-    if (infos) infos[c] = inf;
-    if (st < 0) return st;
-    if (st != FPC_OK) worst = st;
-  }
-  return worst;
+  fpc_status st = FPC_OK;
+  fpc_status g = guard(h, [&] {
+    st = fgmres_batch(h, k, B, ldb, X, ldx, rtol, infos);
+  });
+  return g != FPC_OK ? g : st;
 }
 
 fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,

@@ -1,0 +1,434 @@
+// Multi-right-hand-side kernels.  A block of KB right-hand sides is stored
+// interleaved: element (n, c) at n * KB + c, so every sparse row is read once
+// for all columns and column accesses of a row are contiguous.
+#include "fpc_apply.hpp"
+
+namespace fpc {
+
+namespace {
+
+__global__ void k_pack(const double* __restrict__ B, int64_t ldb, int64_t n,
+                       int k, int KB, double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * KB) return;
+  const int64_t i = t / KB;
+  const int c = (int)(t % KB);
+  out[t] = c < k ? B[(int64_t)c * ldb + i] : 0.0;
+}
+
+__global__ void k_unpack(const double* __restrict__ Xi, int64_t n, int k,
+                         int KB, double* __restrict__ X, int64_t ldx) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const int c = (int)(t / n);
+  const int64_t i = t % n;
+  X[(int64_t)c * ldx + i] = Xi[i * KB + c];
+}
+
+__global__ void k_face_apply_b(const double* __restrict__ hinv,
+                               const double* __restrict__ in,
+                               double* __restrict__ out, int64_t n_p, int KB,
+                               int trans) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_p * KB) return;
+  const int64_t K = t / KB;
+  const int c = (int)(t % KB);
+  const double* h = hinv + K * 9;
+  const double a = in[(3 * K) * KB + c], b = in[(3 * K + 1) * KB + c],
+               d = in[(3 * K + 2) * KB + c];
+  for (int r = 0; r < 3; ++r) {
+    const double v = trans ? h[0 * 3 + r] * a + h[1 * 3 + r] * b + h[2 * 3 + r] * d
+                           : h[r * 3 + 0] * a + h[r * 3 + 1] * b + h[r * 3 + 2] * d;
+    out[(3 * K + r) * KB + c] = v;
+  }
+}
+
+// y(i, c) = beta y(i, c) + a1 (M1 x1)(i, c) + a2 (M2 x2)(i, c)
+__global__ void k_csr_spmv2_b(const int64_t* rp1, const int32_t* c1,
+                              const double* v1, const double* x1, double a1,
+                              const int64_t* rp2, const int32_t* c2,
+                              const double* v2, const double* x2, double a2,
+                              double* y, double beta, int64_t nrows, int KB) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * KB) return;
+  const int64_t i = t / KB;
+  const int c = (int)(t % KB);
+  double s1 = 0.0;
+  for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e)
+    s1 += v1[e] * x1[(int64_t)c1[e] * KB + c];
+  double r = a1 * s1;
+  if (rp2) {
+    double s2 = 0.0;
+    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e)
+      s2 += v2[e] * x2[(int64_t)c2[e] * KB + c];
+    r += a2 * s2;
+  }
+  y[t] = (beta == 0.0) ? r : beta * y[t] + r;
+}
+
+// level-0 input of the two-column V-cycle per right-hand side:
+// out(i, 2c + sel) = (T)(base(i, c) + a1 (M1 x1)(i, c))
+template <typename T>
+__global__ void k_to_level_b(T* __restrict__ out, int sel, int KB,
+                             const double* __restrict__ base,
+                             const int64_t* rp1, const int32_t* c1,
+                             const double* v1, const double* x1, double a1,
+                             int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * KB) return;
+  const int64_t i = t / KB;
+  const int c = (int)(t % KB);
+  double r = base ? base[t] : 0.0;
+  double s = 0.0;
+  for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e)
+    s += v1[e] * x1[(int64_t)c1[e] * KB + c];
+  r += a1 * s;
+  out[i * (2 * KB) + 2 * c + sel] = (T)r;
+}
+
+template <typename T>
+__global__ void k_from_level_b(const T* __restrict__ xo, int64_t n, int KB,
+                               double* __restrict__ vu) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * KB) return;
+  const int64_t i = t / KB;
+  const int c = (int)(t % KB);
+  vu[t] = (double)xo[i * (2 * KB) + 2 * c] - (double)xo[i * (2 * KB) + 2 * c + 1];
+}
+
+__global__ void k_tface_b(const int64_t* __restrict__ rp,
+                          const int32_t* __restrict__ col,
+                          const double* __restrict__ val,
+                          const double* __restrict__ vu,
+                          const double* __restrict__ t_t,
+                          const double* __restrict__ hinv,
+                          double* __restrict__ v_t, int64_t n_p, int KB) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_p * KB) return;
+  const int64_t K = t / KB;
+  const int c = (int)(t % KB);
+  double s[3];
+  for (int r = 0; r < 3; ++r) {
+    double a = 0.0;
+    const int64_t row = 3 * K + r;
+    for (int64_t e = rp[row]; e < rp[row + 1]; ++e)
+      a += val[e] * vu[(int64_t)col[e] * KB + c];
+    s[r] = a;
+  }
+  const double* h = hinv + K * 9;
+  for (int r = 0; r < 3; ++r)
+    v_t[(3 * K + r) * KB + c] = -t_t[(3 * K + r) * KB + c] +
+                                h[r * 3] * s[0] + h[r * 3 + 1] * s[1] +
+                                h[r * 3 + 2] * s[2];
+}
+
+// dense pressure-block inverse applied to KB columns: one thread per
+// (row, column); the matrix row is read once per wavefront (broadcast)
+template <typename M>
+__global__ __launch_bounds__(256) void k_psolve_b(
+    const M* __restrict__ dense, const int64_t* __restrict__ dense_off,
+    const int64_t* __restrict__ comp_off, const int64_t* __restrict__ comp_pad,
+    const int32_t* __restrict__ comp_of_row, const int32_t* __restrict__ members,
+    const double* __restrict__ in, double* __restrict__ out, int64_t n_p,
+    int KB) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = t / KB;
+  const int c = (int)(t % KB);
+  if (g >= n_p) return;
+  const int cc = comp_of_row[g];
+  const int64_t o = comp_off[cc];
+  const int64_t n = comp_off[cc + 1] - o;
+  const int64_t ld = comp_pad[cc];
+  const M* __restrict__ row = dense + dense_off[cc] + (g - o) * ld;
+  const int32_t* __restrict__ mem = members + o;
+  double a0 = 0.0, a1 = 0.0;
+  int64_t k = 0;
+  for (; k + 1 < n; k += 2) {
+    a0 += (double)row[k] * in[(int64_t)mem[k] * KB + c];
+    a1 += (double)row[k + 1] * in[(int64_t)mem[k + 1] * KB + c];
+  }
+  if (k < n) a0 += (double)row[k] * in[(int64_t)mem[k] * KB + c];
+  out[(int64_t)members[g] * KB + c] = a0 + a1;
+}
+
+// ------------------------------------------------------------- Krylov
+constexpr int BT = 256;
+
+// grid (chunks, nv); block = (BT / KB) row lanes x KB columns
+__global__ __launch_bounds__(BT) void k_bmdot_partial(
+    const double* __restrict__ V, int64_t ldv, const double* __restrict__ W,
+    int64_t n, int KB, double* __restrict__ part) {
+  __shared__ double sh[BT];
+  const int i = blockIdx.y;
+  const int rl = threadIdx.x / KB, c = threadIdx.x % KB;
+  const int nrl = BT / KB;
+  const double* __restrict__ v = V + (int64_t)i * ldv;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t a = (int64_t)blockIdx.x * chunk;
+  const int64_t b = min(n, a + chunk);
+  double acc = 0.0;
+  for (int64_t r = a + rl; r < b; r += nrl) acc += v[r * KB + c] * W[r * KB + c];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nrl; ++q) t += sh[q * KB + c];
+    part[((int64_t)i * gridDim.x + blockIdx.x) * KB + c] = t;
+  }
+}
+
+__global__ void k_bmdot_reduce(const double* __restrict__ part, int np, int KB,
+                               double* __restrict__ out) {
+  const int i = blockIdx.x;
+  const int c = threadIdx.x;
+  if (c >= KB) return;
+  double t = 0.0;
+  for (int q = 0; q < np; ++q) t += part[((int64_t)i * np + q) * KB + c];
+  out[(int64_t)i * KB + c] = t;
+}
+
+// W(n, c) -= sum_i sgn * h(i, c) V_i(n, c)
+__global__ __launch_bounds__(BT) void k_bmaxpy(const double* __restrict__ V,
+                                               int64_t ldv, int nv,
+                                               const double* __restrict__ h,
+                                               double* __restrict__ W,
+                                               int64_t n, int KB) {
+  __shared__ double hs[kMaxKrylov * 32];
+  for (int q = threadIdx.x; q < nv * KB; q += BT) hs[q] = h[q];
+  __syncthreads();
+  const int64_t tot = n * KB;
+  for (int64_t t = (int64_t)blockIdx.x * BT + threadIdx.x; t < tot;
+       t += (int64_t)gridDim.x * BT) {
+    const int c = (int)(t % KB);
+    double acc = W[t];
+    for (int i = 0; i < nv; ++i) acc -= hs[i * KB + c] * V[(int64_t)i * ldv + t];
+    W[t] = acc;
+  }
+}
+
+__global__ void k_bscale(const double* __restrict__ x,
+                         const double* __restrict__ scal, double* __restrict__ y,
+                         int64_t n, int KB) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * KB) return;
+  const double s = scal[t % KB];
+  y[t] = (s != 0.0) ? x[t] / s : 0.0;
+}
+
+__global__ void k_bsub(const double* __restrict__ a, double* __restrict__ b,
+                       int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = a[t] - b[t];
+}
+
+// per column c: Givens update of step j (columns with active[c] == 0 keep
+// their state); scal[c] = h_{j+1,j} (0 on breakdown / inactive),
+// est[c] = |g_{j+1}|, brk[c] = breakdown
+__global__ void k_bgmres_step(double* H, double* cs, double* sn, double* g,
+                              const double* h1, const double* h2,
+                              const double* nrm2, const double* nrm0, int j,
+                              int m, int KB, const int* active, double* scal,
+                              double* est, int* brk) {
+  const int c = threadIdx.x;
+  if (c >= KB) return;
+  if (!active[c]) {
+    scal[c] = 0.0;
+    est[c] = 0.0;
+    brk[c] = 0;
+    return;
+  }
+  double* Hc = H + (int64_t)c * (m + 1) * m;
+  double* csc = cs + c * m;
+  double* snc = sn + c * m;
+  double* gc = g + c * (m + 1);
+  double col[kMaxKrylov + 1];
+  for (int i = 0; i <= j; ++i) col[i] = h1[i * KB + c] + h2[i * KB + c];
+  const double hn = sqrt(fmax(nrm2[c], 0.0));
+  const double w0 = sqrt(fmax(nrm0[c], 0.0));
+  col[j + 1] = hn;
+  const int breakdown = !(hn > 1e-14 * w0);
+  scal[c] = breakdown ? 0.0 : hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = csc[i] * col[i] + snc[i] * col[i + 1];
+    col[i + 1] = -snc[i] * col[i] + csc[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double rho = hypot(col[j], col[j + 1]);
+  const double cj = rho != 0.0 ? col[j] / rho : 1.0;
+  const double sj = rho != 0.0 ? col[j + 1] / rho : 0.0;
+  csc[j] = cj;
+  snc[j] = sj;
+  col[j] = rho;
+  col[j + 1] = 0.0;
+  gc[j + 1] = -sj * gc[j];
+  gc[j] = cj * gc[j];
+  for (int i = 0; i <= j + 1; ++i) Hc[(int64_t)i * m + j] = col[i];
+  est[c] = fabs(gc[j + 1]);
+  brk[c] = breakdown;
+}
+
+__global__ void k_bgmres_init(double* g, int m, int KB, const double* beta2,
+                              const int* active, double* scal) {
+  const int c = threadIdx.x;
+  if (c >= KB) return;
+  const double beta = active[c] ? sqrt(fmax(beta2[c], 0.0)) : 0.0;
+  double* gc = g + c * (m + 1);
+  for (int i = 0; i <= m; ++i) gc[i] = 0.0;
+  gc[0] = beta;
+  scal[c] = beta;
+}
+
+// y(:, c) = R_c^{-1} g_c for the first kc[c] steps; stored y[j * KB + c]
+__global__ void k_btrisolve(const double* H, const double* g, double* y,
+                            const int* kc, int m, int KB) {
+  const int c = threadIdx.x;
+  if (c >= KB) return;
+  const double* Hc = H + (int64_t)c * (m + 1) * m;
+  const double* gc = g + c * (m + 1);
+  const int k = kc[c];
+  for (int j = 0; j < m; ++j) y[j * KB + c] = 0.0;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = gc[i];
+    for (int q = i + 1; q < k; ++q) s -= Hc[(int64_t)i * m + q] * y[q * KB + c];
+    y[i * KB + c] = s / Hc[(int64_t)i * m + i];
+  }
+}
+
+}  // namespace
+
+void pack_cols(const double* B, int64_t ldb, int64_t n, int k, int KB,
+               double* out, hipStream_t s) {
+  k_pack<<<grid_for(n * KB, 256), 256, 0, s>>>(B, ldb, n, k, KB, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void unpack_cols(const double* Xi, int64_t n, int k, int KB, double* X,
+                 int64_t ldx, hipStream_t s) {
+  k_unpack<<<grid_for(n * k, 256), 256, 0, s>>>(Xi, n, k, KB, X, ldx);
+  FPC_LAUNCH_CHECK();
+}
+
+void face_apply_b(const double* hinv, const double* in, double* out,
+                  int64_t n_p, int KB, int trans, hipStream_t s) {
+  if (!n_p) return;
+  k_face_apply_b<<<grid_for(n_p * KB, 256), 256, 0, s>>>(hinv, in, out, n_p,
+                                                          KB, trans);
+  FPC_LAUNCH_CHECK();
+}
+
+void csr_spmv2_b(const Csr* m1, const double* x1, double a1, const Csr* m2,
+                 const double* x2, double a2, double* y, double beta, int KB,
+                 hipStream_t s) {
+  if (!m1->nrows) return;
+  k_csr_spmv2_b<<<grid_for(m1->nrows * KB, 256), 256, 0, s>>>(
+      m1->rowptr.p, m1->col.p, m1->val.p, x1, a1,
+      m2 ? m2->rowptr.p : nullptr, m2 ? m2->col.p : nullptr,
+      m2 ? m2->val.p : nullptr, x2, a2, y, beta, m1->nrows, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+template <typename T>
+void to_level_b(T* out, int sel, int KB, int64_t n, const double* base,
+                const Csr& M1, const double* x1, double a1, hipStream_t s) {
+  if (!n) return;
+  k_to_level_b<T><<<grid_for(n * KB, 256), 256, 0, s>>>(
+      out, sel, KB, base, M1.rowptr.p, M1.col.p, M1.val.p, x1, a1, n);
+  FPC_LAUNCH_CHECK();
+}
+template void to_level_b<double>(double*, int, int, int64_t, const double*,
+                                 const Csr&, const double*, double,
+                                 hipStream_t);
+template void to_level_b<float>(float*, int, int, int64_t, const double*,
+                                const Csr&, const double*, double,
+                                hipStream_t);
+
+template <typename T>
+void from_level_b(const T* xo, int64_t n, int KB, double* vu, hipStream_t s) {
+  if (!n) return;
+  k_from_level_b<T><<<grid_for(n * KB, 256), 256, 0, s>>>(xo, n, KB, vu);
+  FPC_LAUNCH_CHECK();
+}
+template void from_level_b<double>(const double*, int64_t, int, double*,
+                                   hipStream_t);
+template void from_level_b<float>(const float*, int64_t, int, double*,
+                                  hipStream_t);
+
+void tface_b(const Csr& C, const double* vu, const double* t_t,
+             const double* hinv, double* v_t, int64_t n_p, int KB,
+             hipStream_t s) {
+  if (!n_p) return;
+  k_tface_b<<<grid_for(n_p * KB, 128), 128, 0, s>>>(
+      C.rowptr.p, C.col.p, C.val.p, vu, t_t, hinv, v_t, n_p, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+void psolve_apply_b(const PSolve& ps, const double* in, double* out,
+                    int64_t n_p, int KB, hipStream_t s) {
+  if (!n_p) return;
+  const unsigned g = grid_for(n_p * KB, 256);
+  if (ps.dense32.p)
+    k_psolve_b<float><<<g, 256, 0, s>>>(ps.dense32.p, ps.dense_off.p,
+                                        ps.comp_off.p, ps.comp_pad_d.p,
+                                        ps.comp_of_row.p, ps.members.p, in,
+                                        out, n_p, KB);
+  else
+    k_psolve_b<double><<<g, 256, 0, s>>>(ps.dense.p, ps.dense_off.p,
+                                         ps.comp_off.p, ps.comp_pad_d.p,
+                                         ps.comp_of_row.p, ps.members.p, in,
+                                         out, n_p, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+void bmdot(const double* V, int64_t ldv, int nv, const double* W, int64_t n,
+           int KB, double* part, double* out, hipStream_t s) {
+  if (nv <= 0) return;
+  dim3 grid(kDotBlocks, nv);
+  k_bmdot_partial<<<grid, BT, 0, s>>>(V, ldv, W, n, KB, part);
+  FPC_LAUNCH_CHECK();
+  k_bmdot_reduce<<<nv, 64, 0, s>>>(part, kDotBlocks, KB, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void bmaxpy(const double* V, int64_t ldv, int nv, const double* h, double* W,
+            int64_t n, int KB, hipStream_t s) {
+  if (nv <= 0 || !n) return;
+  if (nv > kMaxKrylov || KB > 32) throw Error(FPC_ERR_ARG, "bmaxpy size");
+  unsigned g = grid_for(n * KB, BT);
+  if (g > 16384) g = 16384;
+  k_bmaxpy<<<g, BT, 0, s>>>(V, ldv, nv, h, W, n, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+void bscale(const double* x, const double* scal, double* y, int64_t n, int KB,
+            hipStream_t s) {
+  k_bscale<<<grid_for(n * KB, 256), 256, 0, s>>>(x, scal, y, n, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+void bsub(const double* a, double* b, int64_t n, hipStream_t s) {
+  k_bsub<<<grid_for(n, 256), 256, 0, s>>>(a, b, n);
+  FPC_LAUNCH_CHECK();
+}
+
+void bgmres_step(double* H, double* cs, double* sn, double* g,
+                 const double* h1, const double* h2, const double* nrm2,
+                 const double* nrm0, int j, int m, int KB, const int* active,
+                 double* scal, double* est, int* brk, hipStream_t s) {
+  k_bgmres_step<<<1, 64, 0, s>>>(H, cs, sn, g, h1, h2, nrm2, nrm0, j, m, KB,
+                                 active, scal, est, brk);
+  FPC_LAUNCH_CHECK();
+}
+
+void bgmres_init(double* g, int m, int KB, const double* beta2,
+                 const int* active, double* scal, hipStream_t s) {
+  k_bgmres_init<<<1, 64, 0, s>>>(g, m, KB, beta2, active, scal);
+  FPC_LAUNCH_CHECK();
+}
+
+void btrisolve(const double* H, const double* g, double* y, const int* kc,
+               int m, int KB, hipStream_t s) {
+  k_btrisolve<<<1, 64, 0, s>>>(H, g, y, kc, m, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+}  // namespace fpc

@@ -294,6 +294,11 @@ void launch_vrow(const Vrow<T>& A, Load ld, Epi epi, hipStream_t s) {
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
+  if constexpr (NV >= 16) {
+    // many columns: one thread per (row, column), sliced ELL only
+    if (op.fmt != 0) throw Error(FPC_ERR_ARG, "batched operator layout");
+    return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
+  } else {
   if (op.fmt == 0) return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
   switch (op.v.G) {
     case 4: return launch_vrow<T, BR, BC, NV, 4>(op.v, ld, epi, s);
@@ -301,6 +306,7 @@ void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
     case 64: return launch_vrow<T, BR, BC, NV, 64>(op.v, ld, epi, s);
   }
   throw Error(FPC_ERR_ARG, "launch_op: unsupported row-group width");
+  }
 }
 
 // ---------------------------------------------------------------- coarsest
@@ -457,27 +463,35 @@ __global__ void k_zero(T* p, int64_t n) {
 
 // ---------------------------------------------------------------- V-cycle
 template <typename T>
-const Op<T>& selA(const Level& L, bool tr);
+const Op<T>& selA(const Level& L, bool tr, bool batch);
 template <>
-const Op<double>& selA<double>(const Level& L, bool tr) {
-  return tr ? L.oAT : L.oA;
+const Op<double>& selA<double>(const Level& L, bool tr, bool batch) {
+  return batch ? L.bA : (tr ? L.oAT : L.oA);
 }
 template <>
-const Op<float>& selA<float>(const Level& L, bool tr) {
-  return tr ? L.fAT : L.fA;
+const Op<float>& selA<float>(const Level& L, bool tr, bool batch) {
+  return batch ? L.gA : (tr ? L.fAT : L.fA);
 }
 template <typename T>
-const Op<T>& selP(const Level& L);
+const Op<T>& selP(const Level& L, bool batch);
 template <>
-const Op<double>& selP<double>(const Level& L) { return L.oP; }
+const Op<double>& selP<double>(const Level& L, bool batch) {
+  return batch ? L.bP : L.oP;
+}
 template <>
-const Op<float>& selP<float>(const Level& L) { return L.fP; }
+const Op<float>& selP<float>(const Level& L, bool batch) {
+  return batch ? L.gP : L.fP;
+}
 template <typename T>
-const Op<T>& selR(const Level& L);
+const Op<T>& selR(const Level& L, bool batch);
 template <>
-const Op<double>& selR<double>(const Level& L) { return L.oR; }
+const Op<double>& selR<double>(const Level& L, bool batch) {
+  return batch ? L.bR : L.oR;
+}
 template <>
-const Op<float>& selR<float>(const Level& L) { return L.fR; }
+const Op<float>& selR<float>(const Level& L, bool batch) {
+  return batch ? L.gR : L.fR;
+}
 template <typename T>
 const T* seldinv(const Level& L);
 template <>
@@ -488,7 +502,7 @@ const float* seldinv<float>(const Level& L) { return L.dinv32.p; }
 template <typename T, int BS, int NV>
 void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
                   int phase, KTimer* timer) {
-  const Op<T>& A = selA<T>(L, tr);
+  const Op<T>& A = selA<T>(L, tr, NV >= 16);
   const T* dinv = seldinv<T>(L);
   const T it = T(1.0 / L.theta), c1 = T(L.c1), c2 = T(L.c2);
   if (phase == 0) {
@@ -515,14 +529,14 @@ void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
 template <typename T, int BS, int NB, int NV>
 void restrict_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
                     hipStream_t s) {
-  launch_op<T, NB, BS, NV>(selR<T>(L), LoadX<T, NV>{v.res.p},
+  launch_op<T, NB, BS, NV>(selR<T>(L, NV >= 16), LoadX<T, NV>{v.res.p},
                              EpiStore<T, NB, NV>{vc.b.p}, s);
 }
 
 template <typename T, int BS, int NB, int NV>
 void prolong_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
                    hipStream_t s) {
-  launch_op<T, BS, NB, NV>(selP<T>(L), LoadX<T, NV>{vc.xo.p},
+  launch_op<T, BS, NB, NV>(selP<T>(L, NV >= 16), LoadX<T, NV>{vc.xo.p},
                              EpiAdd<T, BS, NV>{v.x.p}, s);
 }
 
@@ -689,6 +703,23 @@ template void vcycle<double, 1>(Hierarchy&, bool, hipStream_t);
 template void vcycle<double, 2>(Hierarchy&, bool, hipStream_t);
 template void vcycle<float, 1>(Hierarchy&, bool, hipStream_t);
 template void vcycle<float, 2>(Hierarchy&, bool, hipStream_t);
+template void vcycle<double, 16>(Hierarchy&, bool, hipStream_t);
+template void vcycle<double, 64>(Hierarchy&, bool, hipStream_t);
+template void vcycle<float, 16>(Hierarchy&, bool, hipStream_t);
+template void vcycle<float, 64>(Hierarchy&, bool, hipStream_t);
+
+void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,
+               hipStream_t s) {
+  if (A.br != 3 || A.bc != 3) throw Error(FPC_ERR_ARG, "sell_mv_b shape");
+  if (KB == 8)
+    launch_sell<double, 3, 3, 8>(A, LoadX<double, 8>{x},
+                                 EpiStore<double, 3, 8>{y}, s);
+  else if (KB == 32)
+    launch_sell<double, 3, 3, 32>(A, LoadX<double, 32>{x},
+                                  EpiStore<double, 3, 32>{y}, s);
+  else
+    throw Error(FPC_ERR_ARG, "sell_mv_b: batch width");
+}
 
 void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s) {
   if (A.br == 3 && A.bc == 3)

@@ -1,0 +1,102 @@
+"""Production forms on the GPU: batched right-hand sides, the FP32
+preconditioner and the adjoint / autograd gradients (full 48^3 workload)."""
+import numpy as np
+import pytest
+
+import fracgen
+import oracle
+from fracgen.configs import observations, rhs_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return fracgen.make_config("c1")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("k", [3, 12])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_single(torch, c1, k, precision):
+    from paper_2112_12397_amd import solver_from_system
+    s = c1
+    sol = solver_from_system(s, precision=precision)
+    B = rhs_batch(s, k=k)                      # norms 1e-2 .. 1e2
+    Bt = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
+    X, infos, status = sol.solve_batch(Bt)
+    assert status == "FPC_OK"
+    J = s.jacobian()
+    Xn = X.cpu().numpy()
+    for c in range(k):
+        x1, i1 = sol.solve(Bt[c].contiguous())
+        r = np.linalg.norm(B[:, c] - J @ Xn[c]) / np.linalg.norm(B[:, c])
+        assert infos[c]["converged"] == 1 and r <= 1e-8, (c, r, infos[c])
+        assert abs(infos[c]["iterations"] - i1["iterations"]) <= 2
+        assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-5
+
+
+def test_batch_zero_column_and_mask(torch, c1):
+    from paper_2112_12397_amd import solver_from_system
+    s = c1
+    sol = solver_from_system(s)
+    B = rhs_batch(s, k=4)
+    B[:, 2] = 0.0                              # a zero column converges at once
+    Bt = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
+    X, infos, status = sol.solve_batch(Bt)
+    assert status == "FPC_OK"
+    assert infos[2]["iterations"] == 0 and not X[2].any()
+    for c in (0, 1, 3):
+        assert infos[c]["converged"] == 1 and infos[c]["iterations"] > 0
+
+
+def test_adjoint_gradients_c5(torch):
+    """48^3 with 4 full fractures: gradients of 0.5 |p - p_obs|^2 with respect
+    to log transmissibility on 20 seeded faces against central differences
+    (h = 1e-6, 80-bit) and against the oracle's adjoint gradient; the
+    gradient with respect to b is the adjoint solution."""
+    from paper_2112_12397_amd import solver_from_system
+    from paper_2112_12397_amd.autograd import SolveFn
+    s = fracgen.make_config("c5")
+    _, p_obs = observations(s)
+    sol = solver_from_system(s)
+    off = s.n_u + s.n_t
+    b = torch.tensor(s.b, device="cuda", requires_grad=True)
+    logu = torch.tensor(np.log(s.upsilon), device="cuda", requires_grad=True)
+    flow = (torch.tensor(s.flow_pairs), torch.tensor(s.flow_ndir))
+    x = SolveFn.apply(b, logu, sol, flow, 1e-11)
+    pobs = torch.tensor(p_obs, device="cuda")
+    loss = 0.5 * ((x[off:] - pobs) ** 2).sum()
+    loss.backward()
+    g_logu = logu.grad.cpu().numpy()
+    g_b = b.grad.cpu().numpy()
+    rng = np.random.default_rng(2024)
+    faces = rng.choice(s.n_p, 20, replace=False)
+    fd = oracle.adjoint.fd_grad_log_trans(s.flow_pairs, s.flow_ndir,
+                                          s.upsilon, s.T_stab, s.b[off:],
+                                          p_obs, faces, h=1e-6)
+    err = np.abs(g_logu[faces] - fd)
+    assert (err <= 1e-6 * np.abs(fd) + 1e-9 * np.abs(fd).max()).all(), \
+        (err / np.abs(fd)).max()
+    # oracle adjoint (its own forward and adjoint FGMRES)
+    pc = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p, coords=s.coords)
+    xo, _ = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-11)
+    L, gx = oracle.adjoint.loss_and_grad_x(xo, s.n_u, s.n_t, p_obs)
+    lam, _ = oracle.fgmres(pc.matvec_T, pc.apply_T, gx, rtol=1e-11)
+    go = oracle.adjoint.grad_log_trans(s.flow_pairs, s.flow_ndir, s.upsilon,
+                                       lam[off:], xo[off:])
+    assert _rel(g_logu, go) <= 1e-7
+    assert _rel(g_b, lam) <= 1e-7
+    # with no open faces the adjoint has zero displacement / traction parts
+    assert np.abs(g_b[:off]).max() <= 1e-8 * np.abs(g_b[off:]).max()
