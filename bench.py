@@ -217,7 +217,9 @@ def main():
         "true_rel_residual": infos[-1]["true_rel_residual"],
         "setup_s": t_setup / K,
         "setup_parts_s": setup_parts,
-        "amg_levels": [{"dofs": d["n_dofs"], "nnz": d["nnz_scalar"]}
+        "amg_levels": [{"dofs": d["n_dofs"], "nnz": d["nnz_scalar"],
+                        "layout_A_P_R": d["layout"],
+                        "tuned_us_A_P_R": [round(t, 1) for t in d["tune_us"]]}
                        for d in levels],
         "vcycle": {"seconds": vc_s, "algorithmic_bytes": vc_bytes,
                    "GBps": vc_bytes / vc_s / 1e9,

@@ -123,6 +123,10 @@ typedef struct {
   int64_t p_nnzb, r_nnzb;  /* blocks of P_l and R_l = P_l^T                 */
   double lam_hi;           /* Chebyshev upper bound                         */
   int64_t n_agg;           /* aggregates formed on this level (0 coarsest)  */
+  int layout[3];           /* apply layout picked for A_l, P_l, R_l: 1 =    */
+                           /* sliced ELL, 4/16/64 = row groups of that many */
+                           /* lanes, 0 = none (coarsest)                    */
+  double tune_us[3];       /* the winner's measured time per product (us)   */
 } fpc_level_desc;
 
 /* Fracture flow graph for the transmissibility gradient: TPFA face pairs

@@ -15,7 +15,8 @@ void vcycle(Hierarchy& H, bool transpose, hipStream_t s);
 // Autotuned apply layout of one operator for `nv` columns; *choice = 1 for
 // sliced ELL, else the row-group width.
 template <typename T>
-void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice);
+void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
+             double* best_us);
 
 void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s);
 void sell_mv_dinv(const Sell<double>& A, const double* dinv, const double* x,
@@ -34,6 +35,8 @@ void tface(const Csr& C, const double* vu, const double* t_t,
            hipStream_t s);
 void psolve_apply(const PSolve& ps, const double* in, double* out,
                   int64_t n_p, int trans, hipStream_t s);
+void pack_sym_tiles(const double* D, int64_t ld, int nt, double* out64,
+                    float* out32, hipStream_t s);
 
 // ---------------------------------------------------------------- batches
 void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,

@@ -24,6 +24,7 @@ struct Level {
   Op<double> oAT;
   Op<float> fAT;
   int layout[3] = {0, 0, 0};   // tuner choice for A, P, R (1 = sliced ELL)
+  double tune_us[3] = {0, 0, 0};  // winning time per product (us)
   // multi-right-hand-side operators (sliced ELL, one thread per row and
   // column), built on the first batched solve
   Op<double> bA, bP, bR;
@@ -42,6 +43,7 @@ struct Level {
 template <typename T>
 struct LevelVecs {
   DevBuf<T> x, xo, d, r, res, b;
+  DevBuf<T> d0;  // first Chebyshev direction D^{-1} b / theta
 };
 
 // Per (precision, column count) set of level vectors.
@@ -110,6 +112,18 @@ struct PSolve {
   DevBuf<double> dense;
   DevBuf<float> dense32;      // FP32 copy (FP32 preconditioner); dense freed
   int64_t dense_elems = 0;
+  // the same symmetric inverses as packed lower-triangular 64 x 64 tiles:
+  // tile (I, J), J <= I, of component c is tile tile_base[c] + I(I+1)/2 + J,
+  // row-major; diagonal tiles are stored full and exactly symmetric
+  int64_t n_tiles = 0, n_rowblk = 0;
+  std::vector<int64_t> tile_base_h;
+  DevBuf<int64_t> tile_base;
+  DevBuf<int32_t> tile_info;  // (c, I, J) per tile
+  DevBuf<int32_t> rowblk;     // (c, K) per 64-row block
+  DevBuf<int32_t> n_tiles_c;  // tiles per side, per component
+  DevBuf<double> packed;
+  DevBuf<float> packed32;
+  DevBuf<double> part;        // 128 partial sums per tile
 };
 
 // Per right-hand-side block of Krylov work space.

@@ -271,6 +271,49 @@ void build_psolve(fpc_handle* h) {
     gj_inverse(D, pad, /*spd=*/1, h->flags.p, s);
   }
   check_flags(h, "pressure block");
+  // packed symmetric tiles for the single-vector apply
+  {
+    std::vector<int32_t> info, rb, ntc(ps.n_comp);
+    ps.tile_base_h.assign(ps.n_comp + 1, 0);
+    for (int64_t c = 0; c < ps.n_comp; ++c) {
+      const int nt = (int)(ps.comp_pad[c] / 64);
+      ntc[c] = nt;
+      ps.tile_base_h[c + 1] = ps.tile_base_h[c] + (int64_t)nt * (nt + 1) / 2;
+      for (int I = 0; I < nt; ++I) {
+        rb.push_back((int32_t)c);
+        rb.push_back(I);
+        for (int J = 0; J <= I; ++J) {
+          info.push_back((int32_t)c);
+          info.push_back(I);
+          info.push_back(J);
+        }
+      }
+    }
+    ps.n_tiles = ps.tile_base_h[ps.n_comp];
+    ps.n_rowblk = (int64_t)rb.size() / 2;
+    ps.tile_base.alloc(ps.n_comp + 1);
+    ps.tile_info.alloc(info.size());
+    ps.rowblk.alloc(rb.size());
+    ps.n_tiles_c.alloc(ps.n_comp);
+    FPC_HIP(hipMemcpyAsync(ps.tile_base.p, ps.tile_base_h.data(),
+                           (ps.n_comp + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    FPC_HIP(hipMemcpyAsync(ps.tile_info.p, info.data(),
+                           info.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    FPC_HIP(hipMemcpyAsync(ps.rowblk.p, rb.data(), rb.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    FPC_HIP(hipMemcpyAsync(ps.n_tiles_c.p, ntc.data(), ntc.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    const bool f32 = h->opt.precision == FPC_FP32_PREC;
+    if (f32) ps.packed32.alloc(ps.n_tiles * 4096);
+    else ps.packed.alloc(ps.n_tiles * 4096);
+    ps.part.alloc(ps.n_tiles * 128);
+    for (int64_t c = 0; c < ps.n_comp; ++c)
+      pack_sym_tiles(ps.dense.p + ps.dense_off_h[c], ps.comp_pad[c], ntc[c],
+                     f32 ? nullptr : ps.packed.p + ps.tile_base_h[c] * 4096,
+                     f32 ? ps.packed32.p + ps.tile_base_h[c] * 4096 : nullptr, s);
+    FPC_HIP(hipStreamSynchronize(s));
+  }
   if (h->opt.precision == FPC_FP32_PREC) {
     ps.dense32.alloc(ps.dense_elems);
     cast_f64_f32(ps.dense.p, ps.dense32.p, ps.dense_elems, s);
@@ -402,13 +445,19 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
       L.dinv32.alloc(n);
       k_cast_dinv<<<grid_for(n, 256), 256, 0, s>>>(L.dinv.p, L.dinv32.p, n);
       FPC_LAUNCH_CHECK();
-      tune_op<float>(L.A, nv, L.fA, s, &L.layout[0]);
-      tune_op<float>(L.P, nv, L.fP, s, &L.layout[1]);
-      tune_op<float>(L.R, nv, L.fR, s, &L.layout[2]);
+      tune_op<float>(L.A, nv, L.fA, s, &L.layout[0],
+                      &L.tune_us[0]);
+      tune_op<float>(L.P, nv, L.fP, s, &L.layout[1],
+                      &L.tune_us[1]);
+      tune_op<float>(L.R, nv, L.fR, s, &L.layout[2],
+                      &L.tune_us[2]);
     } else {
-      tune_op<double>(L.A, nv, L.oA, s, &L.layout[0]);
-      tune_op<double>(L.P, nv, L.oP, s, &L.layout[1]);
-      tune_op<double>(L.R, nv, L.oR, s, &L.layout[2]);
+      tune_op<double>(L.A, nv, L.oA, s, &L.layout[0],
+                      &L.tune_us[0]);
+      tune_op<double>(L.P, nv, L.oP, s, &L.layout[1],
+                      &L.tune_us[1]);
+      tune_op<double>(L.R, nv, L.oR, s, &L.layout[2],
+                      &L.tune_us[2]);
     }
   }
   FPC_HIP(hipStreamSynchronize(s));
@@ -430,8 +479,8 @@ void ensure_transposes(fpc_handle* h) {
   for (Level& L : H.L) {
     if (L.coarsest) continue;
     bsr_transpose(L.A, L.AT, s);
-    if (h->opt.precision == FPC_FP32_PREC) tune_op<float>(L.AT, 1, L.fAT, s, nullptr);
-    else tune_op<double>(L.AT, 1, L.oAT, s, nullptr);
+    if (h->opt.precision == FPC_FP32_PREC) tune_op<float>(L.AT, 1, L.fAT, s, nullptr, nullptr);
+    else tune_op<double>(L.AT, 1, L.oAT, s, nullptr, nullptr);
   }
   H.AinvT.alloc(H.ncpad * H.ncpad);
   dim3 g((unsigned)((H.ncpad + 31) / 32), (unsigned)((H.ncpad + 31) / 32));
@@ -1145,6 +1194,10 @@ fpc_status fpc_level_info(const fpc_handle* h, int level, fpc_level_desc* d) {
   d->r_nnzb = L.coarsest ? 0 : L.R.nnzb;
   d->lam_hi = L.lam_hi;
   d->n_agg = L.coarsest ? 0 : L.n_agg;
+  for (int k = 0; k < 3; ++k) {
+    d->layout[k] = L.coarsest ? 0 : L.layout[k];
+    d->tune_us[k] = L.coarsest ? 0.0 : L.tune_us[k];
+  }
   return FPC_OK;
 }
 

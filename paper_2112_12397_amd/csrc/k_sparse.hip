@@ -373,6 +373,12 @@ __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
 #pragma unroll
     for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
   }
+  // padding slots up to the slice's longest row keep zero values and repeat
+  // the row's last column (column 0 for an empty row), so a product may read
+  // them unguarded: a padded term adds 0 * x[c] for a c the row already uses
+  const int maxlen = (int)((slice_ptr[s + 1] - base) / kSliceH);
+  const int32_t cpad = len > 0 ? col[a + len - 1] : 0;
+  for (int k = len; k < maxlen; ++k) scol[base + (int64_t)k * kSliceH + l] = cpad;
 }
 
 __global__ void k_vrow_count(const int64_t* rowptr, int64_t nrows, int G,

@@ -38,66 +38,78 @@ struct LoadX {
   __device__ T operator()(int64_t dof, int v) const { return x[dof * NV + v]; }
 };
 
-// first Chebyshev direction d0 = D^{-1} b / theta, formed on the fly
-template <typename T, int NV>
-struct LoadScaled {
-  const T* __restrict__ b;
-  const T* __restrict__ dinv;
-  T inv_theta;
-  __device__ T operator()(int64_t dof, int v) const {
-    return dinv[dof] * b[dof * NV + v] * inv_theta;
-  }
-};
 
 // ---------------------------------------------------------------- epilogues
-// Every epilogue works element-wise on (block row, component i, column v):
-// `one` handles one element, operator() a whole block row of one column.
-#define FPC_EPI_ROW                                                   \
-  __device__ void operator()(int64_t row, int v, const T* acc) const { \
-    _Pragma("unroll") for (int i = 0; i < BR; ++i) one(row, i, v, acc[i]); \
-  }
-
-template <typename T, int BR, int NV>
+// Every epilogue works element-wise on (dof, column): element (dof, v) of an
+// NV-column vector sits at k = dof * NV + v.  `load` fetches the element's
+// inputs into registers, `store` combines them with the product value `a`
+// and writes the outputs.  Callers issue all loads of a row before any store,
+// so the loads are in flight together (the compiler cannot reorder them past
+// stores through other pointers on its own).
+template <typename T, int NV>
 struct EpiStore {
+  static constexpr int NIN = 1;
   T* __restrict__ y;
-  __device__ void one(int64_t row, int i, int v, T a) const {
-    y[(row * BR + i) * NV + v] = a;
-  }
-  FPC_EPI_ROW
+  __device__ void load(int64_t, int64_t, T*) const {}
+  __device__ void store(int64_t, int64_t k, T a, const T*) const { y[k] = a; }
 };
 
-template <typename T, int BR, int NV>
+template <typename T, int NV>
 struct EpiAdd {
+  static constexpr int NIN = 1;
   T* __restrict__ y;
-  __device__ void one(int64_t row, int i, int v, T a) const {
-    y[(row * BR + i) * NV + v] += a;
+  __device__ void load(int64_t, int64_t k, T* in) const { in[0] = y[k]; }
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    y[k] = in[0] + a;
   }
-  FPC_EPI_ROW
 };
 
-template <typename T, int BR>
+// restriction onto a smoothed level: b = R res and the first Chebyshev
+// direction d0 = D^{-1} b / theta of that level
+template <typename T, int NV>
+struct EpiRestrict {
+  static constexpr int NIN = 1;
+  T* __restrict__ b;
+  T* __restrict__ d0;
+  const T* __restrict__ dinv;
+  T inv_theta;
+  __device__ void load(int64_t dof, int64_t, T* in) const { in[0] = dinv[dof]; }
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    b[k] = a;
+    d0[k] = in[0] * a * inv_theta;
+  }
+};
+
+// y = D^{-1} (A x), one column
+template <typename T, int NV>
 struct EpiDinv {
+  static constexpr int NIN = 1;
   const T* __restrict__ dinv;
   T* __restrict__ y;
-  __device__ void one(int64_t row, int i, int, T a) const {
-    y[row * BR + i] = dinv[row * BR + i] * a;
+  __device__ void load(int64_t dof, int64_t, T* in) const { in[0] = dinv[dof]; }
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    y[k] = in[0] * a;
   }
-  FPC_EPI_ROW
 };
 
-// Pre-smoothing from x = 0, two Chebyshev steps fused around q = A d0:
+// Pre-smoothing from x = 0, two Chebyshev steps fused around q = A d0 (d0
+// was written with b by the restriction, or by k_first_dir on level 0):
 //   R1 = b - q, r1 = D^-1 R1, d1 = c1 d0 + c2 r1, x = d0 + d1.
-template <typename T, int BR, int NV>
+template <typename T, int NV>
 struct EpiPre1 {
+  static constexpr int NIN = 2;
   const T* __restrict__ b;
   const T* __restrict__ dinv;
   T* __restrict__ x;
   T* __restrict__ d;
   T* __restrict__ R;
   T inv_theta, c1, c2;
-  __device__ void one(int64_t row, int i, int v, T a) const {
-    const int64_t dof = row * BR + i, k = dof * NV + v;
-    const T bi = b[k], di = dinv[dof];
+  __device__ void load(int64_t dof, int64_t k, T* in) const {
+    in[0] = b[k];
+    in[1] = dinv[dof];
+  }
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    const T bi = in[0], di = in[1];
     const T d0 = di * bi * inv_theta;
     const T R1 = bi - a;
     const T r1 = di * R1;
@@ -106,25 +118,25 @@ struct EpiPre1 {
     d[k] = d1;
     R[k] = R1;
   }
-  FPC_EPI_ROW
 };
 
 // residual after pre-smoothing: res = R1 - A d1 = b - A x
-template <typename T, int BR, int NV>
+template <typename T, int NV>
 struct EpiRes {
+  static constexpr int NIN = 1;
   const T* __restrict__ R;
   T* __restrict__ res;
-  __device__ void one(int64_t row, int i, int v, T a) const {
-    const int64_t k = (row * BR + i) * NV + v;
-    res[k] = R[k] - a;
+  __device__ void load(int64_t, int64_t k, T* in) const { in[0] = R[k]; }
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    res[k] = in[0] - a;
   }
-  FPC_EPI_ROW
 };
 
 // post-smoothing step 1 around q = A x: r0 = D^-1 (b - q), d0 = r0 / theta,
 // xo = x + d0
-template <typename T, int BR, int NV>
+template <typename T, int NV>
 struct EpiPost1 {
+  static constexpr int NIN = 3;
   const T* __restrict__ b;
   const T* __restrict__ dinv;
   const T* __restrict__ xin;
@@ -132,41 +144,166 @@ struct EpiPost1 {
   T* __restrict__ d;
   T* __restrict__ r;
   T inv_theta;
-  __device__ void one(int64_t row, int i, int v, T a) const {
-    const int64_t dof = row * BR + i, k = dof * NV + v;
-    const T r0 = dinv[dof] * (b[k] - a);
+  __device__ void load(int64_t dof, int64_t k, T* in) const {
+    in[0] = b[k];
+    in[1] = dinv[dof];
+    in[2] = xin[k];
+  }
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    const T r0 = in[1] * (in[0] - a);
     const T d0 = r0 * inv_theta;
-    xo[k] = xin[k] + d0;
+    xo[k] = in[2] + d0;
     d[k] = d0;
     r[k] = r0;
   }
-  FPC_EPI_ROW
 };
 
 // post-smoothing step 2 around q = A d0: r1 = r0 - D^-1 q,
 // d1 = c1 d0 + c2 r1, xo += d1
-template <typename T, int BR, int NV>
+template <typename T, int NV>
 struct EpiPost2 {
+  static constexpr int NIN = 4;
   const T* __restrict__ dinv;
   const T* __restrict__ r;
   const T* __restrict__ din;
   T* __restrict__ xo;
   T c1, c2;
-  __device__ void one(int64_t row, int i, int v, T a) const {
-    const int64_t dof = row * BR + i, k = dof * NV + v;
-    const T r1 = r[k] - dinv[dof] * a;
-    xo[k] += c1 * din[k] + c2 * r1;
+  __device__ void load(int64_t dof, int64_t k, T* in) const {
+    in[0] = dinv[dof];
+    in[1] = r[k];
+    in[2] = din[k];
+    in[3] = xo[k];
   }
-  FPC_EPI_ROW
+  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+    const T r1 = in[1] - in[0] * a;
+    xo[k] = in[3] + (c1 * in[2] + c2 * r1);
+  }
 };
 
+// All NV columns of one block row: loads first, then stores.
+template <typename T, int BR, int NV, class Epi>
+__device__ inline void epi_row(const Epi& e, int64_t row, const T (&acc)[NV][BR]) {
+  T in[NV][BR][Epi::NIN];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+      const int64_t dof = row * BR + i;
+      e.load(dof, dof * NV + v, in[v][i]);
+    }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+      const int64_t dof = row * BR + i;
+      e.store(dof, dof * NV + v, acc[v][i], in[v][i]);
+    }
+}
+
+// One column v of one block row.
+template <typename T, int BR, int NV, class Epi>
+__device__ inline void epi_col(const Epi& e, int64_t row, int v, const T (&acc)[BR]) {
+  T in[BR][Epi::NIN];
+#pragma unroll
+  for (int i = 0; i < BR; ++i) {
+    const int64_t dof = row * BR + i;
+    e.load(dof, dof * NV + v, in[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < BR; ++i) {
+    const int64_t dof = row * BR + i;
+    e.store(dof, dof * NV + v, acc[i], in[i]);
+  }
+}
+
+// One element (component i, column v) of one block row.
+template <typename T, int BR, int NV, class Epi>
+__device__ inline void epi_one(const Epi& e, int64_t row, int i, int v, T a) {
+  T in[Epi::NIN];
+  const int64_t dof = row * BR + i;
+  e.load(dof, dof * NV + v, in);
+  e.store(dof, dof * NV + v, a, in);
+}
+
 // ---------------------------------------------------------------- SpMV
-// One thread per (block row, column); a wavefront covers 64/NV consecutive
-// block rows of one 64-row slice, so the block components of a slot group
-// are read as contiguous 64-wide vectors.
+// Few columns (NV <= 2): one wavefront per 64-row slice, one thread per block
+// row carrying all NV columns, so each matrix block is read by one lane only.
+// Every lane runs to the slice's longest row: padding slots hold zero values
+// and a column of their own row, so they need no guard.  Blocks are taken U
+// at a time: the column indices of the next batch are fetched one batch
+// ahead, then the x values and all block values of the batch are in flight
+// together.
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
-__global__ __launch_bounds__(256) void k_sell(SellView<T> A, Load ld,
-                                              Epi epi) {
+__global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
+                                                   Epi epi) {
+  constexpr int U = BR * BC <= 9 ? 3 : (BR * BC <= 18 ? 2 : 1);
+  const int slice = __builtin_amdgcn_readfirstlane(
+      (int)(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+  if (slice >= A.nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)slice * kSliceH + lane;
+  const int64_t base = A.slice_ptr[slice];
+  const int maxlen = (int)((A.slice_ptr[slice + 1] - base) / kSliceH);
+  const int32_t* __restrict__ cp = A.col + base + lane;
+  const T* __restrict__ vp = A.val + base * (BR * BC) + lane;
+  T acc[NV][BR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[v][i] = T(0);
+  int cn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) cn[u] = u < maxlen ? cp[(int64_t)u * kSliceH] : 0;
+  for (int k0 = 0; k0 < maxlen; k0 += U) {
+    int cc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cc[u] = cn[u];
+    T xv[U][BC][NV];
+    T a[U][BR * BC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u < maxlen) {
+#pragma unroll
+        for (int j = 0; j < BC; ++j)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) xv[u][j][v] = ld((int64_t)cc[u] * BC + j, v);
+        const T* __restrict__ vb = vp + (int64_t)(k0 + u) * kSliceH * (BR * BC);
+#pragma unroll
+        for (int q = 0; q < BR * BC; ++q) a[u][q] = vb[q * kSliceH];
+      } else {
+#pragma unroll
+        for (int j = 0; j < BC; ++j)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) xv[u][j][v] = T(0);
+#pragma unroll
+        for (int q = 0; q < BR * BC; ++q) a[u][q] = T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kn = k0 + U + u;
+      cn[u] = kn < maxlen ? cp[(int64_t)kn * kSliceH] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int j = 0; j < BC; ++j)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v][i] += a[u][i * BC + j] * xv[u][j][v];
+  }
+  if (row >= A.nrows) return;
+  epi_row<T, BR, NV>(epi, row, acc);
+}
+
+// Many columns (interleaved right-hand sides): one thread per (block row,
+// column); a wavefront covers 64/NV consecutive block rows of one slice, so
+// the columns of one x row are read as one contiguous segment and every
+// matrix block is broadcast to the NV lanes of its row.
+template <typename T, int BR, int BC, int NV, class Load, class Epi>
+__global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
+                                                   Epi epi) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t gw = blk * 4 + wave;
@@ -196,15 +333,20 @@ __global__ __launch_bounds__(256) void k_sell(SellView<T> A, Load ld,
 #pragma unroll
       for (int j = 0; j < BC; ++j) acc[i] += vb[(i * BC + j) * kSliceH] * xv[j];
   }
-  epi(row, v, acc);
+  epi_col<T, BR, NV>(epi, row, v, acc);
 }
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 void launch_sell(const Sell<T>& A, Load ld, Epi epi, hipStream_t s) {
   if (A.nrows == 0) return;
-  const int64_t waves = A.nslices * NV;
-  const unsigned grid = (unsigned)((waves + 3) / 4);
-  k_sell<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
+  if constexpr (NV <= 2) {
+    const unsigned grid = (unsigned)((A.nslices + 3) / 4);
+    k_sell_rows<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
+  } else {
+    const int64_t waves = A.nslices * NV;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    k_sell_cols<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
+  }
   FPC_LAUNCH_CHECK();
 }
 
@@ -278,7 +420,7 @@ __global__ __launch_bounds__(256) void k_vrow(VrowView<T> A, Load ld, Epi epi) {
 #pragma unroll
         for (int ii = 0; ii < BR; ++ii)
           if (ii * NV + vv == q) a = acc[vv][ii];
-      epi.one(row, q / NV, q % NV, a);
+      epi_one<T, BR, NV>(epi, row, q / NV, q % NV, a);
     }
   }
 }
@@ -417,42 +559,107 @@ __global__ void k_tface(const int64_t* __restrict__ rp,
   }
 }
 
-// exact pressure-block solve: one wavefront per (component, row); each lane
-// keeps four independent loads of the dense inverse row in flight.
+// Exact pressure-block solve with the symmetric dense inverse of every
+// connected component, stored as packed lower-triangular 64 x 64 tiles.  A
+// tile (I, J) is read once and yields both its row-block product A_IJ x_J
+// (for block row I) and, off the diagonal, its transposed product
+// A_IJ^T x_I (for block row J).  The 128 partial sums per tile are combined
+// per block row by k_psym_reduce in a fixed order.
 template <typename M>
-__global__ __launch_bounds__(256) void k_psolve(
-    const M* __restrict__ dense, const int64_t* __restrict__ dense_off,
-    const int64_t* __restrict__ comp_off, const int64_t* __restrict__ comp_pad,
-    const int32_t* __restrict__ comp_of_row, const int32_t* __restrict__ members,
-    const double* __restrict__ in, double* __restrict__ out, int64_t n_p,
-    int trans) {
-  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (g >= n_p) return;
-  const int c = comp_of_row[g];
-  const int64_t o = comp_off[c];
-  const int64_t n = comp_off[c + 1] - o;
-  const int64_t ld = comp_pad[c];
-  const int64_t r = g - o;
-  const M* __restrict__ D = dense + dense_off[c];
-  const int32_t* __restrict__ mem = members + o;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t k = lane;
-  if (!trans) {
-    const M* __restrict__ row = D + r * ld;
-    for (; k + 192 < n; k += 256) {
-      a0 += (double)row[k] * in[mem[k]];
-      a1 += (double)row[k + 64] * in[mem[k + 64]];
-      a2 += (double)row[k + 128] * in[mem[k + 128]];
-      a3 += (double)row[k + 192] * in[mem[k + 192]];
-    }
-    for (; k < n; k += 64) a0 += (double)row[k] * in[mem[k]];
-  } else {
-    for (; k < n; k += 64) a0 += (double)D[k * ld + r] * in[mem[k]];
+__global__ __launch_bounds__(256) void k_psym_tile(
+    const M* __restrict__ packed, const int32_t* __restrict__ tile_info,
+    const int64_t* __restrict__ comp_off, const int32_t* __restrict__ members,
+    const double* __restrict__ in, double* __restrict__ part) {
+  __shared__ double xs[2][64];
+  __shared__ double rs[64][65];
+  __shared__ double cs[4][64];
+  const int64_t t = blockIdx.x;
+  const int c = tile_info[3 * t], I = tile_info[3 * t + 1], J = tile_info[3 * t + 2];
+  const int64_t o = comp_off[c], n = comp_off[c + 1] - o;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const M* __restrict__ tp = packed + t * 4096 + (int64_t)(w * 16) * 64 + lane;
+  M a[16];
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) a[rr] = tp[rr * 64];
+  if (tid < 128) {
+    const int64_t idx = (int64_t)(tid < 64 ? J : I) * 64 + lane;
+    xs[tid >> 6][lane] = idx < n ? in[members[o + idx]] : 0.0;
   }
-  double acc = (a0 + a1) + (a2 + a3);
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) out[members[g]] = acc;
+  __syncthreads();
+  const double xj = xs[0][lane];
+  double col = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    const double av = (double)a[rr];
+    rs[w * 16 + rr][lane] = av * xj;
+    col += av * xs[1][w * 16 + rr];
+  }
+  cs[w][lane] = col;
+  __syncthreads();
+  const int r = tid >> 2, q = tid & 3;
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) sum += rs[r][q * 16 + k];
+  sum += __shfl_xor(sum, 1, 64);
+  sum += __shfl_xor(sum, 2, 64);
+  if (q == 0) part[t * 128 + r] = sum;
+  if (tid < 64)
+    part[t * 128 + 64 + tid] =
+        I != J ? (cs[0][tid] + cs[1][tid]) + (cs[2][tid] + cs[3][tid]) : 0.0;
+}
+
+// Block row K of component c: the row parts of tiles (K, J), J <= K, then the
+// transposed parts of tiles (I, K), I > K; wavefront w takes every fourth
+// term and the four sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_psym_reduce(
+    const int32_t* __restrict__ rowblk, const int64_t* __restrict__ tile_base,
+    const int32_t* __restrict__ n_tiles_c, const int64_t* __restrict__ comp_off,
+    const int32_t* __restrict__ members, const double* __restrict__ part,
+    double* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int64_t rb = blockIdx.x;
+  const int c = rowblk[2 * rb], K = rowblk[2 * rb + 1];
+  const int64_t base = tile_base[c];
+  const int nt = n_tiles_c[c];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int e = w; e < nt; e += 4) {
+    const int64_t off =
+        e <= K ? (base + (int64_t)K * (K + 1) / 2 + e) * 128 + lane
+               : (base + (int64_t)e * (e + 1) / 2 + K) * 128 + 64 + lane;
+    acc += part[off];
+  }
+  sh[w][lane] = acc;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t o = comp_off[c], n = comp_off[c + 1] - o;
+    const int64_t idx = (int64_t)K * 64 + lane;
+    if (idx < n)
+      out[members[o + idx]] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+  }
+}
+
+// One tile per block: tile index tt of the component -> (I, J), then the
+// 64 x 64 copy; the upper half of a diagonal tile mirrors its lower half.
+template <typename M>
+__global__ __launch_bounds__(256) void k_pack_sym(const double* __restrict__ D,
+                                                  int64_t ld, M* __restrict__ out) {
+  const int64_t tt = blockIdx.x;
+  int I = (int)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(I + 1) * (I + 2) / 2 <= tt) ++I;
+  while ((int64_t)I * (I + 1) / 2 > tt) --I;
+  const int J = (int)(tt - (int64_t)I * (I + 1) / 2);
+  M* __restrict__ dst = out + tt * 4096;
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+    const int r = e >> 6, cc = e & 63;
+    int64_t gr = (int64_t)I * 64 + r, gc = (int64_t)J * 64 + cc;
+    if (I == J && cc > r) {
+      gr = (int64_t)I * 64 + cc;
+      gc = (int64_t)I * 64 + r;
+    }
+    dst[e] = (M)D[gr * ld + gc];
+  }
 }
 
 template <typename T, int NV>
@@ -506,38 +713,46 @@ void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
   const T* dinv = seldinv<T>(L);
   const T it = T(1.0 / L.theta), c1 = T(L.c1), c2 = T(L.c2);
   if (phase == 0) {
-    launch_op<T, BS, BS, NV>(A, LoadScaled<T, NV>{v.b.p, dinv, it},
-                               EpiPre1<T, BS, NV>{v.b.p, dinv, v.x.p, v.d.p,
+    launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d0.p},
+                               EpiPre1<T, NV>{v.b.p, dinv, v.x.p, v.d.p,
                                                   v.r.p, it, c1, c2},
                                s);
     if (timer) timer->begin(s);
     launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
-                               EpiRes<T, BS, NV>{v.r.p, v.res.p}, s);
+                               EpiRes<T, NV>{v.r.p, v.res.p}, s);
     if (timer) timer->end(s);
   } else {
     launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.x.p},
-                               EpiPost1<T, BS, NV>{v.b.p, dinv, v.x.p, v.xo.p,
+                               EpiPost1<T, NV>{v.b.p, dinv, v.x.p, v.xo.p,
                                                    v.d.p, v.r.p, it},
                                s);
     launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
-                               EpiPost2<T, BS, NV>{dinv, v.r.p, v.d.p, v.xo.p,
+                               EpiPost2<T, NV>{dinv, v.r.p, v.d.p, v.xo.p,
                                                    c1, c2},
                                s);
   }
 }
 
 template <typename T, int BS, int NB, int NV>
-void restrict_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
-                    hipStream_t s) {
-  launch_op<T, NB, BS, NV>(selR<T>(L, NV >= 16), LoadX<T, NV>{v.res.p},
-                             EpiStore<T, NB, NV>{vc.b.p}, s);
+void restrict_level(const Level& L, const Level& Lc, LevelVecs<T>& v,
+                    LevelVecs<T>& vc, hipStream_t s) {
+  if (Lc.coarsest) {
+    launch_op<T, NB, BS, NV>(selR<T>(L, NV >= 16), LoadX<T, NV>{v.res.p},
+                               EpiStore<T, NV>{vc.b.p}, s);
+  } else {
+    launch_op<T, NB, BS, NV>(
+        selR<T>(L, NV >= 16), LoadX<T, NV>{v.res.p},
+        EpiRestrict<T, NV>{vc.b.p, vc.d0.p, seldinv<T>(Lc),
+                               T(1.0 / Lc.theta)},
+        s);
+  }
 }
 
 template <typename T, int BS, int NB, int NV>
 void prolong_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
                    hipStream_t s) {
   launch_op<T, BS, NB, NV>(selP<T>(L, NV >= 16), LoadX<T, NV>{vc.xo.p},
-                             EpiAdd<T, BS, NV>{v.x.p}, s);
+                             EpiAdd<T, NV>{v.x.p}, s);
 }
 
 template <typename T, int NV>
@@ -548,18 +763,26 @@ void dispatch_smooth(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
 }
 
 template <typename T, int NV>
-void dispatch_transfer(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
-                       hipStream_t s, bool restr) {
+void dispatch_transfer(const Level& L, const Level& Lc, LevelVecs<T>& v,
+                       LevelVecs<T>& vc, hipStream_t s, bool restr) {
   if (L.bs == 3 && L.nb == 6) {
-    if (restr) restrict_level<T, 3, 6, NV>(L, v, vc, s);
+    if (restr) restrict_level<T, 3, 6, NV>(L, Lc, v, vc, s);
     else prolong_level<T, 3, 6, NV>(L, v, vc, s);
   } else if (L.bs == 3 && L.nb == 3) {
-    if (restr) restrict_level<T, 3, 3, NV>(L, v, vc, s);
+    if (restr) restrict_level<T, 3, 3, NV>(L, Lc, v, vc, s);
     else prolong_level<T, 3, 3, NV>(L, v, vc, s);
   } else {
-    if (restr) restrict_level<T, 6, 6, NV>(L, v, vc, s);
+    if (restr) restrict_level<T, 6, 6, NV>(L, Lc, v, vc, s);
     else prolong_level<T, 6, 6, NV>(L, v, vc, s);
   }
+}
+
+// d0 = D^{-1} b / theta on the finest level, whose b the caller wrote
+template <typename T, int NV>
+__global__ void k_first_dir(const T* __restrict__ b, const T* __restrict__ dinv,
+                            T inv_theta, T* __restrict__ d0, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * NV) d0[i] = dinv[i / NV] * b[i] * inv_theta;
 }
 
 template <typename T, int NV>
@@ -575,10 +798,17 @@ void vcycle_rec(Hierarchy& H, CycleVecs<T>& cv, size_t l, bool tr,
     return;
   }
   KTimer* timer = (l == 0) ? H.timer : nullptr;
+  if (l == 0) {
+    const int64_t n = L.n_nodes * L.bs;
+    k_first_dir<T, NV><<<grid_for(n * NV, 256), 256, 0, s>>>(
+        v.b.p, seldinv<T>(L), T(1.0 / L.theta), v.d0.p, n);
+    FPC_LAUNCH_CHECK();
+  }
   dispatch_smooth<T, NV>(L, v, tr, s, 0, timer);
-  dispatch_transfer<T, NV>(L, v, cv.lv[l + 1], s, true);
+  const Level& Lc = H.L[l + 1];
+  dispatch_transfer<T, NV>(L, Lc, v, cv.lv[l + 1], s, true);
   vcycle_rec<T, NV>(H, cv, l + 1, tr, s);
-  dispatch_transfer<T, NV>(L, v, cv.lv[l + 1], s, false);
+  dispatch_transfer<T, NV>(L, Lc, v, cv.lv[l + 1], s, false);
   dispatch_smooth<T, NV>(L, v, tr, s, 1, nullptr);
 }
 
@@ -596,13 +826,13 @@ std::vector<CycleVecs<float>>& vec_sets<float>(Hierarchy& H) {
 // ---------------------------------------------------------------- tuner
 template <typename T, int BR, int BC, int NV>
 double time_op(const Op<T>& op, const T* x, T* y, hipStream_t s, int reps) {
-  launch_op<T, BR, BC, NV>(op, LoadX<T, NV>{x}, EpiStore<T, BR, NV>{y}, s);
+  launch_op<T, BR, BC, NV>(op, LoadX<T, NV>{x}, EpiStore<T, NV>{y}, s);
   hipEvent_t e0, e1;
   FPC_HIP(hipEventCreate(&e0));
   FPC_HIP(hipEventCreate(&e1));
   FPC_HIP(hipEventRecord(e0, s));
   for (int r = 0; r < reps; ++r)
-    launch_op<T, BR, BC, NV>(op, LoadX<T, NV>{x}, EpiStore<T, BR, NV>{y}, s);
+    launch_op<T, BR, BC, NV>(op, LoadX<T, NV>{x}, EpiStore<T, NV>{y}, s);
   FPC_HIP(hipEventRecord(e1, s));
   FPC_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -628,7 +858,8 @@ double time_any(const Op<T>& op, int br, int bc, const T* x, T* y,
 // row) or row groups of 4, 16 or 64 lanes, by timing `reps` products with
 // `nv` columns on the device; only the winner is kept.
 template <typename T>
-void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice) {
+void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
+             double* best_us) {
   DevBuf<T> x(std::max<int64_t>(M.nbc * M.bc * nv, 1));
   DevBuf<T> y(std::max<int64_t>(M.nbr * M.br * nv, 1));
   FPC_HIP(hipMemsetAsync(x.p, 0, x.bytes(), s));
@@ -663,10 +894,13 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice) {
   }
   out = std::move(best);
   if (choice) *choice = cbest;
+  if (best_us) *best_us = 1e3 * tbest;
   FPC_HIP(hipStreamSynchronize(s));
 }
-template void tune_op<double>(const Bsr&, int, Op<double>&, hipStream_t, int*);
-template void tune_op<float>(const Bsr&, int, Op<float>&, hipStream_t, int*);
+template void tune_op<double>(const Bsr&, int, Op<double>&, hipStream_t, int*,
+                              double*);
+template void tune_op<float>(const Bsr&, int, Op<float>&, hipStream_t, int*,
+                             double*);
 
 template <typename T>
 CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv) {
@@ -687,6 +921,7 @@ CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv) {
       v.d.alloc(n);
       v.r.alloc(n);
       v.res.alloc(n);
+      v.d0.alloc(n);
     }
   }
   return c;
@@ -713,10 +948,10 @@ void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,
   if (A.br != 3 || A.bc != 3) throw Error(FPC_ERR_ARG, "sell_mv_b shape");
   if (KB == 8)
     launch_sell<double, 3, 3, 8>(A, LoadX<double, 8>{x},
-                                 EpiStore<double, 3, 8>{y}, s);
+                                 EpiStore<double, 8>{y}, s);
   else if (KB == 32)
     launch_sell<double, 3, 3, 32>(A, LoadX<double, 32>{x},
-                                  EpiStore<double, 3, 32>{y}, s);
+                                  EpiStore<double, 32>{y}, s);
   else
     throw Error(FPC_ERR_ARG, "sell_mv_b: batch width");
 }
@@ -724,10 +959,10 @@ void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,
 void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s) {
   if (A.br == 3 && A.bc == 3)
     launch_sell<double, 3, 3, 1>(A, LoadX<double, 1>{x},
-                                 EpiStore<double, 3, 1>{y}, s);
+                                 EpiStore<double, 1>{y}, s);
   else if (A.br == 6 && A.bc == 6)
     launch_sell<double, 6, 6, 1>(A, LoadX<double, 1>{x},
-                                 EpiStore<double, 6, 1>{y}, s);
+                                 EpiStore<double, 1>{y}, s);
   else
     throw Error(FPC_ERR_ARG, "sell_mv: unsupported block shape");
 }
@@ -736,10 +971,10 @@ void sell_mv_dinv(const Sell<double>& A, const double* dinv, const double* x,
                   double* y, hipStream_t s) {
   if (A.br == 3 && A.bc == 3)
     launch_sell<double, 3, 3, 1>(A, LoadX<double, 1>{x},
-                                 EpiDinv<double, 3>{dinv, y}, s);
+                                 EpiDinv<double, 1>{dinv, y}, s);
   else if (A.br == 6 && A.bc == 6)
     launch_sell<double, 6, 6, 1>(A, LoadX<double, 1>{x},
-                                 EpiDinv<double, 6>{dinv, y}, s);
+                                 EpiDinv<double, 1>{dinv, y}, s);
   else
     throw Error(FPC_ERR_ARG, "sell_mv_dinv: unsupported block shape");
 }
@@ -793,18 +1028,28 @@ void tface(const Csr& C, const double* vu, const double* t_t,
 
 void psolve_apply(const PSolve& ps, const double* in, double* out,
                   int64_t n_p, int trans, hipStream_t s) {
+  // the stored inverse is exactly symmetric: the transposed solve is the same
+  (void)trans;
   if (n_p == 0) return;
-  const unsigned g = (unsigned)((n_p + 3) / 4);
-  if (ps.dense32.p)
-    k_psolve<float><<<g, 256, 0, s>>>(ps.dense32.p, ps.dense_off.p,
-                                      ps.comp_off.p, ps.comp_pad_d.p,
-                                      ps.comp_of_row.p, ps.members.p, in, out,
-                                      n_p, trans);
+  if (ps.packed32.p)
+    k_psym_tile<float><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
+        ps.packed32.p, ps.tile_info.p, ps.comp_off.p, ps.members.p, in, ps.part.p);
   else
-    k_psolve<double><<<g, 256, 0, s>>>(ps.dense.p, ps.dense_off.p,
-                                       ps.comp_off.p, ps.comp_pad_d.p,
-                                       ps.comp_of_row.p, ps.members.p, in,
-                                       out, n_p, trans);
+    k_psym_tile<double><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
+        ps.packed.p, ps.tile_info.p, ps.comp_off.p, ps.members.p, in, ps.part.p);
+  FPC_LAUNCH_CHECK();
+  k_psym_reduce<<<(unsigned)ps.n_rowblk, 256, 0, s>>>(
+      ps.rowblk.p, ps.tile_base.p, ps.n_tiles_c.p, ps.comp_off.p, ps.members.p,
+      ps.part.p, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void pack_sym_tiles(const double* D, int64_t ld, int nt, double* out64,
+                    float* out32, hipStream_t s) {
+  const unsigned g = (unsigned)((int64_t)nt * (nt + 1) / 2);
+  if (!g) return;
+  if (out64) k_pack_sym<double><<<g, 256, 0, s>>>(D, ld, out64);
+  else k_pack_sym<float><<<g, 256, 0, s>>>(D, ld, out32);
   FPC_LAUNCH_CHECK();
 }
 

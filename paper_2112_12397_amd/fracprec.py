@@ -69,10 +69,14 @@ class FpcLevelDesc(C.Structure):
                 ("block", C.c_int), ("nnzb", C.c_int64),
                 ("nnz_scalar", C.c_int64), ("p_nnzb", C.c_int64),
                 ("r_nnzb", C.c_int64), ("lam_hi", C.c_double),
-                ("n_agg", C.c_int64)]
+                ("n_agg", C.c_int64), ("layout", C.c_int * 3),
+                ("tune_us", C.c_double * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out["layout"] = list(self.layout)
+        out["tune_us"] = list(self.tune_us)
+        return out
 
 
 class FpcFlowGraph(C.Structure):
