@@ -87,7 +87,7 @@ typedef struct {
   int max_coarse;          /* coarsest level when dofs <= this (2000)      */
   int max_levels;          /* 12                                            */
   int cheb_degree;         /* Chebyshev degree, pre and post (2; only 2)    */
-  double cheb_ratio;       /* interval [lambda_hi / ratio, lambda_hi] (10)  */
+  double cheb_ratio;       /* interval [lambda_hi / ratio, lambda_hi] (5)   */
   int power_its;           /* power iterations for lambda (10)              */
   double lam_safety;       /* lambda_hi = safety * estimate (1.1)           */
   double omega_factor;     /* prolongator smoothing omega = f / lambda_hi   */
@@ -101,6 +101,8 @@ typedef struct {
   int maxit;               /* total iteration cap (1000)                    */
   double rtol;             /* default relative tolerance (1e-8)             */
   int max_batch;           /* right-hand sides per fpc_solve_batch (32)     */
+  int graphs;              /* 1: the batched V-cycle is captured once into  */
+                           /* a HIP graph and replayed (default); 0: eager  */
   fpc_amg_options amg;
 } fpc_options;
 
@@ -143,7 +145,7 @@ typedef struct {
 typedef struct fpc_handle fpc_handle;
 
 /* Fill *opt with the defaults listed above (mode t-u-p, FP64, FGMRES(50),
- * rtol 1e-8, AMG: 2000 / 12 / degree 2 / ratio 10 / 10 its / 1.1 / 4/3 /
+ * rtol 1e-8, AMG: 2000 / 12 / degree 2 / ratio 5 / 10 its / 1.1 / 4/3 /
  * 1e-10). */
 void fpc_default_options(fpc_options* opt);
 

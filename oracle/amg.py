@@ -15,9 +15,11 @@ specifies one from published methods:
 * smoothed prolongator ``P = (I - 4/3 / lambda_hi D^{-1} A) P_tent``,
   Galerkin coarse operator ``P^T A P``,
 * Chebyshev smoothing of degree 2 on ``D^{-1} A`` over
-  ``[lambda_hi / 10, lambda_hi]`` (Saad, Iterative Methods, Alg. 12.1; Adams
+  ``[lambda_hi / 5, lambda_hi]`` (Saad, Iterative Methods, Alg. 12.1; Adams
   et al., J. Comput. Phys. 188 (2003)), ``lambda_hi`` from 10 power
-  iterations times 1.1,
+  iterations times 1.1.  The ratio 5 leaves the lowest fifth of the spectrum
+  to the coarse space; with ratio 10 the degree-2 polynomial damps the upper
+  part only by 1/2 and the iteration counts grow with the mesh,
 * dense LU with partial pivoting on the coarsest level (<= 2000 dofs).
 """
 from dataclasses import dataclass, field
@@ -39,7 +41,7 @@ class AMGOptions:
     max_coarse: int = 2000
     max_levels: int = 12
     cheb_degree: int = 2
-    cheb_ratio: float = 10.0
+    cheb_ratio: float = 5.0
     power_its: int = 10
     lam_safety: float = 1.1
     omega_factor: float = 4.0 / 3.0

@@ -91,8 +91,40 @@ struct KTimer {
   }
 };
 
+// Captured V-cycles, keyed by (precision, column count).  The graphs refer to
+// the level operators and vectors of one hierarchy and are dropped with it.
+struct GraphCache {
+  struct Slot {
+    int key;
+    hipGraph_t g;
+    hipGraphExec_t e;
+  };
+  std::vector<Slot> slots;
+  hipStream_t cap = nullptr;  // private stream used only for capturing
+  GraphCache() = default;
+  GraphCache(const GraphCache&) = delete;
+  GraphCache& operator=(const GraphCache&) = delete;
+  ~GraphCache() {
+    clear();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  void clear() {
+    for (Slot& s : slots) {
+      if (s.e) (void)hipGraphExecDestroy(s.e);
+      if (s.g) (void)hipGraphDestroy(s.g);
+    }
+    slots.clear();
+  }
+  hipGraphExec_t find(int key) const {
+    for (const Slot& s : slots)
+      if (s.key == key) return s.e;
+    return nullptr;
+  }
+};
+
 struct Hierarchy {
   KTimer* timer = nullptr;
+  GraphCache* graphs = nullptr;  // non-null: batched V-cycles replay graphs
   std::vector<Level> L;
   int64_t nc = 0, ncpad = 0;  // coarsest dofs (padded) and dense size
   DevBuf<double> Ainv;        // ncpad x ncpad, row-major
@@ -174,6 +206,7 @@ struct fpc_handle {
   fpc::Krylov kry1;            // single right-hand side
   fpc::Krylov kryB;            // batched
   fpc::KTimer ktimer;
+  fpc::GraphCache graphs;
   fpc::BatchWork bw;
   std::string last_error;
   double setup_times[5] = {0, 0, 0, 0, 0};

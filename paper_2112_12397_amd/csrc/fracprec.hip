@@ -344,8 +344,10 @@ double power_lambda(fpc_handle* h, Level& L, int key_stride) {
 
 void build_hierarchy(fpc_handle* h, Bsr&& S1) {
   Hierarchy& H = h->amg;
+  h->graphs.clear();  // captured cycles refer to the old hierarchy
   H = Hierarchy();
   H.timer = h->ktimer.on ? &h->ktimer : nullptr;
+  H.graphs = h->opt.graphs ? &h->graphs : nullptr;
   hipStream_t s = h->stream;
   const fpc_amg_options& o = h->opt.amg;
   const int nb = h->has_coords ? 6 : 3;
@@ -944,10 +946,11 @@ void fpc_default_options(fpc_options* o) {
   o->maxit = 1000;
   o->rtol = 1e-8;
   o->max_batch = 32;
+  o->graphs = 1;
   o->amg.max_coarse = 2000;
   o->amg.max_levels = 12;
   o->amg.cheb_degree = 2;
-  o->amg.cheb_ratio = 10.0;
+  o->amg.cheb_ratio = 5.0;
   o->amg.power_its = 10;
   o->amg.lam_safety = 1.1;
   o->amg.omega_factor = 4.0 / 3.0;
@@ -970,7 +973,8 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
       (o.precision != FPC_FP64 && o.precision != FPC_FP32_PREC) ||
       o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
-      o.amg.cheb_ratio <= 1.0 || o.max_batch < 1) {
+      o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 ||
+      (o.graphs != 0 && o.graphs != 1)) {
     delete h;
     return FPC_ERR_ARG;
   }

@@ -929,9 +929,39 @@ CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv) {
 template CycleVecs<double>& cycle_vecs<double>(Hierarchy&, int);
 template CycleVecs<float>& cycle_vecs<float>(Hierarchy&, int);
 
+// Batched forward cycles are captured once (on a private stream, so that the
+// caller's stream may be the legacy default stream) and replayed on `s`; the
+// cycle holds no memset or allocation, only kernel launches on fixed
+// buffers.  The per-launch kernel timer needs the eager path.
 template <typename T, int NV>
 void vcycle(Hierarchy& H, bool transpose, hipStream_t s) {
   CycleVecs<T>& cv = cycle_vecs<T>(H, NV);
+  if (NV >= 16 && H.graphs && !transpose && !H.timer) {
+    GraphCache& gc = *H.graphs;
+    const int key = (int)sizeof(T) * 1000 + NV;
+    hipGraphExec_t e = gc.find(key);
+    if (!e) {
+      if (!gc.cap) FPC_HIP(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      FPC_HIP(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
+      try {
+        vcycle_rec<T, NV>(H, cv, 0, false, gc.cap);
+      } catch (...) {
+        (void)hipStreamEndCapture(gc.cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      FPC_HIP(hipStreamEndCapture(gc.cap, &g));
+      const hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        FPC_HIP(ie);
+      }
+      gc.slots.push_back({key, g, e});
+    }
+    FPC_HIP(hipGraphLaunch(e, s));
+    return;
+  }
   vcycle_rec<T, NV>(H, cv, 0, transpose, s);
 }
 template void vcycle<double, 1>(Hierarchy&, bool, hipStream_t);

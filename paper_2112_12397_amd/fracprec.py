@@ -52,7 +52,7 @@ class FpcOptions(C.Structure):
     _fields_ = [("mode", C.c_int), ("precision", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int),
                 ("rtol", C.c_double), ("max_batch", C.c_int),
-                ("amg", FpcAmgOptions)]
+                ("graphs", C.c_int), ("amg", FpcAmgOptions)]
 
 
 class FpcInfo(C.Structure):
