@@ -12,7 +12,8 @@ Printed: one JSON line.  ``value`` is the FGMRES time-to-1e-8 in seconds of
 the plain FP64 path (mean over the timed steps); the FP32-preconditioned
 solve time and its speedup, the V-cycle bandwidth, the roofline of the
 dominant kernel (level-0 residual SpMV of the V-cycle, timed with HIP events
-inside the timed region) and the CPU oracle baseline are added as objects.
+inside the timed region), the production forms on their own workloads
+(``forms``) and the CPU oracle baseline are added as objects.
 """
 import argparse
 import json
@@ -68,6 +69,29 @@ def vcycle_bytes(levels, nv=1, sv=8):
     return total
 
 
+COUNTERS = os.path.join(ROOT, "profiles",
+                        "level0_residual_spmv_c2_fp64_counters.json")
+
+
+def counter_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, each scaled by what the counter
+    reads for a plain 2 GiB copy; None once the kernel source differs from
+    the one the counters were taken on."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        with open(os.path.join(ROOT, c["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if sha != c["source_sha256"]:
+        return None
+    return 1024.0 * (c["fetch_kib_per_launch"] * c["fetch_scale"]
+                     + c["write_kib_per_launch"] * c["write_scale"])
+
+
 def device_blocks(torch, s):
     out = {}
     for k, M in s.blocks().items():
@@ -112,6 +136,107 @@ def cpu_baseline(s, gpu_iters, sample_its):
             "cpu_model": cpu, "host": platform.node()}
 
 
+def _timed(torch, fn, reps=1):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def forms(torch, s2, blocks2, coords2, b2, fp64_solve_s):
+    """The production forms on their own workloads, each after one untimed
+    warm-up call: t-p-u mode on the 80^3 system, the 32-right-hand-side batch
+    (64^3, FP32 preconditioner) against the same columns solved one by one,
+    the FP32 hierarchy on the 128x128x64 layered system, and the adjoint
+    solve with the transmissibility gradient on the 48^3 system."""
+    import fracgen
+    from fracgen.configs import observations, rhs_batch
+    from paper_2112_12397_amd import Solver, solver_from_system
+    out = {}
+    # t-p-u (Alg 3.2): one AMG call per application
+    sol = Solver(blocks2, s2.n_u, s2.n_t, s2.n_p, coords=coords2, mode="tpu")
+    x = torch.empty_like(b2)
+    sol.solve(b2, out=x)
+    t, (_, inf) = _timed(torch, lambda: sol.solve(b2, out=x), 2)
+    out["tpu_80cube"] = {"solve_s": t, "iterations": inf["iterations"],
+                         "true_rel_residual": inf["true_rel_residual"],
+                         "speedup_vs_tup": fp64_solve_s / t}
+    del sol
+    # batch of 32 right-hand sides
+    s4 = fracgen.make_config("c4")
+    sol = solver_from_system(s4, precision="fp32")
+    B = torch.tensor(np.ascontiguousarray(rhs_batch(s4, k=32).T), device="cuda")
+    X = torch.empty_like(B)
+    sol.solve_batch(B, out=X)
+    tb, (_, infs, st) = _timed(torch, lambda: sol.solve_batch(B, out=X))
+    xs = torch.empty_like(B[0])
+    sol.solve(B[0].contiguous(), out=xs)
+
+    def seq():
+        its = []
+        for c in range(32):
+            _, i1 = sol.solve(B[c].contiguous(), out=xs)
+            its.append(i1["iterations"])
+        return its
+    tq, its1 = _timed(torch, seq)
+    out["batch32_64cube_fp32prec"] = {
+        "workload": "64^3 Q1 hex, 6 random fractures, 32 RHS (norms 1e-2..1e2)",
+        "batch_s": tb, "per_rhs_s": tb / 32, "sequential_s": tq,
+        "speedup_vs_sequential": tq / tb, "status": st,
+        "iterations_max": max(i["iterations"] for i in infs),
+        "iterations_mean": float(np.mean([i["iterations"] for i in infs])),
+        "sequential_iterations_mean": float(np.mean(its1)),
+        "worst_true_rel_residual": max(i["true_rel_residual"] for i in infs),
+        "n_u": s4.n_u, "n_t": s4.n_t, "n_p": s4.n_p}
+    del sol, s4
+    # FP32 hierarchy on the layered 128x128x64 system
+    s3 = fracgen.make_config("c3")
+    b3 = torch.tensor(s3.b, device="cuda")
+    res = {"workload": "128x128x64 Q1 hex, 12 random fractures, layered E",
+           "n_u": s3.n_u, "n_t": s3.n_t, "n_p": s3.n_p}
+    xx = {}
+    for prec in ("fp64", "fp32"):
+        sol = solver_from_system(s3, precision=prec)
+        x3 = torch.empty_like(b3)
+        sol.solve(b3, out=x3)
+        t, (_, inf) = _timed(torch, lambda: sol.solve(b3, out=x3), 2)
+        res[prec] = {"solve_s": t, "iterations": inf["iterations"],
+                     "true_rel_residual": inf["true_rel_residual"]}
+        xx[prec] = x3.clone()
+        del sol
+    res["fp32_speedup"] = res["fp64"]["solve_s"] / res["fp32"]["solve_s"]
+    res["rel_diff_fp32_vs_fp64"] = float(
+        (xx["fp32"] - xx["fp64"]).norm() / xx["fp64"].norm())
+    out["precision_128x128x64"] = res
+    del s3, b3, xx
+    # adjoint solve and transmissibility gradient
+    s5 = fracgen.make_config("c5")
+    _, p_obs = observations(s5)
+    sol = solver_from_system(s5)
+    b5 = torch.tensor(s5.b, device="cuda")
+    x5, _ = sol.solve(b5)
+    off = s5.n_u + s5.n_t
+    g = torch.zeros_like(b5)
+    g[off:] = x5[off:] - torch.tensor(p_obs, device="cuda")
+    sol.solve_T(g, rtol=1e-11)
+    tf, (_, inff) = _timed(torch, lambda: sol.solve(b5, rtol=1e-11))
+    ta, (lam, infa) = _timed(torch, lambda: sol.solve_T(g, rtol=1e-11))
+    pairs = torch.tensor(s5.flow_pairs)
+    ndir = torch.tensor(s5.flow_ndir)
+    ups = torch.tensor(s5.upsilon)
+    tg, _ = _timed(torch, lambda: sol.grad_log_trans(pairs, ndir, ups,
+                                                     lam[off:], x5[off:]))
+    out["adjoint_48cube"] = {
+        "workload": "48^3 Q1 hex, 4 full fractures (9,216 faces), rtol 1e-11",
+        "forward_s": tf, "forward_iterations": inff["iterations"],
+        "adjoint_s": ta, "adjoint_iterations": infa["iterations"],
+        "gradient_s": tg}
+    del sol, s5
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +246,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=2)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batch / precision / adjoint / t-p-u runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; multi-GPU runs "
@@ -227,7 +354,10 @@ def main():
                    "columns": 1, "dtype": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 "
+                                     "FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "level-0 residual SpMV (sliced-ELL 3x3 blocks, "
                                "2 columns, FP64)",
                      "bytes_per_launch": k_bytes,
@@ -251,6 +381,9 @@ def main():
                             "converged": bool(i32["converged"]),
                             "speedup_vs_fp64": (t_solve / K) / t32}
         del sol32
+
+    if not args.no_forms and args.config == "c2":
+        out["forms"] = forms(torch, s, blocks, coords, b, t_solve / K)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, iters, args.cpu_sample_its)
