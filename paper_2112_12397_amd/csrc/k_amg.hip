@@ -415,10 +415,16 @@ __global__ void k_pad_identity(double* D, int64_t n, int64_t npad) {
 }
 
 // ------------------------------------------------------------- dense GJ
+// Blocked Gauss-Jordan inverse, in place, without pivoting (SPD pressure
+// blocks; the coarsest Galerkin operator).  Panels of 64 columns are handled
+// by the tile kernels below; matrices larger than 256 use 256-wide panels
+// whose diagonal block is inverted with the 64-wide kernels and whose row
+// panel, trailing update and column panel are FP64 MFMA products
+// (k_gemm_f64).  `ld` is the row pitch, `n` the order.
 constexpr int GT = 64;  // tile
 
 // Gauss-Jordan inverse of the diagonal tile (in place, in LDS).
-__global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t n,
+__global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t ld,
                                                  int64_t kb, int spd,
                                                  int* flags) {
   __shared__ double a[GT][GT + 1];
@@ -428,7 +434,7 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t n,
   const int64_t o = kb * GT;
   for (int q = tid; q < GT * GT; q += 256) {
     int r = q / GT, c = q % GT;
-    a[r][c] = D[(o + r) * n + o + c];
+    a[r][c] = D[(o + r) * ld + o + c];
   }
   __syncthreads();
   for (int k = 0; k < GT; ++k) {
@@ -454,22 +460,20 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t n,
   }
   for (int q = tid; q < GT * GT; q += 256) {
     int r = q / GT, c = q % GT;
-    D[(o + r) * n + o + c] = a[r][c];
+    D[(o + r) * ld + o + c] = a[r][c];
   }
 }
 
-// C (64x64 tile at (ci, cj)) = alpha * X(xi, xj) * Y(yi, yj) + beta * C,
-// skipping tiles in `skip_row` / `skip_col`.  grid.x enumerates the tiles of
-// the target row/column set.
-__device__ inline void tile_gemm(const double* D, int64_t n, int64_t xi,
+// acc = X(xi, xj) * Y(yi, yj) for 64x64 tiles (tile coordinates).
+__device__ inline void tile_gemm(const double* D, int64_t ld, int64_t xi,
                                  int64_t xj, int64_t yi, int64_t yj,
                                  double (*sa)[GT + 1], double (*sb)[GT + 1],
                                  double acc[4][4]) {
   const int tid = threadIdx.x;
   for (int q = tid; q < GT * GT; q += 256) {
     int r = q / GT, c = q % GT;
-    sa[r][c] = D[(xi * GT + r) * n + xj * GT + c];
-    sb[r][c] = D[(yi * GT + r) * n + yj * GT + c];
+    sa[r][c] = D[(xi * GT + r) * ld + xj * GT + c];
+    sb[r][c] = D[(yi * GT + r) * ld + yj * GT + c];
   }
   __syncthreads();
   const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
@@ -485,23 +489,23 @@ __device__ inline void tile_gemm(const double* D, int64_t n, int64_t xi,
 }
 
 // row panel: A[kb, j] <- Dinv * A[kb, j], j != kb
-__global__ __launch_bounds__(256) void k_gj_rowpanel(double* D, int64_t n,
+__global__ __launch_bounds__(256) void k_gj_rowpanel(double* D, int64_t ld,
                                                      int64_t kb) {
   __shared__ double sa[GT][GT + 1];
   __shared__ double sb[GT][GT + 1];
   int64_t j = blockIdx.x;
   if (j >= kb) ++j;
   double acc[4][4];
-  tile_gemm(D, n, kb, kb, kb, j, sa, sb, acc);
+  tile_gemm(D, ld, kb, kb, kb, j, sa, sb, acc);
   __syncthreads();
   const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
   for (int i = 0; i < 4; ++i)
     for (int jj = 0; jj < 4; ++jj)
-      D[(kb * GT + tr + i) * n + j * GT + tc + jj] = acc[i][jj];
+      D[(kb * GT + tr + i) * ld + j * GT + tc + jj] = acc[i][jj];
 }
 
 // trailing update: A[i, j] -= A[i, kb] A[kb, j], i != kb, j != kb
-__global__ __launch_bounds__(256) void k_gj_update(double* D, int64_t n,
+__global__ __launch_bounds__(256) void k_gj_update(double* D, int64_t ld,
                                                    int64_t kb, int64_t nt) {
   __shared__ double sa[GT][GT + 1];
   __shared__ double sb[GT][GT + 1];
@@ -510,27 +514,145 @@ __global__ __launch_bounds__(256) void k_gj_update(double* D, int64_t n,
   if (i >= kb) ++i;
   if (j >= kb) ++j;
   double acc[4][4];
-  tile_gemm(D, n, i, kb, kb, j, sa, sb, acc);
+  tile_gemm(D, ld, i, kb, kb, j, sa, sb, acc);
   const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
   for (int r = 0; r < 4; ++r)
     for (int c = 0; c < 4; ++c)
-      D[(i * GT + tr + r) * n + j * GT + tc + c] -= acc[r][c];
+      D[(i * GT + tr + r) * ld + j * GT + tc + c] -= acc[r][c];
 }
 
 // column panel: A[i, kb] <- -A[i, kb] * Dinv, i != kb
-__global__ __launch_bounds__(256) void k_gj_colpanel(double* D, int64_t n,
+__global__ __launch_bounds__(256) void k_gj_colpanel(double* D, int64_t ld,
                                                      int64_t kb) {
   __shared__ double sa[GT][GT + 1];
   __shared__ double sb[GT][GT + 1];
   int64_t i = blockIdx.x;
   if (i >= kb) ++i;
   double acc[4][4];
-  tile_gemm(D, n, i, kb, kb, kb, sa, sb, acc);
+  tile_gemm(D, ld, i, kb, kb, kb, sa, sb, acc);
   __syncthreads();
   const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
   for (int r = 0; r < 4; ++r)
     for (int c = 0; c < 4; ++c)
-      D[(i * GT + tr + r) * n + kb * GT + tc + c] = -acc[r][c];
+      D[(i * GT + tr + r) * ld + kb * GT + tc + c] = -acc[r][c];
+}
+
+// Logical index l -> physical index: the range [at, at + len) is skipped.
+struct SkipMap {
+  int64_t at, len;
+  __device__ int64_t operator()(int64_t l) const { return l < at ? l : l + len; }
+};
+
+// C[rm(i), cm(j)] = alpha * sum_k A[rm(i), k] B[k, cm(j)] + beta * C[..]
+// (row-major, pitches lda / ldb / ldc).  128 x 128 output tile per
+// workgroup, 64 x 64 per wavefront as 4 x 4 tiles of v_mfma_f64_16x16x4f64,
+// K in chunks of 16 through LDS with the next chunk's loads in flight during
+// the products.  Operand layout of that instruction: lane l holds A[l%16]
+// [l/16] and B[l/16][l%16]; result register r of lane l is D[l/16 + 4r]
+// [l%16].  Requires K and N multiples of 16 and skip offsets that are
+// multiples of 8 (eight consecutive logical columns stay contiguous).
+constexpr int GM_T = 128, GM_KC = 16, GM_LP = 16;
+
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(
+    int64_t M, int64_t N, int K, double alpha, double beta,
+    const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+    int64_t ldb, double* __restrict__ C, int64_t ldc, SkipMap rm, SkipMap cm) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int AQ = GM_KC / 2, BQ = GM_KC * GM_T / 256;
+  __shared__ double As[GM_KC][GM_T + GM_LP];
+  __shared__ double Bs[GM_KC][GM_T + GM_LP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t tiles_n = (N + GM_T - 1) / GM_T;
+  const int64_t i0 = (int64_t)(blockIdx.x / tiles_n) * GM_T;
+  const int64_t j0 = (int64_t)(blockIdx.x % tiles_n) * GM_T;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ar = tid >> 1, ak = (tid & 1) * AQ;
+  const int bk = tid / (GM_T / BQ), bc = (tid % (GM_T / BQ)) * BQ;
+  const bool aok = i0 + ar < M;
+  const double* __restrict__ ap = A + (aok ? rm(i0 + ar) : 0) * lda + ak;
+  const bool bok = j0 + bc < N;
+  const double* __restrict__ bp = B + (int64_t)bk * ldb + (bok ? cm(j0 + bc) : 0);
+  double av[AQ], bv[BQ];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) av[q] = aok ? ap[k0 + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) bv[q] = bok ? bp[(int64_t)k0 * ldb + q] : 0.0;
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += GM_KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) As[ak + q][ar] = av[q];
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) Bs[bk][bc + q] = bv[q];
+    __syncthreads();
+    if (k0 + GM_KC < K) load(k0 + GM_KC);
+#pragma unroll
+    for (int kk = 0; kk < GM_KC; kk += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = As[kk + (lane >> 4)][wm + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = Bs[kk + (lane >> 4)][wn + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gi = i0 + wm + a * 16 + (lane >> 4) + 4 * r;
+      if (gi >= M) continue;
+      double* __restrict__ crow = C + rm(gi) * ldc;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t gj = j0 + wn + b * 16 + (lane & 15);
+        if (gj < N) {
+          double* c = crow + cm(gj);
+          const double v = alpha * acc[a][b][r];
+          *c = beta == 0.0 ? v : beta * *c + v;
+        }
+      }
+    }
+}
+
+void gemm_f64(int64_t M, int64_t N, int K, double alpha, double beta,
+              const double* A, int64_t lda, const double* B, int64_t ldb,
+              double* C, int64_t ldc, SkipMap rm, SkipMap cm, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return;
+  if (K % GM_KC || N % 16 || (rm.len && (rm.at % 8 || rm.len % 8)) ||
+      (cm.len && (cm.at % 8 || cm.len % 8)))
+    throw Error(FPC_ERR_ARG, "gemm_f64: shape not supported");
+  const int64_t tiles = ((M + GM_T - 1) / GM_T) * ((N + GM_T - 1) / GM_T);
+  k_gemm_f64<<<(unsigned)tiles, 256, 0, s>>>(M, N, K, alpha, beta, A, lda, B,
+                                              ldb, C, ldc, rm, cm);
+  FPC_LAUNCH_CHECK();
+}
+
+// 64-wide Gauss-Jordan on the n x n block at D (pitch ld).
+void gj_inverse64(double* D, int64_t n, int64_t ld, int spd, int* flags,
+                  hipStream_t s) {
+  const int64_t nt = n / GT;
+  for (int64_t kb = 0; kb < nt; ++kb) {
+    k_gj_diag<<<1, 256, 0, s>>>(D, ld, kb, spd, flags);
+    if (nt > 1) {
+      k_gj_rowpanel<<<(unsigned)(nt - 1), 256, 0, s>>>(D, ld, kb);
+      k_gj_update<<<(unsigned)((nt - 1) * (nt - 1)), 256, 0, s>>>(D, ld, kb,
+                                                                  nt);
+      k_gj_colpanel<<<(unsigned)(nt - 1), 256, 0, s>>>(D, ld, kb);
+    }
+    FPC_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace
@@ -706,17 +828,33 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
 
 void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
   if (n % GT) throw Error(FPC_ERR_ARG, "gj_inverse: size not a multiple of 64");
-  const int64_t nt = n / GT;
-  for (int64_t kb = 0; kb < nt; ++kb) {
-    k_gj_diag<<<1, 256, 0, s>>>(D, n, kb, spd, flags);
-    if (nt > 1) {
-      k_gj_rowpanel<<<(unsigned)(nt - 1), 256, 0, s>>>(D, n, kb);
-      k_gj_update<<<(unsigned)((nt - 1) * (nt - 1)), 256, 0, s>>>(D, n, kb,
-                                                                  nt);
-      k_gj_colpanel<<<(unsigned)(nt - 1), 256, 0, s>>>(D, n, kb);
-    }
-    FPC_LAUNCH_CHECK();
+  constexpr int64_t NB = 256;
+  if (n <= NB) return gj_inverse64(D, n, n, spd, flags, s);
+  // 256-wide panels: copies of the panel row / column feed the panel
+  // products, which may not read what they write
+  DevBuf<double> prow(NB * n), pcol(n * NB);
+  const SkipMap none{INT64_MAX, 0};
+  for (int64_t o = 0; o < n; o += NB) {
+    const int64_t nb = std::min<int64_t>(NB, n - o);
+    const SkipMap skip{o, nb};
+    double* Dkk = D + o * n + o;
+    gj_inverse64(Dkk, nb, n, spd, flags, s);        // Dkk <- Dkk^-1
+    FPC_HIP(hipMemcpyAsync(prow.p, D + o * n, nb * n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    FPC_HIP(hipMemcpy2DAsync(pcol.p, nb * sizeof(double), D + o,
+                             n * sizeof(double), nb * sizeof(double), n,
+                             hipMemcpyDeviceToDevice, s));
+    // row panel: D[o.., j] = Dkk^-1 D[o.., j], j outside the panel
+    gemm_f64(nb, n - nb, (int)nb, 1.0, 0.0, Dkk, n, prow.p, n, D + o * n, n,
+             none, skip, s);
+    // trailing update with the old column panel and the new row panel
+    gemm_f64(n - nb, n - nb, (int)nb, -1.0, 1.0, pcol.p, nb, D + o * n, n, D,
+             n, skip, skip, s);
+    // column panel: D[i, o..] = -D[i, o..] Dkk^-1, i outside the panel
+    gemm_f64(n - nb, nb, (int)nb, -1.0, 0.0, pcol.p, nb, Dkk, n, D + o, n,
+             skip, none, s);
   }
+  FPC_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace fpc
