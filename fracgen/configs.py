@@ -21,16 +21,20 @@ from typing import List, Optional, Tuple
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from .problem import BlockSystem, Fracture, build_system, assemble_T
+from .problem import (APERTURE_REF, BlockSystem, Fracture, assemble_T,
+                      build_system)
 
 CONFIGS = ("c1", "c2", "c3", "c4", "c5")
+# with open faces (eq. Q2vsQ1): the c1 and c2 meshes with part of the faces
+# open; not among the five workloads above
+OPEN_CONFIGS = ("c1o", "c2o")
 TRANS_MEDIAN_SI = 1e-10     # m^3 / (Pa s)
 PA_PER_MPA = 1e6
 
 
 def _streams(seed: int):
     ss = np.random.SeedSequence(seed)
-    names = ("E", "upsilon", "state", "slipdir", "frac", "rhs", "obs")
+    names = ("E", "upsilon", "state", "slipdir", "frac", "rhs", "obs", "open")
     return {n: np.random.Generator(np.random.PCG64(s))
             for n, s in zip(names, ss.spawn(len(names)))}
 
@@ -109,12 +113,24 @@ def make_config(name: str, seed: int = 0) -> BlockSystem:
         fr = [Fracture(0, i, 0, 48, 0, 48) for i in (10, 19, 29, 38)]
         E = _lognormal_E(rs["E"], 48 ** 3)
         slip_p = 0.0
+    elif name == "c1o":
+        shape, h = (10, 10, 10), 0.1
+        fr = [Fracture(0, 5, 0, 10, 0, 10)]
+        E = _lognormal_E(rs["E"], 1000)
+        return _finish(name, shape, h, fr, E, 0.2, rs, seed, open_p=0.3)
+    elif name == "c2o":
+        shape, h = (80, 80, 80), 1.0 / 80
+        fr = [Fracture(0, 40, 0, 80, 0, 80), Fracture(1, 40, 0, 80, 0, 80),
+              Fracture(2, 40, 0, 80, 0, 80)]
+        E = _lognormal_E(rs["E"], 80 ** 3)
+        return _finish(name, shape, h, fr, E, 0.3, rs, seed, open_p=0.1)
     else:
         raise KeyError(name)
     return _finish(name, shape, h, fr, E, slip_p, rs, seed)
 
 
-def _finish(name, shape, h, fr, E, slip_p, rs, seed, top_load=True):
+def _finish(name, shape, h, fr, E, slip_p, rs, seed, top_load=True,
+            open_p=0.0):
     n_p = sum(f.nfaces for f in fr)
     # median 1e-10 m^3/(Pa s) in SI, expressed in the MPa unit system of the
     # mechanics (E in MPa): 1e-10 m^3/(Pa s) = 1e-4 m^3/(MPa s)
@@ -123,8 +139,15 @@ def _finish(name, shape, h, fr, E, slip_p, rs, seed, top_load=True):
     state = (rs["state"].random(n_p) < slip_p).astype(np.int64)
     ang = rs["slipdir"].uniform(0.0, 2 * np.pi, n_p)
     q = rs["rhs"].standard_normal(n_p)
+    aperture = None
+    if open_p > 0:
+        # Bernoulli(open_p) open faces (overriding slip), openings
+        # U[0.5, 1.5] x APERTURE_REF
+        state[rs["open"].random(n_p) < open_p] = 2
+        aperture = APERTURE_REF * rs["open"].uniform(0.5, 1.5, n_p)
     s = build_system(shape, h, fr, E, ups, face_state=state, slip_angle=ang,
-                     q=q, name=name, seed=seed, top_load=top_load)
+                     q=q, name=name, seed=seed, top_load=top_load,
+                     aperture=aperture)
     s.extras["rng_obs"] = rs["obs"]
     s.extras["rng_rhs"] = rs["rhs"]
     return s
@@ -132,7 +155,7 @@ def _finish(name, shape, h, fr, E, slip_p, rs, seed, top_load=True):
 
 def tiny_system(shape=(3, 3, 3), fractures: Optional[List[Fracture]] = None,
                 slip_p: float = 0.0, seed: int = 0, uniform_E: bool = False,
-                name: str = "tiny") -> BlockSystem:
+                name: str = "tiny", open_p: float = 0.0) -> BlockSystem:
     """A small system for exact / brute-force checks (unit cube)."""
     rs = _streams(seed)
     n = int(np.prod(shape))
@@ -140,7 +163,8 @@ def tiny_system(shape=(3, 3, 3), fractures: Optional[List[Fracture]] = None,
     if fractures is None:
         fractures = [Fracture(0, shape[0] // 2, 0, shape[1], 0, shape[2])]
     E = np.full(n, 1e4) if uniform_E else _lognormal_E(rs["E"], n)
-    return _finish(name, shape, h, fractures, E, slip_p, rs, seed)
+    return _finish(name, shape, h, fractures, E, slip_p, rs, seed,
+                   open_p=open_p)
 
 
 def rhs_batch(s: BlockSystem, k: int = 32) -> np.ndarray:

@@ -12,7 +12,8 @@ blocks are those of eq. block_def:
 * ``C2`` -- ``C1^T`` on stick faces, the linearised Coulomb rows on slip faces,
 * ``H``  -- the jump stabilization ``j_t`` (eq. jump_bilinear_form) plus the
   slip terms,
-* ``Q2`` -- empty (no open faces),
+* ``Q2`` -- ``-Psi(Q1^T)/dt + F_u`` on open faces and their neighbours
+  (empty without open faces),
 * ``T``  -- the TPFA transmissibility (eq. FV_inner_product) plus
   ``j_p / dt``.
 
@@ -36,6 +37,8 @@ POISSON = 0.25
 SIGMA0 = 10.0
 # Scaling of the isotropic stabilization tensor Upsilon^(e) = GAMMA h^3/E I.
 GAMMA_STAB = 0.25
+APERTURE_REF = 1e-3      # m, opening of open faces when none is given
+P_STATE = 0.01           # MPa, amplitude of the linearisation pressure
 
 
 @dataclass
@@ -228,14 +231,16 @@ def build_system(shape: Sequence[int], h: float, fractures: List[Fracture],
                  face_state: Optional[np.ndarray] = None,
                  slip_angle: Optional[np.ndarray] = None,
                  q: Optional[np.ndarray] = None, name: str = "custom",
-                 seed: int = 0, top_load: bool = True) -> BlockSystem:
+                 seed: int = 0, top_load: bool = True,
+                 aperture: Optional[np.ndarray] = None) -> BlockSystem:
     """Assemble the block system on an ``nx x ny x nz`` grid of cubes.
 
     ``E`` holds one Young modulus per cell (cell id ``i + nx (j + ny k)``),
     ``upsilon`` one transmissibility per fracture face, ``face_state`` 0
-    (stick) or 1 (slip) per face, ``slip_angle`` the angle of the slip
-    direction in the (T1, T2) plane and ``q`` the pressure source (``b_p =
-    q / |q|``).
+    (stick), 1 (slip) or 2 (open) per face, ``slip_angle`` the angle of the
+    slip direction in the (T1, T2) plane, ``q`` the pressure source (``b_p =
+    q / |q|``) and ``aperture`` the current normal opening of every face
+    (used on open faces only; default ``APERTURE_REF``).
     """
     g = _Grid(shape, h)
     nx, ny, nz = (int(v) for v in g.n)
@@ -434,16 +439,35 @@ def build_system(shape: Sequence[int], h: float, fractures: List[Fracture],
     # ---------------- states, H and C2 --------------------------------------
     if face_state is None:
         face_state = np.zeros(n_p, np.int64)
-    face_state = np.asarray(face_state, np.int64)
+    face_state = np.asarray(face_state, np.int64).copy()
+    if (face_state == 2).any():
+        # a stick / slip face none of whose coplanar neighbours is closed has
+        # no edge for j_t: its block of Bdiag(H, 3) would vanish; such an
+        # island inside an open region is taken as open
+        closed = face_state != 2
+        n_closed = (np.bincount(K_, closed[L_], n_p)
+                    + np.bincount(L_, closed[K_], n_p))
+        face_state[closed & (n_closed == 0)] = 2
     if slip_angle is None:
         slip_angle = np.zeros(n_p)
     slip_dir = np.stack([np.cos(slip_angle), np.sin(slip_angle)], axis=1)
 
+    is_open = face_state == 2
+    # j_t acts on edges between stick / slip faces only (eq. Hdef)
+    closed_edge = ~is_open[K_] & ~is_open[L_]
+    Kc, Lc, wc = K_[closed_edge], L_[closed_edge], stab_w[closed_edge]
     hr, hc, hv = [], [], []
     for ld in range(3):
-        hr += [3 * K_ + ld, 3 * L_ + ld, 3 * K_ + ld, 3 * L_ + ld]
-        hc += [3 * K_ + ld, 3 * L_ + ld, 3 * L_ + ld, 3 * K_ + ld]
-        hv += [stab_w, stab_w, -stab_w, -stab_w]
+        hr += [3 * Kc + ld, 3 * Lc + ld, 3 * Kc + ld, 3 * Lc + ld]
+        hc += [3 * Kc + ld, 3 * Lc + ld, 3 * Lc + ld, 3 * Kc + ld]
+        hv += [wc, wc, -wc, -wc]
+    opn = np.flatnonzero(is_open)
+    if opn.size:
+        # -(1/k)(mu_i, mu_j) on open faces: -|K|/k_K = -2 s_K, all components
+        for ld in range(3):
+            hr.append(3 * opn + ld)
+            hc.append(3 * opn + ld)
+            hv.append(-2.0 * s_face[opn])
     slip = np.flatnonzero(face_state == 1)
     if slip.size:
         # (1/k) terms with k_K = |K| / (2 s_K): -2 s_K on TT and
@@ -477,6 +501,11 @@ def build_system(shape: Sequence[int], h: float, fractures: List[Fracture],
         C2 = Mrow @ C1T
     else:
         C2 = C1T
+    if opn.size:
+        # no traction-jump coupling on open faces (eq. C2def)
+        keep_rows = np.ones(n_t)
+        keep_rows[np.concatenate([3 * opn, 3 * opn + 1, 3 * opn + 2])] = 0.0
+        C2 = sp.diags(keep_rows) @ C2
     C2 = _canon(C2)
 
     # ---------------- T: TPFA + j_p/dt + Dirichlet -------------------------
@@ -522,6 +551,20 @@ def build_system(shape: Sequence[int], h: float, fractures: List[Fracture],
     upsilon = np.asarray(upsilon, np.float64)
     assert upsilon.shape == (n_p,)
 
+    # ---------------- open faces: Q2 (eq. Q2def, eq. Q2vsQ1) ----------------
+    if aperture is None:
+        aperture = np.full(n_p, APERTURE_REF)
+    aperture = np.asarray(aperture, np.float64)
+    centre = np.zeros((n_p, 3))
+    for a in range(3):
+        m = face_axis == a
+        centre[m, a] = face_plane[m] * g.h
+        centre[m, (a + 1) % 3] = (face_ib[m] + 0.5) * g.h
+        centre[m, (a + 2) % 3] = (face_ic[m] + 0.5) * g.h
+    p_state = pressure_state(centre)
+    Q2 = open_face_q2(Q1, face_state, upsilon, aperture, p_state, flow_pairs,
+                      flow_ndir, g.h * g.h)
+
     # ---------------- right-hand side ---------------------------------------
     b = np.zeros(n_u + n_t + n_p)
     if top_load:
@@ -538,7 +581,7 @@ def build_system(shape: Sequence[int], h: float, fractures: List[Fracture],
     sysm = BlockSystem(
         name=name, shape=tuple(int(v) for v in g.n), h=g.h, n_u=n_u, n_t=n_t,
         n_p=n_p, A=_canon(A), C1=_canon(C1), Q1=Q1, C2=C2, H=_canon(H),
-        Q2=_canon(sp.csr_matrix((n_p, n_u))), T=None, b=b, coords=coords,
+        Q2=Q2, T=None, b=b, coords=coords,
         dirichlet=dirichlet, n_nodes_orig=n_nodes0, fractures=list(fractures),
         face_frac=face_frac, face_axis=face_axis,
         face_cells=np.stack([minus_cell, plus_cell], axis=1),
@@ -547,6 +590,9 @@ def build_system(shape: Sequence[int], h: float, fractures: List[Fracture],
         stab_pairs=stab_pairs, stab_weight=stab_w, T_stab=T_stab, seed=seed)
     sysm.T = assemble_T(sysm, upsilon)
     sysm.extras["conn"] = conn
+    sysm.extras["aperture"] = aperture
+    sysm.extras["p_state"] = p_state
+    sysm.extras["face_centre"] = centre
     sysm.extras["orig_of_node"] = orig_of_node
     return sysm
 
@@ -557,6 +603,52 @@ def _laplacian(pairs, w, n):
     c = np.concatenate([K, L, L, K])
     v = np.concatenate([w, w, -w, -w])
     return _canon(_csr(r, c, v, (n, n)))
+
+
+def pressure_state(centre: np.ndarray) -> np.ndarray:
+    """The current fracture pressure the Newton step linearises about (a
+    smooth synthetic field, amplitude ``P_STATE``), per face centre."""
+    x, y, z = centre[:, 0], centre[:, 1], centre[:, 2]
+    return P_STATE * (np.cos(2 * np.pi * x) * np.cos(2 * np.pi * y)
+                      * np.cos(2 * np.pi * z))
+
+
+def open_face_q2(Q1, face_state, upsilon, aperture, p_state, flow_pairs,
+                 flow_ndir, area) -> sp.csr_matrix:
+    """``Q2 = -Psi(Q1^T)/dt + F_u`` (eq. Q2vsQ1).
+
+    The storage term of an open face K, ``|K| g_K / dt`` with the
+    face-averaged opening ``g_K = -(Q1^T u)_K / |K|``, gives ``-Q1^T/dt`` on
+    the open rows.  ``F_u`` is the derivative of the TPFA fluxes
+    (eq. FV_inner_product) at the pressure state ``p_state`` through the
+    cubic law ``Upsilon_K ~ g_K^3`` on open faces: ``dUpsilon_K / dg_K =
+    3 Upsilon_K / g_K``, chained through the harmonic average.  Rows of
+    faces without an open neighbour and without opening are empty.
+    """
+    n_p = face_state.size
+    n_u = Q1.shape[0]
+    is_open = face_state == 2
+    if not is_open.any():
+        return _canon(sp.csr_matrix((n_p, n_u)))
+    Q1T = sp.csr_matrix(Q1.T)
+    G = -Q1T / area                               # row K: d g_K / d u
+    dU = np.where(is_open, 3.0 * upsilon / aperture, 0.0)
+    K, L = flow_pairs[:, 0], flow_pairs[:, 1]
+    uK, uL = upsilon[K], upsilon[L]
+    den = (uK + uL) ** 2
+    cK = 2.0 * uL * uL / den * dU[K]             # d U_KL / d g_K
+    cL = 2.0 * uK * uK / den * dU[L]             # d U_KL / d g_L
+    dp = p_state[L] - p_state[K]
+    # flux row K: -U_KL (p_L - p_K); row L: +U_KL (p_L - p_K); Dirichlet
+    # edges: n_dir U_K p_K
+    rows = np.concatenate([K, K, L, L, np.arange(n_p)])
+    cols = np.concatenate([K, L, K, L, np.arange(n_p)])
+    vals = np.concatenate([-dp * cK, -dp * cL, dp * cK, dp * cL,
+                           flow_ndir * p_state * dU])
+    W = sp.csr_matrix((vals, (rows, cols)), shape=(n_p, n_p))
+    W.eliminate_zeros()
+    storage = sp.diags(np.where(is_open, -1.0 / DT, 0.0)) @ Q1T
+    return _canon(sp.csr_matrix(storage + W @ G))
 
 
 def transmissibility_pairs(upsilon: np.ndarray, pairs: np.ndarray):

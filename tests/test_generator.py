@@ -181,3 +181,56 @@ def test_slip_blocks():
     for K in range(s.n_p):
         blk = H[3 * K:3 * K + 3, 3 * K:3 * K + 3]
         assert abs(np.linalg.det(blk)) > 0
+
+
+def _open_residual(s, u):
+    """Pressure residual of the open-face model at displacement u: storage
+    |K| g_K / dt on open faces plus the TPFA fluxes T(Upsilon(g)) p at the
+    linearisation pressure, with g_K = g0_K - (Q1^T u)_K / |K| and the cubic
+    law Upsilon_K = Upsilon0_K (g_K / g0_K)^3 on open faces."""
+    from fracgen.problem import assemble_T, DT
+    area = s.h * s.h
+    g0 = s.extras["aperture"]
+    opn = s.face_state == 2
+    g = g0 - (s.Q1.T @ u) / area
+    ups = np.where(opn, s.upsilon * (g / g0) ** 3, s.upsilon)
+    storage = np.where(opn, area * g / DT, 0.0)
+    return storage + assemble_T(s, ups) @ s.extras["p_state"]
+
+
+@pytest.mark.parametrize("name", ["tiny_open", "c1o"])
+def test_open_face_q2_is_the_residual_derivative(name):
+    """Q2 (eq. Q2def / Q2vsQ1) against central differences of the pressure
+    residual along random displacement directions."""
+    if name == "tiny_open":
+        s = fracgen.tiny_system((4, 4, 4), slip_p=0.3, open_p=0.4, seed=3)
+    else:
+        s = fracgen.make_config(name)
+    assert (s.face_state == 2).any() and s.Q2.nnz > 0
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        v = rng.standard_normal(s.n_u)
+        v[s.dirichlet] = 0.0
+        eps = 1e-7
+        fd = (_open_residual(s, eps * v) - _open_residual(s, -eps * v)) / (2 * eps)
+        q2v = s.Q2 @ v
+        assert np.linalg.norm(fd - q2v) <= 1e-7 * np.linalg.norm(q2v)
+
+
+def test_open_faces_decouple_the_traction_rows():
+    """Open faces: C2 rows vanish, H is -|K|/k I per face with no edge
+    stabilization, and stick / slip faces keep their rows."""
+    s = fracgen.make_config("c1o")
+    opn = np.flatnonzero(s.face_state == 2)
+    rows = np.concatenate([3 * opn, 3 * opn + 1, 3 * opn + 2])
+    assert np.abs(s.C2[rows]).sum() == 0.0
+    H = s.H.tocsr()
+    for K in opn:
+        blk = H[3 * K:3 * K + 3].toarray()
+        diag = blk[:, 3 * K:3 * K + 3]
+        assert np.allclose(diag, diag[0, 0] * np.eye(3)) and diag[0, 0] < 0
+        off = blk.copy()
+        off[:, 3 * K:3 * K + 3] = 0.0
+        assert not off.any()
+    closed = np.flatnonzero(s.face_state != 2)
+    assert np.abs(s.C2[3 * closed]).sum() > 0
