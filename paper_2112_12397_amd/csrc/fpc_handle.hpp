@@ -202,7 +202,9 @@ struct fpc_handle {
   fpc::PSolve ps;
   fpc::DevBuf<int> flags;
   // apply-path scratch (FP64)
-  fpc::DevBuf<double> t_t, tmp_u, tmp_u2, tmp_p, scratchN;
+  fpc::DevBuf<double> t_t, tmp_u, tmp_u2, tmp_p, tmp_p2, scratchN;
+  bool has_q2 = false;          // open faces: Q2 not empty
+  fpc::DevBuf<double> S_K;     // fixed-stress diagonal (t-u-p with Q2)
   fpc::Krylov kry1;            // single right-hand side
   fpc::Krylov kryB;            // batched
   fpc::KTimer ktimer;

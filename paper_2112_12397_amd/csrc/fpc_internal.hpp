@@ -207,6 +207,13 @@ int64_t bsr_count_nonzeros(const Bsr& a, hipStream_t s);
 void hinv_setup(const Csr& H, int64_t n_p, double* hinv, int* flags,
                 hipStream_t s);
 void bsr_block_row_scale(Bsr& b, const double* blocks3x3, hipStream_t s);
+// [S_K]_k = Q2[k, K] S1[K, K]^{-1} Q1[K, k], K = nz(Q1 col k) U nz(Q2 row k)
+// (eq. FS_algebraic); flags[FLAG_OVERFLOW] if |K| > 64.
+void fixed_stress(const Bsr& S1, const Csr& Q1T, const Csr& Q2, double* out,
+                  int* flags, hipStream_t s);
+// block row i of a one-row-block BSR times alpha / M[i][i]
+void bsr_row_scale_inv_diag(Bsr& b, const Csr& M, double alpha, int* flags,
+                            hipStream_t s);
 void bsr_dinv(const Bsr& a, double* dinv, int* flags, hipStream_t s);
 // MIS-2 aggregation on the block pattern; returns n_agg, fills agg.
 int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,

@@ -78,6 +78,16 @@ __global__ void k_scatter_T(const int64_t* rp, const int32_t* col,
     D[(int64_t)pos[i] * ld + pos[col[e]]] = val[e];
 }
 
+// S~2 = T - S_K: subtract the fixed-stress diagonal in the dense blocks
+__global__ void k_sub_diag(const double* sk, int64_t n, const int32_t* comp,
+                           const int32_t* pos, const int64_t* dense_off,
+                           const int64_t* pad, double* dense) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = comp[i];
+  dense[dense_off[c] + (int64_t)pos[i] * pad[c] + pos[i]] -= sk[i];
+}
+
 __global__ void k_pad_diag(double* D, int64_t n, int64_t ld) {
   int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ld) D[i * ld + i] = 1.0;
@@ -262,13 +272,21 @@ void build_psolve(fpc_handle* h) {
   k_scatter_T<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, T.val.p, n, comp.p, pos.p,
                                 ps.dense_off.p, ps.comp_pad_d.p, ps.dense.p);
   FPC_LAUNCH_CHECK();
+  // t-u-p with open faces: S~2 = T - FS(Q2, S1, Q1) (Alg 3.3), symmetric but
+  // possibly indefinite, so its elimination only checks for zero pivots
+  const bool fs = h->opt.mode == FPC_TUP && h->has_q2;
+  if (fs) {
+    k_sub_diag<<<g, 256, 0, s>>>(h->S_K.p, n, comp.p, pos.p, ps.dense_off.p,
+                                 ps.comp_pad_d.p, ps.dense.p);
+    FPC_LAUNCH_CHECK();
+  }
   for (int64_t c = 0; c < ps.n_comp; ++c) {
     double* D = ps.dense.p + ps.dense_off_h[c];
     const int64_t pad = ps.comp_pad[c];
     if (pad > ps.comp_n[c])
       k_pad_diag<<<grid_for(pad - ps.comp_n[c], 64), 64, 0, s>>>(D, ps.comp_n[c], pad);
     FPC_LAUNCH_CHECK();
-    gj_inverse(D, pad, /*spd=*/1, h->flags.p, s);
+    gj_inverse(D, pad, /*spd=*/fs ? 0 : 1, h->flags.p, s);
   }
   check_flags(h, "pressure block");
   // packed symmetric tiles for the single-vector apply
@@ -518,7 +536,36 @@ void apply_fwd(fpc_handle* h, const double* w, double* v) {
   const double *wu = w, *wt = w + nu, *wp = w + nu + nt;
   double *vu = v, *vt = v + nu, *vp = v + nu + nt;
   face_apply(h->hinv.p, wt, h->t_t.p, np, 0, s);            // t_t = H~^-1 w_t
-  if (h->opt.mode == FPC_TUP) {
+  if (h->has_q2 && h->opt.mode == FPC_TUP) {
+    // Alg 3.4 with open faces: t_p depends on s_u, the AMG calls of steps 3
+    // and 7 run one after the other
+    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+    double* su = h->tmp_u.p;
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, nullptr,
+                nullptr, 0.0, s);                            // t_u
+    vcycle<T, 1>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, su, 0, s);          // s_u
+    FPC_HIP(hipMemcpyAsync(h->tmp_p.p, wp, np * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    csr_spmv2(&h->Q2, su, -1.0, nullptr, nullptr, 0.0, h->tmp_p.p, 1.0, s);
+    psolve_apply(h->ps, h->tmp_p.p, vp, np, 0, s);          // v_p = S~2^-1 t_p
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, nullptr, &h->Q1, vp, 1.0, nullptr,
+                nullptr, 0.0, s);                            // Q1 v_p
+    vcycle<T, 1>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    axpby(1.0, su, -1.0, vu, nu, s);                        // v_u = s_u - AMG
+  } else if (h->has_q2) {
+    // Alg 3.2 with open faces: v_p = t_p - T^-1 Q2 v_u
+    psolve_apply(h->ps, wp, h->tmp_p.p, np, 0, s);          // t_p = T^-1 w_p
+    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, &h->Q1,
+                h->tmp_p.p, -1.0, s);
+    vcycle<T, 1>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    csr_spmv2(&h->Q2, vu, 1.0, nullptr, nullptr, 0.0, h->tmp_p2.p, 0.0, s);
+    psolve_apply(h->ps, h->tmp_p2.p, vp, np, 0, s);
+    axpby(1.0, h->tmp_p.p, -1.0, vp, np, s);
+  } else if (h->opt.mode == FPC_TUP) {
     // Alg 3.4 with Q2 = 0: t_p = w_p, so v_p = S~2^-1 w_p is known before the
     // first V-cycle and the two AMG calls (steps 3 and 7) run as one
     // two-column cycle on [w_u + C1 t_t, Q1 v_p].
@@ -555,14 +602,36 @@ void apply_adj(fpc_handle* h, const double* w, double* v) {
   // coincides when Q2 = 0.
   face_apply(h->hinv.p, wt, h->t_t.p, np, 1, s);
   CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+  if (h->has_q2 && h->opt.mode == FPC_TPU) {
+    // M1^{-T} (transposed factors of eq. P1): t_p = T^-T w_p; t_u = w_u +
+    // C2^T t_t - Q2^T t_p; v_u = AMG^T(t_u); v_p = t_p - T^-T Q1^T v_u
+    psolve_apply(h->ps, wp, h->tmp_p.p, np, 1, s);
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C2T, h->t_t.p, 1.0, &h->Q2T,
+                h->tmp_p.p, -1.0, s);
+    vcycle<T, 1>(h->amg, true, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    csr_spmv2(&h->Q1T, vu, 1.0, nullptr, nullptr, 0.0, h->tmp_p2.p, 0.0, s);
+    psolve_apply(h->ps, h->tmp_p2.p, vp, np, 1, s);
+    axpby(1.0, h->tmp_p.p, -1.0, vp, np, s);
+    tface(h->C1T, vu, h->t_t.p, h->hinv.p, vt, np, 1, s);
+    return;
+  }
   to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C2T, h->t_t.p, 1.0, nullptr,
               nullptr, 0.0, s);
   vcycle<T, 1>(h->amg, true, s);
-  from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+  from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);            // s_u
   FPC_HIP(hipMemcpyAsync(h->tmp_p.p, wp, np * sizeof(double),
                          hipMemcpyDeviceToDevice, s));
   csr_spmv2(&h->Q1T, vu, -1.0, nullptr, nullptr, 0.0, h->tmp_p.p, 1.0, s);
   psolve_apply(h->ps, h->tmp_p.p, vp, np, 1, s);
+  if (h->has_q2) {
+    // second transposed AMG call on Q2^T v_p
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, nullptr, &h->Q2T, vp, 1.0, nullptr,
+                nullptr, 0.0, s);
+    vcycle<T, 1>(h->amg, true, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, h->tmp_u.p, 0, s);
+    axpby(-1.0, h->tmp_u.p, 1.0, vu, nu, s);                // v_u = s_u - AMG^T
+  }
   tface(h->C1T, vu, h->t_t.p, h->hinv.p, vt, np, 1, s);
 }
 
@@ -803,6 +872,9 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
   hipStream_t s = h->stream;
   if (h->opt.mode != FPC_TUP)
     throw Error(FPC_ERR_UNSUPPORTED, "batched solve uses the t-u-p mode");
+  if (h->has_q2)
+    throw Error(FPC_ERR_UNSUPPORTED,
+                "batched solve needs Q2 = 0 (its two AMG calls share one cycle)");
   const int KB = k <= 8 ? 8 : 32;
   ensure_batch_ops(h);
   BatchWork& w = batch_work(h, KB);
@@ -1027,9 +1099,7 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     for (const Csr* m : {&h->A, &h->C1, &h->Q1, &h->C2, &h->H, &h->Q2, &h->T})
       csr_validate(*m, h->flags.p, s);
     check_flags(h, "input");
-    if (h->Q2.nnz > 0)
-      throw Error(FPC_ERR_UNSUPPORTED,
-                  "open fracture faces (non-empty Q2) are outside this build");
+    h->has_q2 = h->Q2.nnz > 0;
     const double t1 = now_s();
     // H~ = Bdiag(H, 3) and its inverse
     h->hinv.alloc(std::max<int64_t>(np * 9, 1));
@@ -1045,6 +1115,24 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     spgemm(C1b, Xb, CX, h->flags.p, s);
     bsr_add(h->Ab, CX, S1, s);
     check_flags(h, "S1 = A + C1 H~^-1 C2");
+    if (h->has_q2 && h->opt.mode == FPC_TUP) {
+      // Alg 3.3: [S_K]_k = Q2^(k)T S1^(k)^-1 Q1^(k)
+      Csr Q1T;
+      csr_transpose(h->Q1, Q1T, s);
+      h->S_K.alloc(std::max<int64_t>(np, 1));
+      fixed_stress(S1, Q1T, h->Q2, h->S_K.p, h->flags.p, s);
+      check_flags(h, "fixed stress FS(Q2, S1, Q1)");
+    } else if (h->has_q2) {
+      // Alg 3.1: S~ = S1 - Q1 T~^-1 Q2, T~ = diag(T)
+      Bsr Q1b, Q2b, QQ, St;
+      csr_to_bsr(h->Q1, 3, 1, Q1b, s);
+      csr_to_bsr(h->Q2, 1, 3, Q2b, s);
+      bsr_row_scale_inv_diag(Q2b, h->T, -1.0, h->flags.p, s);
+      spgemm(Q1b, Q2b, QQ, h->flags.p, s);
+      bsr_add(S1, QQ, St, s);
+      S1 = std::move(St);
+      check_flags(h, "S~ = S1 - Q1 T~^-1 Q2");
+    }
     bsr_to_sell(h->Ab, h->sAJ, s);
     const double t2 = now_s();
     build_psolve(h);
@@ -1053,10 +1141,14 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     const double t4 = now_s();
     h->t_t.alloc(std::max<int64_t>(nt, 1));
     h->tmp_p.alloc(std::max<int64_t>(np, 1));
+    if (h->has_q2) {
+      h->tmp_u.alloc(nu);
+      h->tmp_p2.alloc(std::max<int64_t>(np, 1));
+    }
     h->scratchN.alloc(h->N);
     // work vectors of the solve path, so that solves allocate nothing
     ensure_krylov(h, h->kry1, 1);
-    const int nvf = h->opt.mode == FPC_TUP ? 2 : 1;
+    const int nvf = h->opt.mode == FPC_TUP && !h->has_q2 ? 2 : 1;
     if (h->opt.precision == FPC_FP32_PREC) cycle_vecs<float>(h->amg, nvf);
     else cycle_vecs<double>(h->amg, nvf);
     FPC_HIP(hipStreamSynchronize(s));
@@ -1156,6 +1248,10 @@ fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
   if (!g || !lam_p || !p || !grad || g->n_p != h->n_p || g->n_pairs < 0)
     return FPC_ERR_ARG;
   return guard(h, [&] {
+    if (h->has_q2)
+      throw Error(FPC_ERR_UNSUPPORTED,
+                  "transmissibility gradient assumes Q2 = 0 (Q2 depends on "
+                  "the transmissibility on open faces)");
     hipStream_t s = h->stream;
     const int64_t m = g->n_pairs, n = g->n_p;
     Csr inc;

@@ -655,6 +655,155 @@ void gj_inverse64(double* D, int64_t n, int64_t ld, int spd, int* flags,
   }
 }
 
+// ------------------------------------------------------------- fixed stress
+constexpr int FS_KMAX = 64;
+
+// entry (r, c) of a 3 x 3 block matrix with sorted block columns
+__device__ inline double bsr3_get(const int64_t* rp, const int32_t* col,
+                                  const double* val, int64_t r, int64_t c) {
+  const int64_t br = r / 3, bc = c / 3;
+  int64_t lo = rp[br], hi = rp[br + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < bc) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < rp[br + 1] && col[lo] == bc) ? val[lo * 9 + (r % 3) * 3 + c % 3]
+                                             : 0.0;
+}
+
+// Algebraic fixed stress (eq. Ak, eq. FS_algebraic), one wavefront per face
+// k: K = nz(Q1 column k) U nz(Q2 row k) (scalar dofs), S1^(k) = S1[K, K],
+// [S_K]_k = Q2[k, K] S1^(k)^{-1} Q1[K, k]; faces with an empty Q2 row give 0.
+// The dense solve is Gaussian elimination with partial pivoting in LDS.
+__global__ __launch_bounds__(64) void k_fixed_stress(
+    const int64_t* __restrict__ srp, const int32_t* __restrict__ scol,
+    const double* __restrict__ sval, const int64_t* __restrict__ arp,
+    const int32_t* __restrict__ acol, const double* __restrict__ aval,
+    const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
+    const double* __restrict__ bval, int64_t n_p, double* __restrict__ out,
+    int* flags) {
+  __shared__ double Sk[FS_KMAX][FS_KMAX + 1];
+  __shared__ double q1[FS_KMAX], q2[FS_KMAX];
+  __shared__ int32_t idx[FS_KMAX];
+  __shared__ int nK, piv;
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (k >= n_p) return;
+  const int64_t b0 = brp[k], b1 = brp[k + 1];   // Q2 row k
+  if (b0 == b1) {
+    if (lane == 0) out[k] = 0.0;
+    return;
+  }
+  if (lane == 0) {
+    const int64_t a0 = arp[k], a1 = arp[k + 1];  // Q1^T row k = Q1 column k
+    int n = 0;
+    int64_t i = a0, j = b0;
+    bool over = false;
+    while (i < a1 || j < b1) {
+      int32_t c;
+      double v1 = 0.0, v2 = 0.0;
+      if (j >= b1 || (i < a1 && acol[i] < bcol[j])) {
+        c = acol[i];
+        v1 = aval[i++];
+      } else if (i >= a1 || bcol[j] < acol[i]) {
+        c = bcol[j];
+        v2 = bval[j++];
+      } else {
+        c = acol[i];
+        v1 = aval[i++];
+        v2 = bval[j++];
+      }
+      if (n == FS_KMAX) {
+        over = true;
+        break;
+      }
+      idx[n] = c;
+      q1[n] = v1;
+      q2[n] = v2;
+      ++n;
+    }
+    nK = over ? -1 : n;
+  }
+  __syncthreads();
+  const int n = nK;
+  if (n < 0) {
+    if (lane == 0) {
+      atomicOr(&flags[FLAG_OVERFLOW], 1);
+      out[k] = 0.0;
+    }
+    return;
+  }
+  for (int e = lane; e < n * n; e += 64) {
+    const int r = e / n, c = e % n;
+    Sk[r][c] = bsr3_get(srp, scol, sval, idx[r], idx[c]);
+  }
+  __syncthreads();
+  for (int c = 0; c < n; ++c) {
+    if (lane == 0) {
+      int p = c;
+      double best = fabs(Sk[c][c]);
+      for (int r = c + 1; r < n; ++r)
+        if (fabs(Sk[r][c]) > best) {
+          best = fabs(Sk[r][c]);
+          p = r;
+        }
+      piv = p;
+      if (!(best > 0.0) || !isfinite(best)) atomicOr(&flags[FLAG_SINGULAR], 1);
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != c) {
+      for (int j = lane; j < n; j += 64) {
+        const double t = Sk[c][j];
+        Sk[c][j] = Sk[p][j];
+        Sk[p][j] = t;
+      }
+      if (lane == 0) {
+        const double t = q1[c];
+        q1[c] = q1[p];
+        q1[p] = t;
+      }
+    }
+    __syncthreads();
+    const double d = Sk[c][c] != 0.0 ? Sk[c][c] : 1.0;
+    for (int r = c + 1 + lane; r < n; r += 64) {
+      const double f = Sk[r][c] / d;
+      for (int j = c + 1; j < n; ++j) Sk[r][j] -= f * Sk[c][j];
+      q1[r] -= f * q1[c];
+    }
+    __syncthreads();
+  }
+  if (lane == 0) {
+    for (int r = n - 1; r >= 0; --r) {
+      double t = q1[r];
+      for (int j = r + 1; j < n; ++j) t -= Sk[r][j] * q1[j];
+      q1[r] = t / (Sk[r][r] != 0.0 ? Sk[r][r] : 1.0);
+    }
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += q2[i] * q1[i];
+    out[k] = acc;
+  }
+}
+
+// Block row i of a BSR with one-row blocks times alpha / M[i][i] (M a
+// square CSR): -T~^{-1} Q2 with T~ = diag(T) for the t-p-u surrogate.
+__global__ void k_row_scale_inv_diag(const int64_t* rp, double* val,
+                                     int64_t nbr, int bc,
+                                     const int64_t* mrp, const int32_t* mcol,
+                                     const double* mval, double alpha,
+                                     int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbr) return;
+  double d = csr_get(mrp, mcol, mval, i, (int32_t)i);
+  if (!(d != 0.0) || !isfinite(d)) {
+    atomicOr(&flags[FLAG_SINGULAR], 1);
+    d = 1.0;
+  }
+  const double f = alpha / d;
+  for (int64_t e = rp[i] * bc; e < rp[i + 1] * bc; ++e) val[e] *= f;
+}
+
 }  // namespace
 
 void hinv_setup(const Csr& H, int64_t n_p, double* hinv, int* flags,
@@ -855,6 +1004,26 @@ void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
              skip, none, s);
   }
   FPC_HIP(hipStreamSynchronize(s));
+}
+
+void fixed_stress(const Bsr& S1, const Csr& Q1T, const Csr& Q2, double* out,
+                  int* flags, hipStream_t s) {
+  if (S1.br != 3 || S1.bc != 3) throw Error(FPC_ERR_ARG, "fixed_stress: S1 blocks");
+  if (Q2.nrows == 0) return;
+  k_fixed_stress<<<(unsigned)Q2.nrows, 64, 0, s>>>(
+      S1.rowptr.p, S1.col.p, S1.val.p, Q1T.rowptr.p, Q1T.col.p, Q1T.val.p,
+      Q2.rowptr.p, Q2.col.p, Q2.val.p, Q2.nrows, out, flags);
+  FPC_LAUNCH_CHECK();
+}
+
+void bsr_row_scale_inv_diag(Bsr& b, const Csr& M, double alpha, int* flags,
+                            hipStream_t s) {
+  if (b.br != 1 || M.nrows != b.nbr) throw Error(FPC_ERR_ARG, "row scaling shape");
+  if (!b.nbr) return;
+  k_row_scale_inv_diag<<<grid_for(b.nbr, 128), 128, 0, s>>>(
+      b.rowptr.p, b.val.p, b.nbr, b.bc, M.rowptr.p, M.col.p, M.val.p, alpha,
+      flags);
+  FPC_LAUNCH_CHECK();
 }
 
 }  // namespace fpc

@@ -36,6 +36,13 @@ def _cases():
             (7, 6, 5), [Fracture(2, 2, 1, 6, 1, 5), Fracture(0, 4, 0, 2, 0, 3)],
             slip_p=0.5, seed=3), 90),
         "c1": (lambda: fracgen.make_config("c1"), 2000),
+        # open faces: Q2 = -Psi(Q1^T)/dt + F_u (eq. Q2vsQ1)
+        "tiny_open": (lambda: tiny_system((4, 4, 4), slip_p=0.3, open_p=0.4,
+                                          seed=3), 40),
+        "tiny_open_cross": (lambda: tiny_system(
+            (5, 5, 5), [Fracture(0, 2, 0, 5, 0, 5), Fracture(1, 3, 0, 5, 0, 5)],
+            slip_p=0.2, open_p=0.3, seed=5), 60),
+        "c1o": (lambda: fracgen.make_config("c1o"), 2000),
     }
 
 
@@ -79,11 +86,24 @@ def _bsr_to_csr(rp, col, blocks, nrows, ncols_nodes):
 
 
 NAMES = list(_cases().keys())
+OPEN_NAMES = ["tiny_open", "tiny_open_cross", "c1o"]
 
 
 @pytest.mark.parametrize("name", NAMES)
 def test_hierarchy_parity(torch, name):
-    s, pc, sol = _get(name)
+    _check_hierarchy(*_get(name))
+
+
+@pytest.mark.parametrize("name", OPEN_NAMES)
+def test_hierarchy_parity_tpu_open(torch, name):
+    """t-p-u with open faces: the AMG is built on S~ = S1 - Q1 T~^{-1} Q2
+    (Alg 3.1), whose node pattern gains the Q1 Q2 couplings."""
+    s, pc, sol = _get(name, "tpu")
+    assert s.Q2.nnz > 0
+    _check_hierarchy(s, pc, sol)
+
+
+def _check_hierarchy(s, pc, sol):
     H = pc.amg
     assert sol.num_levels() == H.n_levels
     ranks_prev = None
@@ -160,7 +180,24 @@ def test_matvec(torch, name):
 
 @pytest.mark.parametrize("name", NAMES)
 def test_solve(torch, name):
-    s, pc, sol = _get(name)
+    _check_solve(torch, *_get(name))
+
+
+@pytest.mark.parametrize("name", OPEN_NAMES)
+def test_solve_tpu_open(torch, name):
+    _check_solve(torch, *_get(name, "tpu"))
+
+
+@pytest.mark.parametrize("name", OPEN_NAMES)
+def test_apply_prec_T_tpu_open(torch, name):
+    s, pc, sol = _get(name, "tpu")
+    rng = np.random.default_rng(16)
+    w = rng.standard_normal(s.N)
+    v = sol.apply_prec_T(torch.tensor(w, device="cuda")).cpu().numpy()
+    assert _rel(v, pc.apply_T(w)) <= TOL
+
+
+def _check_solve(torch, s, pc, sol):
     x, info = sol.solve(torch.tensor(s.b, device="cuda"))
     xo, io = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8, ortho="cgs2")
     assert info["converged"] == 1 and info["status"] == "FPC_OK"
@@ -264,12 +301,20 @@ def test_error_paths(torch):
         from paper_2112_12397_amd import Solver
         Solver(bad, s.n_u, s.n_t, s.n_p)
     assert e.value.status == -3
-    # open faces (non-empty Q2) are outside this build
-    bad = s.blocks()
-    bad["Q2"] = sp.csr_matrix(s.Q1.T)
+    # open faces: batched solves (one shared two-column cycle) and the
+    # transmissibility gradient (Q2 depends on it) need Q2 = 0
+    so = tiny_system((4, 4, 4), slip_p=0.3, open_p=0.4, seed=3)
+    solo = solver_from_system(so)
+    Bo = torch.tensor(np.ascontiguousarray(np.stack([so.b, so.b])),
+                      device="cuda")
     with pytest.raises(FpcError) as e:
-        from paper_2112_12397_amd import Solver
-        Solver(bad, s.n_u, s.n_t, s.n_p)
+        solo.solve_batch(Bo)
+    assert e.value.status == -10
+    zp = torch.zeros(so.n_p, dtype=torch.float64, device="cuda")
+    with pytest.raises(FpcError) as e:
+        solo.grad_log_trans(torch.tensor(so.flow_pairs),
+                            torch.tensor(so.flow_ndir),
+                            torch.tensor(so.upsilon), zp, zp)
     assert e.value.status == -10
     # zero right-hand side gives x = 0 at once; NaN right-hand side rejected
     sol = solver_from_system(s)
