@@ -234,6 +234,27 @@ def forms(torch, s2, blocks2, coords2, b2, fp64_solve_s):
         "adjoint_s": ta, "adjoint_iterations": infa["iterations"],
         "gradient_s": tg}
     del sol, s5
+    # open faces (Q2 != 0): sequential AMG calls (t-u-p) or S~ (t-p-u)
+    so = fracgen.make_config("c2o")
+    bo = torch.tensor(so.b, device="cuda")
+    res = {"workload": "80^3 Q1 hex, three intersecting fractures, 30% slip, "
+                       "10% open faces (Q2 != 0)",
+           "faces_stick_slip_open": [int(c) for c in
+                                     np.bincount(so.face_state, minlength=3)],
+           "q2_nnz": int(so.Q2.nnz)}
+    for mode in ("tup", "tpu"):
+        t0 = time.perf_counter()
+        sol = solver_from_system(so, mode=mode)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        xo = torch.empty_like(bo)
+        sol.solve(bo, out=xo)
+        t, (_, inf) = _timed(torch, lambda: sol.solve(bo, out=xo), 2)
+        res[mode] = {"solve_s": t, "iterations": inf["iterations"],
+                     "true_rel_residual": inf["true_rel_residual"],
+                     "setup_s_incl_upload": ts}
+        del sol
+    out["open_faces_80cube"] = res
     return out
 
 
