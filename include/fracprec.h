@@ -57,7 +57,10 @@ typedef enum {
 } fpc_status;
 
 enum { FPC_HOST = 0, FPC_DEVICE = 1 };
-enum { FPC_TUP = 0, FPC_TPU = 1 };
+/* Preconditioner: t-u-p M2 (Alg 3.3 / 3.4), t-p-u M1 (Alg 3.1 / 3.2), or
+ * M2* = D2^{-1} L2^{-1} of eq. LDU2 (the incomplete factorization of the
+ * remark after Prop 3.2: one AMG call per application). */
+enum { FPC_TUP = 0, FPC_TPU = 1, FPC_TUP_STAR = 2 };
 enum { FPC_FP64 = 0, FPC_FP32_PREC = 1 };
 
 /* Compressed sparse rows, 0-based, column indices strictly increasing in
@@ -95,7 +98,7 @@ typedef struct {
 } fpc_amg_options;
 
 typedef struct {
-  int mode;                /* FPC_TUP (default) or FPC_TPU                  */
+  int mode;                /* FPC_TUP (default), FPC_TPU or FPC_TUP_STAR    */
   int precision;           /* FPC_FP64 or FPC_FP32_PREC (FP32 hierarchy)    */
   int restart;             /* FGMRES restart length (50)                    */
   int maxit;               /* total iteration cap (1000)                    */

@@ -21,7 +21,7 @@ from .blocks import (bdiag_apply, bdiag_inv, fixed_stress, node_pattern,
 class BlockPrecond:
     def __init__(self, blocks, n_u, n_t, n_p, mode="tup", inner="amg",
                  coords=None, amg_opts=None):
-        if mode not in ("tup", "tpu"):
+        if mode not in ("tup", "tpu", "tup_star"):
             raise ValueError(mode)
         self.mode, self.inner_kind = mode, inner
         self.n_u, self.n_t, self.n_p = n_u, n_t, n_p
@@ -35,7 +35,7 @@ class BlockPrecond:
         # H~ = Bdiag(H, 3)
         self.Hinv = bdiag_inv(self.H, n_p)
         pattern = s1_node_pattern(self.A, self.C1, self.C2)
-        if mode == "tup":
+        if mode in ("tup", "tup_star"):
             # Alg 3.3: S1 = A + C1 H~^{-1} C2;  S~2 = T - FS(Q2, S1, Q1)
             self.K = schur1(self.A, self.C1, self.Hinv, self.C2)
             self.S_K = fixed_stress(self.K, self.Q1, self.Q2)
@@ -79,11 +79,13 @@ class BlockPrecond:
     # -- applications -------------------------------------------------------
     def apply(self, w):
         """v = M^{-1} w."""
-        return self._tup(w) if self.mode == "tup" else self._tpu(w)
+        return {"tup": self._tup, "tpu": self._tpu,
+                "tup_star": self._tup_star}[self.mode](w)
 
     def apply_T(self, w):
         """v = M^{-T} w."""
-        return self._tup_T(w) if self.mode == "tup" else self._tpu_T(w)
+        return {"tup": self._tup_T, "tpu": self._tpu_T,
+                "tup_star": self._tup_star_T}[self.mode](w)
 
     def _tup(self, w):
         """Alg 3.4 (app_tup)."""
@@ -114,6 +116,25 @@ class BlockPrecond:
         v_u = s_u - v_u
         s_t = self.C1T @ v_u
         v_t = -t_t + bdiag_apply(self.Hinv, s_t, transpose=True)
+        return np.concatenate([v_u, v_t, v_p])
+
+    def _tup_star(self, w):
+        """M2*^{-1} = D2^{-1} L2^{-1} of eq. LDU2 (the incomplete block
+        factorization of the remark after Prop 3.2), in the t-u-p order:
+        steps 1-5 of Alg 3.4 with v_u = s_u and v_t = -t_t."""
+        w_u, w_t, w_p = self.split(np.asarray(w, np.float64))
+        t_t = bdiag_apply(self.Hinv, w_t)
+        v_u = self.inner(w_u + self.C1 @ t_t)
+        v_p = self.psolve(w_p - self.Q2 @ v_u)
+        return np.concatenate([v_u, -t_t, v_p])
+
+    def _tup_star_T(self, w):
+        """M2*^{-T} = L2^{-T} D2^{-T}."""
+        w_u, w_t, w_p = self.split(np.asarray(w, np.float64))
+        v_p = self.psolve(w_p, transpose=True)
+        v_u = self.inner(w_u - self.Q2T @ v_p, transpose=True)
+        t_t = bdiag_apply(self.Hinv, w_t, transpose=True)
+        v_t = -t_t + bdiag_apply(self.Hinv, self.C1T @ v_u, transpose=True)
         return np.concatenate([v_u, v_t, v_p])
 
     def _tpu(self, w):

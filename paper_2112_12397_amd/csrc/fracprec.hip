@@ -274,7 +274,7 @@ void build_psolve(fpc_handle* h) {
   FPC_LAUNCH_CHECK();
   // t-u-p with open faces: S~2 = T - FS(Q2, S1, Q1) (Alg 3.3), symmetric but
   // possibly indefinite, so its elimination only checks for zero pivots
-  const bool fs = h->opt.mode == FPC_TUP && h->has_q2;
+  const bool fs = h->opt.mode != FPC_TPU && h->has_q2;
   if (fs) {
     k_sub_diag<<<g, 256, 0, s>>>(h->S_K.p, n, comp.p, pos.p, ps.dense_off.p,
                                  ps.comp_pad_d.p, ps.dense.p);
@@ -456,7 +456,7 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
   gj_inverse(H.Ainv.p, H.ncpad, /*spd=*/0, h->flags.p, s);
   check_flags(h, "coarsest level");
   // apply layouts, tuned for the column count of the preconditioner
-  const int nv = h->opt.mode == FPC_TUP ? 2 : 1;
+  const int nv = h->opt.mode == FPC_TUP && !h->has_q2 ? 2 : 1;
   for (Level& L : H.L) {
     if (L.coarsest) continue;
     L.sA = Sell<double>();
@@ -536,6 +536,25 @@ void apply_fwd(fpc_handle* h, const double* w, double* v) {
   const double *wu = w, *wt = w + nu, *wp = w + nu + nt;
   double *vu = v, *vt = v + nu, *vp = v + nu + nt;
   face_apply(h->hinv.p, wt, h->t_t.p, np, 0, s);            // t_t = H~^-1 w_t
+  if (h->opt.mode == FPC_TUP_STAR) {
+    // M2* = D2^-1 L2^-1 (eq. LDU2): steps 1-5 of Alg 3.4 with v_u = s_u,
+    // v_t = -t_t; one AMG call
+    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, nullptr,
+                nullptr, 0.0, s);
+    vcycle<T, 1>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);          // v_u
+    if (h->has_q2) {
+      FPC_HIP(hipMemcpyAsync(h->tmp_p.p, wp, np * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      csr_spmv2(&h->Q2, vu, -1.0, nullptr, nullptr, 0.0, h->tmp_p.p, 1.0, s);
+      psolve_apply(h->ps, h->tmp_p.p, vp, np, 0, s);
+    } else {
+      psolve_apply(h->ps, wp, vp, np, 0, s);
+    }
+    axpby(-1.0, h->t_t.p, 0.0, vt, nt, s);                  // v_t = -t_t
+    return;
+  }
   if (h->has_q2 && h->opt.mode == FPC_TUP) {
     // Alg 3.4 with open faces: t_p depends on s_u, the AMG calls of steps 3
     // and 7 run one after the other
@@ -602,6 +621,17 @@ void apply_adj(fpc_handle* h, const double* w, double* v) {
   // coincides when Q2 = 0.
   face_apply(h->hinv.p, wt, h->t_t.p, np, 1, s);
   CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+  if (h->opt.mode == FPC_TUP_STAR) {
+    // M2*^{-T} = L2^-T D2^-T: v_p = S~2^-T w_p; v_u = AMG^T(w_u - Q2^T v_p);
+    // v_t = -t_t + H~^-T C1^T v_u
+    psolve_apply(h->ps, wp, vp, np, 1, s);
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, h->has_q2 ? &h->Q2T : nullptr, vp,
+                -1.0, nullptr, nullptr, 0.0, s);
+    vcycle<T, 1>(h->amg, true, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    tface(h->C1T, vu, h->t_t.p, h->hinv.p, vt, np, 1, s);
+    return;
+  }
   if (h->has_q2 && h->opt.mode == FPC_TPU) {
     // M1^{-T} (transposed factors of eq. P1): t_p = T^-T w_p; t_u = w_u +
     // C2^T t_t - Q2^T t_p; v_u = AMG^T(t_u); v_p = t_p - T^-T Q1^T v_u
@@ -1041,7 +1071,7 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
   if (opt) h->opt = *opt;
   else fpc_default_options(&h->opt);
   const fpc_options& o = h->opt;
-  if ((o.mode != FPC_TUP && o.mode != FPC_TPU) ||
+  if ((o.mode != FPC_TUP && o.mode != FPC_TPU && o.mode != FPC_TUP_STAR) ||
       (o.precision != FPC_FP64 && o.precision != FPC_FP32_PREC) ||
       o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
@@ -1115,7 +1145,7 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     spgemm(C1b, Xb, CX, h->flags.p, s);
     bsr_add(h->Ab, CX, S1, s);
     check_flags(h, "S1 = A + C1 H~^-1 C2");
-    if (h->has_q2 && h->opt.mode == FPC_TUP) {
+    if (h->has_q2 && h->opt.mode != FPC_TPU) {
       // Alg 3.3: [S_K]_k = Q2^(k)T S1^(k)^-1 Q1^(k)
       Csr Q1T;
       csr_transpose(h->Q1, Q1T, s);

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfracprec.so")
 
 FPC_HOST, FPC_DEVICE = 0, 1
-FPC_TUP, FPC_TPU = 0, 1
+FPC_TUP, FPC_TPU, FPC_TUP_STAR = 0, 1, 2
 FPC_FP64, FPC_FP32_PREC = 0, 1
 
 STATUS = {0: "FPC_OK", 1: "FPC_NOT_CONVERGED", -1: "FPC_ERR_ARG",
@@ -154,7 +154,8 @@ def default_options(**kw) -> FpcOptions:
     amg = kw.pop("amg", None) or {}
     for k, v in kw.items():
         if k == "mode":
-            v = {"tup": FPC_TUP, "tpu": FPC_TPU}.get(v, v)
+            v = {"tup": FPC_TUP, "tpu": FPC_TPU,
+                 "tup_star": FPC_TUP_STAR}.get(v, v)
         if k == "precision":
             v = {"fp64": FPC_FP64, "fp32": FPC_FP32_PREC,
                  "fp32prec": FPC_FP32_PREC}.get(v, v)

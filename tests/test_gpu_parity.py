@@ -145,7 +145,7 @@ def test_vcycle_parity(torch, name):
 
 
 @pytest.mark.parametrize("name", NAMES)
-@pytest.mark.parametrize("mode", ["tup", "tpu"])
+@pytest.mark.parametrize("mode", ["tup", "tpu", "tup_star"])
 def test_apply_prec_parity(torch, name, mode):
     s, pc, sol = _get(name, mode)
     rng = np.random.default_rng(5)
@@ -195,6 +195,19 @@ def test_apply_prec_T_tpu_open(torch, name):
     w = rng.standard_normal(s.N)
     v = sol.apply_prec_T(torch.tensor(w, device="cuda")).cpu().numpy()
     assert _rel(v, pc.apply_T(w)) <= TOL
+
+
+@pytest.mark.parametrize("name", ["tiny_slip_cross", "c1", "tiny_open_cross",
+                                  "c1o"])
+def test_tup_star_transpose_and_solve(torch, name):
+    """M2* = D2^{-1} L2^{-1} (remark after Prop 3.2): transposed application
+    and FGMRES against the oracle."""
+    s, pc, sol = _get(name, "tup_star")
+    rng = np.random.default_rng(17)
+    w = rng.standard_normal(s.N)
+    v = sol.apply_prec_T(torch.tensor(w, device="cuda")).cpu().numpy()
+    assert _rel(v, pc.apply_T(w)) <= TOL
+    _check_solve(torch, s, pc, sol)
 
 
 def _check_solve(torch, s, pc, sol):

@@ -82,6 +82,32 @@ def test_tup_matches_inverse_of_ldu2():
     assert np.abs(MT - M.T).max() <= 1e-10 * np.abs(M).max()
 
 
+def test_tup_star_matches_inverse_of_l2d2():
+    """M2* (remark after Prop 3.2) is (L2 D2)^{-1} with the factors of
+    eq. LDU2, and its transposed application is the transpose."""
+    s, blocks = _system()
+    pc = _pc(s, blocks, "tup_star")
+    M = _explicit(pc.apply, s.N)
+    D = _dense_blocks(blocks)
+    Sinv = _explicit(pc.inner, s.n_u)
+    S1t = np.linalg.inv(Sinv)
+    Ht = np.linalg.inv(oracle.bdiag_matrix(pc.Hinv).toarray())
+    S2t = pc.S2t.toarray()
+    It, Iu, Ip = np.eye(s.n_t), np.eye(s.n_u), np.eye(s.n_p)
+    Z = np.zeros
+    L2 = np.block([[It, Z((s.n_t, s.n_u)), Z((s.n_t, s.n_p))],
+                   [-D["C1"] @ np.linalg.inv(Ht), Iu, Z((s.n_u, s.n_p))],
+                   [Z((s.n_p, s.n_t)), D["Q2"] @ Sinv, Ip]])
+    D2 = np.block([[-Ht, Z((s.n_t, s.n_u)), Z((s.n_t, s.n_p))],
+                   [Z((s.n_u, s.n_t)), S1t, Z((s.n_u, s.n_p))],
+                   [Z((s.n_p, s.n_t)), Z((s.n_p, s.n_u)), S2t]])
+    Q2p = _perm(s, "tup")
+    ref = Q2p.T @ np.linalg.inv(L2 @ D2) @ Q2p
+    assert np.abs(M - ref).max() <= 1e-8 * np.abs(ref).max()
+    MT = _explicit(pc.apply_T, s.N)
+    assert np.abs(MT - M.T).max() <= 1e-10 * np.abs(M).max()
+
+
 def test_tpu_matches_inverse_of_ldu1():
     s, blocks = _system()
     pc = _pc(s, blocks, "tpu")
