@@ -330,9 +330,9 @@ def main():
     levels = [sol.level_info(l) for l in range(sol.num_levels())]
     setup_parts = sol.setup_times()
 
-    # dominant kernel: level-0 residual SpMV of the two-column V-cycle
+    # dominant kernel: level-0 residual SpMV of the V-cycle (one column)
     d0 = levels[0]
-    nv = 2
+    nv = 1
     k_bytes = spmv_bytes(d0["nnz_scalar"], s.n_u, s.n_u, nv=nv, extra_vec=1)
     k_avg_s = kernel_ms / max(launches, 1) / 1e3
     achieved = k_bytes / k_avg_s / 1e9
@@ -389,7 +389,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 "
                                      "FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "level-0 residual SpMV (sliced-ELL 3x3 blocks, "
-                               "2 columns, FP64)",
+                               "1 column, FP64)",
                      "bytes_per_launch": k_bytes,
                      "avg_launch_us": k_avg_s * 1e6,
                      "launches": launches},

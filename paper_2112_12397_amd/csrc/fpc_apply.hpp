@@ -51,8 +51,9 @@ void csr_spmv2_b(const Csr* m1, const double* x1, double a1, const Csr* m2,
                  const double* x2, double a2, double* y, double beta, int KB,
                  hipStream_t s);
 template <typename T>
-void to_level_b(T* out, int sel, int KB, int64_t n, const double* base,
-                const Csr& M1, const double* x1, double a1, hipStream_t s);
+void to_level_b(T* out, int KB, int64_t n, const double* base,
+                const Csr& M1, const double* x1, double a1, const Csr& M2,
+                const double* x2, double a2, hipStream_t s);
 template <typename T>
 void from_level_b(const T* xo, int64_t n, int KB, double* vu, hipStream_t s);
 void tface_b(const Csr& C, const double* vu, const double* t_t,

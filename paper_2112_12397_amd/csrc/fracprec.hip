@@ -456,7 +456,7 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
   gj_inverse(H.Ainv.p, H.ncpad, /*spd=*/0, h->flags.p, s);
   check_flags(h, "coarsest level");
   // apply layouts, tuned for the column count of the preconditioner
-  const int nv = h->opt.mode == FPC_TUP && !h->has_q2 ? 2 : 1;
+  const int nv = 1;
   for (Level& L : H.L) {
     if (L.coarsest) continue;
     L.sA = Sell<double>();
@@ -584,20 +584,12 @@ void apply_fwd(fpc_handle* h, const double* w, double* v) {
     csr_spmv2(&h->Q2, vu, 1.0, nullptr, nullptr, 0.0, h->tmp_p2.p, 0.0, s);
     psolve_apply(h->ps, h->tmp_p2.p, vp, np, 0, s);
     axpby(1.0, h->tmp_p.p, -1.0, vp, np, s);
-  } else if (h->opt.mode == FPC_TUP) {
-    // Alg 3.4 with Q2 = 0: t_p = w_p, so v_p = S~2^-1 w_p is known before the
-    // first V-cycle and the two AMG calls (steps 3 and 7) run as one
-    // two-column cycle on [w_u + C1 t_t, Q1 v_p].
-    psolve_apply(h->ps, wp, vp, np, 0, s);
-    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 2);
-    to_level<T>(cv.lv[0].b.p, 2, 0, nu, wu, &h->C1, h->t_t.p, 1.0, nullptr,
-                nullptr, 0.0, s);
-    to_level<T>(cv.lv[0].b.p, 2, 1, nu, nullptr, &h->Q1, vp, 1.0, nullptr,
-                nullptr, 0.0, s);
-    vcycle<T, 2>(h->amg, false, s);
-    from_level<T>(cv.lv[0].xo.p, 2, nu, vu, 1, s);          // v_u = s_u - AMG(Q1 v_p)
   } else {
-    // Alg 3.2 with Q2 = 0: t_p = T^-1 w_p is also v_p.
+    // Q2 = 0.  Alg 3.4: t_p = w_p, so v_p = S~2^-1 w_p (S~2 = T) is known
+    // before the first AMG call, and since the V-cycle is a fixed linear
+    // operator the two calls of steps 3 and 7 combine into one:
+    // v_u = AMG(t_u) - AMG(Q1 v_p) = AMG(w_u + C1 t_t - Q1 v_p).
+    // Alg 3.2: t_p = T^-1 w_p is also v_p, and v_u is the same cycle.
     psolve_apply(h->ps, wp, vp, np, 0, s);
     CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
     to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, &h->Q1, vp,
@@ -863,20 +855,21 @@ void matvec_b(fpc_handle* h, const double* X, double* Y, int KB) {
   csr_spmv2_b(&h->Q2, Xu, 1.0, &h->T, Xp, 1.0, Yp, 0.0, KB, s);
 }
 
-// Alg 3.4 on KB right-hand sides at once (Q2 = 0: the two AMG calls of every
-// column run in one V-cycle over 2 KB interleaved columns).
+// Alg 3.4 on KB right-hand sides at once.  With Q2 = 0 the two AMG calls of a
+// column combine into one (the V-cycle is linear), so the cycle runs on KB
+// interleaved columns w_u + C1 t_t - Q1 v_p.
 template <typename T, int NV>
 void apply_fwd_b(fpc_handle* h, BatchWork& w, const double* W, double* V) {
   hipStream_t s = h->stream;
-  const int KB = NV / 2;
+  const int KB = NV;
   const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
   const double *Wu = W, *Wt = W + nu * KB, *Wp = W + (nu + nt) * KB;
   double *Vu = V, *Vt = V + nu * KB, *Vp = V + (nu + nt) * KB;
   face_apply_b(h->hinv.p, Wt, w.tt.p, np, KB, 0, s);
   psolve_apply_b(h->ps, Wp, Vp, np, KB, s);
   CycleVecs<T>& cv = cycle_vecs<T>(h->amg, NV);
-  to_level_b<T>(cv.lv[0].b.p, 0, KB, nu, Wu, h->C1, w.tt.p, 1.0, s);
-  to_level_b<T>(cv.lv[0].b.p, 1, KB, nu, nullptr, h->Q1, Vp, 1.0, s);
+  to_level_b<T>(cv.lv[0].b.p, KB, nu, Wu, h->C1, w.tt.p, 1.0, h->Q1, Vp, -1.0,
+                s);
   vcycle<T, NV>(h->amg, false, s);
   from_level_b<T>(cv.lv[0].xo.p, nu, KB, Vu, s);
   tface_b(h->C2, Vu, w.tt.p, h->hinv.p, Vt, np, KB, s);
@@ -885,11 +878,11 @@ void apply_fwd_b(fpc_handle* h, BatchWork& w, const double* W, double* V) {
 void apply_b(fpc_handle* h, BatchWork& w, const double* W, double* V) {
   const bool fp32 = h->opt.precision == FPC_FP32_PREC;
   if (w.KB == 8) {
-    if (fp32) apply_fwd_b<float, 16>(h, w, W, V);
-    else apply_fwd_b<double, 16>(h, w, W, V);
+    if (fp32) apply_fwd_b<float, 8>(h, w, W, V);
+    else apply_fwd_b<double, 8>(h, w, W, V);
   } else {
-    if (fp32) apply_fwd_b<float, 64>(h, w, W, V);
-    else apply_fwd_b<double, 64>(h, w, W, V);
+    if (fp32) apply_fwd_b<float, 32>(h, w, W, V);
+    else apply_fwd_b<double, 32>(h, w, W, V);
   }
 }
 
@@ -1178,9 +1171,8 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     h->scratchN.alloc(h->N);
     // work vectors of the solve path, so that solves allocate nothing
     ensure_krylov(h, h->kry1, 1);
-    const int nvf = h->opt.mode == FPC_TUP && !h->has_q2 ? 2 : 1;
-    if (h->opt.precision == FPC_FP32_PREC) cycle_vecs<float>(h->amg, nvf);
-    else cycle_vecs<double>(h->amg, nvf);
+    if (h->opt.precision == FPC_FP32_PREC) cycle_vecs<float>(h->amg, 1);
+    else cycle_vecs<double>(h->amg, 1);
     FPC_HIP(hipStreamSynchronize(s));
     h->ready = true;
     h->setup_times[0] = t4 - t0;

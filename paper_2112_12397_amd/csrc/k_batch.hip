@@ -69,10 +69,12 @@ __global__ void k_csr_spmv2_b(const int64_t* rp1, const int32_t* c1,
 // level-0 input of the two-column V-cycle per right-hand side:
 // out(i, 2c + sel) = (T)(base(i, c) + a1 (M1 x1)(i, c))
 template <typename T>
-__global__ void k_to_level_b(T* __restrict__ out, int sel, int KB,
+__global__ void k_to_level_b(T* __restrict__ out, int KB,
                              const double* __restrict__ base,
                              const int64_t* rp1, const int32_t* c1,
                              const double* v1, const double* x1, double a1,
+                             const int64_t* rp2, const int32_t* c2,
+                             const double* v2, const double* x2, double a2,
                              int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * KB) return;
@@ -83,7 +85,11 @@ __global__ void k_to_level_b(T* __restrict__ out, int sel, int KB,
   for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e)
     s += v1[e] * x1[(int64_t)c1[e] * KB + c];
   r += a1 * s;
-  out[i * (2 * KB) + 2 * c + sel] = (T)r;
+  s = 0.0;
+  for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e)
+    s += v2[e] * x2[(int64_t)c2[e] * KB + c];
+  r += a2 * s;
+  out[t] = (T)r;
 }
 
 template <typename T>
@@ -93,7 +99,7 @@ __global__ void k_from_level_b(const T* __restrict__ xo, int64_t n, int KB,
   if (t >= n * KB) return;
   const int64_t i = t / KB;
   const int c = (int)(t % KB);
-  vu[t] = (double)xo[i * (2 * KB) + 2 * c] - (double)xo[i * (2 * KB) + 2 * c + 1];
+  vu[t] = (double)xo[i * KB + c];
 }
 
 __global__ void k_tface_b(const int64_t* __restrict__ rp,
@@ -328,19 +334,21 @@ void csr_spmv2_b(const Csr* m1, const double* x1, double a1, const Csr* m2,
 }
 
 template <typename T>
-void to_level_b(T* out, int sel, int KB, int64_t n, const double* base,
-                const Csr& M1, const double* x1, double a1, hipStream_t s) {
+void to_level_b(T* out, int KB, int64_t n, const double* base,
+                const Csr& M1, const double* x1, double a1, const Csr& M2,
+                const double* x2, double a2, hipStream_t s) {
   if (!n) return;
   k_to_level_b<T><<<grid_for(n * KB, 256), 256, 0, s>>>(
-      out, sel, KB, base, M1.rowptr.p, M1.col.p, M1.val.p, x1, a1, n);
+      out, KB, base, M1.rowptr.p, M1.col.p, M1.val.p, x1, a1, M2.rowptr.p,
+      M2.col.p, M2.val.p, x2, a2, n);
   FPC_LAUNCH_CHECK();
 }
-template void to_level_b<double>(double*, int, int, int64_t, const double*,
-                                 const Csr&, const double*, double,
-                                 hipStream_t);
-template void to_level_b<float>(float*, int, int, int64_t, const double*,
-                                const Csr&, const double*, double,
-                                hipStream_t);
+template void to_level_b<double>(double*, int, int64_t, const double*,
+                                 const Csr&, const double*, double, const Csr&,
+                                 const double*, double, hipStream_t);
+template void to_level_b<float>(float*, int, int64_t, const double*,
+                                const Csr&, const double*, double, const Csr&,
+                                const double*, double, hipStream_t);
 
 template <typename T>
 void from_level_b(const T* xo, int64_t n, int KB, double* vu, hipStream_t s) {

@@ -436,7 +436,7 @@ void launch_vrow(const Vrow<T>& A, Load ld, Epi epi, hipStream_t s) {
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
-  if constexpr (NV >= 16) {
+  if constexpr (NV > 2) {
     // many columns: one thread per (row, column), sliced ELL only
     if (op.fmt != 0) throw Error(FPC_ERR_ARG, "batched operator layout");
     return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
@@ -709,7 +709,7 @@ const float* seldinv<float>(const Level& L) { return L.dinv32.p; }
 template <typename T, int BS, int NV>
 void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
                   int phase, KTimer* timer) {
-  const Op<T>& A = selA<T>(L, tr, NV >= 16);
+  const Op<T>& A = selA<T>(L, tr, NV > 2);
   const T* dinv = seldinv<T>(L);
   const T it = T(1.0 / L.theta), c1 = T(L.c1), c2 = T(L.c2);
   if (phase == 0) {
@@ -737,11 +737,11 @@ template <typename T, int BS, int NB, int NV>
 void restrict_level(const Level& L, const Level& Lc, LevelVecs<T>& v,
                     LevelVecs<T>& vc, hipStream_t s) {
   if (Lc.coarsest) {
-    launch_op<T, NB, BS, NV>(selR<T>(L, NV >= 16), LoadX<T, NV>{v.res.p},
+    launch_op<T, NB, BS, NV>(selR<T>(L, NV > 2), LoadX<T, NV>{v.res.p},
                                EpiStore<T, NV>{vc.b.p}, s);
   } else {
     launch_op<T, NB, BS, NV>(
-        selR<T>(L, NV >= 16), LoadX<T, NV>{v.res.p},
+        selR<T>(L, NV > 2), LoadX<T, NV>{v.res.p},
         EpiRestrict<T, NV>{vc.b.p, vc.d0.p, seldinv<T>(Lc),
                                T(1.0 / Lc.theta)},
         s);
@@ -751,7 +751,7 @@ void restrict_level(const Level& L, const Level& Lc, LevelVecs<T>& v,
 template <typename T, int BS, int NB, int NV>
 void prolong_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
                    hipStream_t s) {
-  launch_op<T, BS, NB, NV>(selP<T>(L, NV >= 16), LoadX<T, NV>{vc.xo.p},
+  launch_op<T, BS, NB, NV>(selP<T>(L, NV > 2), LoadX<T, NV>{vc.xo.p},
                              EpiAdd<T, NV>{v.x.p}, s);
 }
 
@@ -936,7 +936,7 @@ template CycleVecs<float>& cycle_vecs<float>(Hierarchy&, int);
 template <typename T, int NV>
 void vcycle(Hierarchy& H, bool transpose, hipStream_t s) {
   CycleVecs<T>& cv = cycle_vecs<T>(H, NV);
-  if (NV >= 16 && H.graphs && !transpose && !H.timer) {
+  if (NV > 2 && H.graphs && !transpose && !H.timer) {
     GraphCache& gc = *H.graphs;
     const int key = (int)sizeof(T) * 1000 + NV;
     hipGraphExec_t e = gc.find(key);
@@ -965,13 +965,11 @@ void vcycle(Hierarchy& H, bool transpose, hipStream_t s) {
   vcycle_rec<T, NV>(H, cv, 0, transpose, s);
 }
 template void vcycle<double, 1>(Hierarchy&, bool, hipStream_t);
-template void vcycle<double, 2>(Hierarchy&, bool, hipStream_t);
 template void vcycle<float, 1>(Hierarchy&, bool, hipStream_t);
-template void vcycle<float, 2>(Hierarchy&, bool, hipStream_t);
-template void vcycle<double, 16>(Hierarchy&, bool, hipStream_t);
-template void vcycle<double, 64>(Hierarchy&, bool, hipStream_t);
-template void vcycle<float, 16>(Hierarchy&, bool, hipStream_t);
-template void vcycle<float, 64>(Hierarchy&, bool, hipStream_t);
+template void vcycle<double, 8>(Hierarchy&, bool, hipStream_t);
+template void vcycle<double, 32>(Hierarchy&, bool, hipStream_t);
+template void vcycle<float, 8>(Hierarchy&, bool, hipStream_t);
+template void vcycle<float, 32>(Hierarchy&, bool, hipStream_t);
 
 void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,
                hipStream_t s) {
