@@ -236,6 +236,8 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s);
 // In-place Gauss-Jordan inverse of an n x n (n multiple of 64) row-major
 // matrix without pivoting; flags[FLAG_SINGULAR] / [FLAG_NOT_SPD] if a pivot
 // is not positive when spd != 0 or is tiny.
+// inverse of a symmetric matrix (lower-triangle block sweeps, no pivoting)
+void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s);
 void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s);
 
 // ---------------------------------------------------------------- k_krylov

@@ -286,7 +286,7 @@ void build_psolve(fpc_handle* h) {
     if (pad > ps.comp_n[c])
       k_pad_diag<<<grid_for(pad - ps.comp_n[c], 64), 64, 0, s>>>(D, ps.comp_n[c], pad);
     FPC_LAUNCH_CHECK();
-    gj_inverse(D, pad, /*spd=*/fs ? 0 : 1, h->flags.p, s);
+    sym_inverse(D, pad, /*spd=*/fs ? 0 : 1, h->flags.p, s);
   }
   check_flags(h, "pressure block");
   // packed symmetric tiles for the single-vector apply

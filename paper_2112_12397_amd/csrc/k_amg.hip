@@ -556,7 +556,8 @@ constexpr int GM_T = 128, GM_KC = 16, GM_LP = 16;
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(
     int64_t M, int64_t N, int K, double alpha, double beta,
     const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-    int64_t ldb, double* __restrict__ C, int64_t ldc, SkipMap rm, SkipMap cm) {
+    int64_t ldb, double* __restrict__ C, int64_t ldc, SkipMap rm, SkipMap cm,
+    int lower) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int AQ = GM_KC / 2, BQ = GM_KC * GM_T / 256;
   __shared__ double As[GM_KC][GM_T + GM_LP];
@@ -565,6 +566,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(
   const int64_t tiles_n = (N + GM_T - 1) / GM_T;
   const int64_t i0 = (int64_t)(blockIdx.x / tiles_n) * GM_T;
   const int64_t j0 = (int64_t)(blockIdx.x % tiles_n) * GM_T;
+  // lower: only tiles reaching the lower triangle (i >= j) are computed
+  if (lower && i0 + GM_T - 1 < j0) return;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   d4 acc[4][4];
 #pragma unroll
@@ -628,15 +631,67 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(
 
 void gemm_f64(int64_t M, int64_t N, int K, double alpha, double beta,
               const double* A, int64_t lda, const double* B, int64_t ldb,
-              double* C, int64_t ldc, SkipMap rm, SkipMap cm, hipStream_t s) {
+              double* C, int64_t ldc, SkipMap rm, SkipMap cm, hipStream_t s,
+              int lower = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return;
   if (K % GM_KC || N % 16 || (rm.len && (rm.at % 8 || rm.len % 8)) ||
       (cm.len && (cm.at % 8 || cm.len % 8)))
     throw Error(FPC_ERR_ARG, "gemm_f64: shape not supported");
   const int64_t tiles = ((M + GM_T - 1) / GM_T) * ((N + GM_T - 1) / GM_T);
   k_gemm_f64<<<(unsigned)tiles, 256, 0, s>>>(M, N, K, alpha, beta, A, lda, B,
-                                              ldb, C, ldc, rm, cm);
+                                              ldb, C, ldc, rm, cm, lower);
   FPC_LAUNCH_CHECK();
+}
+
+// dst[c * ldd + r] = src[r * lds + c] for r < rows, c < cols (32 x 32 tiles)
+__global__ void k_tr_copy(const double* __restrict__ src, int64_t lds,
+                          int64_t rows, int64_t cols, double* __restrict__ dst,
+                          int64_t ldd) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) t[k][threadIdx.x] = src[r * lds + c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) dst[c * ldd + r] = t[threadIdx.x][k];
+  }
+}
+
+void tr_copy(const double* src, int64_t lds, int64_t rows, int64_t cols,
+             double* dst, int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 g((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  k_tr_copy<<<g, dim3(32, 8), 0, s>>>(src, lds, rows, cols, dst, ldd);
+  FPC_LAUNCH_CHECK();
+}
+
+// nb x nb block at D (pitch ld): upper triangle <- lower triangle
+__global__ void k_mirror_lower(double* D, int64_t ld, int64_t nb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * nb) return;
+  const int64_t i = e / nb, j = e % nb;
+  if (j > i) D[i * ld + j] = D[j * ld + i];
+}
+
+// nb x nb block at D (pitch ld) <- -itself
+__global__ void k_negate_block(double* D, int64_t ld, int64_t nb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * nb) return;
+  D[(e / nb) * ld + e % nb] = -D[(e / nb) * ld + e % nb];
+}
+
+// full symmetric matrix from the lower triangle, negated: D[i][j] = D[j][i]
+// = -D[max][min]
+__global__ void k_sym_negate(double* D, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.y * 16 + threadIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 16 + threadIdx.x;
+  if (i >= n || j > i) return;
+  const double v = -D[i * n + j];
+  D[i * n + j] = v;
+  if (j != i) D[j * n + i] = v;
 }
 
 // 64-wide Gauss-Jordan on the n x n block at D (pitch ld).
@@ -973,6 +1028,61 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
   if (npad > n)
     k_pad_identity<<<grid_for(npad - n, 256), 256, 0, s>>>(D, n, npad);
   FPC_LAUNCH_CHECK();
+}
+
+// Inverse of a symmetric matrix by block sweeps (Goodnight's sweep operator
+// in 256-wide panels), in place, touching only the lower triangle: sweeping
+// block k with panel P (the off-diagonal part of block column k) and
+// D_kk^-1 gives D_ij -= P_i D_kk^-1 P_j^T, new panel P D_kk^-1 and
+// D_kk <- -D_kk^-1; after all blocks the lower triangle holds -A^{-1}, which
+// the last pass mirrors and negates.  Half the flops of Gauss-Jordan (the
+// trailing products cover the lower triangle only); no pivoting (a zero
+// pivot of a diagonal block is reported).
+void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
+  if (n % GT) throw Error(FPC_ERR_ARG, "sym_inverse: size not a multiple of 64");
+  constexpr int64_t NB = 256;
+  if (n <= NB) return gj_inverse64(D, n, n, spd, flags, s);
+  DevBuf<double> prow(NB * n), pcol(n * NB), z(n * NB);
+  const SkipMap none{INT64_MAX, 0};
+  for (int64_t o = 0; o < n; o += NB) {
+    const int64_t nb = std::min<int64_t>(NB, n - o), e = o + nb;
+    const SkipMap skip{o, nb};
+    double* Dkk = D + o * n + o;
+    k_mirror_lower<<<grid_for(nb * nb, 256), 256, 0, s>>>(Dkk, n, nb);
+    FPC_LAUNCH_CHECK();
+    gj_inverse64(Dkk, nb, n, spd, flags, s);           // Dkk <- Dkk^-1
+    // P (n x nb, rows outside the panel): lower tiles (i, k) for i >= e,
+    // transposed lower tiles (k, i) for i < o; P^T likewise (nb x n)
+    if (e < n)
+      FPC_HIP(hipMemcpy2DAsync(pcol.p + e * nb, nb * sizeof(double),
+                               D + e * n + o, n * sizeof(double),
+                               nb * sizeof(double), n - e,
+                               hipMemcpyDeviceToDevice, s));
+    tr_copy(D + o * n, n, nb, o, pcol.p, nb, s);
+    if (o > 0)
+      FPC_HIP(hipMemcpy2DAsync(prow.p, n * sizeof(double), D + o * n,
+                               n * sizeof(double), o * sizeof(double), nb,
+                               hipMemcpyDeviceToDevice, s));
+    tr_copy(D + e * n + o, n, n - e, nb, prow.p + e, n, s);
+    // Z = P Dkk^-1
+    gemm_f64(n - nb, nb, (int)nb, 1.0, 0.0, pcol.p, nb, Dkk, n, z.p, nb, skip,
+             none, s);
+    // lower trailing update D_ij -= Z_i P_j^T
+    gemm_f64(n - nb, n - nb, (int)nb, -1.0, 1.0, z.p, nb, prow.p, n, D, n,
+             skip, skip, s, /*lower=*/1);
+    // new panel Z into the lower tiles; Dkk <- -Dkk^-1
+    if (e < n)
+      FPC_HIP(hipMemcpy2DAsync(D + e * n + o, n * sizeof(double), z.p + e * nb,
+                               nb * sizeof(double), nb * sizeof(double), n - e,
+                               hipMemcpyDeviceToDevice, s));
+    tr_copy(z.p, nb, o, nb, D + o * n, n, s);
+    k_negate_block<<<grid_for(nb * nb, 256), 256, 0, s>>>(Dkk, n, nb);
+    FPC_LAUNCH_CHECK();
+  }
+  dim3 g((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16));
+  k_sym_negate<<<g, dim3(16, 16), 0, s>>>(D, n);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipStreamSynchronize(s));
 }
 
 void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
