@@ -210,25 +210,47 @@ __global__ void k_bsr_add(const int64_t* ra, const int32_t* ca,
 }
 
 // ------------------------------------------------------------- SpGEMM
-constexpr int HS_BITS = 12;
-constexpr int HS = 1 << HS_BITS;
+// The hash table of a row lives in LDS; its size (a power of two, at most
+// 4096 slots) is twice the largest possible row length of A*B (the sum of
+// the B row lengths over an A row), so small products run at high occupancy.
+constexpr int HS_MAX_BITS = 12;
 
-__device__ inline int hslot(int c) {
-  return (int)(((uint32_t)c * 2654435761u) >> (32 - HS_BITS));
+__device__ inline int hslot(int c, int bits) {
+  return (int)(((uint32_t)c * 2654435761u) >> (32 - bits));
 }
 
-__device__ inline bool hinsert(int* tab, int* ucount, int c) {
-  int h = hslot(c);
-  for (int probe = 0; probe < HS; ++probe) {
+__device__ inline bool hinsert(int* tab, int bits, int* ucount, int c) {
+  const int hs = 1 << bits;
+  int h = hslot(c, bits);
+  for (int probe = 0; probe < hs; ++probe) {
     int old = atomicCAS(&tab[h], -1, c);
     if (old == -1) {
       atomicAdd(ucount, 1);
       return true;
     }
     if (old == c) return true;
-    h = (h + 1) & (HS - 1);
+    h = (h + 1) & (hs - 1);
   }
   return false;
+}
+
+// out = max over rows of sum_{k in row of A} |row k of B| (upper bound on
+// the row length of A*B)
+__global__ void k_spgemm_bound(const int64_t* ra, const int32_t* ca,
+                               const int64_t* rb, int64_t nrows,
+                               unsigned long long* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  unsigned long long t = 0;
+  for (int64_t e = ra[i]; e < ra[i + 1]; ++e)
+    t += (unsigned long long)(rb[ca[e] + 1] - rb[ca[e]]);
+  atomicMax(out, t);
+}
+
+__global__ void k_max_count(const int64_t* cnt, int64_t n,
+                            unsigned long long* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicMax(out, (unsigned long long)cnt[i]);
 }
 
 // One 64-thread block per row: hash the block columns of the row of A*B;
@@ -236,15 +258,17 @@ __device__ inline bool hinsert(int* tab, int* ucount, int c) {
 __global__ __launch_bounds__(64) void k_spgemm_sym(
     const int64_t* ra, const int32_t* ca, const int64_t* rb,
     const int32_t* cb, int64_t nrows, const int64_t* rc, int64_t* cnt,
-    int32_t* cc, int* flags) {
-  __shared__ int tab[HS];
-  __shared__ int lst[HS];
+    int32_t* cc, int* flags, int bits) {
+  extern __shared__ int dyn[];
   __shared__ int ucount;
   __shared__ int fail;
+  const int hs = 1 << bits;
+  int* tab = dyn;
+  int* lst = dyn + hs;
   const int64_t row = blockIdx.x;
   const int lane = threadIdx.x;
   if (row >= nrows) return;
-  for (int s = lane; s < HS; s += 64) tab[s] = -1;
+  for (int s = lane; s < hs; s += 64) tab[s] = -1;
   if (lane == 0) {
     ucount = 0;
     fail = 0;
@@ -253,9 +277,9 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
   for (int64_t ea = ra[row]; ea < ra[row + 1]; ++ea) {
     int32_t k = ca[ea];
     for (int64_t eb = rb[k] + lane; eb < rb[k + 1]; eb += 64)
-      if (!hinsert(tab, &ucount, cb[eb])) fail = 1;
+      if (!hinsert(tab, bits, &ucount, cb[eb])) fail = 1;
     __syncthreads();
-    if (ucount > (HS * 3) / 4) fail = 1;
+    if (ucount > (hs * 3) / 4) fail = 1;
     if (fail) break;
   }
   __syncthreads();
@@ -272,8 +296,8 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
   }
   // compact the occupied slots, then rank-sort into the output row
   int base = 0;
-  for (int s0 = 0; s0 < HS; s0 += 64) {
-    int c = tab[s0 + lane];
+  for (int s0 = 0; s0 < hs; s0 += 64) {
+    int c = s0 + lane < hs ? tab[s0 + lane] : -1;
     bool v = c >= 0;
     unsigned long long m = __ballot(v);
     int before = __popcll(m & ((1ull << lane) - 1ull));
@@ -289,6 +313,55 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
     for (int f = 0; f < n; ++f) r += (lst[f] < c);
     cc[out + r] = c;
   }
+}
+
+// Numeric phase with the output row accumulated in LDS (cap blocks at most):
+// the same order of operations as k_spgemm_num below, one global write per
+// output value.
+template <int BM, int BK, int BN>
+__global__ __launch_bounds__(64) void k_spgemm_num_lds(
+    const int64_t* ra, const int32_t* ca, const double* va, const int64_t* rb,
+    const int32_t* cb, const double* vb, int64_t nrows, const int64_t* rc,
+    const int32_t* cc, double* vc, int cap) {
+  extern __shared__ double sacc[];
+  int* scol = (int*)(sacc + (int64_t)cap * BM * BN);
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (row >= nrows) return;
+  const int64_t c0 = rc[row];
+  const int clen = (int)(rc[row + 1] - c0);
+  for (int q = lane; q < clen * BM * BN; q += 64) sacc[q] = 0.0;
+  for (int q = lane; q < clen; q += 64) scol[q] = cc[c0 + q];
+  __syncthreads();
+  for (int64_t ea = ra[row]; ea < ra[row + 1]; ++ea) {
+    const int32_t k = ca[ea];
+    double a[BM * BK];
+#pragma unroll
+    for (int q = 0; q < BM * BK; ++q) a[q] = va[ea * (BM * BK) + q];
+    for (int64_t eb = rb[k] + lane; eb < rb[k + 1]; eb += 64) {
+      const int32_t j = cb[eb];
+      int lo = 0, hi = clen;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (scol[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo >= clen || scol[lo] != j) continue;
+      const double* b = vb + eb * (BK * BN);
+      double* o = sacc + lo * (BM * BN);
+#pragma unroll
+      for (int r = 0; r < BM; ++r)
+#pragma unroll
+        for (int c = 0; c < BN; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < BK; ++t) acc += a[r * BK + t] * b[t * BN + c];
+          o[r * BN + c] += acc;
+        }
+    }
+    __syncthreads();
+  }
+  for (int q = lane; q < clen * BM * BN; q += 64) vc[c0 * BM * BN + q] = sacc[q];
 }
 
 // Numeric phase: C row i = sum_k A(i,k) B(k,:).  The loop over the entries
@@ -490,26 +563,49 @@ void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
   c.nbr = a.nbr;
   c.nbc = b.nbc;
   DevBuf<int64_t> cnt(std::max<int64_t>(c.nbr, 1));
+  DevBuf<unsigned long long> mx(2);
   c.rowptr.alloc(c.nbr + 1);
-  if (c.nbr)
-    k_spgemm_sym<<<(unsigned)c.nbr, 64, 0, s>>>(a.rowptr.p, a.col.p,
-                                                b.rowptr.p, b.col.p, c.nbr,
-                                                nullptr, cnt.p, nullptr, flags);
+  if (!c.nbr) {
+    c.nnzb = scan_counts_total(cnt.p, c.rowptr.p, 0, s);
+    return;
+  }
+  FPC_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(unsigned long long), s));
+  k_spgemm_bound<<<grid_for(c.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.col.p,
+                                                       b.rowptr.p, c.nbr, mx.p);
+  FPC_LAUNCH_CHECK();
+  unsigned long long h[2];
+  FPC_HIP(hipMemcpyAsync(h, mx.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  int bits = 6;
+  while (bits < HS_MAX_BITS && (1ull << bits) < 2 * h[0]) ++bits;
+  const size_t hbytes = 2 * (size_t(1) << bits) * sizeof(int);
+  k_spgemm_sym<<<(unsigned)c.nbr, 64, hbytes, s>>>(
+      a.rowptr.p, a.col.p, b.rowptr.p, b.col.p, c.nbr, nullptr, cnt.p, nullptr,
+      flags, bits);
+  FPC_LAUNCH_CHECK();
+  k_max_count<<<grid_for(c.nbr, 256), 256, 0, s>>>(cnt.p, c.nbr, mx.p + 1);
   FPC_LAUNCH_CHECK();
   c.nnzb = scan_counts_total(cnt.p, c.rowptr.p, c.nbr, s);
   c.col.alloc(std::max<int64_t>(c.nnzb, 1));
   c.val.alloc(std::max<int64_t>(c.nnzb * BM * BN, 1));
-  if (c.nbr) {
-    k_spgemm_sym<<<(unsigned)c.nbr, 64, 0, s>>>(a.rowptr.p, a.col.p,
-                                                b.rowptr.p, b.col.p, c.nbr,
-                                                c.rowptr.p, nullptr, c.col.p,
-                                                flags);
-    FPC_LAUNCH_CHECK();
+  k_spgemm_sym<<<(unsigned)c.nbr, 64, hbytes, s>>>(
+      a.rowptr.p, a.col.p, b.rowptr.p, b.col.p, c.nbr, c.rowptr.p, nullptr,
+      c.col.p, flags, bits);
+  FPC_LAUNCH_CHECK();
+  FPC_HIP(hipMemcpyAsync(h, mx.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  FPC_HIP(hipStreamSynchronize(s));
+  const int64_t cap = (int64_t)h[1];
+  const size_t abytes = (size_t)cap * (BM * BN * sizeof(double) + sizeof(int));
+  if (abytes <= 60 * 1024) {
+    k_spgemm_num_lds<BM, BK, BN><<<(unsigned)c.nbr, 64, abytes, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
+        c.rowptr.p, c.col.p, c.val.p, (int)cap);
+  } else {
     k_spgemm_num<BM, BK, BN><<<(unsigned)c.nbr, 64, 0, s>>>(
         a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
         c.rowptr.p, c.col.p, c.val.p);
-    FPC_LAUNCH_CHECK();
   }
+  FPC_LAUNCH_CHECK();
 }
 
 template <typename T, int B>
