@@ -256,10 +256,16 @@ __global__ void k_agg_fill(const int32_t* agg, int64_t n,
   if (agg[i] >= 0) members[atomicAdd(&cursor[agg[i]], 1ull)] = (int32_t)i;
 }
 
-__global__ void k_agg_sort(const int64_t* off, int64_t n_agg,
-                           int32_t* members) {
+// Rows (members x block size) an aggregate may have for k_tentative_w.
+constexpr int TENT_ROWS = 2048;
+
+// Insertion sort of the members of the aggregates with more than min_rows
+// rows (the others are sorted inside k_tentative_w).
+__global__ void k_agg_sort(const int64_t* off, int64_t n_agg, int bs,
+                           int64_t min_rows, int32_t* members) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n_agg) return;
+  if ((off[a + 1] - off[a]) * bs <= min_rows) return;
   for (int64_t e = off[a] + 1; e < off[a + 1]; ++e) {
     int32_t v = members[e];
     int64_t f = e - 1;
@@ -275,13 +281,16 @@ __global__ void k_agg_sort(const int64_t* off, int64_t n_agg,
 // by modified Gram-Schmidt applied twice; columns whose remaining norm is
 // <= drop_tol * (largest column norm) are dropped.  Q is written over the
 // rows of ptent (kept columns first, the rest zero), R into Bc.
+// (Thread per aggregate; used for the aggregates with more than min_rows
+// rows.)
 __global__ void k_tentative(const int64_t* off, const int32_t* members,
                             int64_t n_agg, int bs, int nb, const double* B,
                             double drop_tol, double* ptent, double* Bc,
-                            int32_t* rank) {
+                            int32_t* rank, int64_t min_rows) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n_agg) return;
   const int64_t m0 = off[a], m1 = off[a + 1];
+  if ((m1 - m0) * bs <= min_rows) return;
   double R[36];
   for (int q = 0; q < 36; ++q) R[q] = 0.0;
   double scale = 0.0;
@@ -337,6 +346,157 @@ __global__ void k_tentative(const int64_t* off, const int32_t* members,
   double* o = Bc + a * nb * nb;
   for (int k = 0; k < nb; ++k)
     for (int j = 0; j < nb; ++j) o[k * nb + j] = (k < kc) ? R[k * 6 + j] : 0.0;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the WPA waves of one aggregate group, in a fixed order, so every
+// thread of the group gets the same value.
+template <int WPA>
+__device__ inline double group_sum(double v, double* red) {
+  v = wave_sum(v);
+  if constexpr (WPA == 1) {
+    return v;
+  } else {
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int i = 1; i < WPA; ++i) r += red[i];
+    __syncthreads();
+    return r;
+  }
+}
+
+// The same QR as k_tentative, with WPA waves per aggregate and T rows per
+// thread, for aggregates with lo < rows <= 64 * WPA * T (a 256-thread block
+// holds 4 / WPA aggregates).  Thread g of the group holds rows g, g + 64 WPA,
+// ... of the stacked block; the members are first put in ascending order in
+// LDS (rank sort).  Dot products are butterfly sums over the wave, then over
+// the group's waves in a fixed order, identical in every thread, so all take
+// the same keep/drop decision.
+template <int WPA, int T>
+__global__ __launch_bounds__(256) void k_tentative_w(
+    const int64_t* off, const int32_t* members, int64_t n_agg, int bs, int nb,
+    const double* B, double drop_tol, double* ptent, double* Bc,
+    int32_t* rank, int64_t lo) {
+  constexpr int GS = 64 * WPA;    // threads per aggregate
+  constexpr int CAP = GS * T;     // rows per aggregate
+  __shared__ int32_t smem[4 / WPA][CAP];
+  __shared__ double red[4];
+  const int g = threadIdx.x % GS;
+  const int grp = threadIdx.x / GS;
+  const int64_t a = (int64_t)blockIdx.x * (4 / WPA) + grp;
+  const int64_t m0 = a < n_agg ? off[a] : 0;
+  const int64_t len = a < n_agg ? off[a + 1] - m0 : 0;
+  const bool valid = a < n_agg && len * bs > lo && len * bs <= CAP;
+  // groups without work keep m = 0 and take part in the barriers only
+  const int m = valid ? (int)len : 0;
+  const int M = m * bs;
+  int32_t* sm = smem[grp];
+  int32_t mine[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int e = g + GS * t;
+    mine[t] = e < m ? members[m0 + e] : 0;
+    if (e < m) sm[e] = mine[t];
+  }
+  __syncthreads();
+  int32_t sorted_pos[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    int r = 0;
+    if (g + GS * t < m)
+      for (int f = 0; f < m; ++f) r += sm[f] < mine[t];
+    sorted_pos[t] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+    if (g + GS * t < m) sm[sorted_pos[t]] = mine[t];
+  __syncthreads();
+  // past the last barrier shared by groups (with WPA = 4 the block is one
+  // aggregate, so valid is uniform over the block)
+  if (!valid) return;
+  double Q[T][6];
+  int64_t rowoff[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int rho = g + GS * t;
+    const bool in = rho < M;
+    const int64_t node = in ? sm[rho / bs] : 0;
+    rowoff[t] = in ? (node * bs + rho % bs) * nb : -1;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) Q[t][j] = 0.0;
+  }
+  double* o = Bc + a * nb * nb;
+  if (g == 0)
+    for (int q = 0; q < nb * nb; ++q) o[q] = 0.0;
+  double scale = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    if (j >= nb) break;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const double x = rowoff[t] >= 0 ? B[rowoff[t] + j] : 0.0;
+      v += x * x;
+    }
+    scale = fmax(scale, sqrt(group_sum<WPA>(v, red)));
+  }
+  int kc = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    if (j >= nb) break;
+    double v[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) v[t] = rowoff[t] >= 0 ? B[rowoff[t] + j] : 0.0;
+    double rj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (k >= kc) break;
+        double d = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) d += Q[t][k] * v[t];
+        d = group_sum<WPA>(d, red);
+        rj[k] += d;
+#pragma unroll
+        for (int t = 0; t < T; ++t) v[t] -= d * Q[t][k];
+      }
+    double nv = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) nv += v[t] * v[t];
+    nv = sqrt(group_sum<WPA>(nv, red));
+    const bool keep = nv > drop_tol * scale;
+    if (g == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < kc) o[k * nb + j] = rj[k];
+      if (keep) o[kc * nb + j] = nv;
+    }
+    if (keep) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k == kc)
+#pragma unroll
+          for (int t = 0; t < T; ++t) Q[t][k] = v[t] / nv;
+      ++kc;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+    if (rowoff[t] >= 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < nb) ptent[rowoff[t] + k] = Q[t][k];
+  if (g == 0) rank[a] = kc;
 }
 
 __global__ void k_ptent_count(const int32_t* agg, int64_t n, int64_t* cnt) {
@@ -423,45 +583,70 @@ __global__ void k_pad_identity(double* D, int64_t n, int64_t npad) {
 // (k_gemm_f64).  `ld` is the row pitch, `n` the order.
 constexpr int GT = 64;  // tile
 
-// Gauss-Jordan inverse of the diagonal tile (in place, in LDS).
+// Gauss-Jordan inverse of the diagonal tile, in place.  Thread (tr, tc)
+// keeps rows 4tr..4tr+3 x columns 4tc..4tc+3 in registers; at step k the
+// owners of row k and of column k publish them in LDS (two buffers, so one
+// barrier per step) and every thread updates its 16 entries.
 __global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t ld,
                                                  int64_t kb, int spd,
                                                  int* flags) {
-  __shared__ double a[GT][GT + 1];
-  __shared__ double prow[GT];
-  __shared__ double pcol[GT];
+  __shared__ double rowb[2][GT];
+  __shared__ double colb[2][GT];
   const int tid = threadIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
   const int64_t o = kb * GT;
-  for (int q = tid; q < GT * GT; q += 256) {
-    int r = q / GT, c = q % GT;
-    a[r][c] = D[(o + r) * ld + o + c];
-  }
-  __syncthreads();
+  double a[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      a[i][j] = D[(o + 4 * tr + i) * ld + o + 4 * tc + j];
   for (int k = 0; k < GT; ++k) {
-    double p = a[k][k];
-    bool bad = spd ? !(p > 0.0) : !(fabs(p) > 0.0);
+    const int buf = k & 1;
+    const int kq = k >> 2, kr = k & 3;
+    if (tr == kq) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i == kr)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) rowb[buf][4 * tc + j] = a[i][j];
+    }
+    if (tc == kq) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j == kr)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) colb[buf][4 * tr + i] = a[i][j];
+    }
+    __syncthreads();
+    double p = rowb[buf][k];
+    const bool bad = spd ? !(p > 0.0) : !(fabs(p) > 0.0);
     if (bad || !isfinite(p)) {
       if (tid == 0) atomicOr(&flags[spd ? FLAG_NOT_SPD : FLAG_SINGULAR], 1);
       p = 1.0;
     }
     const double ip = 1.0 / p;
-    if (tid < GT) {
-      prow[tid] = (tid == k) ? ip : a[k][tid] * ip;
-      pcol[tid] = a[tid][k];
+    double pr[4], pc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * tc + j;
+      pr[j] = (c == k) ? ip : rowb[buf][c] * ip;
     }
-    __syncthreads();
-    for (int q = tid; q < GT * GT; q += 256) {
-      int r = q / GT, c = q % GT;
-      if (r == k) a[r][c] = prow[c];
-      else if (c == k) a[r][c] = -pcol[r] * ip;
-      else a[r][c] = a[r][c] - pcol[r] * prow[c];
-    }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pc[i] = colb[buf][4 * tr + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * tr + i, c = 4 * tc + j;
+        a[i][j] = (r == k) ? pr[j] : ((c == k) ? 0.0 : a[i][j]) - pc[i] * pr[j];
+      }
   }
-  for (int q = tid; q < GT * GT; q += 256) {
-    int r = q / GT, c = q % GT;
-    D[(o + r) * ld + o + c] = a[r][c];
-  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      D[(o + 4 * tr + i) * ld + o + 4 * tc + j] = a[i][j];
 }
 
 // acc = X(xi, xj) * Y(yi, yj) for 64x64 tiles (tile coordinates).
@@ -955,6 +1140,8 @@ void rigid_modes(const double* coords, int64_t n_nodes, int nb, double* B,
 void tentative(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
                int nb, const double* B, double drop_tol, double* ptent,
                double* Bc, int32_t* rank, hipStream_t s) {
+  if (nb < 1 || nb > 6)
+    throw Error(FPC_ERR_ARG, "tentative: 1 to 6 near-nullspace vectors");
   DevBuf<unsigned long long> cnt(n_agg + 1);
   FPC_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
   k_agg_count<<<grid_for(n_nodes, 256), 256, 0, s>>>(agg, n_nodes, cnt.p);
@@ -967,12 +1154,19 @@ void tentative(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
   DevBuf<int32_t> members(std::max<int64_t>(n_nodes, 1));
   k_agg_fill<<<grid_for(n_nodes, 256), 256, 0, s>>>(agg, n_nodes, cursor.p,
                                                     members.p);
-  k_agg_sort<<<grid_for(n_agg, 64), 64, 0, s>>>(off.p, n_agg, members.p);
+  k_agg_sort<<<grid_for(n_agg, 64), 64, 0, s>>>(off.p, n_agg, bs, TENT_ROWS,
+                                                members.p);
   FPC_HIP(hipMemsetAsync(ptent, 0, (size_t)n_nodes * bs * nb * sizeof(double),
                          s));
-  k_tentative<<<grid_for(n_agg, 64), 64, 0, s>>>(off.p, members.p, n_agg, bs,
-                                                 nb, B, drop_tol, ptent, Bc,
-                                                 rank);
+  if (n_agg) {
+    k_tentative_w<1, 4><<<(unsigned)((n_agg + 3) / 4), 256, 0, s>>>(
+        off.p, members.p, n_agg, bs, nb, B, drop_tol, ptent, Bc, rank, 0);
+    k_tentative_w<4, 8><<<(unsigned)n_agg, 256, 0, s>>>(
+        off.p, members.p, n_agg, bs, nb, B, drop_tol, ptent, Bc, rank, 256);
+    k_tentative<<<grid_for(n_agg, 64), 64, 0, s>>>(
+        off.p, members.p, n_agg, bs, nb, B, drop_tol, ptent, Bc, rank,
+        TENT_ROWS);
+  }
   FPC_LAUNCH_CHECK();
   FPC_HIP(hipStreamSynchronize(s));
 }

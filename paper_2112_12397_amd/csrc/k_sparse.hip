@@ -262,6 +262,8 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
   extern __shared__ int dyn[];
   __shared__ int ucount;
   __shared__ int fail;
+  __shared__ int64_t pstart[64];
+  __shared__ int pend[64];
   const int hs = 1 << bits;
   int* tab = dyn;
   int* lst = dyn + hs;
@@ -274,10 +276,38 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
     fail = 0;
   }
   __syncthreads();
-  for (int64_t ea = ra[row]; ea < ra[row + 1]; ++ea) {
-    int32_t k = ca[ea];
-    for (int64_t eb = rb[k] + lane; eb < rb[k + 1]; eb += 64)
-      if (!hinsert(tab, bits, &ucount, cb[eb])) fail = 1;
+  // up to 64 A entries at a time; their (A entry, B entry) pairs are spread
+  // over the lanes through an inclusive scan of the B row lengths
+  const int64_t aend = ra[row + 1];
+  for (int64_t ea0 = ra[row]; ea0 < aend; ea0 += 64) {
+    const int64_t ea = ea0 + lane;
+    int len = 0;
+    int64_t st = 0;
+    if (ea < aend) {
+      const int32_t k = ca[ea];
+      st = rb[k];
+      len = (int)(rb[k + 1] - st);
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    pstart[lane] = st;
+    pend[lane] = incl;
+    const int total = __shfl(incl, 63, 64);
+    __syncthreads();
+    for (int p = lane; p < total; p += 64) {
+      int lo = 0, hi = 63;  // first entry with pend > p
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pend[mid] > p) hi = mid;
+        else lo = mid + 1;
+      }
+      const int off = p - (lo ? pend[lo - 1] : 0);
+      if (!hinsert(tab, bits, &ucount, cb[pstart[lo] + off])) fail = 1;
+    }
     __syncthreads();
     if (ucount > (hs * 3) / 4) fail = 1;
     if (fail) break;
@@ -315,18 +345,22 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
   }
 }
 
-// Numeric phase with the output row accumulated in LDS (cap blocks at most):
-// the same order of operations as k_spgemm_num below, one global write per
-// output value.
+// Numeric phase with the output row accumulated in LDS (cap blocks at most).
+// Lane (e, c) = (lane / BN, lane % BN) takes block column c of B entry e of
+// each group of 64 / BN entries; per output value the terms are added in the
+// same order as in k_spgemm_num below (A entries ascending), one global
+// write per output value.
 template <int BM, int BK, int BN>
 __global__ __launch_bounds__(64) void k_spgemm_num_lds(
     const int64_t* ra, const int32_t* ca, const double* va, const int64_t* rb,
     const int32_t* cb, const double* vb, int64_t nrows, const int64_t* rc,
     const int32_t* cc, double* vc, int cap) {
+  constexpr int EPP = 64 / BN;
   extern __shared__ double sacc[];
   int* scol = (int*)(sacc + (int64_t)cap * BM * BN);
   const int64_t row = blockIdx.x;
   const int lane = threadIdx.x;
+  const int le = lane / BN, c = lane % BN;
   if (row >= nrows) return;
   const int64_t c0 = rc[row];
   const int clen = (int)(rc[row + 1] - c0);
@@ -338,7 +372,8 @@ __global__ __launch_bounds__(64) void k_spgemm_num_lds(
     double a[BM * BK];
 #pragma unroll
     for (int q = 0; q < BM * BK; ++q) a[q] = va[ea * (BM * BK) + q];
-    for (int64_t eb = rb[k] + lane; eb < rb[k + 1]; eb += 64) {
+    const int64_t bend = rb[k + 1];
+    for (int64_t eb = rb[k] + le; le < EPP && eb < bend; eb += EPP) {
       const int32_t j = cb[eb];
       int lo = 0, hi = clen;
       while (lo < hi) {
@@ -347,17 +382,18 @@ __global__ __launch_bounds__(64) void k_spgemm_num_lds(
         else hi = mid;
       }
       if (lo >= clen || scol[lo] != j) continue;
-      const double* b = vb + eb * (BK * BN);
-      double* o = sacc + lo * (BM * BN);
+      const double* b = vb + eb * (BK * BN) + c;
+      double bt[BK];
 #pragma unroll
-      for (int r = 0; r < BM; ++r)
+      for (int t = 0; t < BK; ++t) bt[t] = b[t * BN];
+      double* o = sacc + lo * (BM * BN) + c;
 #pragma unroll
-        for (int c = 0; c < BN; ++c) {
-          double acc = 0.0;
+      for (int r = 0; r < BM; ++r) {
+        double acc = 0.0;
 #pragma unroll
-          for (int t = 0; t < BK; ++t) acc += a[r * BK + t] * b[t * BN + c];
-          o[r * BN + c] += acc;
-        }
+        for (int t = 0; t < BK; ++t) acc += a[r * BK + t] * bt[t];
+        o[r * BN] += acc;
+      }
     }
     __syncthreads();
   }
@@ -455,32 +491,36 @@ __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
 }
 
 __global__ void k_vrow_count(const int64_t* rowptr, int64_t nrows, int G,
-                             int64_t* cnt) {
+                             int64_t* cnt, int32_t* row_len) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int64_t len = rowptr[r + 1] - rowptr[r];
   cnt[r] = (len + G - 1) / G;
+  row_len[r] = (int32_t)len;
 }
 
+// One thread per stored value: block entry e = t / B of row r (binary
+// search of rowptr), component q = t % B.
 template <typename T, int B>
 __global__ void k_vrow_fill(const int64_t* rowptr, const int32_t* col,
-                            const double* val, int64_t nrows, int G,
-                            const int64_t* chunk_ptr, int32_t* row_len,
-                            int32_t* vcol, T* vval) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  const int64_t a = rowptr[r];
-  const int len = (int)(rowptr[r + 1] - a);
-  row_len[r] = len;
-  const int64_t c0 = chunk_ptr[r];
-  for (int k = 0; k < len; ++k) {
-    const int64_t grp = (c0 + k / G) * G;
-    const int sl = k % G;
-    vcol[grp + sl] = col[a + k];
-    T* dst = vval + grp * B + sl;
-#pragma unroll
-    for (int q = 0; q < B; ++q) dst[(int64_t)q * G] = (T)val[(a + k) * B + q];
+                            const double* val, int64_t nrows, int64_t nnzb,
+                            int G, const int64_t* chunk_ptr, int32_t* vcol,
+                            T* vval) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnzb * B) return;
+  const int64_t e = t / B;
+  const int q = (int)(t - e * B);
+  int64_t lo = 0, hi = nrows;  // last row with rowptr[r] <= e
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rowptr[mid] <= e) lo = mid;
+    else hi = mid;
   }
+  const int k = (int)(e - rowptr[lo]);
+  const int64_t grp = (chunk_ptr[lo] + k / G) * G;
+  const int sl = k % G;
+  if (q == 0) vcol[grp + sl] = col[e];
+  vval[grp * B + (int64_t)q * G + sl] = (T)val[t];
 }
 
 __global__ void k_count_nz(const double* v, int64_t n,
@@ -754,20 +794,20 @@ void to_vrow_impl(const Bsr& a, int G, Vrow<T>& out, hipStream_t s) {
   out.nnzb = a.nnzb;
   DevBuf<int64_t> cnt(std::max<int64_t>(a.nbr, 1));
   out.chunk_ptr.alloc(a.nbr + 1);
+  out.row_len.alloc(std::max<int64_t>(a.nbr, 1));
   if (a.nbr)
     k_vrow_count<<<grid_for(a.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.nbr, G,
-                                                      cnt.p);
+                                                      cnt.p, out.row_len.p);
   FPC_LAUNCH_CHECK();
   out.nchunks = scan_counts_total(cnt.p, out.chunk_ptr.p, a.nbr, s);
-  out.row_len.alloc(std::max<int64_t>(a.nbr, 1));
   out.col.alloc(std::max<int64_t>(out.nchunks * G, 1));
   out.val.alloc(std::max<int64_t>(out.nchunks * G * B, 1));
   fill_i32(out.col.p, 0, out.nchunks * G, s);
   FPC_HIP(hipMemsetAsync(out.val.p, 0, out.val.bytes(), s));
-  if (a.nbr)
-    k_vrow_fill<T, B><<<grid_for(a.nbr, 256), 256, 0, s>>>(
-        a.rowptr.p, a.col.p, a.val.p, a.nbr, G, out.chunk_ptr.p,
-        out.row_len.p, out.col.p, out.val.p);
+  if (a.nnzb)
+    k_vrow_fill<T, B><<<grid_for(a.nnzb * B, 256), 256, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nbr, a.nnzb, G, out.chunk_ptr.p,
+        out.col.p, out.val.p);
   FPC_LAUNCH_CHECK();
 }
 
