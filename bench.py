@@ -101,10 +101,11 @@ def device_blocks(torch, s):
     return out
 
 
-def cpu_baseline(s, gpu_iters, sample_its):
+def cpu_baseline(s, gpu_iters, sample_its, v_gpu=None):
     """The CPU oracle on the same workload, one thread: preconditioner setup
     (untimed for the value), then ``sample_its`` FGMRES iterations, scaled to
-    the GPU's iteration count."""
+    the GPU's iteration count.  With ``v_gpu`` (the GPU's M^-1 b) the oracle's
+    application to the same b is compared with it."""
     import oracle
     from threadpoolctl import threadpool_limits
     with threadpool_limits(1):
@@ -116,6 +117,10 @@ def cpu_baseline(s, gpu_iters, sample_its):
         _, info = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8,
                                 maxit=sample_its)
         t_its = time.perf_counter() - t0
+        apply_diff = None
+        if v_gpu is not None:
+            vo = pc.apply(s.b)
+            apply_diff = float(np.linalg.norm(v_gpu - vo) / np.linalg.norm(vo))
     per_it = t_its / max(info.iterations, 1)
     cpu = "unknown"
     try:
@@ -133,7 +138,33 @@ def cpu_baseline(s, gpu_iters, sample_its):
                        f"({t_setup:.1f} s, not in value), scaled to the GPU "
                        f"iteration count {gpu_iters}"),
             "per_iteration_s": per_it, "setup_s": t_setup,
+            "gpu_vs_oracle_apply_rel_diff": apply_diff,
             "cpu_model": cpu, "host": platform.node()}
+
+
+def stream_triad(torch, sol, n=1 << 29, reps=10):
+    """a = b + s c over three n-double arrays (4 GiB each by default) with the
+    library's triad kernel; HIP events on the current stream, best of
+    ``reps`` after a warm-up, 24 bytes per element."""
+    b = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    sol.stream_triad(b, c, 3.0, a)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sol.stream_triad(b, c, 3.0, a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    ok = bool((a == 7.0).all())
+    del a, b, c
+    torch.cuda.empty_cache()
+    gbs = 24.0 * n / best / 1e9
+    return {"GBps": gbs, "frac": gbs / HBM_PEAK_GBS, "seconds": best,
+            "array_bytes": 8 * n, "check": ok}
 
 
 def _timed(torch, fn, reps=1):
@@ -353,6 +384,22 @@ def main():
     vc_s = ev0.elapsed_time(ev1) / nrep / 1e3
     vc_bytes = vcycle_bytes(levels)
 
+    # pressure-block solve alone (one per application in t-u-p with Q2 = 0)
+    wp = torch.randn(s.n_p, dtype=torch.float64, device="cuda")
+    vp = torch.empty_like(wp)
+    for _ in range(3):
+        sol.psolve(wp, out=vp)
+    ev0.record()
+    for _ in range(nrep):
+        sol.psolve(wp, out=vp)
+    ev1.record()
+    torch.cuda.synchronize()
+    ps_s = ev0.elapsed_time(ev1) / nrep / 1e3
+    del wp, vp
+
+    # measured STREAM triad (three 4 GiB arrays) as the achievable HBM rate
+    triad = stream_triad(torch, sol)
+
     out = {
         "metric": METRIC,
         "value": t_solve / K,
@@ -378,13 +425,21 @@ def main():
                         "layout_A_P_R": d["layout"],
                         "tuned_us_A_P_R": [round(t, 1) for t in d["tune_us"]]}
                        for d in levels],
-        "vcycle": {"seconds": vc_s, "algorithmic_bytes": vc_bytes,
+        "vcycle": {"seconds": vc_s, "vcycles_per_s": 1.0 / vc_s,
+                   "algorithmic_bytes": vc_bytes,
                    "GBps": vc_bytes / vc_s / 1e9,
                    "frac": vc_bytes / vc_s / 1e9 / HBM_PEAK_GBS,
+                   "frac_of_triad": vc_bytes / vc_s / 1e9 / triad["GBps"],
                    "columns": 1, "dtype": "f64"},
+        "psolve": {"seconds": ps_s,
+                   "share_of_iteration": ps_s / (t_solve / K / max(iters, 1)),
+                   "note": "exact pressure-block solve, one per "
+                           "preconditioner application"},
+        "stream_triad": triad,
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     "frac_of_triad": achieved / triad["GBps"],
                      "traffic": counter_traffic(),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 "
                                      "FETCH_SIZE + WRITE_SIZE, copy-scaled)",
@@ -416,7 +471,9 @@ def main():
         out["forms"] = forms(torch, s, blocks, coords, b, t_solve / K)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(s, iters, args.cpu_sample_its)
+        v_gpu = sol.apply_prec(b).cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(s, iters, args.cpu_sample_its,
+                                           v_gpu)
     print(json.dumps(out), flush=True)
 
 

@@ -181,6 +181,21 @@ fpc_status fpc_matvec(fpc_handle* h, int trans, const double* x, double* y);
 /* One V-cycle x = AMG(S1, b) on the u block only (length n_u, device). */
 fpc_status fpc_vcycle(fpc_handle* h, const double* b, double* x);
 
+/* The pressure-block solve of the preconditioner by itself (device vectors
+ * of length n_p): v = S~2^{-1} w (Alg 3.4 step 5; S~2 = T - FS(Q2, S1, Q1),
+ * eq. S2approx, = T when Q2 = 0) in t-u-p and M2*, v = T^{-1} w (Alg 3.2
+ * steps 1 and 7) in t-p-u; trans = 1 applies the transpose (the stored
+ * inverse is symmetric, so the result is the same).  Runs on the handle's
+ * stream in the precision of the hierarchy's pressure inverse. */
+fpc_status fpc_psolve(fpc_handle* h, int trans, const double* w, double* v);
+
+/* Measurement aid, not a step of the method: a = b + scalar * c over n
+ * doubles (device, 16-byte aligned), the STREAM triad used as the achievable
+ * HBM bandwidth next to the roofline figures.  Any handle (set up or not)
+ * supplies the stream. */
+fpc_status fpc_stream_triad(fpc_handle* h, int64_t n, const double* b,
+                            const double* c, double scalar, double* a);
+
 /* Right-preconditioned FGMRES(restart) on J x = b (Sec. 4: zero initial
  * guess, stop at |b - J x| <= rtol |b|, the true residual recomputed in
  * FP64).  use_x0 != 0 starts from the values in x (restart / resume).

@@ -166,6 +166,8 @@ constexpr int kRedBlocks = 1024;
 void hash32_range(uint32_t first, int64_t n, uint32_t* out, hipStream_t s);
 void check_finite(const double* v, int64_t n, int* flags, hipStream_t s);
 void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void stream_triad(const double* b, const double* c, double scalar, double* a,
+                  int64_t n, hipStream_t s);
 double read_f64(const double* p, hipStream_t s);
 int64_t read_i64(const int64_t* p, hipStream_t s);
 int read_i32(const int32_t* p, hipStream_t s);

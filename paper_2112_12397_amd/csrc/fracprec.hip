@@ -1298,6 +1298,18 @@ fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
   });
 }
 
+fpc_status fpc_psolve(fpc_handle* h, int trans, const double* w, double* v) {
+  FPC_REQUIRE_READY(h);
+  if (!w || !v || trans < 0 || trans > 1) return FPC_ERR_ARG;
+  return guard(h, [&] { psolve_apply(h->ps, w, v, h->n_p, trans, h->stream); });
+}
+
+fpc_status fpc_stream_triad(fpc_handle* h, int64_t n, const double* b,
+                            const double* c, double scalar, double* a) {
+  if (!h || n < 0 || (n && (!a || !b || !c))) return FPC_ERR_ARG;
+  return guard(h, [&] { stream_triad(b, c, scalar, a, n, h->stream); });
+}
+
 int fpc_num_levels(const fpc_handle* h) {
   return (h && h->ready) ? (int)h->amg.L.size() : 0;
 }

@@ -220,6 +220,42 @@ void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
   FPC_LAUNCH_CHECK();
 }
 
+// a = b + scalar * c, two doubles per thread and step (16-byte accesses),
+// grid-stride over 2048 blocks of 256 threads; odd tail by the first thread.
+__global__ __launch_bounds__(256) void k_triad(const double2* __restrict__ b,
+                                               const double2* __restrict__ c,
+                                               double scalar,
+                                               double2* __restrict__ a,
+                                               int64_t n2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+       i += stride) {
+    const double2 x = b[i], y = c[i];
+    a[i] = make_double2(x.x + scalar * y.x, x.y + scalar * y.y);
+  }
+}
+
+__global__ void k_triad_tail(const double* b, const double* c, double scalar,
+                             double* a, int64_t i) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) a[i] = b[i] + scalar * c[i];
+}
+
+void stream_triad(const double* b, const double* c, double scalar, double* a,
+                  int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15)
+    throw Error(FPC_ERR_ARG, "stream_triad: arrays must be 16-byte aligned");
+  const int64_t n2 = n / 2;
+  if (n2) {
+    const int64_t need = (n2 + 255) / 256;
+    const unsigned g = (unsigned)std::min<int64_t>(need, 2048);
+    k_triad<<<g, 256, 0, s>>>((const double2*)b, (const double2*)c, scalar,
+                              (double2*)a, n2);
+  }
+  if (n & 1) k_triad_tail<<<1, 64, 0, s>>>(b, c, scalar, a, n - 1);
+  FPC_LAUNCH_CHECK();
+}
+
 double read_f64(const double* p, hipStream_t s) {
   double v = 0;
   FPC_HIP(hipMemcpyAsync(&v, p, sizeof(double), hipMemcpyDeviceToHost, s));

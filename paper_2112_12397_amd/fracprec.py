@@ -91,7 +91,7 @@ EXPORTS = ("fpc_default_options", "fpc_create", "fpc_setup", "fpc_apply_prec",
            "fpc_num_levels", "fpc_level_info", "fpc_export_aggregates",
            "fpc_export_level_matrix", "fpc_setup_times", "fpc_destroy",
            "fpc_status_string", "fpc_last_error", "fpc_hash32_device",
-           "fpc_kernel_timer")
+           "fpc_kernel_timer", "fpc_psolve", "fpc_stream_triad")
 
 _lib = None
 
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
         "fpc_apply_prec_T": (i32, [H, vp, vp]),
         "fpc_matvec": (i32, [H, i32, vp, vp]),
         "fpc_vcycle": (i32, [H, vp, vp]),
+        "fpc_psolve": (i32, [H, i32, vp, vp]),
+        "fpc_stream_triad": (i32, [H, i64, vp, vp, dbl, vp]),
         "fpc_solve": (i32, [H, vp, vp, dbl, i32, C.POINTER(FpcInfo)]),
         "fpc_solve_T": (i32, [H, vp, vp, dbl, C.POINTER(FpcInfo)]),
         "fpc_solve_batch": (i32, [H, i32, vp, i64, vp, i64, dbl,
@@ -293,6 +295,20 @@ class Solver:
         self._check(self.lib.fpc_vcycle(self.h, self._ptr(b), self._ptr(x)),
                     "vcycle")
         return x
+
+    def psolve(self, w, trans=False, out=None):
+        """Pressure-block solve of the preconditioner (length n_p)."""
+        v = self._vec(self.n_p) if out is None else out
+        self._check(self.lib.fpc_psolve(self.h, int(bool(trans)), self._ptr(w),
+                                        self._ptr(v)), "psolve")
+        return v
+
+    def stream_triad(self, b, c, scalar, out):
+        """a = b + scalar c (HBM bandwidth reference)."""
+        self._check(self.lib.fpc_stream_triad(self.h, b.numel(), self._ptr(b),
+                                              self._ptr(c), float(scalar),
+                                              self._ptr(out)), "stream_triad")
+        return out
 
     def solve(self, b, rtol=0.0, x0=None, out=None):
         x = self._vec() if out is None else out

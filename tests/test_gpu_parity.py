@@ -159,6 +159,21 @@ def test_apply_prec_parity(torch, name, mode):
 
 
 @pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("mode", ["tup", "tpu", "tup_star"])
+def test_psolve_parity(torch, name, mode):
+    """The pressure-block solve alone: S~2^{-1} w (t-u-p, M2*; with open
+    faces S~2 = T - diag(S_K), the algebraic fixed stress) or T^{-1} w
+    (t-p-u), against the oracle's sparse LU of the same matrix."""
+    s, pc, sol = _get(name, mode)
+    rng = np.random.default_rng(9)
+    w = rng.standard_normal(s.n_p)
+    wd = torch.tensor(w, device="cuda")
+    for trans in (False, True):
+        v = sol.psolve(wd, trans=trans).cpu().numpy()
+        assert _rel(v, pc.psolve(w, transpose=trans)) <= TOL
+
+
+@pytest.mark.parametrize("name", NAMES)
 def test_apply_prec_T_parity(torch, name):
     s, pc, sol = _get(name)
     rng = np.random.default_rng(6)
@@ -346,3 +361,22 @@ def test_error_paths(torch):
     # restart from the last iterate converges
     x2, info2 = sol.solve(torch.tensor(s.b, device="cuda"), x0=x)
     assert info2["converged"] == 1
+
+
+def test_stream_triad(torch):
+    """The bandwidth reference kernel: a = b + s c, odd length (tail element),
+    and the alignment check on the host."""
+    from paper_2112_12397_amd import FpcError
+    s, pc, sol = _get("c1")
+    for n in (1, 7, 1_000_001):
+        g = torch.Generator(device="cuda").manual_seed(n)
+        b = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        c = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        a = torch.empty_like(b)
+        sol.stream_triad(b, c, 0.75, a)
+        ref = b + 0.75 * c
+        assert torch.allclose(a, ref, rtol=5e-16, atol=2e-15)
+    big = torch.zeros(9, dtype=torch.float64, device="cuda")
+    with pytest.raises(FpcError) as e:
+        sol.stream_triad(big[1:], big[1:], 1.0, big[1:])
+    assert e.value.status == -1
