@@ -220,24 +220,34 @@ void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
   FPC_LAUNCH_CHECK();
 }
 
-// a = b + scalar * c, two doubles per thread and step (16-byte accesses),
-// grid-stride over 2048 blocks of 256 threads; odd tail by the first thread.
-__global__ __launch_bounds__(256) void k_triad(const double2* __restrict__ b,
-                                               const double2* __restrict__ c,
+// a = b + scalar * c.  Main part: each thread moves four 16-byte pairs, all
+// loads issued before the stores, nontemporal (the arrays are streamed
+// once); 1024 pairs per block.  The rest (fewer than 2049 doubles) by a
+// plain one-element-per-thread kernel.
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void k_triad(const dpair* __restrict__ b,
+                                               const dpair* __restrict__ c,
                                                double scalar,
-                                               double2* __restrict__ a,
-                                               int64_t n2) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
-       i += stride) {
-    const double2 x = b[i], y = c[i];
-    a[i] = make_double2(x.x + scalar * y.x, x.y + scalar * y.y);
+                                               dpair* __restrict__ a) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  dpair x[4], y[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    x[u] = __builtin_nontemporal_load(b + base + 256 * u);
+    y[u] = __builtin_nontemporal_load(c + base + 256 * u);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const dpair r = {x[u].x + scalar * y[u].x, x[u].y + scalar * y[u].y};
+    __builtin_nontemporal_store(r, a + base + 256 * u);
   }
 }
 
 __global__ void k_triad_tail(const double* b, const double* c, double scalar,
-                             double* a, int64_t i) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) a[i] = b[i] + scalar * c[i];
+                             double* a, int64_t i0, int64_t n) {
+  const int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = b[i] + scalar * c[i];
 }
 
 void stream_triad(const double* b, const double* c, double scalar, double* a,
@@ -245,14 +255,13 @@ void stream_triad(const double* b, const double* c, double scalar, double* a,
   if (n <= 0) return;
   if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15)
     throw Error(FPC_ERR_ARG, "stream_triad: arrays must be 16-byte aligned");
-  const int64_t n2 = n / 2;
-  if (n2) {
-    const int64_t need = (n2 + 255) / 256;
-    const unsigned g = (unsigned)std::min<int64_t>(need, 2048);
-    k_triad<<<g, 256, 0, s>>>((const double2*)b, (const double2*)c, scalar,
-                              (double2*)a, n2);
-  }
-  if (n & 1) k_triad_tail<<<1, 64, 0, s>>>(b, c, scalar, a, n - 1);
+  const int64_t nblk = n / 2048;  // 1024 pairs each
+  if (nblk)
+    k_triad<<<(unsigned)nblk, 256, 0, s>>>((const dpair*)b, (const dpair*)c,
+                                           scalar, (dpair*)a);
+  const int64_t i0 = nblk * 2048;
+  if (i0 < n)
+    k_triad_tail<<<grid_for(n - i0, 256), 256, 0, s>>>(b, c, scalar, a, i0, n);
   FPC_LAUNCH_CHECK();
 }
 

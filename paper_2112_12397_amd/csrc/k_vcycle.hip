@@ -226,6 +226,14 @@ __device__ inline void epi_one(const Epi& e, int64_t row, int i, int v, T a) {
 }
 
 // ---------------------------------------------------------------- SpMV
+// Streamed operands (matrix values and indices read once per product, larger
+// than the last-level cache at the sizes that matter) are loaded with the
+// nontemporal hint, so they do not evict the gathered vector.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // Few columns (NV <= 2): one wavefront per 64-row slice, one thread per block
 // row carrying all NV columns, so each matrix block is read by one lane only.
 // Every lane runs to the slice's longest row: padding slots hold zero values
@@ -253,7 +261,8 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
     for (int i = 0; i < BR; ++i) acc[v][i] = T(0);
   int cn[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) cn[u] = u < maxlen ? cp[(int64_t)u * kSliceH] : 0;
+  for (int u = 0; u < U; ++u)
+    cn[u] = u < maxlen ? ld_stream(cp + (int64_t)u * kSliceH) : 0;
   for (int k0 = 0; k0 < maxlen; k0 += U) {
     int cc[U];
 #pragma unroll
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
           for (int v = 0; v < NV; ++v) xv[u][j][v] = ld((int64_t)cc[u] * BC + j, v);
         const T* __restrict__ vb = vp + (int64_t)(k0 + u) * kSliceH * (BR * BC);
 #pragma unroll
-        for (int q = 0; q < BR * BC; ++q) a[u][q] = vb[q * kSliceH];
+        for (int q = 0; q < BR * BC; ++q) a[u][q] = ld_stream(vb + q * kSliceH);
       } else {
 #pragma unroll
         for (int j = 0; j < BC; ++j)
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int kn = k0 + U + u;
-      cn[u] = kn < maxlen ? cp[(int64_t)kn * kSliceH] : 0;
+      cn[u] = kn < maxlen ? ld_stream(cp + (int64_t)kn * kSliceH) : 0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(256) void k_psym_tile(
   const M* __restrict__ tp = packed + t * 4096 + (int64_t)(w * 16) * 64 + lane;
   M a[16];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) a[rr] = tp[rr * 64];
+  for (int rr = 0; rr < 16; ++rr) a[rr] = ld_stream(tp + rr * 64);
   if (tid < 128) {
     const int64_t idx = (int64_t)(tid < 64 ? J : I) * 64 + lane;
     xs[tid >> 6][lane] = idx < n ? in[members[o + idx]] : 0.0;
