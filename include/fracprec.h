@@ -167,6 +167,24 @@ fpc_status fpc_create(fpc_handle** h, const fpc_options* opt, void* stream);
  * faces), FPC_ERR_OOM.  A second call replaces the previous setup. */
 fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J);
 
+/* Numeric re-setup for the next Newton or active-set iteration (Sec. 2.2:
+ * the first block row does not change, C2, H and Q2 change in values and in
+ * pattern as faces switch between stick, slip and open; Sec. 4: each
+ * nonlinear iteration solves a new system with the same mesh).  Same sizes
+ * as the setup; every block is uploaded and checked again and may have a new
+ * pattern; the coordinates of the setup are kept.  When the block pattern of
+ * the AMG operator (S1, or S~ in t-p-u with Q2 != 0) is unchanged, the
+ * aggregates, tentative prolongators and apply layouts of the previous
+ * hierarchy are reused (they depend on patterns and coordinates only) and
+ * everything else is recomputed, so the result equals fpc_setup on the new
+ * system; otherwise the hierarchy is rebuilt from scratch.  Errors as
+ * fpc_setup; on error the handle is left not set up (FPC_ERR_STATE). */
+fpc_status fpc_update_values(fpc_handle* h, const fpc_block_system* J);
+
+/* 1 if the last fpc_setup / fpc_update_values reused the pattern-only parts
+ * of the previous AMG hierarchy, 0 if it built them, -1 for a NULL handle. */
+int fpc_hierarchy_reused(const fpc_handle* h);
+
 /* v = M^{-1} w: Alg 3.4 app_tup (or Alg 3.2 app_tpu) with one V-cycle per
  * AMG(S1, .) call.  w, v: device, length n_u + n_t + n_p, distinct. */
 fpc_status fpc_apply_prec(fpc_handle* h, const double* w, double* v);

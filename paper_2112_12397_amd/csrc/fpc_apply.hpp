@@ -18,6 +18,10 @@ template <typename T>
 void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
              double* best_us);
 
+// The apply layout `choice` (as returned by tune_op) of one operator.
+template <typename T>
+void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s);
+
 void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s);
 void sell_mv_dinv(const Sell<double>& A, const double* dinv, const double* x,
                   double* y, hipStream_t s);

@@ -17,6 +17,7 @@ struct Level {
   int64_t n_nodes = 0;
   int64_t n_dofs_real = 0;  // without padding dofs
   Bsr A, P, R;              // FP64 block CSR (setup, export, transposes)
+  Bsr Pt;                   // tentative prolongator (kept for re-setups)
   Sell<double> sA;          // FP64 A in sliced ELL (power iteration)
   Op<double> oA, oP, oR;    // apply operators (layout chosen by the tuner)
   Op<float> fA, fP, fR;
@@ -204,6 +205,7 @@ struct fpc_handle {
   // apply-path scratch (FP64)
   fpc::DevBuf<double> t_t, tmp_u, tmp_u2, tmp_p, tmp_p2, scratchN;
   bool has_q2 = false;          // open faces: Q2 not empty
+  bool reused_hierarchy = false;  // last construction reused the AMG patterns
   fpc::DevBuf<double> S_K;     // fixed-stress diagonal (t-u-p with Q2)
   fpc::Krylov kry1;            // single right-hand side
   fpc::Krylov kryB;            // batched

@@ -166,6 +166,11 @@ constexpr int kRedBlocks = 1024;
 void hash32_range(uint32_t first, int64_t n, uint32_t* out, hipStream_t s);
 void check_finite(const double* v, int64_t n, int* flags, hipStream_t s);
 void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+// True if the two CSR / block-CSR patterns (nrows + 1 row pointers, nnz
+// column indices, device) are identical.
+bool same_pattern(const int64_t* rp_a, const int32_t* col_a,
+                  const int64_t* rp_b, const int32_t* col_b, int64_t nrows,
+                  int64_t nnz, hipStream_t s);
 void stream_triad(const double* b, const double* c, double scalar, double* a,
                   int64_t n, hipStream_t s);
 double read_f64(const double* p, hipStream_t s);
@@ -229,8 +234,8 @@ void tentative(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
                double* Bc, int32_t* rank, hipStream_t s);
 void ptent_bsr(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
                int nb, const double* ptent, Bsr& P, hipStream_t s);
-void smooth_prolongator(Bsr& AP, const int32_t* agg, const double* ptent,
-                        const double* dinv, double omega, hipStream_t s);
+void smooth_prolongator(Bsr& AP, const double* dinv, double omega,
+                        hipStream_t s);
 void dummy_diag(Bsr& Ac, const int32_t* rank, hipStream_t s);
 void power_start(int64_t n_nodes, int bs, int key_stride,
                  const int32_t* node_rank, double* x, hipStream_t s);

@@ -360,7 +360,13 @@ double power_lambda(fpc_handle* h, Level& L, int key_stride) {
   return read_f64(sc.p + 1, s);
 }
 
-void build_hierarchy(fpc_handle* h, Bsr&& S1) {
+// With `prev` (a hierarchy built on the same level-0 block pattern), the
+// pattern-only parts are taken over instead of recomputed: the aggregates
+// (structure-only MIS-2), the tentative prolongators and coarse ranks (they
+// depend on the aggregates and the coordinates only) and the apply layouts
+// picked by the tuner.  Everything that depends on values is recomputed, so
+// the result equals a fresh build.
+void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
   Hierarchy& H = h->amg;
   h->graphs.clear();  // captured cycles refer to the old hierarchy
   H = Hierarchy();
@@ -377,10 +383,17 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
     L0.n_nodes = L0.A.nbr;
     L0.n_dofs_real = 3 * L0.n_nodes;
   }
-  DevBuf<double> B(H.L[0].n_nodes * 3 * nb);
-  rigid_modes(h->has_coords ? h->coords.p : nullptr, H.L[0].n_nodes, nb, B.p, s);
+  DevBuf<double> B;
+  if (!prev) {
+    B.alloc(H.L[0].n_nodes * 3 * nb);
+    rigid_modes(h->has_coords ? h->coords.p : nullptr, H.L[0].n_nodes, nb, B.p,
+                s);
+  }
   while (true) {
     Level& L = H.L.back();
+    const size_t li = H.L.size() - 1;
+    Level* pv = prev && li < prev->L.size() ? &prev->L[li] : nullptr;
+    if (prev && !pv) throw Error(FPC_ERR_STATE, "re-setup: level count changed");
     L.dinv.alloc(L.n_nodes * L.bs);
     bsr_dinv(L.A, L.dinv.p, h->flags.p, s);
     check_flags(h, "AMG diagonal");
@@ -389,9 +402,16 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
       L.coarsest = true;
       break;
     }
-    L.agg.alloc(L.n_nodes);
-    DevBuf<int32_t> roots;
-    L.n_agg = aggregate_mis2(L.A, L.agg.p, roots, s);
+    if (pv) {
+      if (pv->coarsest || pv->n_nodes != L.n_nodes)
+        throw Error(FPC_ERR_STATE, "re-setup: hierarchy shape changed");
+      L.agg = std::move(pv->agg);
+      L.n_agg = pv->n_agg;
+    } else {
+      L.agg.alloc(L.n_nodes);
+      DevBuf<int32_t> roots;
+      L.n_agg = aggregate_mis2(L.A, L.agg.p, roots, s);
+    }
     if (L.n_agg == 0) {
       L.coarsest = true;
       break;
@@ -409,18 +429,23 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
     L.c1 = rho1 * rho0;
     L.c2 = 2.0 * rho1 / L.delta;
     // tentative prolongator
-    DevBuf<double> ptent(L.n_nodes * L.bs * nb), Bc(L.n_agg * nb * nb);
-    L.rank.alloc(L.n_agg);
-    tentative(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, B.p, o.drop_tol, ptent.p,
-              Bc.p, L.rank.p, s);
-    Bsr Pt;
-    ptent_bsr(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, ptent.p, Pt, s);
+    DevBuf<double> Bc;
+    if (pv) {
+      L.rank = std::move(pv->rank);
+      L.Pt = std::move(pv->Pt);
+    } else {
+      DevBuf<double> ptent(L.n_nodes * L.bs * nb);
+      Bc.alloc(L.n_agg * nb * nb);
+      L.rank.alloc(L.n_agg);
+      tentative(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, B.p, o.drop_tol,
+                ptent.p, Bc.p, L.rank.p, s);
+      ptent_bsr(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, ptent.p, L.Pt, s);
+    }
     Bsr AP0;
-    spgemm(L.A, Pt, AP0, h->flags.p, s);
+    spgemm(L.A, L.Pt, AP0, h->flags.p, s);
     // P = P_tent - omega D^{-1} (A P_tent)
-    smooth_prolongator(AP0, L.agg.p, ptent.p, L.dinv.p,
-                       o.omega_factor / L.lam_hi, s);
-    bsr_add(Pt, AP0, L.P, s);
+    smooth_prolongator(AP0, L.dinv.p, o.omega_factor / L.lam_hi, s);
+    bsr_add(L.Pt, AP0, L.P, s);
     bsr_transpose(L.P, L.R, s);
     Bsr AP, Ac;
     spgemm(L.A, L.P, AP, h->flags.p, s);
@@ -444,7 +469,7 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
     k_copy_i32<<<grid_for(n_agg, 256), 256, 0, s>>>(L.rank.p, next.node_rank.p,
                                                     n_agg);
     FPC_LAUNCH_CHECK();
-    B = std::move(Bc);
+    if (!pv) B = std::move(Bc);
     H.L.push_back(std::move(next));
   }
   // coarsest level: dense inverse (FP64)
@@ -457,9 +482,32 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1) {
   check_flags(h, "coarsest level");
   // apply layouts, tuned for the column count of the preconditioner
   const int nv = 1;
-  for (Level& L : H.L) {
+  for (size_t li = 0; li < H.L.size(); ++li) {
+    Level& L = H.L[li];
     if (L.coarsest) continue;
     L.sA = Sell<double>();
+    if (prev) {
+      // the layouts picked for the same patterns
+      const Level& pv = prev->L[li];
+      for (int k = 0; k < 3; ++k) {
+        L.layout[k] = pv.layout[k];
+        L.tune_us[k] = pv.tune_us[k];
+      }
+      if (h->opt.precision == FPC_FP32_PREC) {
+        const int64_t n = L.n_nodes * L.bs;
+        L.dinv32.alloc(n);
+        k_cast_dinv<<<grid_for(n, 256), 256, 0, s>>>(L.dinv.p, L.dinv32.p, n);
+        FPC_LAUNCH_CHECK();
+        build_op<float>(L.A, L.layout[0], L.fA, s);
+        build_op<float>(L.P, L.layout[1], L.fP, s);
+        build_op<float>(L.R, L.layout[2], L.fR, s);
+      } else {
+        build_op<double>(L.A, L.layout[0], L.oA, s);
+        build_op<double>(L.P, L.layout[1], L.oP, s);
+        build_op<double>(L.R, L.layout[2], L.oR, s);
+      }
+      continue;
+    }
     if (h->opt.precision == FPC_FP32_PREC) {
       const int64_t n = L.n_nodes * L.bs;
       L.dinv32.alloc(n);
@@ -1027,6 +1075,113 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
   return all ? FPC_OK : FPC_NOT_CONVERGED;
 }
 
+// Shapes and array presence of the seven blocks (nothing is read yet).
+void check_block_shapes(const fpc_block_system* J) {
+  const int64_t nu = J->n_u, nt = J->n_t, np = J->n_p;
+  const struct { const fpc_csr* m; int64_t r, c; const char* name; } b[] = {
+      {&J->A, nu, nu, "A"},  {&J->C1, nu, nt, "C1"}, {&J->Q1, nu, np, "Q1"},
+      {&J->C2, nt, nu, "C2"}, {&J->H, nt, nt, "H"},  {&J->Q2, np, nu, "Q2"},
+      {&J->T, np, np, "T"}};
+  for (const auto& e : b) {
+    if (e.m->nrows != e.r || e.m->ncols != e.c)
+      throw Error(FPC_ERR_DIM, std::string(e.name) + ": shape mismatch");
+    if (e.m->nnz < 0 || !e.m->rowptr ||
+        (e.m->nnz > 0 && (!e.m->colind || !e.m->val)))
+      throw Error(FPC_ERR_ARG, std::string(e.name) + ": null array");
+  }
+}
+
+// The seven blocks from the caller into handle-owned device CSR, checked.
+void upload_blocks(fpc_handle* h, const fpc_block_system* J) {
+  hipStream_t s = h->stream;
+  const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
+  upload_csr(J->A, J->ptr_space, nu, nu, h->A, s, "A");
+  upload_csr(J->C1, J->ptr_space, nu, nt, h->C1, s, "C1");
+  upload_csr(J->Q1, J->ptr_space, nu, np, h->Q1, s, "Q1");
+  upload_csr(J->C2, J->ptr_space, nt, nu, h->C2, s, "C2");
+  upload_csr(J->H, J->ptr_space, nt, nt, h->H, s, "H");
+  upload_csr(J->Q2, J->ptr_space, np, nu, h->Q2, s, "Q2");
+  upload_csr(J->T, J->ptr_space, np, np, h->T, s, "T");
+  for (const Csr* m : {&h->A, &h->C1, &h->Q1, &h->C2, &h->H, &h->Q2, &h->T})
+    csr_validate(*m, h->flags.p, s);
+}
+
+// Alg 3.3 cpt_tup / Alg 3.1 cpt_tpu on the uploaded blocks.  `prev`: the
+// previous hierarchy, whose pattern-only parts are reused when the level-0
+// block pattern is unchanged.
+void construct(fpc_handle* h, Hierarchy* prev, double t0) {
+  hipStream_t s = h->stream;
+  const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
+  h->has_q2 = h->Q2.nnz > 0;
+  const double t1 = now_s();
+  // H~ = Bdiag(H, 3) and its inverse
+  h->hinv.alloc(std::max<int64_t>(np * 9, 1));
+  hinv_setup(h->H, np, h->hinv.p, h->flags.p, s);
+  check_flags(h, "H~ = Bdiag(H,3)");
+  // S1 = A + C1 (H~^{-1} C2)
+  Bsr C1b, Xb, CX, S1;
+  h->Ab = Bsr();
+  csr_to_bsr(h->A, 3, 3, h->Ab, s);
+  csr_to_bsr(h->C1, 3, 3, C1b, s);
+  csr_to_bsr(h->C2, 3, 3, Xb, s);
+  bsr_block_row_scale(Xb, h->hinv.p, s);
+  spgemm(C1b, Xb, CX, h->flags.p, s);
+  bsr_add(h->Ab, CX, S1, s);
+  check_flags(h, "S1 = A + C1 H~^-1 C2");
+  if (h->has_q2 && h->opt.mode != FPC_TPU) {
+    // Alg 3.3: [S_K]_k = Q2^(k)T S1^(k)^-1 Q1^(k)
+    Csr Q1T;
+    csr_transpose(h->Q1, Q1T, s);
+    h->S_K.alloc(std::max<int64_t>(np, 1));
+    fixed_stress(S1, Q1T, h->Q2, h->S_K.p, h->flags.p, s);
+    check_flags(h, "fixed stress FS(Q2, S1, Q1)");
+  } else if (h->has_q2) {
+    // Alg 3.1: S~ = S1 - Q1 T~^-1 Q2, T~ = diag(T)
+    Bsr Q1b, Q2b, QQ, St;
+    csr_to_bsr(h->Q1, 3, 1, Q1b, s);
+    csr_to_bsr(h->Q2, 1, 3, Q2b, s);
+    bsr_row_scale_inv_diag(Q2b, h->T, -1.0, h->flags.p, s);
+    spgemm(Q1b, Q2b, QQ, h->flags.p, s);
+    bsr_add(S1, QQ, St, s);
+    S1 = std::move(St);
+    check_flags(h, "S~ = S1 - Q1 T~^-1 Q2");
+  }
+  bsr_to_sell(h->Ab, h->sAJ, s);
+  // the previous hierarchy is reusable iff the operator it was built on has
+  // the same block pattern (values and contact states may differ)
+  if (prev) {
+    const Bsr* A0 = prev->L.empty() ? nullptr : &prev->L[0].A;
+    const bool same = A0 && A0->nbr == S1.nbr && A0->nnzb == S1.nnzb &&
+                      same_pattern(A0->rowptr.p, A0->col.p, S1.rowptr.p,
+                                   S1.col.p, S1.nbr, S1.nnzb, s);
+    if (!same) prev = nullptr;
+  }
+  h->reused_hierarchy = prev != nullptr;
+  const double t2 = now_s();
+  build_psolve(h);
+  const double t3 = now_s();
+  build_hierarchy(h, std::move(S1), prev);
+  const double t4 = now_s();
+  h->t_t.alloc(std::max<int64_t>(nt, 1));
+  h->tmp_p.alloc(std::max<int64_t>(np, 1));
+  if (h->has_q2) {
+    h->tmp_u.alloc(nu);
+    h->tmp_p2.alloc(std::max<int64_t>(np, 1));
+  }
+  h->scratchN.alloc(h->N);
+  // work vectors of the solve path, so that solves allocate nothing
+  ensure_krylov(h, h->kry1, 1);
+  if (h->opt.precision == FPC_FP32_PREC) cycle_vecs<float>(h->amg, 1);
+  else cycle_vecs<double>(h->amg, 1);
+  FPC_HIP(hipStreamSynchronize(s));
+  h->ready = true;
+  h->setup_times[0] = t4 - t0;
+  h->setup_times[1] = t1 - t0;
+  h->setup_times[2] = t2 - t1;
+  h->setup_times[3] = t3 - t2;
+  h->setup_times[4] = t4 - t3;
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -1103,13 +1258,7 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
     h->n_p = np;
     h->N = nu + nt + np;
     fill_i32(h->flags.p, 0, FLAG_COUNT, s);
-    upload_csr(J->A, J->ptr_space, nu, nu, h->A, s, "A");
-    upload_csr(J->C1, J->ptr_space, nu, nt, h->C1, s, "C1");
-    upload_csr(J->Q1, J->ptr_space, nu, np, h->Q1, s, "Q1");
-    upload_csr(J->C2, J->ptr_space, nt, nu, h->C2, s, "C2");
-    upload_csr(J->H, J->ptr_space, nt, nt, h->H, s, "H");
-    upload_csr(J->Q2, J->ptr_space, np, nu, h->Q2, s, "Q2");
-    upload_csr(J->T, J->ptr_space, np, np, h->T, s, "T");
+    upload_blocks(h, J);
     h->has_coords = J->coords != nullptr;
     if (h->has_coords) {
       h->coords.alloc(nu);
@@ -1119,67 +1268,8 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
                              s));
       check_finite(h->coords.p, nu, h->flags.p, s);
     }
-    for (const Csr* m : {&h->A, &h->C1, &h->Q1, &h->C2, &h->H, &h->Q2, &h->T})
-      csr_validate(*m, h->flags.p, s);
     check_flags(h, "input");
-    h->has_q2 = h->Q2.nnz > 0;
-    const double t1 = now_s();
-    // H~ = Bdiag(H, 3) and its inverse
-    h->hinv.alloc(std::max<int64_t>(np * 9, 1));
-    hinv_setup(h->H, np, h->hinv.p, h->flags.p, s);
-    check_flags(h, "H~ = Bdiag(H,3)");
-    // S1 = A + C1 (H~^{-1} C2)
-    Bsr C1b, Xb, CX, S1;
-    h->Ab = Bsr();
-    csr_to_bsr(h->A, 3, 3, h->Ab, s);
-    csr_to_bsr(h->C1, 3, 3, C1b, s);
-    csr_to_bsr(h->C2, 3, 3, Xb, s);
-    bsr_block_row_scale(Xb, h->hinv.p, s);
-    spgemm(C1b, Xb, CX, h->flags.p, s);
-    bsr_add(h->Ab, CX, S1, s);
-    check_flags(h, "S1 = A + C1 H~^-1 C2");
-    if (h->has_q2 && h->opt.mode != FPC_TPU) {
-      // Alg 3.3: [S_K]_k = Q2^(k)T S1^(k)^-1 Q1^(k)
-      Csr Q1T;
-      csr_transpose(h->Q1, Q1T, s);
-      h->S_K.alloc(std::max<int64_t>(np, 1));
-      fixed_stress(S1, Q1T, h->Q2, h->S_K.p, h->flags.p, s);
-      check_flags(h, "fixed stress FS(Q2, S1, Q1)");
-    } else if (h->has_q2) {
-      // Alg 3.1: S~ = S1 - Q1 T~^-1 Q2, T~ = diag(T)
-      Bsr Q1b, Q2b, QQ, St;
-      csr_to_bsr(h->Q1, 3, 1, Q1b, s);
-      csr_to_bsr(h->Q2, 1, 3, Q2b, s);
-      bsr_row_scale_inv_diag(Q2b, h->T, -1.0, h->flags.p, s);
-      spgemm(Q1b, Q2b, QQ, h->flags.p, s);
-      bsr_add(S1, QQ, St, s);
-      S1 = std::move(St);
-      check_flags(h, "S~ = S1 - Q1 T~^-1 Q2");
-    }
-    bsr_to_sell(h->Ab, h->sAJ, s);
-    const double t2 = now_s();
-    build_psolve(h);
-    const double t3 = now_s();
-    build_hierarchy(h, std::move(S1));
-    const double t4 = now_s();
-    h->t_t.alloc(std::max<int64_t>(nt, 1));
-    h->tmp_p.alloc(std::max<int64_t>(np, 1));
-    if (h->has_q2) {
-      h->tmp_u.alloc(nu);
-      h->tmp_p2.alloc(std::max<int64_t>(np, 1));
-    }
-    h->scratchN.alloc(h->N);
-    // work vectors of the solve path, so that solves allocate nothing
-    ensure_krylov(h, h->kry1, 1);
-    if (h->opt.precision == FPC_FP32_PREC) cycle_vecs<float>(h->amg, 1);
-    else cycle_vecs<double>(h->amg, 1);
-    FPC_HIP(hipStreamSynchronize(s));
-    h->ready = true;
-    h->setup_times[0] = t4 - t0;
-    h->setup_times[1] = t1 - t0;
-    h->setup_times[2] = t2 - t1;
-    h->setup_times[3] = t3 - t2;
-    h->setup_times[4] = t4 - t3;
+    construct(h, nullptr, t0);
   });
 }
 
@@ -1191,6 +1281,27 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
       return FPC_ERR_STATE;                                   \
     }                                                         \
   } while (0)
+
+fpc_status fpc_update_values(fpc_handle* h, const fpc_block_system* J) {
+  FPC_REQUIRE_READY(h);
+  if (!J) return FPC_ERR_ARG;
+  return guard(h, [&] {
+    const double t0 = now_s();
+    if (J->n_u != h->n_u || J->n_t != h->n_t || J->n_p != h->n_p)
+      throw Error(FPC_ERR_DIM, "fpc_update_values: sizes differ from the setup");
+    if (J->ptr_space != FPC_HOST && J->ptr_space != FPC_DEVICE)
+      throw Error(FPC_ERR_ARG, "ptr_space");
+    check_block_shapes(J);
+    h->ready = false;
+    h->have_T = false;
+    fill_i32(h->flags.p, 0, FLAG_COUNT, h->stream);
+    upload_blocks(h, J);
+    check_flags(h, "input");
+    Hierarchy prev = std::move(h->amg);
+    h->amg = Hierarchy();
+    construct(h, &prev, t0);
+  });
+}
 
 fpc_status fpc_apply_prec(fpc_handle* h, const double* w, double* v) {
   FPC_REQUIRE_READY(h);
@@ -1308,6 +1419,10 @@ fpc_status fpc_stream_triad(fpc_handle* h, int64_t n, const double* b,
                             const double* c, double scalar, double* a) {
   if (!h || n < 0 || (n && (!a || !b || !c))) return FPC_ERR_ARG;
   return guard(h, [&] { stream_triad(b, c, scalar, a, n, h->stream); });
+}
+
+int fpc_hierarchy_reused(const fpc_handle* h) {
+  return h ? (h->reused_hierarchy ? 1 : 0) : -1;
 }
 
 int fpc_num_levels(const fpc_handle* h) {

@@ -1189,10 +1189,8 @@ void ptent_bsr(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
   FPC_LAUNCH_CHECK();
 }
 
-void smooth_prolongator(Bsr& AP, const int32_t* agg, const double* ptent,
-                        const double* dinv, double omega, hipStream_t s) {
-  (void)agg;
-  (void)ptent;
+void smooth_prolongator(Bsr& AP, const double* dinv, double omega,
+                        hipStream_t s) {
   if (AP.nbr == 0) return;
   k_neg_row_scale<<<grid_for(AP.nbr, 128), 128, 0, s>>>(
       AP.rowptr.p, AP.val.p, AP.nbr, AP.br, AP.bc, dinv, omega);

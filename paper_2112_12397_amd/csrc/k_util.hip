@@ -265,6 +265,25 @@ void stream_triad(const double* b, const double* c, double scalar, double* a,
   FPC_LAUNCH_CHECK();
 }
 
+template <typename I>
+__global__ void k_neq(const I* a, const I* b, int64_t n, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && a[i] != b[i]) atomicOr(flag, 1);
+}
+
+bool same_pattern(const int64_t* rp_a, const int32_t* col_a,
+                  const int64_t* rp_b, const int32_t* col_b, int64_t nrows,
+                  int64_t nnz, hipStream_t s) {
+  DevBuf<int> f(1);
+  FPC_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
+  k_neq<int64_t><<<grid_for(nrows + 1, 256), 256, 0, s>>>(rp_a, rp_b,
+                                                          nrows + 1, f.p);
+  if (nnz > 0)
+    k_neq<int32_t><<<grid_for(nnz, 256), 256, 0, s>>>(col_a, col_b, nnz, f.p);
+  FPC_LAUNCH_CHECK();
+  return read_i32(f.p, s) == 0;
+}
+
 double read_f64(const double* p, hipStream_t s) {
   double v = 0;
   FPC_HIP(hipMemcpyAsync(&v, p, sizeof(double), hipMemcpyDeviceToHost, s));

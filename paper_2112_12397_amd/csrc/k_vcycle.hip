@@ -906,6 +906,22 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
   if (best_us) *best_us = 1e3 * tbest;
   FPC_HIP(hipStreamSynchronize(s));
 }
+template <typename T>
+void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s) {
+  out = Op<T>();
+  if (choice == 1) {
+    out.fmt = 0;
+    bsr_to_sell(M, out.s, s);
+  } else if (choice == 4 || choice == 16 || choice == 64) {
+    out.fmt = 1;
+    bsr_to_vrow(M, choice, out.v, s);
+  } else {
+    throw Error(FPC_ERR_ARG, "build_op: unknown layout");
+  }
+}
+template void build_op<double>(const Bsr&, int, Op<double>&, hipStream_t);
+template void build_op<float>(const Bsr&, int, Op<float>&, hipStream_t);
+
 template void tune_op<double>(const Bsr&, int, Op<double>&, hipStream_t, int*,
                               double*);
 template void tune_op<float>(const Bsr&, int, Op<float>&, hipStream_t, int*,

@@ -91,7 +91,8 @@ EXPORTS = ("fpc_default_options", "fpc_create", "fpc_setup", "fpc_apply_prec",
            "fpc_num_levels", "fpc_level_info", "fpc_export_aggregates",
            "fpc_export_level_matrix", "fpc_setup_times", "fpc_destroy",
            "fpc_status_string", "fpc_last_error", "fpc_hash32_device",
-           "fpc_kernel_timer", "fpc_psolve", "fpc_stream_triad")
+           "fpc_kernel_timer", "fpc_psolve", "fpc_stream_triad",
+           "fpc_update_values", "fpc_hierarchy_reused")
 
 _lib = None
 
@@ -112,6 +113,8 @@ def load_library(path: str = LIB_PATH):
         "fpc_default_options": (None, [C.POINTER(FpcOptions)]),
         "fpc_create": (i32, [C.POINTER(H), C.POINTER(FpcOptions), vp]),
         "fpc_setup": (i32, [H, C.POINTER(FpcBlockSystem)]),
+        "fpc_update_values": (i32, [H, C.POINTER(FpcBlockSystem)]),
+        "fpc_hierarchy_reused": (i32, [H]),
         "fpc_apply_prec": (i32, [H, vp, vp]),
         "fpc_apply_prec_T": (i32, [H, vp, vp]),
         "fpc_matvec": (i32, [H, i32, vp, vp]),
@@ -230,6 +233,22 @@ class Solver:
 
     def setup(self, blocks, coords=None):
         """(Re)build the preconditioner for a new Jacobian."""
+        sysm, keep = self._system(blocks, coords)
+        self._check(self.lib.fpc_setup(self.h, C.byref(sysm)), "fpc_setup")
+        del keep
+
+    def update_values(self, blocks):
+        """Numeric re-setup for a new Jacobian of the same sizes (next Newton
+        or active-set iteration); the setup's coordinates are kept."""
+        sysm, keep = self._system(blocks, None)
+        self._check(self.lib.fpc_update_values(self.h, C.byref(sysm)),
+                    "fpc_update_values")
+        del keep
+
+    def hierarchy_reused(self):
+        return bool(self.lib.fpc_hierarchy_reused(self.h) == 1)
+
+    def _system(self, blocks, coords):
         keep = []
         first = blocks["A"]
         device = isinstance(first, tuple)
@@ -257,8 +276,7 @@ class Solver:
                 keep.append(X)
                 sysm.coords = X.ctypes.data
         sysm.ptr_space = FPC_DEVICE if device else FPC_HOST
-        self._check(self.lib.fpc_setup(self.h, C.byref(sysm)), "fpc_setup")
-        del keep
+        return sysm, keep
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

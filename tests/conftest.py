@@ -24,3 +24,12 @@ def gpu_available():
 @pytest.fixture(scope="session")
 def has_gpu():
     return gpu_available()
+
+
+@pytest.fixture(scope="session")
+def torch():
+    """The torch module, for GPU tests (skips without a GPU)."""
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
