@@ -798,11 +798,21 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
       apply(h, trans, vj, zj);
       matvec(h, trans, zj, K.w.p);
       mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
-      // classical Gram-Schmidt, twice
-      mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
-      maxpy(K.V.p, N, j + 1, K.h1.p, K.w.p, N, s);
-      mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h2.p, s);
-      maxpy(K.V.p, N, j + 1, K.h2.p, K.w.p, N, s);
+      if (h->opt.ortho == FPC_MGS) {
+        // modified Gram-Schmidt: h_ij = v_i^T w with the w of step i
+        for (int i = 0; i <= j; ++i) {
+          const double* vi = K.V.p + (int64_t)i * N;
+          mdot(vi, N, 1, K.w.p, N, K.partials.p, K.h1.p + i, s);
+          maxpy(vi, N, 1, K.h1.p + i, K.w.p, N, s);
+        }
+        FPC_HIP(hipMemsetAsync(K.h2.p, 0, (j + 1) * sizeof(double), s));
+      } else {
+        // classical Gram-Schmidt, twice
+        mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
+        maxpy(K.V.p, N, j + 1, K.h1.p, K.w.p, N, s);
+        mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h2.p, s);
+        maxpy(K.V.p, N, j + 1, K.h2.p, K.w.p, N, s);
+      }
       mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 5, s);
       gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
                  sc + 4, j, sc, K.ctrl.p, s);
@@ -1197,6 +1207,7 @@ void fpc_default_options(fpc_options* o) {
   o->rtol = 1e-8;
   o->max_batch = 32;
   o->graphs = 1;
+  o->ortho = FPC_CGS2;
   o->amg.max_coarse = 2000;
   o->amg.max_levels = 12;
   o->amg.cheb_degree = 2;
@@ -1224,7 +1235,8 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
       o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
       o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 ||
-      (o.graphs != 0 && o.graphs != 1)) {
+      (o.graphs != 0 && o.graphs != 1) ||
+      (o.ortho != FPC_CGS2 && o.ortho != FPC_MGS)) {
     delete h;
     return FPC_ERR_ARG;
   }

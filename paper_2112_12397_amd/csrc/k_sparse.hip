@@ -462,6 +462,33 @@ __global__ void k_slice_len(const int64_t* rowptr, int64_t nrows,
   slots[s] = m * kSliceH;
 }
 
+// 3x3 blocks whose row and column i0 are zero off the diagonal (a zero
+// pattern that is common in stiffness blocks) are stored as five values,
+// (m[i0][i0], m[i1][i1], m[i1][i2], m[i2][i1], m[i2][i2]) with i1 < i2 the
+// other two indices, in the first five value planes of their slot; the class
+// (0 full, 1 + i0 packed) sits in bits 30-31 of the column index.
+__device__ inline int class33(const double* v) {
+#pragma unroll
+  for (int i0 = 0; i0 < 3; ++i0) {
+    bool zero = true;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j != i0) zero = zero && v[i0 * 3 + j] == 0.0 && v[j * 3 + i0] == 0.0;
+    if (zero) return 1 + i0;
+  }
+  return 0;
+}
+
+__device__ inline void pack33(const double* v, int cls, double* p) {
+  const int i0 = cls - 1;
+  const int i1 = i0 == 0 ? 1 : 0, i2 = i0 == 2 ? 1 : 2;
+  p[0] = v[i0 * 3 + i0];
+  p[1] = v[i1 * 3 + i1];
+  p[2] = v[i1 * 3 + i2];
+  p[3] = v[i2 * 3 + i1];
+  p[4] = v[i2 * 3 + i2];
+}
+
 template <typename T, int B>
 __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
                             const double* val, int64_t nrows,
@@ -475,18 +502,45 @@ __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
   const int64_t a = rowptr[r];
   const int len = (int)(rowptr[r + 1] - a);
   row_len[r] = len;
-  for (int k = 0; k < len; ++k) {
-    const int64_t grp = base + (int64_t)k * kSliceH;
-    scol[grp + l] = col[a + k];
-    T* dst = sval + grp * B + l;
+  int32_t cbits = 0;
+  if constexpr (B == 9) {
+    // full blocks first, then the packed ones (each group in column order),
+    // so that the slots of neighbouring rows tend to agree on their class
+    int k = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int e = 0; e < len; ++e) {
+        const double* v = val + (a + e) * 9;
+        const int cls = class33(v);
+        if ((cls == 0) != (pass == 0)) continue;
+        const int64_t grp = base + (int64_t)k * kSliceH;
+        scol[grp + l] = (int32_t)((uint32_t)col[a + e] | ((uint32_t)cls << 30));
+        T* dst = sval + grp * 9 + l;
+        if (cls == 0) {
 #pragma unroll
-    for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
+          for (int q = 0; q < 9; ++q) dst[q * kSliceH] = (T)v[q];
+        } else {
+          double p[5];
+          pack33(v, cls, p);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) dst[q * kSliceH] = (T)p[q];
+        }
+        ++k;
+      }
+    cbits = (int32_t)(1u << 30);  // padding slots: packed zeros
+  } else {
+    for (int k = 0; k < len; ++k) {
+      const int64_t grp = base + (int64_t)k * kSliceH;
+      scol[grp + l] = col[a + k];
+      T* dst = sval + grp * B + l;
+#pragma unroll
+      for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
+    }
   }
   // padding slots up to the slice's longest row keep zero values and repeat
   // the row's last column (column 0 for an empty row), so a product may read
   // them unguarded: a padded term adds 0 * x[c] for a c the row already uses
   const int maxlen = (int)((slice_ptr[s + 1] - base) / kSliceH);
-  const int32_t cpad = len > 0 ? col[a + len - 1] : 0;
+  const int32_t cpad = (len > 0 ? col[a + len - 1] : 0) | cbits;
   for (int k = len; k < maxlen; ++k) scol[base + (int64_t)k * kSliceH + l] = cpad;
 }
 
@@ -655,6 +709,8 @@ void to_sell_impl(const Bsr& a, Sell<T>& out, hipStream_t s) {
   out.nrows = a.nbr;
   out.nnzb = a.nnzb;
   out.nslices = (a.nbr + kSliceH - 1) / kSliceH;
+  if (B == 9 && a.nbc >= (int64_t(1) << 30))
+    throw Error(FPC_ERR_UNSUPPORTED, "sliced ELL: 2^30 block columns or more");
   DevBuf<int64_t> slots(std::max<int64_t>(out.nslices, 1));
   out.slice_ptr.alloc(out.nslices + 1);
   if (out.nslices)

@@ -234,6 +234,41 @@ __device__ __forceinline__ T ld_stream(const T* p) {
   return __builtin_nontemporal_load(p);
 }
 
+// 3x3 sliced-ELL slots carry a class in bits 30-31 of the column index:
+// 0 = nine values, 1 + i0 = five values (row and column i0 zero off the
+// diagonal; planes m[i0][i0], m[i1][i1], m[i1][i2], m[i2][i1], m[i2][i2]).
+// Only full slots read value planes 5-8.
+__device__ __forceinline__ int slot_col(int32_t raw) { return raw & 0x3fffffff; }
+__device__ __forceinline__ int slot_class(int32_t raw) {
+  return (int)((uint32_t)raw >> 30);
+}
+
+template <typename T>
+__device__ __forceinline__ void load33(const T* __restrict__ vb, int cls,
+                                       T* m) {
+  T p[9];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) p[q] = ld_stream(vb + q * kSliceH);
+  if (cls == 0) {
+#pragma unroll
+    for (int q = 5; q < 9; ++q) p[q] = ld_stream(vb + q * kSliceH);
+  } else {
+#pragma unroll
+    for (int q = 5; q < 9; ++q) p[q] = T(0);
+  }
+  const bool f = cls == 0;
+  const T z = T(0);
+  m[0] = (f || cls == 1) ? p[0] : p[1];
+  m[1] = f ? p[1] : (cls == 3 ? p[2] : z);
+  m[2] = f ? p[2] : (cls == 2 ? p[2] : z);
+  m[3] = f ? p[3] : (cls == 3 ? p[3] : z);
+  m[4] = f ? p[4] : (cls == 1 ? p[1] : (cls == 2 ? p[0] : p[4]));
+  m[5] = f ? p[5] : (cls == 1 ? p[2] : z);
+  m[6] = f ? p[6] : (cls == 2 ? p[3] : z);
+  m[7] = f ? p[7] : (cls == 1 ? p[3] : z);
+  m[8] = f ? p[8] : (cls == 3 ? p[0] : p[4]);
+}
+
 // Few columns (NV <= 2): one wavefront per 64-row slice, one thread per block
 // row carrying all NV columns, so each matrix block is read by one lane only.
 // Every lane runs to the slice's longest row: padding slots hold zero values
@@ -245,6 +280,7 @@ template <typename T, int BR, int BC, int NV, class Load, class Epi>
 __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
                                                    Epi epi) {
   constexpr int U = BR * BC <= 9 ? 3 : (BR * BC <= 18 ? 2 : 1);
+  constexpr bool kPacked33 = BR == 3 && BC == 3;
   const int slice = __builtin_amdgcn_readfirstlane(
       (int)(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
   if (slice >= A.nslices) return;
@@ -272,13 +308,18 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (k0 + u < maxlen) {
+        const int64_t col = kPacked33 ? slot_col(cc[u]) : cc[u];
 #pragma unroll
         for (int j = 0; j < BC; ++j)
 #pragma unroll
-          for (int v = 0; v < NV; ++v) xv[u][j][v] = ld((int64_t)cc[u] * BC + j, v);
+          for (int v = 0; v < NV; ++v) xv[u][j][v] = ld(col * BC + j, v);
         const T* __restrict__ vb = vp + (int64_t)(k0 + u) * kSliceH * (BR * BC);
+        if constexpr (kPacked33) {
+          load33(vb, slot_class(cc[u]), a[u]);
+        } else {
 #pragma unroll
-        for (int q = 0; q < BR * BC; ++q) a[u][q] = ld_stream(vb + q * kSliceH);
+          for (int q = 0; q < BR * BC; ++q) a[u][q] = ld_stream(vb + q * kSliceH);
+        }
       } else {
 #pragma unroll
         for (int j = 0; j < BC; ++j)
@@ -332,15 +373,23 @@ __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
   for (int i = 0; i < BR; ++i) acc[i] = T(0);
 #pragma unroll 2
   for (int k = 0; k < len; ++k) {
-    const int64_t c = cp[(int64_t)k * kSliceH];
+    const int32_t raw = cp[(int64_t)k * kSliceH];
+    const int64_t c = (BR == 3 && BC == 3) ? slot_col(raw) : raw;
     const T* __restrict__ vb = vp + (int64_t)k * kSliceH * (BR * BC);
     T xv[BC];
 #pragma unroll
     for (int j = 0; j < BC; ++j) xv[j] = ld(c * BC + j, v);
+    T m[BR * BC];
+    if constexpr (BR == 3 && BC == 3) {
+      load33(vb, slot_class(raw), m);
+    } else {
+#pragma unroll
+      for (int q = 0; q < BR * BC; ++q) m[q] = vb[q * kSliceH];
+    }
 #pragma unroll
     for (int i = 0; i < BR; ++i)
 #pragma unroll
-      for (int j = 0; j < BC; ++j) acc[i] += vb[(i * BC + j) * kSliceH] * xv[j];
+      for (int j = 0; j < BC; ++j) acc[i] += m[i * BC + j] * xv[j];
   }
   epi_col<T, BR, NV>(epi, row, v, acc);
 }

@@ -51,3 +51,43 @@ def test_default_options_and_status_strings():
     # calls on a null handle fail cleanly
     assert lib.fpc_apply_prec(None, None, None) == -1
     assert lib.fpc_num_levels(None) == 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the sizes and field offsets
+    the C compiler gives the header's definitions."""
+    import shutil
+    import subprocess
+    from paper_2112_12397_amd import fracprec as F
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"fpc_csr": F.FpcCsr, "fpc_block_system": F.FpcBlockSystem,
+               "fpc_amg_options": F.FpcAmgOptions, "fpc_options": F.FpcOptions,
+               "fpc_info": F.FpcInfo, "fpc_level_desc": F.FpcLevelDesc,
+               "fpc_flow_graph": F.FpcFlowGraph}
+    lines = ['#include <stdio.h>', '#include <stddef.h>',
+             '#include "fracprec.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", '
+                         f'offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            parts = line.split()
+            got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, \
+                (cname, fname)

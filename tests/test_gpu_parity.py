@@ -236,6 +236,21 @@ def _check_solve(torch, s, pc, sol):
     assert _rel(x, xo) <= 1e-5
 
 
+@pytest.mark.parametrize("name", ["tiny_slip_cross", "c1", "c1o"])
+def test_solve_mgs(torch, name):
+    """FGMRES with modified Gram-Schmidt against the oracle's textbook
+    FGMRES (MGS): same iteration count within 2, same solution."""
+    from paper_2112_12397_amd import solver_from_system
+    s, pc, _ = _get(name)
+    mc = _cases()[name][1]
+    sol = solver_from_system(s, ortho="mgs", amg={"max_coarse": mc})
+    x, info = sol.solve(torch.tensor(s.b, device="cuda"))
+    xo, io = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8, ortho="mgs")
+    assert info["converged"] == 1 and info["true_rel_residual"] <= 1e-8
+    assert abs(info["iterations"] - io.iterations) <= 2
+    assert _rel(x.cpu().numpy(), xo) <= 1e-5
+
+
 def test_fp32_preconditioner(torch):
     s, pc, sol64 = _get("c1")
     _, _, sol32 = _get("c1", precision="fp32")
