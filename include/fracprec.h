@@ -62,6 +62,10 @@ enum { FPC_HOST = 0, FPC_DEVICE = 1 };
  * remark after Prop 3.2: one AMG call per application). */
 enum { FPC_TUP = 0, FPC_TPU = 1, FPC_TUP_STAR = 2 };
 enum { FPC_FP64 = 0, FPC_FP32_PREC = 1 };
+/* Arnoldi orthogonalization of the single-right-hand-side FGMRES: classical
+ * Gram-Schmidt applied twice (two multi-dot passes per iteration) or the
+ * textbook modified Gram-Schmidt (j + 1 dependent dot products). */
+enum { FPC_CGS2 = 0, FPC_MGS = 1 };
 
 /* Compressed sparse rows, 0-based, column indices strictly increasing in
  * every row.  Arrays live in host or device memory (fpc_block_system.ptr_space)
@@ -106,6 +110,8 @@ typedef struct {
   int max_batch;           /* right-hand sides per fpc_solve_batch (32)     */
   int graphs;              /* 1: the batched V-cycle is captured once into  */
                            /* a HIP graph and replayed (default); 0: eager  */
+  int ortho;               /* FPC_CGS2 (default) or FPC_MGS; batched solves */
+                           /* always use CGS2                               */
   fpc_amg_options amg;
 } fpc_options;
 

@@ -52,7 +52,8 @@ class FpcOptions(C.Structure):
     _fields_ = [("mode", C.c_int), ("precision", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int),
                 ("rtol", C.c_double), ("max_batch", C.c_int),
-                ("graphs", C.c_int), ("amg", FpcAmgOptions)]
+                ("graphs", C.c_int), ("ortho", C.c_int),
+                ("amg", FpcAmgOptions)]
 
 
 class FpcInfo(C.Structure):
@@ -161,6 +162,8 @@ def default_options(**kw) -> FpcOptions:
         if k == "mode":
             v = {"tup": FPC_TUP, "tpu": FPC_TPU,
                  "tup_star": FPC_TUP_STAR}.get(v, v)
+        if k == "ortho":
+            v = {"cgs2": 0, "mgs": 1}.get(v, v)
         if k == "precision":
             v = {"fp64": FPC_FP64, "fp32": FPC_FP32_PREC,
                  "fp32prec": FPC_FP32_PREC}.get(v, v)
