@@ -723,9 +723,16 @@ __global__ __launch_bounds__(256) void k_gj_colpanel(double* D, int64_t ld,
 }
 
 // Logical index l -> physical index: the range [at, at + len) is skipped.
+// Logical -> stored row (or column) index of a GEMM operand: either the
+// identity with the range [at, at + len) skipped, or (tiles != null) the
+// 64-row tiles listed in `tiles`, in order.
 struct SkipMap {
   int64_t at, len;
-  __device__ int64_t operator()(int64_t l) const { return l < at ? l : l + len; }
+  const int32_t* tiles = nullptr;
+  __device__ int64_t operator()(int64_t l) const {
+    if (tiles) return (int64_t)tiles[l >> 6] * 64 + (l & 63);
+    return l < at ? l : l + len;
+  }
 };
 
 // C[rm(i), cm(j)] = alpha * sum_k A[rm(i), k] B[k, cm(j)] + beta * C[..]
@@ -1222,6 +1229,56 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
   FPC_LAUNCH_CHECK();
 }
 
+// flag[t] = 1 if rows 64t .. 64t+63 of the n x w row-major panel P hold a
+// nonzero (tiles inside [skip_at, skip_at + skip_len) are left 0).
+__global__ __launch_bounds__(256) void k_tile_nonzero(const double* P, int64_t w,
+                                                      int64_t skip_at,
+                                                      int64_t skip_len,
+                                                      int32_t* flag) {
+  __shared__ int any;
+  const int64_t t = blockIdx.x;
+  const int64_t r0 = t * 64;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const bool skipped = r0 >= skip_at && r0 < skip_at + skip_len;
+  if (!skipped) {
+    int nz = 0;
+    for (int64_t q = threadIdx.x; q < 64 * w; q += 256)
+      nz |= P[(r0 + q / w) * w + q % w] != 0.0;
+    if (nz) any = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flag[t] = skipped ? 0 : any;
+}
+
+// list = indices t with flag[t] = 1, ascending; count[0] = their number
+// (one workgroup; nt <= 65536).
+__global__ __launch_bounds__(256) void k_tile_compact(const int32_t* flag,
+                                                      int64_t nt, int32_t* list,
+                                                      int32_t* count) {
+  __shared__ int32_t part[256];
+  const int tid = threadIdx.x;
+  const int64_t per = (nt + 255) / 256;
+  const int64_t a = tid * per, b = a + per < nt ? a + per : nt;
+  int32_t c = 0;
+  for (int64_t t = a; t < b; ++t) c += flag[t];
+  part[tid] = c;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const int32_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    count[0] = run;
+  }
+  __syncthreads();
+  int32_t o = part[tid];
+  for (int64_t t = a; t < b; ++t)
+    if (flag[t]) list[o++] = (int32_t)t;
+}
+
 // Inverse of a symmetric matrix by block sweeps (Goodnight's sweep operator
 // in 256-wide panels), in place, touching only the lower triangle: sweeping
 // block k with panel P (the off-diagonal part of block column k) and
@@ -1229,12 +1286,20 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
 // D_kk <- -D_kk^-1; after all blocks the lower triangle holds -A^{-1}, which
 // the last pass mirrors and negates.  Half the flops of Gauss-Jordan (the
 // trailing products cover the lower triangle only); no pivoting (a zero
-// pivot of a diagonal block is reported).
+// pivot of a diagonal block is reported).  The trailing product only visits
+// the 64-row tiles where the panel P has a nonzero: Z_i P_j^T is exactly zero
+// when P_i or P_j is, so the skipped tiles are exactly the unchanged ones.
+// For a sparse matrix swept in a banded order the unswept part away from the
+// band keeps its zeros, and the product shrinks to the swept rows and the
+// band (about a third of the dense flops for a 2D face graph).
 void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
   if (n % GT) throw Error(FPC_ERR_ARG, "sym_inverse: size not a multiple of 64");
   constexpr int64_t NB = 256;
   if (n <= NB) return gj_inverse64(D, n, n, spd, flags, s);
+  const int64_t nt = n / GT;
+  if (nt > 65536) throw Error(FPC_ERR_UNSUPPORTED, "sym_inverse: order too large");
   DevBuf<double> prow(NB * n), pcol(n * NB), z(n * NB);
+  DevBuf<int32_t> tflag(nt), tlist(nt), tcount(1);
   const SkipMap none{INT64_MAX, 0};
   for (int64_t o = 0; o < n; o += NB) {
     const int64_t nb = std::min<int64_t>(NB, n - o), e = o + nb;
@@ -1259,9 +1324,16 @@ void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
     // Z = P Dkk^-1
     gemm_f64(n - nb, nb, (int)nb, 1.0, 0.0, pcol.p, nb, Dkk, n, z.p, nb, skip,
              none, s);
-    // lower trailing update D_ij -= Z_i P_j^T
-    gemm_f64(n - nb, n - nb, (int)nb, -1.0, 1.0, z.p, nb, prow.p, n, D, n,
-             skip, skip, s, /*lower=*/1);
+    // lower trailing update D_ij -= Z_i P_j^T over the tiles with P_i != 0
+    k_tile_nonzero<<<(unsigned)nt, 256, 0, s>>>(pcol.p, nb, o, nb, tflag.p);
+    k_tile_compact<<<1, 256, 0, s>>>(tflag.p, nt, tlist.p, tcount.p);
+    FPC_LAUNCH_CHECK();
+    const int64_t mt = read_i32(tcount.p, s);
+    if (mt > 0) {
+      const SkipMap sel{0, 0, tlist.p};
+      gemm_f64(mt * GT, mt * GT, (int)nb, -1.0, 1.0, z.p, nb, prow.p, n, D, n,
+               sel, sel, s, /*lower=*/1);
+    }
     // new panel Z into the lower tiles; Dkk <- -Dkk^-1
     if (e < n)
       FPC_HIP(hipMemcpy2DAsync(D + e * n + o, n * sizeof(double), z.p + e * nb,
