@@ -65,6 +65,45 @@ __global__ void k_place(const int32_t* comp, int32_t c, const int64_t* scan,
   comp_of_row[off + local] = c;
 }
 
+// Breadth-first levels of every component from its smallest face (level 0):
+// step `cur` gives level cur + 1 to the unvisited neighbours of level cur.
+__global__ void k_bfs_init(const int32_t* lab, int64_t n, int32_t* level) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) level[i] = lab[i] == i ? 0 : -1;
+}
+
+__global__ void k_bfs_step(const int64_t* rp, const int32_t* col, int64_t n,
+                           int32_t cur, int32_t* level, int* changed) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || level[i] != -1) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+    if (level[col[e]] == cur) {
+      level[i] = cur + 1;
+      atomicOr(changed, 1);
+      return;
+    }
+}
+
+// Reorder the members of every component by (BFS level, face index): the
+// rank of each member among its component's members gives its new local
+// position.
+__global__ void k_level_rank(const int32_t* members, const int64_t* comp_off,
+                             const int32_t* comp_of_row, const int32_t* level,
+                             int64_t n, int32_t* pos, int32_t* members2) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t c = comp_of_row[e];
+  const int64_t a = comp_off[c], b = comp_off[c + 1];
+  const int32_t m = members[e], lm = level[m];
+  int32_t rank = 0;
+  for (int64_t f = a; f < b; ++f) {
+    const int32_t mf = members[f], lf = level[mf];
+    rank += (lf < lm) || (lf == lm && mf < m);
+  }
+  pos[m] = rank;
+  members2[a + rank] = m;
+}
+
 __global__ void k_scatter_T(const int64_t* rp, const int32_t* col,
                             const double* val, int64_t n, const int32_t* comp,
                             const int32_t* pos, const int64_t* dense_off,
@@ -267,6 +306,30 @@ void build_psolve(fpc_handle* h) {
                          hipMemcpyHostToDevice, s));
   FPC_HIP(hipMemcpyAsync(ps.comp_pad_d.p, ps.comp_pad.data(),
                          ps.n_comp * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  // local order inside each component: breadth-first levels from its smallest
+  // face, so that the dense block is banded and the sweeps of the inverse
+  // skip the tiles that stay zero (the inverse itself does not depend on the
+  // order; the apply gathers and scatters through `members`)
+  {
+    DevBuf<int32_t> level(n), members2(n);
+    k_bfs_init<<<g, 256, 0, s>>>(la.p, n, level.p);
+    FPC_LAUNCH_CHECK();
+    for (int32_t cur = 0;; cur += 8) {
+      FPC_HIP(hipMemsetAsync(changed.p, 0, sizeof(int), s));
+      for (int32_t k = 0; k < 8; ++k)
+        k_bfs_step<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, n, cur + k, level.p,
+                                     changed.p);
+      FPC_LAUNCH_CHECK();
+      if (read_i32(changed.p, s) == 0) break;
+      if (cur > n + 8) throw Error(FPC_ERR_HIP, "level ordering stalled");
+    }
+    k_level_rank<<<g, 256, 0, s>>>(ps.members.p, ps.comp_off.p,
+                                   ps.comp_of_row.p, level.p, n, pos.p,
+                                   members2.p);
+    FPC_LAUNCH_CHECK();
+    FPC_HIP(hipMemcpyAsync(ps.members.p, members2.p, n * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+  }
   ps.dense.alloc(ps.dense_elems);
   FPC_HIP(hipMemsetAsync(ps.dense.p, 0, ps.dense.bytes(), s));
   k_scatter_T<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, T.val.p, n, comp.p, pos.p,
