@@ -1280,7 +1280,7 @@ __global__ __launch_bounds__(256) void k_tile_compact(const int32_t* flag,
 }
 
 // Inverse of a symmetric matrix by block sweeps (Goodnight's sweep operator
-// in 512-wide panels), in place, touching only the lower triangle: sweeping
+// in 1024-wide panels), in place, touching only the lower triangle: sweeping
 // block k with panel P (the off-diagonal part of block column k) and
 // D_kk^-1 gives D_ij -= P_i D_kk^-1 P_j^T, new panel P D_kk^-1 and
 // D_kk <- -D_kk^-1; after all blocks the lower triangle holds -A^{-1}, which
@@ -1294,7 +1294,7 @@ __global__ __launch_bounds__(256) void k_tile_compact(const int32_t* flag,
 // band (about a third of the dense flops for a 2D face graph).
 void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
   if (n % GT) throw Error(FPC_ERR_ARG, "sym_inverse: size not a multiple of 64");
-  constexpr int64_t NB = 512;
+  constexpr int64_t NB = 1024;
   if (n <= NB) return gj_inverse64(D, n, n, spd, flags, s);
   const int64_t nt = n / GT;
   if (nt > 65536) throw Error(FPC_ERR_UNSUPPORTED, "sym_inverse: order too large");
