@@ -3,6 +3,8 @@
 // distance-2 MIS aggregation, tentative prolongator (per-aggregate QR of the
 // rigid-body modes), prolongator smoothing, coarse dummy dofs, power-iteration
 // start vectors and the blocked Gauss-Jordan inverse of dense matrices.
+#include <type_traits>
+
 #include "fpc_internal.hpp"
 
 namespace fpc {
@@ -601,46 +603,59 @@ __global__ __launch_bounds__(256) void k_gj_diag(double* D, int64_t ld,
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       a[i][j] = D[(o + 4 * tr + i) * ld + o + 4 * tc + j];
-  for (int k = 0; k < GT; ++k) {
+  // one elimination step; the pivot's position inside the owners' 4 x 4
+  // blocks (KR) is a compile-time constant, so no register is indexed at run
+  // time
+  auto step = [&](const int k, auto kr_c) {
+    constexpr int kr = decltype(kr_c)::value;
     const int buf = k & 1;
-    const int kq = k >> 2, kr = k & 3;
+    const int kq = k >> 2;
+    // owners publish row k and column k
     if (tr == kq) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i == kr)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) rowb[buf][4 * tc + j] = a[i][j];
+      for (int j = 0; j < 4; ++j) rowb[buf][4 * tc + j] = a[kr][j];
     }
     if (tc == kq) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (j == kr)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) colb[buf][4 * tr + i] = a[i][j];
+      for (int i = 0; i < 4; ++i) colb[buf][4 * tr + i] = a[i][kr];
     }
     __syncthreads();
+    // all reads of the step issued together
     double p = rowb[buf][k];
+    double rv[4], pc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rv[j] = rowb[buf][4 * tc + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pc[i] = colb[buf][4 * tr + i];
     const bool bad = spd ? !(p > 0.0) : !(fabs(p) > 0.0);
     if (bad || !isfinite(p)) {
       if (tid == 0) atomicOr(&flags[spd ? FLAG_NOT_SPD : FLAG_SINGULAR], 1);
       p = 1.0;
     }
     const double ip = 1.0 / p;
-    double pr[4], pc[4];
+    double pr[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = 4 * tc + j;
-      pr[j] = (c == k) ? ip : rowb[buf][c] * ip;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) pc[i] = colb[buf][4 * tr + i];
+    for (int j = 0; j < 4; ++j) pr[j] = (4 * tc + j == k) ? ip : rv[j] * ip;
+    // a_rc -= a_rk a_kc / p everywhere, then the owners overwrite column k
+    // (-a_rk / p) and row k (a_kc / p, and 1 / p on the diagonal)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = 4 * tr + i, c = 4 * tc + j;
-        a[i][j] = (r == k) ? pr[j] : ((c == k) ? 0.0 : a[i][j]) - pc[i] * pr[j];
-      }
+      for (int j = 0; j < 4; ++j) a[i][j] -= pc[i] * pr[j];
+    if (tc == kq) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i][kr] = -pc[i] * ip;
+    }
+    if (tr == kq) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[kr][j] = pr[j];
+    }
+  };
+  for (int k0 = 0; k0 < GT; k0 += 4) {
+    step(k0, std::integral_constant<int, 0>{});
+    step(k0 + 1, std::integral_constant<int, 1>{});
+    step(k0 + 2, std::integral_constant<int, 2>{});
+    step(k0 + 3, std::integral_constant<int, 3>{});
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
