@@ -254,12 +254,16 @@ void build_psolve(fpc_handle* h) {
   const unsigned g = grid_for(n, 256);
   k_label_init<<<g, 256, 0, s>>>(la.p, n);
   FPC_LAUNCH_CHECK();
-  for (int it = 0;; ++it) {
+  // eight propagation steps per check of the change flag (steps after
+  // convergence change nothing)
+  for (int it = 0;; it += 8) {
     FPC_HIP(hipMemsetAsync(changed.p, 0, sizeof(int), s));
-    k_label_prop<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, la.p, lb.p, n,
-                                   changed.p);
+    for (int k = 0; k < 8; ++k) {
+      k_label_prop<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, la.p, lb.p, n,
+                                     changed.p);
+      std::swap(la, lb);
+    }
     FPC_LAUNCH_CHECK();
-    std::swap(la, lb);
     if (read_i32(changed.p, s) == 0) break;
     if (it > 4 * n + 8) throw Error(FPC_ERR_HIP, "component labelling stalled");
   }

@@ -1104,15 +1104,19 @@ int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
   const unsigned g = grid_for(n, 256);
   k_agg_init<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, prio.p, state.p, iso.p);
   FPC_LAUNCH_CHECK();
-  for (int round = 0; round < 1000; ++round) {
-    FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
-    k_key<<<g, 256, 0, s>>>(state.p, prio.p, n, key.p);
-    k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
-    k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, m1.p, m2.p);
-    k_mis_update<<<g, 256, 0, s>>>(state.p, key.p, m2.p, n, cnt.p);
+  // four rounds per check (a round after convergence changes nothing); the
+  // count is that of the batch's last round
+  for (int round = 0; round < 1000; round += 4) {
+    for (int k = 0; k < 4; ++k) {
+      if (k == 3) FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+      k_key<<<g, 256, 0, s>>>(state.p, prio.p, n, key.p);
+      k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+      k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, m1.p, m2.p);
+      k_mis_update<<<g, 256, 0, s>>>(state.p, key.p, m2.p, n, cnt.p);
+    }
     FPC_LAUNCH_CHECK();
     if (read_i32(cnt.p, s) == 0) break;
-    if (round == 999) throw Error(FPC_ERR_HIP, "MIS-2 did not terminate");
+    if (round >= 996) throw Error(FPC_ERR_HIP, "MIS-2 did not terminate");
   }
   DevBuf<int64_t> flag(n), scan(n + 1);
   k_is_root<<<g, 256, 0, s>>>(state.p, n, flag.p);

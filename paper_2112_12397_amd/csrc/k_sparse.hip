@@ -553,23 +553,26 @@ __global__ void k_vrow_count(const int64_t* rowptr, int64_t nrows, int G,
   row_len[r] = (int32_t)len;
 }
 
-// One thread per stored value: block entry e = t / B of row r (binary
-// search of rowptr), component q = t % B.
+// row of every block entry
+__global__ void k_entry_row(const int64_t* rowptr, int64_t nrows,
+                            int32_t* row) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) row[e] = (int32_t)r;
+}
+
+// One thread per stored value: block entry e = t / B of row erow[e],
+// component q = t % B.
 template <typename T, int B>
-__global__ void k_vrow_fill(const int64_t* rowptr, const int32_t* col,
-                            const double* val, int64_t nrows, int64_t nnzb,
-                            int G, const int64_t* chunk_ptr, int32_t* vcol,
-                            T* vval) {
+__global__ void k_vrow_fill(const int64_t* rowptr, const int32_t* erow,
+                            const int32_t* col, const double* val,
+                            int64_t nnzb, int G, const int64_t* chunk_ptr,
+                            int32_t* vcol, T* vval) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nnzb * B) return;
   const int64_t e = t / B;
   const int q = (int)(t - e * B);
-  int64_t lo = 0, hi = nrows;  // last row with rowptr[r] <= e
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (rowptr[mid] <= e) lo = mid;
-    else hi = mid;
-  }
+  const int64_t lo = erow[e];
   const int k = (int)(e - rowptr[lo]);
   const int64_t grp = (chunk_ptr[lo] + k / G) * G;
   const int sl = k % G;
@@ -860,10 +863,14 @@ void to_vrow_impl(const Bsr& a, int G, Vrow<T>& out, hipStream_t s) {
   out.val.alloc(std::max<int64_t>(out.nchunks * G * B, 1));
   fill_i32(out.col.p, 0, out.nchunks * G, s);
   FPC_HIP(hipMemsetAsync(out.val.p, 0, out.val.bytes(), s));
-  if (a.nnzb)
+  if (a.nnzb) {
+    DevBuf<int32_t> erow(a.nnzb);
+    k_entry_row<<<grid_for(a.nbr, 256), 256, 0, s>>>(a.rowptr.p, a.nbr,
+                                                     erow.p);
     k_vrow_fill<T, B><<<grid_for(a.nnzb * B, 256), 256, 0, s>>>(
-        a.rowptr.p, a.col.p, a.val.p, a.nbr, a.nnzb, G, out.chunk_ptr.p,
+        a.rowptr.p, erow.p, a.col.p, a.val.p, a.nnzb, G, out.chunk_ptr.p,
         out.col.p, out.val.p);
+  }
   FPC_LAUNCH_CHECK();
 }
 

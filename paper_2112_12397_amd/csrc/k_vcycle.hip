@@ -927,7 +927,7 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
                    : time_any<T, 1>(op, M.br, M.bc, x.p, y.p, s, reps);
   };
   // candidates that cannot win are skipped: sliced ELL for very long rows,
-  // wide row groups for short rows
+  // row groups wider than the average row
   const double avg = M.nbr ? (double)M.nnzb / (double)M.nbr : 0.0;
   Op<T> best;
   double tbest = 1e300;
@@ -939,7 +939,8 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
     cbest = 1;
   }
   for (int G : {4, 16, 64}) {
-    if (cbest != 0 && G > 4 * avg + 4) continue;
+    // groups wider than the average row leave lanes idle
+    if (cbest != 0 && G > avg) continue;
     Op<T> cand;
     cand.fmt = 1;
     bsr_to_vrow(M, G, cand.v, s);
