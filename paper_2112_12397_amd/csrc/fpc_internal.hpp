@@ -38,22 +38,41 @@ struct Error : std::runtime_error {
 
 #define FPC_LAUNCH_CHECK() FPC_HIP(hipGetLastError())
 
+// Device buffers come from the stream-ordered allocator (hipMallocAsync on
+// the stream of the library call in progress, see StreamScope) and go back
+// to it on the same stream, so allocation and release queue behind the work
+// that uses them instead of synchronizing the device; the default memory
+// pool keeps freed blocks for reuse (set up by fpc_create).
+hipStream_t& alloc_stream();
+
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(alloc_stream()) {
+    alloc_stream() = s;
+  }
+  ~StreamScope() { alloc_stream() = prev; }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  hipStream_t st = nullptr;  // stream the allocation is ordered on
   DevBuf() = default;
   explicit DevBuf(size_t n_) { alloc(n_); }
   void alloc(size_t n_) {
     release();
     n = n_;
     if (n) {
-      hipError_t e = hipMalloc(&p, n * sizeof(T));
+      st = alloc_stream();
+      hipError_t e = hipMallocAsync((void**)&p, n * sizeof(T), st);
       if (e != hipSuccess) {
         p = nullptr;
         n = 0;
         throw Error(e == hipErrorOutOfMemory ? FPC_ERR_OOM : FPC_ERR_HIP,
-                    std::string("hipMalloc: ") + hipGetErrorString(e));
+                    std::string("hipMallocAsync: ") + hipGetErrorString(e));
       }
     }
   }
@@ -61,19 +80,23 @@ struct DevBuf {
     if (n < n_) alloc(n_);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, st);
     p = nullptr;
     n = 0;
   }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), st(o.st) {
+    o.p = nullptr;
+    o.n = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
+      st = o.st;
       o.p = nullptr;
       o.n = 0;
     }

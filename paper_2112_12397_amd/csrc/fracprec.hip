@@ -227,6 +227,7 @@ void upload_csr(const fpc_csr& in, int space, int64_t nr, int64_t nc, Csr& out,
 
 template <typename F>
 fpc_status guard(fpc_handle* h, F&& f) {
+  StreamScope scope(h ? h->stream : nullptr);
   try {
     f();
     return FPC_OK;
@@ -1309,6 +1310,13 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
   }
   h->stream = (hipStream_t)stream;
   fpc_status st = guard(h, [&] {
+    // keep freed device memory in the default pool of this device for reuse
+    int dev = 0;
+    FPC_HIP(hipGetDevice(&dev));
+    hipMemPool_t pool;
+    FPC_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t keep = UINT64_MAX;
+    FPC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
     h->flags.alloc(FLAG_COUNT);
     FPC_HIP(hipMemsetAsync(h->flags.p, 0, FLAG_COUNT * sizeof(int), h->stream));
   });
@@ -1605,9 +1613,14 @@ fpc_status fpc_hash32_device(fpc_handle* h, uint32_t first, int64_t n,
 
 void fpc_destroy(fpc_handle* h) {
   if (!h) return;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  // finish the handle's work, release (buffers go back to the pool on
+  // their stream), then wait for the releases
+  hipStream_t s = h->stream;
+  if (s) (void)hipStreamSynchronize(s);
   else (void)hipDeviceSynchronize();
   delete h;
+  if (s) (void)hipStreamSynchronize(s);
+  else (void)hipDeviceSynchronize();
 }
 
 const char* fpc_status_string(fpc_status s) {

@@ -284,6 +284,11 @@ bool same_pattern(const int64_t* rp_a, const int32_t* col_a,
   return read_i32(f.p, s) == 0;
 }
 
+hipStream_t& alloc_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+
 double read_f64(const double* p, hipStream_t s) {
   double v = 0;
   FPC_HIP(hipMemcpyAsync(&v, p, sizeof(double), hipMemcpyDeviceToHost, s));
