@@ -269,81 +269,104 @@ __device__ __forceinline__ void load33(const T* __restrict__ vb, int cls,
   m[8] = f ? p[8] : (cls == 3 ? p[0] : p[4]);
 }
 
-// Few columns (NV <= 2): one wavefront per 64-row slice, one thread per block
-// row carrying all NV columns, so each matrix block is read by one lane only.
-// Every lane runs to the slice's longest row: padding slots hold zero values
-// and a column of their own row, so they need no guard.  Blocks are taken U
-// at a time: the column indices of the next batch are fetched one batch
-// ahead, then the x values and all block values of the batch are in flight
-// together.
+// Few columns (NV <= 2): two wavefronts per 64-row slice, one thread per
+// block row carrying all NV columns, so each matrix block is read by one lane
+// only.  The two wavefronts of a slice take alternate slots (0, 2, 4, ... and
+// 1, 3, 5, ...; full and packed slots spread evenly) and the second one hands
+// its partial sums to the first through LDS, which adds them in that order
+// and runs the epilogue; a 64-row slice per wavefront alone leaves too few
+// wavefronts in flight to cover the memory latency.  Every lane runs to the
+// slice's longest row: padding slots hold zero values and a column of their
+// own row, so they need no guard.  Slots are taken U at a time: the column
+// indices of the next batch are fetched one batch ahead, then the x values
+// and all block values of the batch are in flight together.
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
                                                    Epi epi) {
   constexpr int U = BR * BC <= 9 ? 3 : (BR * BC <= 18 ? 2 : 1);
   constexpr bool kPacked33 = BR == 3 && BC == 3;
+  __shared__ T red[2][64][NV * BR];
+  const int wave = threadIdx.x >> 6;
+  const int half = wave & 1, pair = wave >> 1;
   const int slice = __builtin_amdgcn_readfirstlane(
-      (int)(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
-  if (slice >= A.nslices) return;
+      (int)(xcd_block(blockIdx.x, gridDim.x) * 2 + pair));
+  const bool valid = slice < A.nslices;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)slice * kSliceH + lane;
-  const int64_t base = A.slice_ptr[slice];
-  const int maxlen = (int)((A.slice_ptr[slice + 1] - base) / kSliceH);
-  const int32_t* __restrict__ cp = A.col + base + lane;
-  const T* __restrict__ vp = A.val + base * (BR * BC) + lane;
   T acc[NV][BR];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int i = 0; i < BR; ++i) acc[v][i] = T(0);
-  int cn[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-    cn[u] = u < maxlen ? ld_stream(cp + (int64_t)u * kSliceH) : 0;
-  for (int k0 = 0; k0 < maxlen; k0 += U) {
-    int cc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) cc[u] = cn[u];
-    T xv[U][BC][NV];
-    T a[U][BR * BC];
+  if (valid) {
+    const int64_t base = A.slice_ptr[slice];
+    const int maxlen = (int)((A.slice_ptr[slice + 1] - base) / kSliceH);
+    const int32_t* __restrict__ cp = A.col + base + lane;
+    const T* __restrict__ vp = A.val + base * (BR * BC) + lane;
+    int cn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (k0 + u < maxlen) {
-        const int64_t col = kPacked33 ? slot_col(cc[u]) : cc[u];
+      const int k = half + 2 * u;
+      cn[u] = k < maxlen ? ld_stream(cp + (int64_t)k * kSliceH) : 0;
+    }
+    for (int k0 = half; k0 < maxlen; k0 += 2 * U) {
+      int cc[U];
 #pragma unroll
-        for (int j = 0; j < BC; ++j)
+      for (int u = 0; u < U; ++u) cc[u] = cn[u];
+      T xv[U][BC][NV];
+      T a[U][BR * BC];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) xv[u][j][v] = ld(col * BC + j, v);
-        const T* __restrict__ vb = vp + (int64_t)(k0 + u) * kSliceH * (BR * BC);
-        if constexpr (kPacked33) {
-          load33(vb, slot_class(cc[u]), a[u]);
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + 2 * u;
+        if (k < maxlen) {
+          const int64_t col = kPacked33 ? slot_col(cc[u]) : cc[u];
+#pragma unroll
+          for (int j = 0; j < BC; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xv[u][j][v] = ld(col * BC + j, v);
+          const T* __restrict__ vb = vp + (int64_t)k * kSliceH * (BR * BC);
+          if constexpr (kPacked33) {
+            load33(vb, slot_class(cc[u]), a[u]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < BR * BC; ++q) a[u][q] = ld_stream(vb + q * kSliceH);
+          }
         } else {
 #pragma unroll
-          for (int q = 0; q < BR * BC; ++q) a[u][q] = ld_stream(vb + q * kSliceH);
+          for (int j = 0; j < BC; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xv[u][j][v] = T(0);
+#pragma unroll
+          for (int q = 0; q < BR * BC; ++q) a[u][q] = T(0);
         }
-      } else {
-#pragma unroll
-        for (int j = 0; j < BC; ++j)
-#pragma unroll
-          for (int v = 0; v < NV; ++v) xv[u][j][v] = T(0);
-#pragma unroll
-        for (int q = 0; q < BR * BC; ++q) a[u][q] = T(0);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int kn = k0 + 2 * U + 2 * u;
+        cn[u] = kn < maxlen ? ld_stream(cp + (int64_t)kn * kSliceH) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+          for (int j = 0; j < BC; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v][i] += a[u][i * BC + j] * xv[u][j][v];
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int kn = k0 + U + u;
-      cn[u] = kn < maxlen ? ld_stream(cp + (int64_t)kn * kSliceH) : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int j = 0; j < BC; ++j)
-#pragma unroll
-          for (int v = 0; v < NV; ++v) acc[v][i] += a[u][i * BC + j] * xv[u][j][v];
   }
-  if (row >= A.nrows) return;
+  if (half == 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int i = 0; i < BR; ++i) red[pair][lane][v * BR + i] = acc[v][i];
+  }
+  __syncthreads();
+  if (half == 1 || !valid || row >= A.nrows) return;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[v][i] += red[pair][lane][v * BR + i];
   epi_row<T, BR, NV>(epi, row, acc);
 }
 
@@ -398,7 +421,7 @@ template <typename T, int BR, int BC, int NV, class Load, class Epi>
 void launch_sell(const Sell<T>& A, Load ld, Epi epi, hipStream_t s) {
   if (A.nrows == 0) return;
   if constexpr (NV <= 2) {
-    const unsigned grid = (unsigned)((A.nslices + 3) / 4);
+    const unsigned grid = (unsigned)((A.nslices + 1) / 2);
     k_sell_rows<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   } else {
     const int64_t waves = A.nslices * NV;
