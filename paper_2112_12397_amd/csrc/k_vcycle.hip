@@ -269,27 +269,30 @@ __device__ __forceinline__ void load33(const T* __restrict__ vb, int cls,
   m[8] = f ? p[8] : (cls == 3 ? p[0] : p[4]);
 }
 
-// Few columns (NV <= 2): two wavefronts per 64-row slice, one thread per
-// block row carrying all NV columns, so each matrix block is read by one lane
-// only.  The two wavefronts of a slice take alternate slots (0, 2, 4, ... and
-// 1, 3, 5, ...; full and packed slots spread evenly) and the second one hands
-// its partial sums to the first through LDS, which adds them in that order
-// and runs the epilogue; a 64-row slice per wavefront alone leaves too few
-// wavefronts in flight to cover the memory latency.  Every lane runs to the
-// slice's longest row: padding slots hold zero values and a column of their
-// own row, so they need no guard.  Slots are taken U at a time: the column
-// indices of the next batch are fetched one batch ahead, then the x values
-// and all block values of the batch are in flight together.
+constexpr int kSliceSplit = 4;
+
+// Few columns (NV <= 2): kSliceSplit wavefronts per 64-row slice, one thread
+// per block row carrying all NV columns, so each matrix block is read by one
+// lane only.  Wavefront h of a slice takes slots h, h + kSliceSplit, ...
+// (full and packed slots spread evenly) and hands its partial sums to
+// wavefront 0 through LDS, which adds them in order and runs the epilogue; a
+// whole slice per wavefront leaves too few wavefronts in flight to cover the
+// memory latency.  Every lane runs to the slice's longest row: padding slots
+// hold zero values and a column of their own row, so they need no guard.
+// Slots are taken U at a time: the column indices of the next batch are
+// fetched one batch ahead, then the x values and all block values of the
+// batch are in flight together.
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
                                                    Epi epi) {
   constexpr int U = BR * BC <= 9 ? 3 : (BR * BC <= 18 ? 2 : 1);
   constexpr bool kPacked33 = BR == 3 && BC == 3;
-  __shared__ T red[2][64][NV * BR];
+  constexpr int SP = kSliceSplit;  // wavefronts per slice
+  __shared__ T red[4 / SP][SP - 1][64][NV * BR];
   const int wave = threadIdx.x >> 6;
-  const int half = wave & 1, pair = wave >> 1;
+  const int half = wave % SP, pair = wave / SP;
   const int slice = __builtin_amdgcn_readfirstlane(
-      (int)(xcd_block(blockIdx.x, gridDim.x) * 2 + pair));
+      (int)(xcd_block(blockIdx.x, gridDim.x) * (4 / SP) + pair));
   const bool valid = slice < A.nslices;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)slice * kSliceH + lane;
@@ -306,10 +309,10 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
     int cn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = half + 2 * u;
+      const int k = half + SP * u;
       cn[u] = k < maxlen ? ld_stream(cp + (int64_t)k * kSliceH) : 0;
     }
-    for (int k0 = half; k0 < maxlen; k0 += 2 * U) {
+    for (int k0 = half; k0 < maxlen; k0 += SP * U) {
       int cc[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) cc[u] = cn[u];
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
       T a[U][BR * BC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + 2 * u;
+        const int k = k0 + SP * u;
         if (k < maxlen) {
           const int64_t col = kPacked33 ? slot_col(cc[u]) : cc[u];
 #pragma unroll
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int kn = k0 + 2 * U + 2 * u;
+        const int kn = k0 + SP * U + SP * u;
         cn[u] = kn < maxlen ? ld_stream(cp + (int64_t)kn * kSliceH) : 0;
       }
 #pragma unroll
@@ -355,18 +358,20 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
             for (int v = 0; v < NV; ++v) acc[v][i] += a[u][i * BC + j] * xv[u][j][v];
     }
   }
-  if (half == 1) {
+  if (half > 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int i = 0; i < BR; ++i) red[pair][lane][v * BR + i] = acc[v][i];
+      for (int i = 0; i < BR; ++i) red[pair][half - 1][lane][v * BR + i] = acc[v][i];
   }
   __syncthreads();
-  if (half == 1 || !valid || row >= A.nrows) return;
+  if (half > 0 || !valid || row >= A.nrows) return;
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
+  for (int h = 0; h < SP - 1; ++h)
 #pragma unroll
-    for (int i = 0; i < BR; ++i) acc[v][i] += red[pair][lane][v * BR + i];
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int i = 0; i < BR; ++i) acc[v][i] += red[pair][h][lane][v * BR + i];
   epi_row<T, BR, NV>(epi, row, acc);
 }
 
@@ -421,7 +426,8 @@ template <typename T, int BR, int BC, int NV, class Load, class Epi>
 void launch_sell(const Sell<T>& A, Load ld, Epi epi, hipStream_t s) {
   if (A.nrows == 0) return;
   if constexpr (NV <= 2) {
-    const unsigned grid = (unsigned)((A.nslices + 1) / 2);
+    const unsigned grid =
+        (unsigned)((A.nslices + 4 / kSliceSplit - 1) / (4 / kSliceSplit));
     k_sell_rows<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   } else {
     const int64_t waves = A.nslices * NV;
