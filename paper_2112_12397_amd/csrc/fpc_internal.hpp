@@ -110,7 +110,14 @@ struct Csr {
   DevBuf<int64_t> rowptr;
   DevBuf<int32_t> col;
   DevBuf<double> val;
+  // rows holding a nonzero (ascending), when computed (nact >= 0): products
+  // that add to a vector visit only these rows
+  DevBuf<int32_t> act;
+  int64_t nact = -1;
 };
+
+// Fill m.act / m.nact.
+void csr_active_rows(Csr& m, hipStream_t s);
 
 struct Bsr {
   int br = 0, bc = 0;

@@ -606,6 +606,8 @@ void ensure_transposes(fpc_handle* h) {
   csr_transpose(h->C2, h->C2T, s);
   csr_transpose(h->Q1, h->Q1T, s);
   csr_transpose(h->Q2, h->Q2T, s);
+  csr_active_rows(h->C2T, s);
+  csr_active_rows(h->Q2T, s);
   csr_transpose(h->H, h->HT, s);
   csr_transpose(h->T, h->TT, s);
   Bsr AbT;
@@ -1182,6 +1184,9 @@ void upload_blocks(fpc_handle* h, const fpc_block_system* J) {
   upload_csr(J->T, J->ptr_space, np, np, h->T, s, "T");
   for (const Csr* m : {&h->A, &h->C1, &h->Q1, &h->C2, &h->H, &h->Q2, &h->T})
     csr_validate(*m, h->flags.p, s);
+  // the coupling blocks of the u rows touch the fracture nodes only
+  csr_active_rows(h->C1, s);
+  csr_active_rows(h->Q1, s);
 }
 
 // Alg 3.3 cpt_tup / Alg 3.1 cpt_tpu on the uploaded blocks.  `prev`: the

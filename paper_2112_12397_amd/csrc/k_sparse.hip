@@ -51,6 +51,42 @@ __global__ void k_csr_spmv2(const int64_t* rp1, const int32_t* c1,
   y[i] = (beta == 0.0) ? r : beta * y[i] + r;
 }
 
+// Products of one or two CSR matrices over a row list (rows where m1 is
+// nonempty, or with skip1 the rows of m2's list where m1 is empty), the same
+// arithmetic per row as k_csr_spmv2: y = beta y + a1 (m1 x1) + a2 (m2 x2).
+__global__ void k_csr_spmv2_rows(const int32_t* rows, int64_t nr, int skip1,
+                                 const int64_t* rp1, const int32_t* c1,
+                                 const double* v1, const double* x1, double a1,
+                                 const int64_t* rp2, const int32_t* c2,
+                                 const double* v2, const double* x2, double a2,
+                                 double* y, double beta) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nr) return;
+  const int64_t i = rows[t];
+  if (skip1 && rp1 && rp1[i] < rp1[i + 1]) return;
+  double s1 = 0.0;
+  if (rp1)
+    for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s1 += v1[e] * x1[c1[e]];
+  double r = a1 * s1;
+  if (rp2) {
+    double s2 = 0.0;
+    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s2 += v2[e] * x2[c2[e]];
+    r += a2 * s2;
+  }
+  y[i] = (beta == 0.0) ? r : beta * y[i] + r;
+}
+
+__global__ void k_row_nonempty(const int64_t* rp, int64_t n, int64_t* f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = rp[i] < rp[i + 1] ? 1 : 0;
+}
+
+__global__ void k_row_list(const int64_t* f, const int64_t* scan, int64_t n,
+                           int32_t* list) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && f[i]) list[scan[i]] = (int32_t)i;
+}
+
 // ------------------------------------------------------------- transpose
 __global__ void k_col_count(const int64_t* rowptr, const int32_t* col,
                             int64_t nrows, unsigned long long* cnt) {
@@ -741,10 +777,40 @@ void csr_validate(const Csr& m, int* flags, hipStream_t s) {
   FPC_LAUNCH_CHECK();
 }
 
+void csr_active_rows(Csr& m, hipStream_t s) {
+  const int64_t n = m.nrows;
+  DevBuf<int64_t> f(std::max<int64_t>(n, 1)), sc(n + 1);
+  if (n) {
+    k_row_nonempty<<<grid_for(n, 256), 256, 0, s>>>(m.rowptr.p, n, f.p);
+    FPC_LAUNCH_CHECK();
+  }
+  m.nact = scan_counts_total(f.p, sc.p, n, s);
+  m.act.alloc(std::max<int64_t>(m.nact, 1));
+  if (n) {
+    k_row_list<<<grid_for(n, 256), 256, 0, s>>>(f.p, sc.p, n, m.act.p);
+    FPC_LAUNCH_CHECK();
+  }
+}
+
 void csr_spmv2(const Csr* m1, const double* x1, double a1, const Csr* m2,
                const double* x2, double a2, double* y, double beta,
                hipStream_t s) {
   if (m1->nrows == 0) return;
+  // adding to y: only rows where m1 or m2 has a nonzero change
+  if (beta == 1.0 && m1->nact >= 0 && (!m2 || m2->nact >= 0)) {
+    const int64_t* rp2 = m2 ? m2->rowptr.p : nullptr;
+    if (m1->nact)
+      k_csr_spmv2_rows<<<grid_for(m1->nact, 256), 256, 0, s>>>(
+          m1->act.p, m1->nact, 0, m1->rowptr.p, m1->col.p, m1->val.p, x1, a1,
+          rp2, m2 ? m2->col.p : nullptr, m2 ? m2->val.p : nullptr, x2, a2, y,
+          beta);
+    if (m2 && m2->nact)
+      k_csr_spmv2_rows<<<grid_for(m2->nact, 256), 256, 0, s>>>(
+          m2->act.p, m2->nact, 1, m1->rowptr.p, m1->col.p, m1->val.p, x1, a1,
+          rp2, m2->col.p, m2->val.p, x2, a2, y, beta);
+    FPC_LAUNCH_CHECK();
+    return;
+  }
   k_csr_spmv2<<<grid_for(m1->nrows, 256), 256, 0, s>>>(
       m1->rowptr.p, m1->col.p, m1->val.p, x1, a1,
       m2 ? m2->rowptr.p : nullptr, m2 ? m2->col.p : nullptr,

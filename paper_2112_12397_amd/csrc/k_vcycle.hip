@@ -614,6 +614,42 @@ __global__ void k_to_level(T* __restrict__ out, int nv, int colv,
 }
 
 template <typename T>
+__global__ void k_base_copy(T* __restrict__ out, int nv, int colv,
+                            const double* __restrict__ base, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i * nv + colv] = (T)(base ? base[i] : 0.0);
+}
+
+// k_to_level on the rows of a list only (rows where m1 is nonempty, or with
+// skip1 the listed rows of m2 where m1 is empty); same arithmetic per row.
+template <typename T>
+__global__ void k_to_level_rows(T* __restrict__ out, int nv, int colv,
+                                const double* __restrict__ base,
+                                const int32_t* rows, int64_t nr, int skip1,
+                                const int64_t* rp1, const int32_t* c1,
+                                const double* v1, const double* x1, double a1,
+                                const int64_t* rp2, const int32_t* c2,
+                                const double* v2, const double* x2, double a2) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nr) return;
+  const int64_t i = rows[t];
+  if (skip1 && rp1 && rp1[i] < rp1[i + 1]) return;
+  double r = base ? base[i] : 0.0;
+  if (rp1) {
+    double s = 0.0;
+    for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s += v1[e] * x1[c1[e]];
+    r += a1 * s;
+  }
+  if (rp2) {
+    double s = 0.0;
+    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s += v2[e] * x2[c2[e]];
+    r += a2 * s;
+  }
+  out[i * nv + colv] = (T)r;
+}
+
+template <typename T>
 __global__ void k_from_level(const T* __restrict__ xo, int nv, int64_t n,
                              double* __restrict__ vu, int diff) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1123,6 +1159,22 @@ void to_level(T* out, int nv, int colv, int64_t n, const double* base,
               const Csr* m1, const double* x1, double a1, const Csr* m2,
               const double* x2, double a2, hipStream_t s) {
   if (n == 0) return;
+  if (m1 && m1->nact >= 0 && (!m2 || m2->nact >= 0)) {
+    // base everywhere, then the rows the coupling blocks touch
+    k_base_copy<T><<<grid_for(n, 256), 256, 0, s>>>(out, nv, colv, base, n);
+    const int64_t* rp2 = m2 ? m2->rowptr.p : nullptr;
+    if (m1->nact)
+      k_to_level_rows<T><<<grid_for(m1->nact, 256), 256, 0, s>>>(
+          out, nv, colv, base, m1->act.p, m1->nact, 0, m1->rowptr.p,
+          m1->col.p, m1->val.p, x1, a1, rp2, m2 ? m2->col.p : nullptr,
+          m2 ? m2->val.p : nullptr, x2, a2);
+    if (m2 && m2->nact)
+      k_to_level_rows<T><<<grid_for(m2->nact, 256), 256, 0, s>>>(
+          out, nv, colv, base, m2->act.p, m2->nact, 1, m1->rowptr.p,
+          m1->col.p, m1->val.p, x1, a1, rp2, m2->col.p, m2->val.p, x2, a2);
+    FPC_LAUNCH_CHECK();
+    return;
+  }
   k_to_level<T><<<grid_for(n, 256), 256, 0, s>>>(
       out, nv, colv, base, m1 ? m1->rowptr.p : nullptr,
       m1 ? m1->col.p : nullptr, m1 ? m1->val.p : nullptr, x1, a1,
