@@ -84,6 +84,8 @@ void btrisolve(const double* H, const double* g, double* y, const int* kc,
 // ---------------------------------------------------------------- Krylov
 // partial[i * G + blk] = <V_i, w> over a chunk; V_i = V + i * ldv
 constexpr int kDotBlocks = 256;
+// Size of the partials buffer mdot needs for nv vectors of length n.
+int64_t mdot_partials(int64_t n, int nv);
 void mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
           double* partials, double* out, hipStream_t s);
 // w -= sum_i h_i V_i

@@ -807,7 +807,7 @@ void ensure_krylov(fpc_handle* h, Krylov& K, int k) {
   K.h1.alloc((int64_t)(m + 1) * k);
   K.h2.alloc((int64_t)(m + 1) * k);
   K.scal.alloc(8 * k);
-  K.partials.alloc((int64_t)(m + 1) * kDotBlocks);
+  K.partials.alloc(mdot_partials(h->N, m + 1));
   K.ctrl.alloc(4 * k);
   if (!K.host) FPC_HIP(hipHostMalloc((void**)&K.host, 64 * sizeof(double)));
 }

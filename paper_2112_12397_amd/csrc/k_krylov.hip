@@ -14,27 +14,52 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// grid (kDotBlocks, nv): partial <V_i, w> of one chunk
-__global__ __launch_bounds__(DT) void k_mdot_partial(const double* __restrict__ V,
-                                                     int64_t ldv,
-                                                     const double* __restrict__ w,
-                                                     int64_t n,
-                                                     double* __restrict__ part) {
-  __shared__ double sh[DT / 64];
-  const int i = blockIdx.y;
-  const double* __restrict__ v = V + (int64_t)i * ldv;
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t a = (int64_t)blockIdx.x * chunk;
-  const int64_t b = min(n, a + chunk);
-  double acc = 0.0;
-  for (int64_t k = a + threadIdx.x; k < b; k += DT) acc += v[k] * w[k];
-  acc = wsum(acc);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int q = 0; q < DT / 64; ++q) t += sh[q];
-    part[(int64_t)i * gridDim.x + blockIdx.x] = t;
+// Partials of <V_i, w> for all i: block b takes rows [b * DT * MR, (b+1) *
+// DT * MR), thread t rows b * DT * MR + t + DT * r (r < MR), whose w values
+// stay in registers while the vectors stream by, four vectors at a time; one
+// partial per block and vector (the four wavefronts added in order),
+// part[i * nblocks + b].
+constexpr int MR = 4;
+
+__global__ __launch_bounds__(DT) void k_mdot_rows(const double* __restrict__ V,
+                                                  int64_t ldv, int nv,
+                                                  const double* __restrict__ w,
+                                                  int64_t n,
+                                                  double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * (DT * MR) + threadIdx.x;
+  double wv[MR];
+#pragma unroll
+  for (int r = 0; r < MR; ++r) {
+    const int64_t k = r0 + (int64_t)DT * r;
+    wv[r] = k < n ? w[k] : 0.0;
+  }
+  __shared__ double red[4][4];
+  const int wave = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < nv; i0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (i0 + q < nv) {
+        const double* __restrict__ v = V + (int64_t)(i0 + q) * ldv;
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+          const int64_t k = r0 + (int64_t)DT * r;
+          if (k < n) acc[q] += v[k] * wv[r];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = wsum(acc[q]);
+      if ((threadIdx.x & 63) == 0) red[wave][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && i0 + (int)threadIdx.x < nv) {
+      const int q = threadIdx.x;
+      part[(int64_t)(i0 + q) * gridDim.x + blockIdx.x] =
+          (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
+    __syncthreads();
   }
 }
 
@@ -142,13 +167,17 @@ __global__ void k_sqrt(const double* in, double* out) {
 
 }  // namespace
 
+int64_t mdot_partials(int64_t n, int nv) {
+  return (int64_t)nv * std::max<int64_t>((n + DT * MR - 1) / (DT * MR), 1);
+}
+
 void mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
           double* partials, double* out, hipStream_t s) {
   if (nv <= 0) return;
-  dim3 grid(kDotBlocks, nv);
-  k_mdot_partial<<<grid, DT, 0, s>>>(V, ldv, w, n, partials);
+  const int64_t nb = std::max<int64_t>((n + DT * MR - 1) / (DT * MR), 1);
+  k_mdot_rows<<<(unsigned)nb, DT, 0, s>>>(V, ldv, nv, w, n, partials);
   FPC_LAUNCH_CHECK();
-  k_mdot_reduce<<<nv, DT, 0, s>>>(partials, kDotBlocks, out);
+  k_mdot_reduce<<<nv, DT, 0, s>>>(partials, (int)nb, out);
   FPC_LAUNCH_CHECK();
 }
 
