@@ -149,3 +149,33 @@ def _c2o():
     if "s" not in _C2O:
         _C2O["s"] = fracgen.make_config("c2o")
     return _C2O["s"]
+
+
+@pytest.mark.parametrize("open_p", [0.0, 0.3])
+def test_pressure_solve_several_panels(open_p):
+    """The pressure inverse of a 4,608-face component (two intersecting full
+    planes of a 48^3 mesh): five 1024-wide sweep panels with the tile-sparse
+    trailing products, against a sparse LU of the same matrix (T, or
+    T - diag(S_K) with open faces)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from fracgen import Fracture
+    from fracgen.configs import tiny_system
+    from paper_2112_12397_amd import solver_from_system
+    s = tiny_system((48, 48, 48), [Fracture(0, 24, 0, 48, 0, 48),
+                                   Fracture(1, 24, 0, 48, 0, 48)],
+                    slip_p=0.2, open_p=open_p, seed=9)
+    assert s.n_p == 4608
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    from oracle.precond import bdiag_inv, fixed_stress, schur1
+    sol = solver_from_system(s)
+    S2 = s.T
+    if s.Q2.nnz:
+        K = schur1(s.A, s.C1, bdiag_inv(s.H, s.n_p), s.C2)
+        S2 = sp.csr_matrix(s.T - sp.diags(fixed_stress(K, s.Q1, s.Q2)))
+    w = np.random.default_rng(10).standard_normal(s.n_p)
+    v = sol.psolve(torch.tensor(w, device="cuda")).cpu().numpy()
+    ref = spl.spsolve(S2.tocsc(), w)
+    assert np.linalg.norm(v - ref) <= 1e-10 * np.linalg.norm(ref)
