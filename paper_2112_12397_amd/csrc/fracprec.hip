@@ -647,12 +647,35 @@ void matvec(fpc_handle* h, int trans, const double* x, double* y) {
   }
 }
 
+// Whether the forward application starts with steps that depend on w only
+// (t_t = H~^-1 w_t and v_p = S~2^-1 w_p: the Q2 = 0 t-u-p and t-p-u paths),
+// so that they may run ahead of the rest.
+bool fwd_has_lead(const fpc_handle* h) {
+  return !h->has_q2 && (h->opt.mode == FPC_TUP || h->opt.mode == FPC_TPU);
+}
+
+// stage 0: the whole application; with fwd_has_lead(h), stage 1 runs the
+// leading face and pressure solves only and stage 2 the rest.
 template <typename T>
-void apply_fwd(fpc_handle* h, const double* w, double* v) {
+void apply_fwd(fpc_handle* h, const double* w, double* v, int stage = 0) {
   hipStream_t s = h->stream;
   const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
   const double *wu = w, *wt = w + nu, *wp = w + nu + nt;
   double *vu = v, *vt = v + nu, *vp = v + nu + nt;
+  if (stage != 0 && fwd_has_lead(h)) {
+    if (stage == 1) {
+      face_apply(h->hinv.p, wt, h->t_t.p, np, 0, s);        // t_t = H~^-1 w_t
+      psolve_apply(h->ps, wp, vp, np, 0, s);                // v_p = S~2^-1 w_p
+      return;
+    }
+    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
+    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, &h->Q1, vp,
+                -1.0, s);
+    vcycle<T, 1>(h->amg, false, s);
+    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    tface(h->C2, vu, h->t_t.p, h->hinv.p, vt, np, 0, s);    // v_t
+    return;
+  }
   face_apply(h->hinv.p, wt, h->t_t.p, np, 0, s);            // t_t = H~^-1 w_t
   if (h->opt.mode == FPC_TUP_STAR) {
     // M2* = D2^-1 L2^-1 (eq. LDU2): steps 1-5 of Alg 3.4 with v_u = s_u,
@@ -775,11 +798,12 @@ void apply_adj(fpc_handle* h, const double* w, double* v) {
   tface(h->C1T, vu, h->t_t.p, h->hinv.p, vt, np, 1, s);
 }
 
-void apply(fpc_handle* h, int trans, const double* w, double* v) {
+void apply(fpc_handle* h, int trans, const double* w, double* v,
+           int stage = 0) {
   const bool fp32 = h->opt.precision == FPC_FP32_PREC;
   if (!trans) {
-    if (fp32) apply_fwd<float>(h, w, v);
-    else apply_fwd<double>(h, w, v);
+    if (fp32) apply_fwd<float>(h, w, v, stage);
+    else apply_fwd<double>(h, w, v, stage);
   } else {
     if (fp32) apply_adj<float>(h, w, v);
     else apply_adj<double>(h, w, v);
@@ -862,10 +886,22 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
     if (its >= h->opt.maxit) break;
     scale_by_inv(K.r.p, sc, K.V.p, N, s);
     int k = 0;
+    // The leading steps of M^-1 v_{j+1} (which need v_{j+1} only) are queued
+    // before the host waits for the convergence test of step j, so the
+    // device has work during that round trip; after the last step of a
+    // cycle they are unused.
+    const bool lead = !trans && fwd_has_lead(h);
+    bool lead_done = false;
     for (int j = 0; j < m; ++j) {
       double* vj = K.V.p + (int64_t)j * N;
       double* zj = K.Z.p + (int64_t)j * N;
-      apply(h, trans, vj, zj);
+      if (lead) {
+        if (!lead_done) apply(h, trans, vj, zj, 1);
+        apply(h, trans, vj, zj, 2);
+        lead_done = false;
+      } else {
+        apply(h, trans, vj, zj);
+      }
       matvec(h, trans, zj, K.w.p);
       mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
       if (h->opt.ortho == FPC_MGS) {
@@ -887,6 +923,11 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
       gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
                  sc + 4, j, sc, K.ctrl.p, s);
       scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
+      if (lead && j + 1 < m) {
+        apply(h, trans, K.V.p + (int64_t)(j + 1) * N,
+              K.Z.p + (int64_t)(j + 1) * N, 1);
+        lead_done = true;
+      }
       FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
                              hipMemcpyDeviceToHost, s));
       FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
