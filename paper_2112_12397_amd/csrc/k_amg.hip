@@ -577,12 +577,13 @@ __global__ void k_pad_identity(double* D, int64_t n, int64_t npad) {
 }
 
 // ------------------------------------------------------------- dense GJ
-// Blocked Gauss-Jordan inverse, in place, without pivoting (SPD pressure
-// blocks; the coarsest Galerkin operator).  Panels of 64 columns are handled
-// by the tile kernels below; matrices larger than 256 use 256-wide panels
-// whose diagonal block is inverted with the 64-wide kernels and whose row
-// panel, trailing update and column panel are FP64 MFMA products
-// (k_gemm_f64).  `ld` is the row pitch, `n` the order.
+// Dense inverses in place, without pivoting.  Panels of 64 columns are
+// handled by the tile kernels below.  gj_inverse (the coarsest Galerkin
+// operator) uses 256-wide Gauss-Jordan panels whose diagonal block is
+// inverted with the 64-wide kernels and whose row panel, trailing update and
+// column panel are FP64 MFMA products (k_gemm_f64); sym_inverse (the
+// symmetric pressure blocks) uses 1024-wide symmetric sweeps on the lower
+// triangle.  `ld` is the row pitch, `n` the order.
 constexpr int GT = 64;  // tile
 
 // Gauss-Jordan inverse of the diagonal tile, in place.  Thread (tr, tc)
