@@ -694,7 +694,6 @@ __global__ __launch_bounds__(256) void k_psym_tile(
     const int64_t* __restrict__ comp_off, const int32_t* __restrict__ members,
     const double* __restrict__ in, double* __restrict__ part) {
   __shared__ double xs[2][64];
-  __shared__ double rs[64][65];
   __shared__ double cs[4][64];
   const int64_t t = blockIdx.x;
   const int c = tile_info[3 * t], I = tile_info[3 * t + 1], J = tile_info[3 * t + 2];
@@ -710,22 +709,51 @@ __global__ __launch_bounds__(256) void k_psym_tile(
   }
   __syncthreads();
   const double xj = xs[0][lane];
+  double v[16];
   double col = 0.0;
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     const double av = (double)a[rr];
-    rs[w * 16 + rr][lane] = av * xj;
+    v[rr] = av * xj;
     col += av * xs[1][w * 16 + rr];
   }
   cs[w][lane] = col;
-  __syncthreads();
-  const int r = tid >> 2, q = tid & 3;
-  double sum = 0.0;
+  // row sums of the wavefront's 16 rows over its 64 lanes by a transposing
+  // butterfly: at lane bit 5, 4, 3, 2 a lane keeps the half of its values
+  // selected by that bit and adds the partner's copy of it, so lane l ends
+  // with row (l >> 2) & 15 summed over 16 lanes; bits 1 and 0 finish it
 #pragma unroll
-  for (int k = 0; k < 16; ++k) sum += rs[r][q * 16 + k];
+  for (int k = 0; k < 8; ++k) {
+    const bool hi = (lane >> 5) & 1;
+    const double send = hi ? v[k] : v[k + 8];
+    const double recv = __shfl_xor(send, 32, 64);
+    v[k] = (hi ? v[k + 8] : v[k]) + recv;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool hi = (lane >> 4) & 1;
+    const double send = hi ? v[k] : v[k + 4];
+    const double recv = __shfl_xor(send, 16, 64);
+    v[k] = (hi ? v[k + 4] : v[k]) + recv;
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const bool hi = (lane >> 3) & 1;
+    const double send = hi ? v[k] : v[k + 2];
+    const double recv = __shfl_xor(send, 8, 64);
+    v[k] = (hi ? v[k + 2] : v[k]) + recv;
+  }
+  {
+    const bool hi = (lane >> 2) & 1;
+    const double send = hi ? v[0] : v[1];
+    const double recv = __shfl_xor(send, 4, 64);
+    v[0] = (hi ? v[1] : v[0]) + recv;
+  }
+  double sum = v[0];
   sum += __shfl_xor(sum, 1, 64);
   sum += __shfl_xor(sum, 2, 64);
-  if (q == 0) part[t * 128 + r] = sum;
+  if ((lane & 3) == 0) part[t * 128 + w * 16 + (lane >> 2)] = sum;
+  __syncthreads();
   if (tid < 64)
     part[t * 128 + 64 + tid] =
         I != J ? (cs[0][tid] + cs[1][tid]) + (cs[2][tid] + cs[3][tid]) : 0.0;
