@@ -1014,7 +1014,7 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
   DevBuf<T> x(std::max<int64_t>(M.nbc * M.bc * nv, 1));
   DevBuf<T> y(std::max<int64_t>(M.nbr * M.br * nv, 1));
   FPC_HIP(hipMemsetAsync(x.p, 0, x.bytes(), s));
-  const int reps = 5;
+  const int reps = 3;
   auto timeit = [&](const Op<T>& op) {
     return nv == 2 ? time_any<T, 2>(op, M.br, M.bc, x.p, y.p, s, reps)
                    : time_any<T, 1>(op, M.br, M.bc, x.p, y.p, s, reps);
@@ -1042,6 +1042,8 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
       tbest = t;
       best = std::move(cand);
       cbest = G;
+    } else if (cbest == 1 && t > 1.25 * tbest) {
+      break;  // rows short enough for sliced ELL: wider groups only lose more
     }
   }
   out = std::move(best);
