@@ -14,13 +14,15 @@ void vcycle(Hierarchy& H, bool transpose, hipStream_t s);
 
 // Autotuned apply layout of one operator for `nv` columns; *choice = 1 for
 // sliced ELL, else the row-group width.
+// `sell`: the operator's sliced-ELL layout if already built (taken over).
 template <typename T>
 void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
-             double* best_us);
+             double* best_us, Sell<T>* sell = nullptr);
 
 // The apply layout `choice` (as returned by tune_op) of one operator.
 template <typename T>
-void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s);
+void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s,
+              Sell<T>* sell = nullptr);
 
 void sell_mv(const Sell<double>& A, const double* x, double* y, hipStream_t s);
 void sell_mv_dinv(const Sell<double>& A, const double* dinv, const double* x,

@@ -553,7 +553,8 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
   for (size_t li = 0; li < H.L.size(); ++li) {
     Level& L = H.L[li];
     if (L.coarsest) continue;
-    L.sA = Sell<double>();
+    // L.sA (built for the power iteration) is handed to the FP64 layout
+    // choice and released otherwise
     if (prev) {
       // the layouts picked for the same patterns
       const Level& pv = prev->L[li];
@@ -570,10 +571,11 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
         build_op<float>(L.P, L.layout[1], L.fP, s);
         build_op<float>(L.R, L.layout[2], L.fR, s);
       } else {
-        build_op<double>(L.A, L.layout[0], L.oA, s);
+        build_op<double>(L.A, L.layout[0], L.oA, s, &L.sA);
         build_op<double>(L.P, L.layout[1], L.oP, s);
         build_op<double>(L.R, L.layout[2], L.oR, s);
       }
+      L.sA = Sell<double>();
       continue;
     }
     if (h->opt.precision == FPC_FP32_PREC) {
@@ -589,12 +591,13 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
                       &L.tune_us[2]);
     } else {
       tune_op<double>(L.A, nv, L.oA, s, &L.layout[0],
-                      &L.tune_us[0]);
+                      &L.tune_us[0], &L.sA);
       tune_op<double>(L.P, nv, L.oP, s, &L.layout[1],
                       &L.tune_us[1]);
       tune_op<double>(L.R, nv, L.oR, s, &L.layout[2],
                       &L.tune_us[2]);
     }
+    L.sA = Sell<double>();
   }
   FPC_HIP(hipStreamSynchronize(s));
 }

@@ -1010,7 +1010,7 @@ double time_any(const Op<T>& op, int br, int bc, const T* x, T* y,
 // `nv` columns on the device; only the winner is kept.
 template <typename T>
 void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
-             double* best_us) {
+             double* best_us, Sell<T>* sell) {
   DevBuf<T> x(std::max<int64_t>(M.nbc * M.bc * nv, 1));
   DevBuf<T> y(std::max<int64_t>(M.nbr * M.br * nv, 1));
   FPC_HIP(hipMemsetAsync(x.p, 0, x.bytes(), s));
@@ -1027,7 +1027,8 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
   int cbest = 0;
   if (avg <= 64.0) {
     best.fmt = 0;
-    bsr_to_sell(M, best.s, s);
+    if (sell && sell->nrows == M.nbr) best.s = std::move(*sell);
+    else bsr_to_sell(M, best.s, s);
     tbest = timeit(best);
     cbest = 1;
   }
@@ -1052,11 +1053,13 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
   FPC_HIP(hipStreamSynchronize(s));
 }
 template <typename T>
-void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s) {
+void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s,
+              Sell<T>* sell) {
   out = Op<T>();
   if (choice == 1) {
     out.fmt = 0;
-    bsr_to_sell(M, out.s, s);
+    if (sell && sell->nrows == M.nbr) out.s = std::move(*sell);
+    else bsr_to_sell(M, out.s, s);
   } else if (choice == 4 || choice == 16 || choice == 64) {
     out.fmt = 1;
     bsr_to_vrow(M, choice, out.v, s);
@@ -1064,13 +1067,15 @@ void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s) {
     throw Error(FPC_ERR_ARG, "build_op: unknown layout");
   }
 }
-template void build_op<double>(const Bsr&, int, Op<double>&, hipStream_t);
-template void build_op<float>(const Bsr&, int, Op<float>&, hipStream_t);
+template void build_op<double>(const Bsr&, int, Op<double>&, hipStream_t,
+                               Sell<double>*);
+template void build_op<float>(const Bsr&, int, Op<float>&, hipStream_t,
+                              Sell<float>*);
 
 template void tune_op<double>(const Bsr&, int, Op<double>&, hipStream_t, int*,
-                              double*);
+                              double*, Sell<double>*);
 template void tune_op<float>(const Bsr&, int, Op<float>&, hipStream_t, int*,
-                             double*);
+                             double*, Sell<float>*);
 
 template <typename T>
 CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv) {
