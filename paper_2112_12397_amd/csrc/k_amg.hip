@@ -1323,7 +1323,6 @@ void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
   const SkipMap none{INT64_MAX, 0};
   for (int64_t o = 0; o < n; o += NB) {
     const int64_t nb = std::min<int64_t>(NB, n - o), e = o + nb;
-    const SkipMap skip{o, nb};
     double* Dkk = D + o * n + o;
     k_mirror_lower<<<grid_for(nb * nb, 256), 256, 0, s>>>(Dkk, n, nb);
     FPC_LAUNCH_CHECK();
@@ -1341,16 +1340,19 @@ void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
                                n * sizeof(double), o * sizeof(double), nb,
                                hipMemcpyDeviceToDevice, s));
     tr_copy(D + e * n + o, n, n - e, nb, prow.p + e, n, s);
-    // Z = P Dkk^-1
-    gemm_f64(n - nb, nb, (int)nb, 1.0, 0.0, pcol.p, nb, Dkk, n, z.p, nb, skip,
-             none, s);
-    // lower trailing update D_ij -= Z_i P_j^T over the tiles with P_i != 0
+    // the 64-row tiles where P has a nonzero; elsewhere Z = P Dkk^-1 and the
+    // trailing update are exactly zero
     k_tile_nonzero<<<(unsigned)nt, 256, 0, s>>>(pcol.p, nb, o, nb, tflag.p);
     k_tile_compact<<<1, 256, 0, s>>>(tflag.p, nt, tlist.p, tcount.p);
     FPC_LAUNCH_CHECK();
     const int64_t mt = read_i32(tcount.p, s);
+    FPC_HIP(hipMemsetAsync(z.p, 0, (size_t)n * nb * sizeof(double), s));
     if (mt > 0) {
       const SkipMap sel{0, 0, tlist.p};
+      // Z = P Dkk^-1 on those tiles
+      gemm_f64(mt * GT, nb, (int)nb, 1.0, 0.0, pcol.p, nb, Dkk, n, z.p, nb, sel,
+               none, s);
+      // lower trailing update D_ij -= Z_i P_j^T
       gemm_f64(mt * GT, mt * GT, (int)nb, -1.0, 1.0, z.p, nb, prow.p, n, D, n,
                sel, sel, s, /*lower=*/1);
     }
