@@ -119,13 +119,21 @@ __global__ void k_key(const int32_t* state, const int64_t* prio, int64_t n,
 }
 
 // out[i] = max(in[i], max over the block row's columns)
+// (four lanes per row, each taking every fourth neighbour, then a shuffle
+// max: more gathers in flight than one lane per row)
 __global__ void k_max_closed(const int64_t* rp, const int32_t* col,
                              int64_t n, const int64_t* in, int64_t* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t m = in[i];
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = max(m, in[col[e]]);
-  out[i] = m;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 2;
+  const int q = (int)(t & 3);
+  int64_t m = INT64_MIN;
+  if (i < n) {
+    if (q == 0) m = in[i];
+    for (int64_t e = rp[i] + q; e < rp[i + 1]; e += 4) m = max(m, in[col[e]]);
+  }
+  m = max(m, (int64_t)__shfl_xor((long long)m, 1, 64));
+  m = max(m, (int64_t)__shfl_xor((long long)m, 2, 64));
+  if (i < n && q == 0) out[i] = m;
 }
 
 __global__ void k_mis_update(int32_t* state, const int64_t* key,
@@ -1103,6 +1111,7 @@ int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
   DevBuf<uint8_t> iso(n);
   DevBuf<int> cnt(1);
   const unsigned g = grid_for(n, 256);
+  const unsigned g4 = grid_for(4 * n, 256);  // k_max_closed: four lanes a row
   k_agg_init<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, prio.p, state.p, iso.p);
   FPC_LAUNCH_CHECK();
   // four rounds per check (a round after convergence changes nothing); the
@@ -1111,8 +1120,8 @@ int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
     for (int k = 0; k < 4; ++k) {
       if (k == 3) FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
       k_key<<<g, 256, 0, s>>>(state.p, prio.p, n, key.p);
-      k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
-      k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, m1.p, m2.p);
+      k_max_closed<<<g4, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+      k_max_closed<<<g4, 256, 0, s>>>(a.rowptr.p, a.col.p, n, m1.p, m2.p);
       k_mis_update<<<g, 256, 0, s>>>(state.p, key.p, m2.p, n, cnt.p);
     }
     FPC_LAUNCH_CHECK();
@@ -1128,7 +1137,7 @@ int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
                                key.p);
   FPC_LAUNCH_CHECK();
   // phase 1: join the adjacent root of largest priority
-  k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+  k_max_closed<<<g4, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
   FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
   k_join<<<g, 256, 0, s>>>(iso.p, m1.p, n, agg, cnt.p);
   FPC_LAUNCH_CHECK();
@@ -1138,7 +1147,7 @@ int64_t aggregate_mis2(const Bsr& a, int32_t* agg, DevBuf<int32_t>& roots,
   for (int sweep = 0; remaining > 0; ++sweep) {
     if (sweep > 64) throw Error(FPC_ERR_HIP, "aggregation left nodes");
     k_rk2<<<g, 256, 0, s>>>(agg, roots.p, prio.p, n, key.p);
-    k_max_closed<<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
+    k_max_closed<<<g4, 256, 0, s>>>(a.rowptr.p, a.col.p, n, key.p, m1.p);
     FPC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
     k_join<<<g, 256, 0, s>>>(iso.p, m1.p, n, agg, cnt.p);
     FPC_LAUNCH_CHECK();
