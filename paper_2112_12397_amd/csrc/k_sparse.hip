@@ -8,24 +8,26 @@ namespace fpc {
 namespace {
 
 // ------------------------------------------------------------- validation
+// Four lanes per row: lane q checks entries e = a + q, a + q + 4, ... (column
+// in range, strictly above the previous entry's, finite value).
 __global__ void k_csr_validate(const int64_t* rowptr, const int32_t* col,
                                const double* val, int64_t nrows,
                                int64_t ncols, int64_t nnz, int* flags) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && (rowptr[0] != 0 || rowptr[nrows] != nnz))
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 2;
+  const int q = (int)(t & 3);
+  if (t == 0 && (rowptr[0] != 0 || rowptr[nrows] != nnz))
     atomicOr(&flags[FLAG_PATTERN], 1);
   if (i >= nrows) return;
-  int64_t a = rowptr[i], b = rowptr[i + 1];
+  const int64_t a = rowptr[i], b = rowptr[i + 1];
   if (a > b || a < 0 || b > nnz) {
-    atomicOr(&flags[FLAG_PATTERN], 1);
+    if (q == 0) atomicOr(&flags[FLAG_PATTERN], 1);
     return;
   }
-  int32_t prev = -1;
   bool bad = false, nan = false;
-  for (int64_t e = a; e < b; ++e) {
-    int32_t c = col[e];
-    if (c <= prev || c >= ncols) bad = true;
-    prev = c;
+  for (int64_t e = a + q; e < b; e += 4) {
+    const int32_t c = col[e];
+    if (c < 0 || c >= ncols || (e > a && c <= col[e - 1])) bad = true;
     if (!isfinite(val[e])) nan = true;
   }
   if (bad) atomicOr(&flags[FLAG_PATTERN], 1);
@@ -772,7 +774,7 @@ void to_sell_impl(const Bsr& a, Sell<T>& out, hipStream_t s) {
 }  // namespace
 
 void csr_validate(const Csr& m, int* flags, hipStream_t s) {
-  k_csr_validate<<<grid_for(std::max<int64_t>(m.nrows, 1), 256), 256, 0, s>>>(
+  k_csr_validate<<<grid_for(4 * std::max<int64_t>(m.nrows, 1), 256), 256, 0, s>>>(
       m.rowptr.p, m.col.p, m.val.p, m.nrows, m.ncols, m.nnz, flags);
   FPC_LAUNCH_CHECK();
 }
