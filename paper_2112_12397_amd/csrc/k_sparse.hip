@@ -173,13 +173,81 @@ __global__ void k_tr_gather(const double* val, const int64_t* src,
 }
 
 // ------------------------------------------------------------- CSR -> BSR
+// Entries of a block row (its BR scalar rows) held in LDS by k_to_bsr_w.
+constexpr int TB_CAP = 512;
+
+__device__ inline int64_t block_row_entries(const int64_t* rowptr,
+                                            int64_t nrows, int64_t I, int br) {
+  const int64_t r0 = I * br, r1 = min(nrows, r0 + br);
+  return rowptr[r1] - rowptr[r0];
+}
+
+// One wavefront per block row with at most TB_CAP scalar entries: entry k
+// (the BR rows concatenated) has block column sbc[k]; it is the first of its
+// block column if no earlier entry has it, and its block's position is the
+// number of first entries with a smaller block column.  Count mode (bcol
+// null) writes the number of blocks, fill mode the blocks.
+template <int BR, int BC>
+__global__ __launch_bounds__(64) void k_to_bsr_w(
+    const int64_t* rowptr, const int32_t* col, const double* val,
+    int64_t nrows, const int64_t* browptr, int64_t* bcount, int32_t* bcol,
+    double* bval) {
+  __shared__ int32_t sbc[TB_CAP];
+  __shared__ uint8_t sfirst[TB_CAP];
+  const int64_t I = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t r0 = I * BR;
+  const int nr = (int)min<int64_t>(BR, nrows - r0);
+  const int64_t a = rowptr[r0];
+  const int m = (int)(rowptr[r0 + nr] - a);
+  if (m > TB_CAP) return;  // done by k_to_bsr
+  // the BR rows are contiguous in the CSR arrays: entry k is col[a + k]
+  for (int k = lane; k < m; k += 64) sbc[k] = col[a + k] / BC;
+  __syncthreads();
+  int cnt = 0;
+  for (int k = lane; k < m; k += 64) {
+    const int32_t b = sbc[k];
+    bool first = true;
+    for (int f = 0; f < k; ++f)
+      if (sbc[f] == b) {
+        first = false;
+        break;
+      }
+    sfirst[k] = first;
+    cnt += first;
+  }
+  __syncthreads();
+  if (!bcol) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0) bcount[I] = cnt;
+    return;
+  }
+  const int64_t out = browptr[I];
+  for (int k = lane; k < m; k += 64) {
+    const int32_t b = sbc[k];
+    int rank = 0;
+    for (int f = 0; f < m; ++f) rank += sfirst[f] && sbc[f] < b;
+    if (sfirst[k]) bcol[out + rank] = b;
+    // scalar row of entry k
+    int r = 0;
+#pragma unroll
+    for (int q = 1; q < BR; ++q)
+      if (q < nr && a + k >= rowptr[r0 + q]) r = q;
+    bval[(out + rank) * (BR * BC) + r * BC + col[a + k] % BC] = val[a + k];
+  }
+}
+
+// Thread per block row (merge of its BR scalar rows); with min_m, only the
+// block rows with more than min_m scalar entries.
 template <int BR, int BC>
 __global__ void k_to_bsr(const int64_t* rowptr, const int32_t* col,
                          const double* val, int64_t nrows, int64_t nbr,
                          const int64_t* browptr, int64_t* bcount,
-                         int32_t* bcol, double* bval) {
+                         int32_t* bcol, double* bval, int64_t min_m) {
   int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nbr) return;
+  if (block_row_entries(rowptr, nrows, I, BR) <= min_m) return;
   int64_t p[BR], e[BR];
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
@@ -674,19 +742,27 @@ void to_bsr_impl(const Csr& a, Bsr& out, hipStream_t s) {
   out.nbc = (a.ncols + BC - 1) / BC;
   DevBuf<int64_t> cnt(std::max<int64_t>(out.nbr, 1));
   out.rowptr.alloc(out.nbr + 1);
-  if (out.nbr)
+  if (out.nbr) {
+    k_to_bsr_w<BR, BC><<<(unsigned)out.nbr, 64, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nrows, nullptr, cnt.p, nullptr,
+        nullptr);
     k_to_bsr<BR, BC><<<grid_for(out.nbr, 128), 128, 0, s>>>(
         a.rowptr.p, a.col.p, a.val.p, a.nrows, out.nbr, nullptr, cnt.p,
-        nullptr, nullptr);
+        nullptr, nullptr, TB_CAP);
+  }
   FPC_LAUNCH_CHECK();
   out.nnzb = scan_counts_total(cnt.p, out.rowptr.p, out.nbr, s);
   out.col.alloc(std::max<int64_t>(out.nnzb, 1));
   out.val.alloc(std::max<int64_t>(out.nnzb * BR * BC, 1));
   fill_f64(out.val.p, 0.0, out.nnzb * BR * BC, s);
-  if (out.nbr)
+  if (out.nbr) {
+    k_to_bsr_w<BR, BC><<<(unsigned)out.nbr, 64, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, a.nrows, out.rowptr.p, nullptr,
+        out.col.p, out.val.p);
     k_to_bsr<BR, BC><<<grid_for(out.nbr, 128), 128, 0, s>>>(
         a.rowptr.p, a.col.p, a.val.p, a.nrows, out.nbr, out.rowptr.p, nullptr,
-        out.col.p, out.val.p);
+        out.col.p, out.val.p, TB_CAP);
+  }
   FPC_LAUNCH_CHECK();
 }
 
