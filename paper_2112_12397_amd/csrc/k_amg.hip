@@ -205,7 +205,7 @@ __global__ void k_bbox_partial(const double* X, int64_t n, double* part) {
   }
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
+    if ((int)threadIdx.x < s)
       for (int d = 0; d < 3; ++d) {
         sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + s]);
         sh[3 + d][threadIdx.x] =

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(DT) void k_maxpy(const double* __restrict__ V,
                                               const double* __restrict__ h,
                                               double* __restrict__ w, int64_t n) {
   __shared__ double hs[kMaxKrylov];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  if ((int)threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   for (int64_t k = (int64_t)blockIdx.x * DT + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * DT) {
