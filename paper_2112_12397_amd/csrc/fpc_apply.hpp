@@ -90,6 +90,18 @@ constexpr int kDotBlocks = 256;
 int64_t mdot_partials(int64_t n, int nv);
 void mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
           double* partials, double* out, hipStream_t s);
+// Classical Gram-Schmidt passes (partials sized by mdot_partials):
+//   cgs_dot:       out[i] = <V_i, w> (i < nv), out[nv] = <w, w>
+//   cgs_axpy_dot:  w -= sum_i h_i V_i, then out[i] = <V_i, w>
+//   cgs_axpy_norm: w -= sum_i h_i V_i, then out[0] = <w, w>
+void cgs_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+             double* partials, double* out, hipStream_t s);
+void cgs_axpy_dot(const double* V, int64_t ldv, int nv, const double* h,
+                  double* w, int64_t n, double* partials, double* out,
+                  hipStream_t s);
+void cgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
+                   double* w, int64_t n, double* partials, double* out,
+                   hipStream_t s);
 // w -= sum_i h_i V_i
 void maxpy(const double* V, int64_t ldv, int nv, const double* h, double* w,
            int64_t n, hipStream_t s);

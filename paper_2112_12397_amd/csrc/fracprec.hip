@@ -906,25 +906,31 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
         apply(h, trans, vj, zj);
       }
       matvec(h, trans, zj, K.w.p);
-      mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
+      // |w|^2 before the projections (breakdown test) at nrm_before
+      const double* nrm_before = sc + 4;
       if (h->opt.ortho == FPC_MGS) {
         // modified Gram-Schmidt: h_ij = v_i^T w with the w of step i
+        mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
         for (int i = 0; i <= j; ++i) {
           const double* vi = K.V.p + (int64_t)i * N;
           mdot(vi, N, 1, K.w.p, N, K.partials.p, K.h1.p + i, s);
           maxpy(vi, N, 1, K.h1.p + i, K.w.p, N, s);
         }
         FPC_HIP(hipMemsetAsync(K.h2.p, 0, (j + 1) * sizeof(double), s));
+        mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 5, s);
       } else {
-        // classical Gram-Schmidt, twice
-        mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
-        maxpy(K.V.p, N, j + 1, K.h1.p, K.w.p, N, s);
-        mdot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h2.p, s);
-        maxpy(K.V.p, N, j + 1, K.h2.p, K.w.p, N, s);
+        // classical Gram-Schmidt, twice, in three passes over the basis:
+        // h1 = V^T w (and |w|^2); w -= V h1 with h2 = V^T w from the same
+        // rows; w -= V h2 with |w|^2
+        cgs_dot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
+        nrm_before = K.h1.p + j + 1;
+        cgs_axpy_dot(K.V.p, N, j + 1, K.h1.p, K.w.p, N, K.partials.p, K.h2.p,
+                     s);
+        cgs_axpy_norm(K.V.p, N, j + 1, K.h2.p, K.w.p, N, K.partials.p, sc + 5,
+                      s);
       }
-      mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 5, s);
       gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
-                 sc + 4, j, sc, K.ctrl.p, s);
+                 nrm_before, j, sc, K.ctrl.p, s);
       scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
       if (lead && j + 1 < m) {
         apply(h, trans, K.V.p + (int64_t)(j + 1) * N,

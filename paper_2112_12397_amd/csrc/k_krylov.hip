@@ -94,6 +94,144 @@ __global__ __launch_bounds__(DT) void k_maxpy(const double* __restrict__ V,
   }
 }
 
+// Base of vector i (clamped to nv - 1) as a wavefront-uniform pointer, so
+// that a load takes it from scalar registers with a 32-bit per-lane offset.
+typedef const __attribute__((address_space(1))) char* gchar_ptr;
+
+__device__ inline gchar_ptr cgs_base(const double* V, uint64_t stride_b, int i,
+                                     int nv) {
+  const int ie = i < nv ? i : nv - 1;
+  const uint64_t a = reinterpret_cast<uint64_t>(V) + (uint64_t)ie * stride_b;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return (gchar_ptr)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline double cgs_load(gchar_ptr base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) double*)(base + off);
+}
+
+// Classical Gram-Schmidt passes over the rows of one grid: block b owns the
+// rows b * DT + t + q * G * DT (G = gridDim.x); each thread keeps its partial
+// sums for all vectors in registers (NV >= nv, a compile-time bound) and the
+// block adds them at the end, wavefronts in order: one partial per block and
+// output, part[i * G + b].
+template <int NV>
+__device__ inline void block_partials(const double (&acc)[NV], int nv,
+                                      double* __restrict__ part,
+                                      bool has_extra = false,
+                                      double extra = 0.0) {
+  __shared__ double red[DT / 64][NV + 1];
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    if (i < nv) {
+      const double t = wsum(acc[i]);
+      if ((threadIdx.x & 63) == 0) red[wave][i] = t;
+    }
+  if (has_extra) {
+    const double t = wsum(extra);
+    if ((threadIdx.x & 63) == 0) red[wave][nv] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv + (has_extra ? 1 : 0)) {
+    const int i = threadIdx.x;
+    part[(int64_t)i * gridDim.x + blockIdx.x] =
+        (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+  }
+}
+
+// <V_i, w> for i < nv and, as output nv, <w, w>.
+template <int NV>
+__global__ __launch_bounds__(DT) void k_cgs_dot(const double* __restrict__ V,
+                                                int64_t ldv, int nv,
+                                                const double* __restrict__ w,
+                                                int64_t n,
+                                                double* __restrict__ part) {
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  double ww = 0.0;
+  const uint64_t stride = (uint64_t)ldv * sizeof(double);
+  for (uint32_t k = blockIdx.x * DT + threadIdx.x; k < (uint64_t)n;
+       k += gridDim.x * DT) {
+    const double wk = w[k];
+    const uint32_t off = k * (uint32_t)sizeof(double);
+    // re-derive the vector bases each row (scalar arithmetic) instead of
+    // holding nv of them live across the loop
+    uint64_t st = stride;
+    asm volatile("" : "+s"(st));
+    // every slot loads (slots beyond nv repeat the last vector, whose rows
+    // are in cache, and their sums are dropped): a load under a condition
+    // would be waited for before the next one is issued
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      v[i] = cgs_load(cgs_base(V, st, i, nv), off);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += v[i] * wk;
+    ww += wk * wk;
+  }
+  block_partials<NV>(acc, nv, part, true, ww);
+}
+
+// w <- w - sum_i h_i V_i, then <V_i, w> with the updated w: the rows of the
+// nv vectors stay in registers between the two uses, so the basis is read
+// once.  The update adds in the order of k_maxpy, so w is the same.
+template <int NV>
+__global__ __launch_bounds__(DT) void k_cgs_axpy_dot(
+    const double* __restrict__ V, int64_t ldv, int nv,
+    const double* __restrict__ h, double* __restrict__ w, int64_t n,
+    double* __restrict__ part) {
+  __shared__ double hs[NV];
+  if ((int)threadIdx.x < NV) hs[threadIdx.x] = (int)threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const uint64_t stride = (uint64_t)ldv * sizeof(double);
+  for (uint32_t k = blockIdx.x * DT + threadIdx.x; k < (uint64_t)n;
+       k += gridDim.x * DT) {
+    const uint32_t off = k * (uint32_t)sizeof(double);
+    // the coefficients are read from LDS where they are used and the vector
+    // bases re-derived each row, so that neither occupies nv registers
+    // across the loop
+    uint64_t st = stride;
+    asm volatile("" : "+s"(st)::"memory");
+    // unconditional loads as in k_cgs_dot; hs is zero beyond nv
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      v[i] = cgs_load(cgs_base(V, st, i, nv), off);
+    double wk = w[k];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) wk -= hs[i] * v[i];
+    w[k] = wk;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += v[i] * wk;
+  }
+  block_partials<NV>(acc, nv, part);
+}
+
+// w <- w - sum_i h_i V_i and the partial of <w, w> (one output).
+__global__ __launch_bounds__(DT) void k_cgs_axpy_norm(
+    const double* __restrict__ V, int64_t ldv, int nv,
+    const double* __restrict__ h, double* __restrict__ w, int64_t n,
+    double* __restrict__ part) {
+  __shared__ double hs[kMaxKrylov];
+  if ((int)threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double acc[1] = {0.0};
+  for (int64_t k = (int64_t)blockIdx.x * DT + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * DT) {
+    double wk = w[k];
+    for (int i = 0; i < nv; ++i) wk -= hs[i] * V[(int64_t)i * ldv + k];
+    w[k] = wk;
+    acc[0] += wk * wk;
+  }
+  block_partials<1>(acc, 1, part);
+}
+
 __global__ void k_scale_inv(const double* __restrict__ x,
                             const double* __restrict__ scal,
                             double* __restrict__ y, int64_t n) {
@@ -167,8 +305,19 @@ __global__ void k_sqrt(const double* in, double* out) {
 
 }  // namespace
 
+// Blocks of the Gram-Schmidt passes: enough to fill the chip at 1 024, one
+// per 256 rows below that.
+constexpr int64_t kCgsBlocks = 1024;
+// Largest vector count whose rows the fused axpy + dot pass keeps in
+// registers (two arrays of NV doubles per thread).
+constexpr int kCgsFusedMax = 48;
+int64_t cgs_blocks(int64_t n) {
+  return std::max<int64_t>(std::min<int64_t>((n + DT - 1) / DT, kCgsBlocks), 1);
+}
+
 int64_t mdot_partials(int64_t n, int nv) {
-  return (int64_t)nv * std::max<int64_t>((n + DT * MR - 1) / (DT * MR), 1);
+  const int64_t nb = std::max<int64_t>((n + DT * MR - 1) / (DT * MR), 1);
+  return (int64_t)nv * std::max(nb, cgs_blocks(n));
 }
 
 void mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
@@ -178,6 +327,70 @@ void mdot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
   k_mdot_rows<<<(unsigned)nb, DT, 0, s>>>(V, ldv, nv, w, n, partials);
   FPC_LAUNCH_CHECK();
   k_mdot_reduce<<<nv, DT, 0, s>>>(partials, (int)nb, out);
+  FPC_LAUNCH_CHECK();
+}
+
+#define FPC_CGS_BUCKETS(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
+
+// The passes address a vector's rows by 32-bit byte offsets.
+constexpr int64_t kCgsMaxRows = int64_t(1) << 29;
+
+void cgs_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+             double* partials, double* out, hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov) throw Error(FPC_ERR_ARG, "cgs_dot: vector count");
+  if (n >= kCgsMaxRows) {
+    mdot(V, ldv, nv, w, n, partials, out, s);
+    mdot(w, 0, 1, w, n, partials, out + nv, s);
+    return;
+  }
+  const int64_t G = cgs_blocks(n);
+  switch ((nv + 7) / 8) {
+#define FPC_CASE(B)                                                          \
+  case B / 8:                                                                \
+    k_cgs_dot<B><<<(unsigned)G, DT, 0, s>>>(V, ldv, nv, w, n, partials);     \
+    break;
+    FPC_CGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+  }
+  FPC_LAUNCH_CHECK();
+  k_mdot_reduce<<<nv + 1, DT, 0, s>>>(partials, (int)G, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void cgs_axpy_dot(const double* V, int64_t ldv, int nv, const double* h,
+                  double* w, int64_t n, double* partials, double* out,
+                  hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov) throw Error(FPC_ERR_ARG, "cgs_axpy_dot: vector count");
+  if (nv > kCgsFusedMax || n >= kCgsMaxRows) {
+    // beyond the register budget: the two passes separately
+    maxpy(V, ldv, nv, h, w, n, s);
+    mdot(V, ldv, nv, w, n, partials, out, s);
+    return;
+  }
+  const int64_t G = cgs_blocks(n);
+  switch ((nv + 7) / 8) {
+#define FPC_CASE(B)                                                        \
+  case B / 8:                                                              \
+    if constexpr (B <= kCgsFusedMax)                                       \
+      k_cgs_axpy_dot<B><<<(unsigned)G, DT, 0, s>>>(V, ldv, nv, h, w, n,    \
+                                                  partials);              \
+    break;
+    FPC_CGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+  }
+  FPC_LAUNCH_CHECK();
+  k_mdot_reduce<<<nv, DT, 0, s>>>(partials, (int)G, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void cgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
+                   double* w, int64_t n, double* partials, double* out,
+                   hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov) throw Error(FPC_ERR_ARG, "cgs_axpy_norm: vector count");
+  const int64_t G = cgs_blocks(n);
+  k_cgs_axpy_norm<<<(unsigned)G, DT, 0, s>>>(V, ldv, nv, h, w, n, partials);
+  FPC_LAUNCH_CHECK();
+  k_mdot_reduce<<<1, DT, 0, s>>>(partials, (int)G, out);
   FPC_LAUNCH_CHECK();
 }
 
