@@ -248,35 +248,49 @@ __global__ void k_axpby(double a, const double* __restrict__ x, double b,
   y[k] = (b == 0.0) ? a * x[k] : a * x[k] + b * y[k];
 }
 
-__global__ void k_gmres_step(double* H, int ldh, double* cs, double* sn,
-                             double* g, const double* h1, const double* h2,
-                             const double* nrm2, const double* nrm2_before,
-                             int j, double* scal, int* ctrl) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double col[kMaxKrylov + 1];
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double hn = sqrt(fmax(nrm2[0], 0.0));
-  const double w0 = sqrt(fmax(nrm2_before[0], 0.0));
-  col[j + 1] = hn;
-  const int breakdown = !(hn > 1e-14 * w0);
-  scal[0] = breakdown ? 0.0 : hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+// One Arnoldi column: h = h1 + h2 and the new subdiagonal |w|, the previous
+// Givens rotations applied to it, the new rotation and the updated residual
+// estimate.  The wavefront stages the column and the rotations in LDS, so
+// the sequential rotation loop of lane 0 waits on LDS rather than memory.
+__global__ __launch_bounds__(64) void k_gmres_step(
+    double* H, int ldh, double* cs, double* sn, double* g, const double* h1,
+    const double* h2, const double* nrm2, const double* nrm2_before, int j,
+    double* scal, int* ctrl) {
+  __shared__ double col[kMaxKrylov + 1], c_s[kMaxKrylov], s_s[kMaxKrylov];
+  for (int i = threadIdx.x; i <= j; i += 64) {
+    col[i] = h1[i] + h2[i];
+    if (i < j) {
+      c_s[i] = cs[i];
+      s_s[i] = sn[i];
+    }
   }
-  const double rho = hypot(col[j], col[j + 1]);
-  const double c = rho != 0.0 ? col[j] / rho : 1.0;
-  const double sgn = rho != 0.0 ? col[j + 1] / rho : 0.0;
-  cs[j] = c;
-  sn[j] = sgn;
-  col[j] = rho;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sgn * g[j];
-  g[j] = c * g[j];
-  for (int i = 0; i <= j + 1; ++i) H[(int64_t)i * ldh + j] = col[i];
-  scal[1] = fabs(g[j + 1]);
-  ctrl[0] = breakdown;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(fmax(nrm2[0], 0.0));
+    const double w0 = sqrt(fmax(nrm2_before[0], 0.0));
+    col[j + 1] = hn;
+    const int breakdown = !(hn > 1e-14 * w0);
+    scal[0] = breakdown ? 0.0 : hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = c_s[i] * col[i] + s_s[i] * col[i + 1];
+      col[i + 1] = -s_s[i] * col[i] + c_s[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double rho = hypot(col[j], col[j + 1]);
+    const double c = rho != 0.0 ? col[j] / rho : 1.0;
+    const double sgn = rho != 0.0 ? col[j + 1] / rho : 0.0;
+    cs[j] = c;
+    sn[j] = sgn;
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sgn * gj;
+    g[j] = c * gj;
+    scal[1] = fabs(sgn * gj);
+    ctrl[0] = breakdown;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 64) H[(int64_t)i * ldh + j] = col[i];
 }
 
 __global__ void k_gmres_init(double* g, int m, const double* beta2,
