@@ -87,21 +87,59 @@ __global__ void k_bfs_step(const int64_t* rp, const int32_t* col, int64_t n,
 // Reorder the members of every component by (BFS level, face index): the
 // rank of each member among its component's members gives its new local
 // position.
-__global__ void k_level_rank(const int32_t* members, const int64_t* comp_off,
-                             const int32_t* comp_of_row, const int32_t* level,
-                             int64_t n, int32_t* pos, int32_t* members2) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int32_t c = comp_of_row[e];
-  const int64_t a = comp_off[c], b = comp_off[c + 1];
-  const int32_t m = members[e], lm = level[m];
-  int32_t rank = 0;
-  for (int64_t f = a; f < b; ++f) {
-    const int32_t mf = members[f], lf = level[mf];
-    rank += (lf < lm) || (lf == lm && mf < m);
+// Rank of a face inside its component by (level, face index).  Block
+// (x, y) takes rows [256 x, 256 x + 256) and the y-th of gridDim.y slices of
+// the positions those rows' components cover; the slice's keys pass through
+// LDS 256 at a time and every thread counts those of its own component that
+// order before its key, adding the count to rank[e] (zeroed before).
+__global__ __launch_bounds__(256) void k_level_count(
+    const int32_t* members, const int64_t* comp_off, const int32_t* comp_of_row,
+    const int32_t* level, int64_t n, int32_t* rank) {
+  __shared__ int64_t keys[256];
+  const int64_t e0 = (int64_t)blockIdx.x * 256;
+  const int64_t e = e0 + threadIdx.x;
+  const bool act = e < n;
+  int64_t a = 0, b = 0, mykey = 0;
+  if (act) {
+    const int32_t c = comp_of_row[e];
+    a = comp_off[c];
+    b = comp_off[c + 1];
+    const int32_t m = members[e];
+    mykey = ((int64_t)level[m] << 32) | (uint32_t)m;
   }
-  pos[m] = rank;
-  members2[a + rank] = m;
+  const int64_t elast = e0 + 255 < n ? e0 + 255 : n - 1;
+  const int64_t lo0 = comp_off[comp_of_row[e0]];
+  const int64_t hi0 = comp_off[comp_of_row[elast] + 1];
+  const int64_t chunk = ((hi0 - lo0 + gridDim.y - 1) / gridDim.y + 255) / 256 * 256;
+  const int64_t lo = lo0 + (int64_t)blockIdx.y * chunk;
+  const int64_t hi = lo + chunk < hi0 ? lo + chunk : hi0;
+  int32_t cnt_total = 0;
+  for (int64_t f0 = lo; f0 < hi; f0 += 256) {
+    __syncthreads();
+    const int64_t f = f0 + threadIdx.x;
+    if (f < hi) {
+      const int32_t mf = members[f];
+      keys[threadIdx.x] = ((int64_t)level[mf] << 32) | (uint32_t)mf;
+    }
+    __syncthreads();
+    const int cnt = hi - f0 < 256 ? (int)(hi - f0) : 256;
+    for (int q = 0; q < cnt; ++q) {
+      const int64_t ff = f0 + q;
+      cnt_total += (ff >= a && ff < b && keys[q] < mykey) ? 1 : 0;
+    }
+  }
+  if (act && cnt_total) atomicAdd(&rank[e], cnt_total);
+}
+
+// Position of every face inside its component from its rank.
+__global__ void k_level_place(const int32_t* members, const int64_t* comp_off,
+                              const int32_t* comp_of_row, const int32_t* rank,
+                              int64_t n, int32_t* pos, int32_t* members2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t m = members[e];
+  pos[m] = rank[e];
+  members2[comp_off[comp_of_row[e]] + rank[e]] = m;
 }
 
 __global__ void k_scatter_T(const int64_t* rp, const int32_t* col,
@@ -328,9 +366,14 @@ void build_psolve(fpc_handle* h) {
       if (read_i32(changed.p, s) == 0) break;
       if (cur > n + 8) throw Error(FPC_ERR_HIP, "level ordering stalled");
     }
-    k_level_rank<<<g, 256, 0, s>>>(ps.members.p, ps.comp_off.p,
-                                   ps.comp_of_row.p, level.p, n, pos.p,
-                                   members2.p);
+    DevBuf<int32_t> rank(n);
+    FPC_HIP(hipMemsetAsync(rank.p, 0, n * sizeof(int32_t), s));
+    k_level_count<<<dim3(g, 16), 256, 0, s>>>(ps.members.p, ps.comp_off.p,
+                                              ps.comp_of_row.p, level.p, n,
+                                              rank.p);
+    k_level_place<<<g, 256, 0, s>>>(ps.members.p, ps.comp_off.p,
+                                    ps.comp_of_row.p, rank.p, n, pos.p,
+                                    members2.p);
     FPC_LAUNCH_CHECK();
     FPC_HIP(hipMemcpyAsync(ps.members.p, members2.p, n * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, s));

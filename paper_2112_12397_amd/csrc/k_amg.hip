@@ -679,10 +679,21 @@ __device__ inline void tile_gemm(const double* D, int64_t ld, int64_t xi,
                                  double (*sa)[GT + 1], double (*sb)[GT + 1],
                                  double acc[4][4]) {
   const int tid = threadIdx.x;
-  for (int q = tid; q < GT * GT; q += 256) {
-    int r = q / GT, c = q % GT;
-    sa[r][c] = D[(xi * GT + r) * ld + xj * GT + c];
-    sb[r][c] = D[(yi * GT + r) * ld + yj * GT + c];
+  {
+    // all 32 loads of a thread in flight before the LDS stores
+    const int c = tid & (GT - 1), r0 = tid >> 6;
+    double ra[16], rb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t r = r0 + 4 * u;
+      ra[u] = D[(xi * GT + r) * ld + xj * GT + c];
+      rb[u] = D[(yi * GT + r) * ld + yj * GT + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      sa[r0 + 4 * u][c] = ra[u];
+      sb[r0 + 4 * u][c] = rb[u];
+    }
   }
   __syncthreads();
   const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
@@ -725,9 +736,18 @@ __global__ __launch_bounds__(256) void k_gj_update(double* D, int64_t ld,
   double acc[4][4];
   tile_gemm(D, ld, i, kb, kb, j, sa, sb, acc);
   const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  // the 16 old values are loaded together, then updated and stored
+  double old[4][4];
+#pragma unroll
   for (int r = 0; r < 4; ++r)
+#pragma unroll
     for (int c = 0; c < 4; ++c)
-      D[(i * GT + tr + r) * ld + j * GT + tc + c] -= acc[r][c];
+      old[r][c] = D[(i * GT + tr + r) * ld + j * GT + tc + c];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      D[(i * GT + tr + r) * ld + j * GT + tc + c] = old[r][c] - acc[r][c];
 }
 
 // column panel: A[i, kb] <- -A[i, kb] * Dinv, i != kb
