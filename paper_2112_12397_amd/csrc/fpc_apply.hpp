@@ -69,6 +69,17 @@ void psolve_apply_b(const PSolve& ps, const double* in, double* out,
                     int64_t n_p, int KB, hipStream_t s);
 void bmdot(const double* V, int64_t ldv, int nv, const double* W, int64_t n,
            int KB, double* part, double* out, hipStream_t s);
+// Batched Gram-Schmidt passes (as cgs_dot / cgs_axpy_dot / cgs_axpy_norm,
+// per column; out[o * KB + c]); partials sized by bdot_partials.
+int64_t bdot_partials(int nv, int KB);
+void bcgs_dot(const double* V, int64_t ldv, int nv, const double* W, int64_t n,
+              int KB, double* part, double* out, hipStream_t s);
+void bcgs_axpy_dot(const double* V, int64_t ldv, int nv, const double* h,
+                   double* W, int64_t n, int KB, double* part, double* out,
+                   hipStream_t s);
+void bcgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
+                    double* W, int64_t n, int KB, double* part, double* out,
+                    hipStream_t s);
 void bmaxpy(const double* V, int64_t ldv, int nv, const double* h, double* W,
             int64_t n, int KB, hipStream_t s);
 void bscale(const double* x, const double* scal, double* y, int64_t n, int KB,
@@ -124,5 +135,23 @@ void gmres_init(double* g, int m, const double* beta2, double* scal,
 void gmres_trisolve(const double* H, int ldh, const double* g, double* y,
                     int k, hipStream_t s);
 void sqrt_dev(const double* in, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- device
+// Base of vector i (clamped to nv - 1) as a wavefront-uniform pointer, so
+// that a load takes it from scalar registers with a 32-bit per-lane offset.
+typedef const __attribute__((address_space(1))) char* gchar_ptr;
+
+__device__ inline gchar_ptr cgs_base(const double* V, uint64_t stride_b, int i,
+                                     int nv) {
+  const int ie = i < nv ? i : nv - 1;
+  const uint64_t a = reinterpret_cast<uint64_t>(V) + (uint64_t)ie * stride_b;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return (gchar_ptr)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline double cgs_load(gchar_ptr base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) double*)(base + off);
+}
 
 }  // namespace fpc

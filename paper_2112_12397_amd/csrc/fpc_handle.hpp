@@ -179,7 +179,7 @@ struct BatchWork {
   int KB = 0, m = 0;
   int64_t N = 0;
   DevBuf<double> V, Z, W, R, Bi, Xi, tt;
-  DevBuf<double> H, cs, sn, g, y, yneg, h1, h2, nrm0, nrm2, beta2, scal, est,
+  DevBuf<double> H, cs, sn, g, y, yneg, h1, h2, nrm2, beta2, scal, est,
       bnorm2, partials;
   DevBuf<int> active, kc, brk;
 };

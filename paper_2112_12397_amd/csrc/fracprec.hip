@@ -1052,13 +1052,12 @@ BatchWork& batch_work(fpc_handle* h, int KB) {
   w->yneg.alloc((int64_t)KB * m);
   w->h1.alloc((int64_t)KB * (m + 1));
   w->h2.alloc((int64_t)KB * (m + 1));
-  w->nrm0.alloc(KB);
   w->nrm2.alloc(KB);
   w->beta2.alloc(KB);
   w->scal.alloc(KB);
   w->est.alloc(KB);
   w->bnorm2.alloc(KB);
-  w->partials.alloc((int64_t)(m + 1) * kDotBlocks * KB);
+  w->partials.alloc(bdot_partials(m + 1, KB));
   w->active.alloc(KB);
   w->kc.alloc(KB);
   w->brk.alloc(KB);
@@ -1184,15 +1183,16 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
       double* Zj = w.Z.p + (int64_t)j * stride;
       apply_b(h, w, Vj, Zj);
       matvec_b(h, Zj, w.W.p, KB);
-      bmdot(w.W.p, 0, 1, w.W.p, N, KB, w.partials.p, w.nrm0.p, s);
-      bmdot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h1.p, s);
-      bmaxpy(w.V.p, stride, j + 1, w.h1.p, w.W.p, N, KB, s);
-      bmdot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h2.p, s);
-      bmaxpy(w.V.p, stride, j + 1, w.h2.p, w.W.p, N, KB, s);
-      bmdot(w.W.p, 0, 1, w.W.p, N, KB, w.partials.p, w.nrm2.p, s);
+      // classical Gram-Schmidt twice in three passes, per column: h1 with
+      // |w|^2 (in h1 row j + 1), w -= V h1 with h2, w -= V h2 with |w|^2
+      bcgs_dot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h1.p, s);
+      bcgs_axpy_dot(w.V.p, stride, j + 1, w.h1.p, w.W.p, N, KB, w.partials.p,
+                    w.h2.p, s);
+      bcgs_axpy_norm(w.V.p, stride, j + 1, w.h2.p, w.W.p, N, KB, w.partials.p,
+                     w.nrm2.p, s);
       bgmres_step(w.H.p, w.cs.p, w.sn.p, w.g.p, w.h1.p, w.h2.p, w.nrm2.p,
-                  w.nrm0.p, j, m, KB, w.active.p, w.scal.p, w.est.p, w.brk.p,
-                  s);
+                  w.h1.p + (int64_t)(j + 1) * KB, j, m, KB, w.active.p,
+                  w.scal.p, w.est.p, w.brk.p, s);
       bscale(w.W.p, w.scal.p, w.V.p + (int64_t)(j + 1) * stride, N, KB, s);
       FPC_HIP(hipMemcpyAsync(estv.data(), w.est.p, KB * sizeof(double),
                              hipMemcpyDeviceToHost, s));

@@ -183,14 +183,24 @@ __global__ __launch_bounds__(BT) void k_bmdot_partial(
   }
 }
 
-__global__ void k_bmdot_reduce(const double* __restrict__ part, int np, int KB,
-                               double* __restrict__ out) {
+// out(i, c) = sum_q part[(i * np + q) * KB + c]: block i, thread (ql, c)
+// = (tid / KB, tid % KB) adds every nql-th partial, then the nql sums are
+// added in order.
+__global__ __launch_bounds__(BT) void k_bmdot_reduce(
+    const double* __restrict__ part, int np, int KB, double* __restrict__ out) {
+  __shared__ double sh[BT];
   const int i = blockIdx.x;
-  const int c = threadIdx.x;
-  if (c >= KB) return;
+  const int ql = threadIdx.x / KB, c = threadIdx.x % KB, nql = BT / KB;
   double t = 0.0;
-  for (int q = 0; q < np; ++q) t += part[((int64_t)i * np + q) * KB + c];
-  out[(int64_t)i * KB + c] = t;
+  if (ql < nql)
+    for (int q = ql; q < np; q += nql) t += part[((int64_t)i * np + q) * KB + c];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  if ((int)threadIdx.x < KB) {
+    double a = 0.0;
+    for (int q = 0; q < nql; ++q) a += sh[q * KB + threadIdx.x];
+    out[(int64_t)i * KB + threadIdx.x] = a;
+  }
 }
 
 // W(n, c) -= sum_i sgn * h(i, c) V_i(n, c)
@@ -210,6 +220,134 @@ __global__ __launch_bounds__(BT) void k_bmaxpy(const double* __restrict__ V,
     for (int i = 0; i < nv; ++i) acc -= hs[i * KB + c] * V[(int64_t)i * ldv + t];
     W[t] = acc;
   }
+}
+
+// Batched classical Gram-Schmidt passes (the three passes of the single
+// right-hand-side solve, per column).  Element t = r * KB + c of a vector
+// (row r, column c); thread (rl, c) = (tid / KB, tid % KB) of block b takes
+// rows r = b * nrl + rl + q * G * nrl with nrl = BT / KB, and keeps one
+// partial per vector in registers; the block adds them per column at the
+// end, part[(o * G + b) * KB + c] for output o.
+__device__ inline double bwsum_cols(double* sh, double val, int KB, int nrl) {
+  // column sums over the block's row lanes; valid in threads tid < KB
+  __syncthreads();
+  sh[threadIdx.x] = val;
+  __syncthreads();
+  double t = 0.0;
+  if ((int)threadIdx.x < KB)
+    for (int q = 0; q < nrl; ++q) t += sh[q * KB + threadIdx.x];
+  return t;
+}
+
+template <int NV>
+__device__ inline void bblock_partials(const double (&acc)[NV], int nv,
+                                       bool has_extra, double extra, int KB,
+                                       double* __restrict__ part) {
+  __shared__ double sh[BT];
+  const int rl = threadIdx.x / KB, nrl = BT / KB;
+  const bool lane_ok = rl < nrl;
+#pragma unroll
+  for (int o = 0; o <= NV; ++o) {
+    if (o > nv || (o == nv && !has_extra)) break;
+    double val = 0.0;
+    if (o < NV) val = acc[o];
+    if (o == nv) val = extra;
+    const double t = bwsum_cols(sh, lane_ok ? val : 0.0, KB, nrl);
+    if ((int)threadIdx.x < KB)
+      part[((int64_t)o * gridDim.x + blockIdx.x) * KB + threadIdx.x] = t;
+  }
+}
+
+// <V_i, W> per column for i < nv and, as output nv, <W, W>.
+template <int NV>
+__global__ __launch_bounds__(BT) void k_bcgs_dot(const double* __restrict__ V,
+                                                 int64_t ldv, int nv,
+                                                 const double* __restrict__ W,
+                                                 int64_t n, int KB,
+                                                 double* __restrict__ part) {
+  const int rl = threadIdx.x / KB, c = threadIdx.x % KB, nrl = BT / KB;
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  double ww = 0.0;
+  if (rl < nrl) {
+    const uint64_t stride = (uint64_t)ldv * sizeof(double);
+    for (int64_t r = (int64_t)blockIdx.x * nrl + rl; r < n;
+         r += (int64_t)gridDim.x * nrl) {
+      const uint32_t t = (uint32_t)(r * KB + c);
+      const double wk = W[t];
+      const uint32_t off = t * (uint32_t)sizeof(double);
+      uint64_t st = stride;
+      asm volatile("" : "+s"(st));
+      double v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = cgs_load(cgs_base(V, st, i, nv), off);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[i] * wk;
+      ww += wk * wk;
+    }
+  }
+  bblock_partials<NV>(acc, nv, true, ww, KB, part);
+}
+
+// W -= sum_i h(i, c) V_i, then <V_i, W> per column from the same rows.
+template <int NV>
+__global__ __launch_bounds__(BT) void k_bcgs_axpy_dot(
+    const double* __restrict__ V, int64_t ldv, int nv,
+    const double* __restrict__ h, double* __restrict__ W, int64_t n, int KB,
+    double* __restrict__ part) {
+  __shared__ double hs[NV * 32];
+  for (int q = threadIdx.x; q < NV * KB; q += BT) hs[q] = q < nv * KB ? h[q] : 0.0;
+  __syncthreads();
+  const int rl = threadIdx.x / KB, c = threadIdx.x % KB, nrl = BT / KB;
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  if (rl < nrl) {
+    const uint64_t stride = (uint64_t)ldv * sizeof(double);
+    for (int64_t r = (int64_t)blockIdx.x * nrl + rl; r < n;
+         r += (int64_t)gridDim.x * nrl) {
+      const uint32_t t = (uint32_t)(r * KB + c);
+      const uint32_t off = t * (uint32_t)sizeof(double);
+      // the coefficients are read from LDS where they are used and the
+      // vector bases re-derived each row
+      uint64_t st = stride;
+      asm volatile("" : "+s"(st)::"memory");
+      double v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = cgs_load(cgs_base(V, st, i, nv), off);
+      double wk = W[t];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) wk -= hs[i * KB + c] * v[i];
+      W[t] = wk;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[i] * wk;
+    }
+  }
+  bblock_partials<NV>(acc, nv, false, 0.0, KB, part);
+}
+
+// W -= sum_i h(i, c) V_i and the partial of <W, W> per column.
+__global__ __launch_bounds__(BT) void k_bcgs_axpy_norm(
+    const double* __restrict__ V, int64_t ldv, int nv,
+    const double* __restrict__ h, double* __restrict__ W, int64_t n, int KB,
+    double* __restrict__ part) {
+  __shared__ double hs[kMaxKrylov * 32];
+  for (int q = threadIdx.x; q < nv * KB; q += BT) hs[q] = h[q];
+  __syncthreads();
+  const int rl = threadIdx.x / KB, c = threadIdx.x % KB, nrl = BT / KB;
+  double acc[1] = {0.0};
+  if (rl < nrl) {
+    for (int64_t r = (int64_t)blockIdx.x * nrl + rl; r < n;
+         r += (int64_t)gridDim.x * nrl) {
+      const int64_t t = r * KB + c;
+      double wk = W[t];
+      for (int i = 0; i < nv; ++i) wk -= hs[i * KB + c] * V[(int64_t)i * ldv + t];
+      W[t] = wk;
+      acc[0] += wk * wk;
+    }
+  }
+  bblock_partials<1>(acc, 1, false, 0.0, KB, part);
 }
 
 __global__ void k_bscale(const double* __restrict__ x,
@@ -393,7 +531,89 @@ void bmdot(const double* V, int64_t ldv, int nv, const double* W, int64_t n,
   dim3 grid(kDotBlocks, nv);
   k_bmdot_partial<<<grid, BT, 0, s>>>(V, ldv, W, n, KB, part);
   FPC_LAUNCH_CHECK();
-  k_bmdot_reduce<<<nv, 64, 0, s>>>(part, kDotBlocks, KB, out);
+  k_bmdot_reduce<<<nv, BT, 0, s>>>(part, kDotBlocks, KB, out);
+  FPC_LAUNCH_CHECK();
+}
+
+// Blocks of the batched Gram-Schmidt passes.
+constexpr int64_t kBcgsBlocks = 1024;
+// Largest vector count the fused axpy + dot pass keeps in registers.
+constexpr int kBcgsFusedMax = 48;
+
+int64_t bcgs_blocks(int64_t n, int KB) {
+  const int64_t nrl = BT / KB;
+  return std::max<int64_t>(std::min<int64_t>((n + nrl - 1) / nrl, kBcgsBlocks), 1);
+}
+
+int64_t bdot_partials(int nv, int KB) {
+  return (int64_t)nv * std::max<int64_t>(kDotBlocks, kBcgsBlocks) * KB;
+}
+
+// 32-bit element offsets address the vectors of the fused passes
+static bool bcgs_fits(int64_t n, int KB) {
+  return n * KB < (int64_t(1) << 29);
+}
+
+#define FPC_BCGS_BUCKETS(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
+
+void bcgs_dot(const double* V, int64_t ldv, int nv, const double* W, int64_t n,
+              int KB, double* part, double* out, hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov || KB < 1 || KB > 32)
+    throw Error(FPC_ERR_ARG, "bcgs_dot size");
+  if (!bcgs_fits(n, KB)) {
+    bmdot(V, ldv, nv, W, n, KB, part, out, s);
+    bmdot(W, 0, 1, W, n, KB, part, out + (int64_t)nv * KB, s);
+    return;
+  }
+  const int64_t G = bcgs_blocks(n, KB);
+  switch ((nv + 7) / 8) {
+#define FPC_CASE(B)                                                         \
+  case B / 8:                                                               \
+    k_bcgs_dot<B><<<(unsigned)G, BT, 0, s>>>(V, ldv, nv, W, n, KB, part);   \
+    break;
+    FPC_BCGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+  }
+  FPC_LAUNCH_CHECK();
+  k_bmdot_reduce<<<nv + 1, BT, 0, s>>>(part, (int)G, KB, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void bcgs_axpy_dot(const double* V, int64_t ldv, int nv, const double* h,
+                   double* W, int64_t n, int KB, double* part, double* out,
+                   hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov || KB < 1 || KB > 32)
+    throw Error(FPC_ERR_ARG, "bcgs_axpy_dot size");
+  if (nv > kBcgsFusedMax || !bcgs_fits(n, KB)) {
+    bmaxpy(V, ldv, nv, h, W, n, KB, s);
+    bmdot(V, ldv, nv, W, n, KB, part, out, s);
+    return;
+  }
+  const int64_t G = bcgs_blocks(n, KB);
+  switch ((nv + 7) / 8) {
+#define FPC_CASE(B)                                                          \
+  case B / 8:                                                                \
+    if constexpr (B <= kBcgsFusedMax)                                        \
+      k_bcgs_axpy_dot<B><<<(unsigned)G, BT, 0, s>>>(V, ldv, nv, h, W, n, KB, \
+                                                   part);                   \
+    break;
+    FPC_BCGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+  }
+  FPC_LAUNCH_CHECK();
+  k_bmdot_reduce<<<nv, BT, 0, s>>>(part, (int)G, KB, out);
+  FPC_LAUNCH_CHECK();
+}
+
+void bcgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
+                    double* W, int64_t n, int KB, double* part, double* out,
+                    hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov || KB < 1 || KB > 32)
+    throw Error(FPC_ERR_ARG, "bcgs_axpy_norm size");
+  const int64_t G = bcgs_blocks(n, KB);
+  k_bcgs_axpy_norm<<<(unsigned)G, BT, 0, s>>>(V, ldv, nv, h, W, n, KB, part);
+  FPC_LAUNCH_CHECK();
+  k_bmdot_reduce<<<1, BT, 0, s>>>(part, (int)G, KB, out);
   FPC_LAUNCH_CHECK();
 }
 

@@ -94,23 +94,6 @@ __global__ __launch_bounds__(DT) void k_maxpy(const double* __restrict__ V,
   }
 }
 
-// Base of vector i (clamped to nv - 1) as a wavefront-uniform pointer, so
-// that a load takes it from scalar registers with a 32-bit per-lane offset.
-typedef const __attribute__((address_space(1))) char* gchar_ptr;
-
-__device__ inline gchar_ptr cgs_base(const double* V, uint64_t stride_b, int i,
-                                     int nv) {
-  const int ie = i < nv ? i : nv - 1;
-  const uint64_t a = reinterpret_cast<uint64_t>(V) + (uint64_t)ie * stride_b;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-  return (gchar_ptr)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ inline double cgs_load(gchar_ptr base, uint32_t off) {
-  return *(const __attribute__((address_space(1))) double*)(base + off);
-}
-
 // Classical Gram-Schmidt passes over the rows of one grid: block b owns the
 // rows b * DT + t + q * G * DT (G = gridDim.x); each thread keeps its partial
 // sums for all vectors in registers (NV >= nv, a compile-time bound) and the
