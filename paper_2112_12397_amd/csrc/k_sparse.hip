@@ -283,36 +283,127 @@ __global__ void k_to_bsr(const int64_t* rowptr, const int32_t* col,
 }
 
 // ------------------------------------------------------------- BSR add
-template <int B>
-__global__ void k_bsr_add(const int64_t* ra, const int32_t* ca,
-                          const double* va, const int64_t* rb,
-                          const int32_t* cb, const double* vb, int64_t nbr,
-                          const int64_t* rc, int64_t* cnt, int32_t* cc,
-                          double* vc) {
+// Count pass of C = A + B: blocks in the union of the two sorted rows.
+__global__ void k_bsr_add_count(const int64_t* ra, const int32_t* ca,
+                                const int64_t* rb, const int32_t* cb,
+                                int64_t nbr, int64_t* cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nbr) return;
   int64_t pa = ra[i], ea = ra[i + 1], pb = rb[i], eb = rb[i + 1];
-  int64_t n = 0, out = rc ? rc[i] : 0;
+  int64_t n = 0;
   while (pa < ea || pb < eb) {
     int32_t x = pa < ea ? ca[pa] : 0x7fffffff;
     int32_t y = pb < eb ? cb[pb] : 0x7fffffff;
     int32_t m = min(x, y);
-    if (cc) {
-      cc[out + n] = m;
-      double* o = vc + (out + n) * B;
-      for (int q = 0; q < B; ++q) o[q] = 0.0;
-      if (x == m) {
-        for (int q = 0; q < B; ++q) o[q] += va[pa * B + q];
-      }
-      if (y == m) {
-        for (int q = 0; q < B; ++q) o[q] += vb[pb * B + q];
-      }
+    if (x == m) ++pa;
+    if (y == m) ++pb;
+    ++n;
+  }
+  cnt[i] = n;
+}
+
+// Fill pass of C = A + B with one wavefront per block row: a row with one
+// source is a contiguous copy; otherwise the two column lists are staged in
+// LDS, lane 0 merges them into (source index, source index) pairs and the
+// wavefront writes the merged blocks.  Rows longer than the LDS lists merge
+// serially on lane 0.  The sums are formed as in k_bsr_add.
+constexpr int ADD_CAP = 256;
+
+template <int B>
+__device__ inline void bsr_add_row_serial(const int32_t* ca, const double* va,
+                                          const int32_t* cb, const double* vb,
+                                          int64_t pa, int64_t ea, int64_t pb,
+                                          int64_t eb, int64_t out, int32_t* cc,
+                                          double* vc) {
+  int64_t n = 0;
+  while (pa < ea || pb < eb) {
+    const int32_t x = pa < ea ? ca[pa] : 0x7fffffff;
+    const int32_t y = pb < eb ? cb[pb] : 0x7fffffff;
+    const int32_t m = min(x, y);
+    cc[out + n] = m;
+    double* o = vc + (out + n) * B;
+    for (int q = 0; q < B; ++q) {
+      double v = 0.0;
+      if (x == m) v += va[pa * B + q];
+      if (y == m) v += vb[pb * B + q];
+      o[q] = v;
     }
     if (x == m) ++pa;
     if (y == m) ++pb;
     ++n;
   }
-  if (cnt) cnt[i] = n;
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_bsr_add_w(
+    const int64_t* __restrict__ ra, const int32_t* __restrict__ ca,
+    const double* __restrict__ va, const int64_t* __restrict__ rb,
+    const int32_t* __restrict__ cb, const double* __restrict__ vb, int64_t nbr,
+    const int64_t* __restrict__ rc, int32_t* __restrict__ cc,
+    double* __restrict__ vc) {
+  __shared__ int32_t sa[4][ADD_CAP], sb[4][ADD_CAP];
+  __shared__ int32_t oa[4][2 * ADD_CAP], ob[4][2 * ADD_CAP];
+  __shared__ int32_t scount[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + w;
+  const bool valid = i < nbr;
+  int64_t pa = 0, ea = 0, pb = 0, eb = 0, out = 0;
+  if (valid) {
+    pa = ra[i];
+    ea = ra[i + 1];
+    pb = rb[i];
+    eb = rb[i + 1];
+    out = rc[i];
+  }
+  const int64_t na = ea - pa, nb = eb - pb;
+  const bool single = valid && (na == 0 || nb == 0);
+  const bool big = valid && !single && (na > ADD_CAP || nb > ADD_CAP);
+  const bool staged = valid && !single && !big;
+  if (single) {
+    const bool fromA = nb == 0;
+    const int64_t p = fromA ? pa : pb, len = fromA ? na : nb;
+    const int32_t* __restrict__ cs = fromA ? ca : cb;
+    const double* __restrict__ vs = fromA ? va : vb;
+    // a one-source sum is 0.0 + value, as in the merge
+    for (int64_t e = lane; e < len; e += 64) cc[out + e] = cs[p + e];
+    for (int64_t e = lane; e < len * B; e += 64) vc[out * B + e] = 0.0 + vs[p * B + e];
+  }
+  if (big && lane == 0) bsr_add_row_serial<B>(ca, va, cb, vb, pa, ea, pb, eb, out, cc, vc);
+  if (staged) {
+    for (int64_t e = lane; e < na; e += 64) sa[w][e] = ca[pa + e];
+    for (int64_t e = lane; e < nb; e += 64) sb[w][e] = cb[pb + e];
+  }
+  __syncthreads();
+  if (staged && lane == 0) {
+    int ka = 0, kb = 0, n = 0;
+    while (ka < na || kb < nb) {
+      const int32_t x = ka < na ? sa[w][ka] : 0x7fffffff;
+      const int32_t y = kb < nb ? sb[w][kb] : 0x7fffffff;
+      const int32_t m = min(x, y);
+      oa[w][n] = x == m ? ka : -1;
+      ob[w][n] = y == m ? kb : -1;
+      if (x == m) ++ka;
+      if (y == m) ++kb;
+      ++n;
+    }
+    scount[w] = n;
+  }
+  __syncthreads();
+  if (staged) {
+    const int n = scount[w];
+    for (int e = lane; e < n; e += 64) {
+      const int ja = oa[w][e], jb = ob[w][e];
+      cc[out + e] = ja >= 0 ? sa[w][ja] : sb[w][jb];
+    }
+    for (int e = lane; e < n * B; e += 64) {
+      const int o = e / B, q = e - o * B;
+      const int ja = oa[w][o], jb = ob[w][o];
+      double v = 0.0;
+      if (ja >= 0) v += va[(pa + ja) * B + q];
+      if (jb >= 0) v += vb[(pb + jb) * B + q];
+      vc[(out + o) * B + q] = v;
+    }
+  }
 }
 
 // ------------------------------------------------------------- SpGEMM
@@ -943,29 +1034,31 @@ void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s) {
   const int B = a.br * a.bc;
   DevBuf<int64_t> cnt(std::max<int64_t>(c.nbr, 1));
   c.rowptr.alloc(c.nbr + 1);
-  auto launch = [&](const int64_t* rc, int64_t* cn, int32_t* cc, double* vc) {
-    if (!c.nbr) return;
-    if (B == 9)
-      k_bsr_add<9><<<grid_for(c.nbr, 128), 128, 0, s>>>(
-          a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
-          rc, cn, cc, vc);
-    else if (B == 18)
-      k_bsr_add<18><<<grid_for(c.nbr, 128), 128, 0, s>>>(
-          a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
-          rc, cn, cc, vc);
-    else if (B == 36)
-      k_bsr_add<36><<<grid_for(c.nbr, 128), 128, 0, s>>>(
-          a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
-          rc, cn, cc, vc);
-    else
-      throw Error(FPC_ERR_ARG, "bsr_add: unsupported block size");
+  if (B != 9 && B != 18 && B != 36)
+    throw Error(FPC_ERR_ARG, "bsr_add: unsupported block size");
+  if (c.nbr) {
+    k_bsr_add_count<<<grid_for(c.nbr, 128), 128, 0, s>>>(
+        a.rowptr.p, a.col.p, b.rowptr.p, b.col.p, c.nbr, cnt.p);
     FPC_LAUNCH_CHECK();
-  };
-  launch(nullptr, cnt.p, nullptr, nullptr);
+  }
   c.nnzb = scan_counts_total(cnt.p, c.rowptr.p, c.nbr, s);
   c.col.alloc(std::max<int64_t>(c.nnzb, 1));
   c.val.alloc(std::max<int64_t>(c.nnzb * B, 1));
-  launch(c.rowptr.p, nullptr, c.col.p, c.val.p);
+  if (!c.nbr) return;
+  const unsigned g = (unsigned)((c.nbr + 3) / 4);
+  if (B == 9)
+    k_bsr_add_w<9><<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, a.val.p, b.rowptr.p,
+                                     b.col.p, b.val.p, c.nbr, c.rowptr.p,
+                                     c.col.p, c.val.p);
+  else if (B == 18)
+    k_bsr_add_w<18><<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, a.val.p, b.rowptr.p,
+                                      b.col.p, b.val.p, c.nbr, c.rowptr.p,
+                                      c.col.p, c.val.p);
+  else
+    k_bsr_add_w<36><<<g, 256, 0, s>>>(a.rowptr.p, a.col.p, a.val.p, b.rowptr.p,
+                                      b.col.p, b.val.p, c.nbr, c.rowptr.p,
+                                      c.col.p, c.val.p);
+  FPC_LAUNCH_CHECK();
 }
 
 void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s) {
