@@ -1291,9 +1291,12 @@ __global__ __launch_bounds__(256) void k_tile_nonzero(const double* P, int64_t w
   __syncthreads();
   const bool skipped = r0 >= skip_at && r0 < skip_at + skip_len;
   if (!skipped) {
+    // the tile's 64 rows are one contiguous range of 64 w values
+    const double* __restrict__ base = P + r0 * w;
+    const int64_t len = 64 * w;
     int nz = 0;
-    for (int64_t q = threadIdx.x; q < 64 * w; q += 256)
-      nz |= P[(r0 + q / w) * w + q % w] != 0.0;
+#pragma unroll 8
+    for (int64_t q = threadIdx.x; q < len; q += 256) nz |= base[q] != 0.0;
     if (nz) any = 1;
   }
   __syncthreads();

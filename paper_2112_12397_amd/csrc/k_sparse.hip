@@ -182,18 +182,32 @@ __device__ inline int64_t block_row_entries(const int64_t* rowptr,
   return rowptr[r1] - rowptr[r0];
 }
 
-// One wavefront per block row with at most TB_CAP scalar entries: entry k
-// (the BR rows concatenated) has block column sbc[k]; it is the first of its
-// block column if no earlier entry has it, and its block's position is the
-// number of first entries with a smaller block column.  Count mode (bcol
-// null) writes the number of blocks, fill mode the blocks.
+// First index in [lo, hi) of the sorted LDS list v whose value is >= b.
+__device__ inline int lds_lower_bound(const int32_t* v, int lo, int hi,
+                                      int32_t b) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (v[mid] < b) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One wavefront per block row with at most TB_CAP scalar entries (the BR
+// rows concatenated, each sorted by column).  Entry k with block column b
+// is the first of b if it starts b in its own row and no earlier row holds
+// b (binary searches in LDS); gp is the exclusive prefix count of first
+// entries.  The block of b sits at the number of distinct block columns
+// below b, which is the sum over rows q of the first entries of q below b:
+// gp at the lower bound of b in row q minus gp at the start of q.  Count
+// mode (bcol null) writes the number of blocks, fill mode the blocks.
 template <int BR, int BC>
 __global__ __launch_bounds__(64) void k_to_bsr_w(
     const int64_t* rowptr, const int32_t* col, const double* val,
     int64_t nrows, const int64_t* browptr, int64_t* bcount, int32_t* bcol,
     double* bval) {
   __shared__ int32_t sbc[TB_CAP];
-  __shared__ uint8_t sfirst[TB_CAP];
+  __shared__ int32_t gp[TB_CAP + 1];
   const int64_t I = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t r0 = I * BR;
@@ -201,39 +215,59 @@ __global__ __launch_bounds__(64) void k_to_bsr_w(
   const int64_t a = rowptr[r0];
   const int m = (int)(rowptr[r0 + nr] - a);
   if (m > TB_CAP) return;  // done by k_to_bsr
+  int rs[BR + 1];
+#pragma unroll
+  for (int q = 0; q <= BR; ++q)
+    rs[q] = (int)(rowptr[r0 + (q < nr ? q : nr)] - a);
   // the BR rows are contiguous in the CSR arrays: entry k is col[a + k]
   for (int k = lane; k < m; k += 64) sbc[k] = col[a + k] / BC;
   __syncthreads();
-  int cnt = 0;
-  for (int k = lane; k < m; k += 64) {
-    const int32_t b = sbc[k];
-    bool first = true;
-    for (int f = 0; f < k; ++f)
-      if (sbc[f] == b) {
-        first = false;
-        break;
-      }
-    sfirst[k] = first;
-    cnt += first;
+  // first flags, then their exclusive prefix over 64-entry chunks
+  int carry = 0;
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int k = k0 + lane;
+    bool first = false;
+    if (k < m) {
+      int r = 0;
+#pragma unroll
+      for (int q = 1; q < BR; ++q)
+        if (q < nr && k >= rs[q]) r = q;
+      const int32_t b = sbc[k];
+      first = k == rs[r] || sbc[k - 1] != b;
+#pragma unroll
+      for (int q = 0; q < BR - 1; ++q)
+        if (q < r && first) {
+          const int p = lds_lower_bound(sbc, rs[q], rs[q + 1], b);
+          first = !(p < rs[q + 1] && sbc[p] == b);
+        }
+    }
+    const uint64_t mask = __ballot(first);
+    if (k < m)
+      gp[k] = carry + __popcll(mask & ((uint64_t(1) << lane) - 1));
+    carry += __popcll(mask);
   }
+  if (lane == 0) gp[m] = carry;
   __syncthreads();
   if (!bcol) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if (lane == 0) bcount[I] = cnt;
+    if (lane == 0) bcount[I] = carry;
     return;
   }
   const int64_t out = browptr[I];
   for (int k = lane; k < m; k += 64) {
     const int32_t b = sbc[k];
-    int rank = 0;
-    for (int f = 0; f < m; ++f) rank += sfirst[f] && sbc[f] < b;
-    if (sfirst[k]) bcol[out + rank] = b;
-    // scalar row of entry k
     int r = 0;
 #pragma unroll
     for (int q = 1; q < BR; ++q)
-      if (q < nr && a + k >= rowptr[r0 + q]) r = q;
+      if (q < nr && k >= rs[q]) r = q;
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < BR; ++q)
+      if (q < nr) {
+        const int p = lds_lower_bound(sbc, rs[q], rs[q + 1], b);
+        rank += gp[p] - gp[rs[q]];
+      }
+    const bool first = gp[k + 1] != gp[k];
+    if (first) bcol[out + rank] = b;
     bval[(out + rank) * (BR * BC) + r * BC + col[a + k] % BC] = val[a + k];
   }
 }
@@ -686,11 +720,14 @@ __device__ inline void pack33(const double* v, int cls, double* p) {
   p[4] = v[i2 * 3 + i2];
 }
 
+// Sliced-ELL fill, one thread per block row, for blocks other than 3x3
+// (those take k_sell_fill_w33): slot k of row r holds its k-th block.
 template <typename T, int B>
 __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
                             const double* val, int64_t nrows,
                             const int64_t* slice_ptr, int32_t* row_len,
                             int32_t* scol, T* sval) {
+  static_assert(B != 9, "3x3 blocks use k_sell_fill_w33");
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int64_t s = r / kSliceH;
@@ -699,46 +736,89 @@ __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
   const int64_t a = rowptr[r];
   const int len = (int)(rowptr[r + 1] - a);
   row_len[r] = len;
-  int32_t cbits = 0;
-  if constexpr (B == 9) {
-    // full blocks first, then the packed ones (each group in column order),
-    // so that the slots of neighbouring rows tend to agree on their class
-    int k = 0;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int e = 0; e < len; ++e) {
-        const double* v = val + (a + e) * 9;
-        const int cls = class33(v);
-        if ((cls == 0) != (pass == 0)) continue;
-        const int64_t grp = base + (int64_t)k * kSliceH;
-        scol[grp + l] = (int32_t)((uint32_t)col[a + e] | ((uint32_t)cls << 30));
-        T* dst = sval + grp * 9 + l;
-        if (cls == 0) {
+  for (int k = 0; k < len; ++k) {
+    const int64_t grp = base + (int64_t)k * kSliceH;
+    scol[grp + l] = col[a + k];
+    T* dst = sval + grp * B + l;
 #pragma unroll
-          for (int q = 0; q < 9; ++q) dst[q * kSliceH] = (T)v[q];
-        } else {
-          double p[5];
-          pack33(v, cls, p);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) dst[q * kSliceH] = (T)p[q];
-        }
-        ++k;
-      }
-    cbits = (int32_t)(1u << 30);  // padding slots: packed zeros
-  } else {
-    for (int k = 0; k < len; ++k) {
-      const int64_t grp = base + (int64_t)k * kSliceH;
-      scol[grp + l] = col[a + k];
-      T* dst = sval + grp * B + l;
-#pragma unroll
-      for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
-    }
+    for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
   }
   // padding slots up to the slice's longest row keep zero values and repeat
   // the row's last column (column 0 for an empty row), so a product may read
   // them unguarded: a padded term adds 0 * x[c] for a c the row already uses
   const int maxlen = (int)((slice_ptr[s + 1] - base) / kSliceH);
-  const int32_t cpad = (len > 0 ? col[a + len - 1] : 0) | cbits;
+  const int32_t cpad = len > 0 ? col[a + len - 1] : 0;
   for (int k = len; k < maxlen; ++k) scol[base + (int64_t)k * kSliceH + l] = cpad;
+}
+
+// Sliced-ELL fill for 3x3 blocks with one wavefront per block row: lane e
+// takes block e of a 64-block chunk, and the slot of a block (full blocks
+// first, then the packed ones, each group in column order) is its rank
+// among the row's blocks of its kind, counted with ballots.  Same layout as
+// k_sell_fill.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sell_fill_w33(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, int64_t nrows,
+    const int64_t* __restrict__ slice_ptr, int32_t* __restrict__ row_len,
+    int32_t* __restrict__ scol, T* __restrict__ sval) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= nrows) return;
+  const int64_t sl = r / kSliceH;
+  const int l = (int)(r % kSliceH);
+  const int64_t base = slice_ptr[sl];
+  const int64_t a = rowptr[r];
+  const int len = (int)(rowptr[r + 1] - a);
+  if (lane == 0) row_len[r] = len;
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  // full blocks of the row (a second pass over the values only for rows
+  // longer than one chunk)
+  int nfull = 0;
+  if (len > 64)
+    for (int e0 = 0; e0 < len; e0 += 64) {
+      const int e = e0 + lane;
+      const bool full = e < len && class33(val + (a + e) * 9) == 0;
+      nfull += __popcll(__ballot(full));
+    }
+  int before_full = 0, before_packed = 0;
+  for (int e0 = 0; e0 < len; e0 += 64) {
+    const int e = e0 + lane;
+    double v[9];
+    int cls = 1;
+    if (e < len) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v[q] = val[(a + e) * 9 + q];
+      cls = class33(v);
+    }
+    const bool full = e < len && cls == 0;
+    const bool packed = e < len && cls != 0;
+    const uint64_t mf = __ballot(full), mp = __ballot(packed);
+    if (len <= 64) nfull = __popcll(mf);
+    if (e < len) {
+      const int k = full ? before_full + __popcll(mf & lt)
+                         : nfull + before_packed + __popcll(mp & lt);
+      const int64_t grp = base + (int64_t)k * kSliceH;
+      scol[grp + l] = (int32_t)((uint32_t)col[a + e] | ((uint32_t)cls << 30));
+      T* dst = sval + grp * 9 + l;
+      if (full) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dst[q * kSliceH] = (T)v[q];
+      } else {
+        double p[5];
+        pack33(v, cls, p);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) dst[q * kSliceH] = (T)p[q];
+      }
+    }
+    before_full += __popcll(mf);
+    before_packed += __popcll(mp);
+  }
+  // padding slots: packed zeros repeating the row's last column
+  const int maxlen = (int)((slice_ptr[sl + 1] - base) / kSliceH);
+  const int32_t cpad = (len > 0 ? col[a + len - 1] : 0) | (int32_t)(1u << 30);
+  for (int k = len + lane; k < maxlen; k += 64)
+    scol[base + (int64_t)k * kSliceH + l] = cpad;
 }
 
 __global__ void k_vrow_count(const int64_t* rowptr, int64_t nrows, int G,
@@ -931,10 +1011,16 @@ void to_sell_impl(const Bsr& a, Sell<T>& out, hipStream_t s) {
   out.val.alloc(std::max<int64_t>(out.nslots * B, 1));
   fill_i32(out.col.p, 0, out.nslots, s);
   FPC_HIP(hipMemsetAsync(out.val.p, 0, out.val.bytes(), s));
-  if (out.nrows)
-    k_sell_fill<T, B><<<grid_for(out.nrows, 256), 256, 0, s>>>(
-        a.rowptr.p, a.col.p, a.val.p, a.nbr, out.slice_ptr.p, out.row_len.p,
-        out.col.p, out.val.p);
+  if (out.nrows) {
+    if constexpr (B == 9)
+      k_sell_fill_w33<T><<<(unsigned)((out.nrows + 3) / 4), 256, 0, s>>>(
+          a.rowptr.p, a.col.p, a.val.p, a.nbr, out.slice_ptr.p, out.row_len.p,
+          out.col.p, out.val.p);
+    else
+      k_sell_fill<T, B><<<grid_for(out.nrows, 256), 256, 0, s>>>(
+          a.rowptr.p, a.col.p, a.val.p, a.nbr, out.slice_ptr.p, out.row_len.p,
+          out.col.p, out.val.p);
+  }
   FPC_LAUNCH_CHECK();
 }
 
