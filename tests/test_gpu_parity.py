@@ -279,6 +279,23 @@ def test_solve_mgs(torch, name):
     assert _rel(x.cpu().numpy(), xo) <= 1e-5
 
 
+def test_solve_long_cycle(torch):
+    """FGMRES(63) to 1e-12 on the long-row case: one restart cycle of about
+    60 steps, so the Gram-Schmidt passes run with up to 60 basis vectors
+    (the widest register buckets and, past 48 vectors, the separate axpy and
+    dot passes); same iteration count as the oracle within 2, same solution."""
+    from paper_2112_12397_amd import solver_from_system
+    s, pc, _ = _get("tiny_wide")
+    sol = solver_from_system(s, restart=63, amg={"max_coarse": 90})
+    x, info = sol.solve(torch.tensor(s.b, device="cuda"), rtol=1e-12)
+    xo, io = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-12, restart=63,
+                           ortho="cgs2")
+    assert io.iterations > 56 and info["restarts"] == io.restarts
+    assert info["converged"] == 1 and info["true_rel_residual"] <= 1e-12
+    assert abs(info["iterations"] - io.iterations) <= 2
+    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+
+
 def test_fp32_preconditioner(torch):
     s, pc, sol64 = _get("c1")
     _, _, sol32 = _get("c1", precision="fp32")
