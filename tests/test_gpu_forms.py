@@ -47,6 +47,32 @@ def test_batch_matches_single(torch, c1, k, precision):
         assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-5
 
 
+def test_batch_long_cycle(torch):
+    """Batched FGMRES(63) to 1e-10 on the long-row system with random
+    right-hand sides: the first cycle runs all 63 steps, so the batched
+    Gram-Schmidt passes go up to 63 basis vectors per column (past 48 the
+    axpy and dot passes run separately); every column against its single
+    solve.  (These right-hand sides stall near 5e-12 in the oracle too.)"""
+    from paper_2112_12397_amd import solver_from_system
+    from systems_extra import wide_system
+    s = wide_system()
+    sol = solver_from_system(s, restart=63, amg={"max_coarse": 90})
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((s.N, 4)) * np.array([1e-2, 1.0, 1e2, 3.0])
+    Bt = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
+    X, infos, status = sol.solve_batch(Bt, rtol=1e-10)
+    assert status == "FPC_OK"
+    J = s.jacobian()
+    Xn = X.cpu().numpy()
+    for c in range(4):
+        x1, i1 = sol.solve(Bt[c].contiguous(), rtol=1e-10)
+        r = np.linalg.norm(B[:, c] - J @ Xn[c]) / np.linalg.norm(B[:, c])
+        assert infos[c]["converged"] == 1 and r <= 1e-10, (c, r, infos[c])
+        assert i1["iterations"] >= 63           # a full first cycle
+        assert abs(infos[c]["iterations"] - i1["iterations"]) <= 2
+        assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-7
+
+
 def test_batch_zero_column_and_mask(torch, c1):
     from paper_2112_12397_amd import solver_from_system
     s = c1
