@@ -104,7 +104,7 @@ typedef struct {
 typedef struct {
   int mode;                /* FPC_TUP (default), FPC_TPU or FPC_TUP_STAR    */
   int precision;           /* FPC_FP64 or FPC_FP32_PREC (FP32 hierarchy)    */
-  int restart;             /* FGMRES restart length (50)                    */
+  int restart;             /* FGMRES restart length (50; 1 to 63)           */
   int maxit;               /* total iteration cap (1000)                    */
   double rtol;             /* default relative tolerance (1e-8)             */
   int max_batch;           /* right-hand sides per fpc_solve_batch (32)     */
