@@ -526,19 +526,23 @@ __global__ void k_ptent_fill(const int32_t* agg, const int64_t* rp, int64_t n,
   for (int q = 0; q < B; ++q) val[e * B + q] = ptent[i * B + q];
 }
 
-__global__ void k_neg_row_scale(const int64_t* rp, double* val, int64_t nbr,
-                                int br, int bc, const double* dinv,
-                                double omega) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// val <- -(omega * dinv[row scalar]) * val, one wavefront per block row: a
+// block row's values are contiguous, so the lanes stride them directly.
+__global__ __launch_bounds__(256) void k_neg_row_scale(const int64_t* rp,
+                                                       double* val, int64_t nbr,
+                                                       int br, int bc,
+                                                       const double* dinv,
+                                                       double omega) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= nbr) return;
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-    for (int r = 0; r < br; ++r) {
-      const double t = omega * dinv[i * br + r];
-      for (int c = 0; c < bc; ++c) {
-        double& v = val[e * br * bc + r * bc + c];
-        v = -(t * v);
-      }
-    }
+  const int B = br * bc;
+  const int64_t v0 = rp[i] * B, v1 = rp[i + 1] * B;
+  for (int64_t v = v0 + lane; v < v1; v += 64) {
+    const int r = (int)((v - v0) % B) / bc;
+    const double t = omega * dinv[i * br + r];
+    val[v] = -(t * val[v]);
+  }
 }
 
 __global__ void k_dummy_diag(const int64_t* rp, const int32_t* col,
@@ -1248,7 +1252,7 @@ void ptent_bsr(const int32_t* agg, int64_t n_nodes, int64_t n_agg, int bs,
 void smooth_prolongator(Bsr& AP, const double* dinv, double omega,
                         hipStream_t s) {
   if (AP.nbr == 0) return;
-  k_neg_row_scale<<<grid_for(AP.nbr, 128), 128, 0, s>>>(
+  k_neg_row_scale<<<(unsigned)((AP.nbr + 3) / 4), 256, 0, s>>>(
       AP.rowptr.p, AP.val.p, AP.nbr, AP.br, AP.bc, dinv, omega);
   FPC_LAUNCH_CHECK();
 }

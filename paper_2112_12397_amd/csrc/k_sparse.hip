@@ -159,17 +159,18 @@ __global__ void k_tr_sort_long(const int64_t* rowptrT, int64_t nrowsT,
   }
 }
 
+// One thread per value of the transposed blocks (consecutive threads write
+// consecutive values; a block's values are read from one source block).
 template <int BR, int BC>
 __global__ void k_tr_gather(const double* val, const int64_t* src,
                             int64_t nnzb, double* valT) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnzb) return;
-  const double* a = val + src[p] * (BR * BC);
-  double* t = valT + p * (BR * BC);
-#pragma unroll
-  for (int r = 0; r < BR; ++r)
-#pragma unroll
-    for (int c = 0; c < BC; ++c) t[c * BR + r] = a[r * BC + c];
+  constexpr int B = BR * BC;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnzb * B) return;
+  const int64_t p = e / B;
+  const int q = (int)(e - p * B);
+  const int c = q / BR, r = q - c * BR;   // valT block is BC x BR
+  valT[e] = val[src[p] * B + r * BC + c];
 }
 
 // ------------------------------------------------------------- CSR -> BSR
@@ -899,7 +900,7 @@ void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s) {
   }
   FPC_LAUNCH_CHECK();
   if (t.nnzb)
-    k_tr_gather<BR, BC><<<grid_for(t.nnzb, 256), 256, 0, s>>>(
+    k_tr_gather<BR, BC><<<grid_for(t.nnzb * BR * BC, 256), 256, 0, s>>>(
         a.val.p, src.p, t.nnzb, t.val.p);
   FPC_LAUNCH_CHECK();
   FPC_HIP(hipStreamSynchronize(s));
