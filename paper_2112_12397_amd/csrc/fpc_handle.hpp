@@ -157,6 +157,7 @@ struct PSolve {
   DevBuf<double> packed;
   DevBuf<float> packed32;
   DevBuf<double> part;        // 128 partial sums per tile
+  DevBuf<double> xperm;       // the input in component (members) order
 };
 
 // Per right-hand-side block of Krylov work space.

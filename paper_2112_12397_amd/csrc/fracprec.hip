@@ -437,6 +437,7 @@ void build_psolve(fpc_handle* h) {
     if (f32) ps.packed32.alloc(ps.n_tiles * 4096);
     else ps.packed.alloc(ps.n_tiles * 4096);
     ps.part.alloc(ps.n_tiles * 128);
+    ps.xperm.alloc(std::max<int64_t>(n, 1));
     for (int64_t c = 0; c < ps.n_comp; ++c)
       pack_sym_tiles(ps.dense.p + ps.dense_off_h[c], ps.comp_pad[c], ntc[c],
                      f32 ? nullptr : ps.packed.p + ps.tile_base_h[c] * 4096,

@@ -688,25 +688,38 @@ __global__ void k_tface(const int64_t* __restrict__ rp,
 // (for block row I) and, off the diagonal, its transposed product
 // A_IJ^T x_I (for block row J).  The 128 partial sums per tile are combined
 // per block row by k_psym_reduce in a fixed order.
+// xperm[e] = in[members[e]]: the pressure input in component order, so that
+// a tile reads its two x segments with one dependent load each.
+__global__ void k_psym_gather(const int32_t* __restrict__ members,
+                              const double* __restrict__ in, int64_t n,
+                              double* __restrict__ xperm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) xperm[e] = in[members[e]];
+}
+
 template <typename M>
 __global__ __launch_bounds__(256) void k_psym_tile(
     const M* __restrict__ packed, const int32_t* __restrict__ tile_info,
-    const int64_t* __restrict__ comp_off, const int32_t* __restrict__ members,
-    const double* __restrict__ in, double* __restrict__ part) {
+    const int64_t* __restrict__ comp_off, const double* __restrict__ xperm,
+    double* __restrict__ part) {
   __shared__ double xs[2][64];
   __shared__ double cs[4][64];
   const int64_t t = blockIdx.x;
   const int c = tile_info[3 * t], I = tile_info[3 * t + 1], J = tile_info[3 * t + 2];
   const int64_t o = comp_off[c], n = comp_off[c + 1] - o;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  // the x segments first: waiting for them then leaves the tile loads,
+  // issued after them, in flight
+  double xv = 0.0;
+  if (tid < 128) {
+    const int64_t idx = (int64_t)(tid < 64 ? J : I) * 64 + lane;
+    if (idx < n) xv = xperm[o + idx];
+  }
   const M* __restrict__ tp = packed + t * 4096 + (int64_t)(w * 16) * 64 + lane;
   M a[16];
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) a[rr] = ld_stream(tp + rr * 64);
-  if (tid < 128) {
-    const int64_t idx = (int64_t)(tid < 64 ? J : I) * 64 + lane;
-    xs[tid >> 6][lane] = idx < n ? in[members[o + idx]] : 0.0;
-  }
+  if (tid < 128) xs[tid >> 6][lane] = xv;
   __syncthreads();
   const double xj = xs[0][lane];
   double v[16];
@@ -1250,12 +1263,14 @@ void psolve_apply(const PSolve& ps, const double* in, double* out,
   // the stored inverse is exactly symmetric: the transposed solve is the same
   (void)trans;
   if (n_p == 0) return;
+  k_psym_gather<<<grid_for(n_p, 256), 256, 0, s>>>(ps.members.p, in, n_p,
+                                                   ps.xperm.p);
   if (ps.packed32.p)
     k_psym_tile<float><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
-        ps.packed32.p, ps.tile_info.p, ps.comp_off.p, ps.members.p, in, ps.part.p);
+        ps.packed32.p, ps.tile_info.p, ps.comp_off.p, ps.xperm.p, ps.part.p);
   else
     k_psym_tile<double><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
-        ps.packed.p, ps.tile_info.p, ps.comp_off.p, ps.members.p, in, ps.part.p);
+        ps.packed.p, ps.tile_info.p, ps.comp_off.p, ps.xperm.p, ps.part.p);
   FPC_LAUNCH_CHECK();
   k_psym_reduce<<<(unsigned)ps.n_rowblk, 256, 0, s>>>(
       ps.rowblk.p, ps.tile_base.p, ps.n_tiles_c.p, ps.comp_off.p, ps.members.p,
