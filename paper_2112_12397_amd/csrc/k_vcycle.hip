@@ -657,29 +657,34 @@ __global__ void k_from_level(const T* __restrict__ xo, int nv, int64_t n,
   vu[i] = diff ? (double)xo[i * nv] - (double)xo[i * nv + 1] : (double)xo[i * nv];
 }
 
-// v_t = -t_t + H~^{-1} (C v_u) face by face (Alg 3.4 steps 9-10)
-__global__ void k_tface(const int64_t* __restrict__ rp,
-                        const int32_t* __restrict__ col,
-                        const double* __restrict__ val,
-                        const double* __restrict__ vu,
-                        const double* __restrict__ t_t,
-                        const double* __restrict__ hinv,
-                        double* __restrict__ v_t, int64_t n_p, int trans) {
-  int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (K >= n_p) return;
-  double s[3];
-  for (int r = 0; r < 3; ++r) {
-    double a = 0.0;
+// v_t = -t_t + H~^{-1} (C v_u) face by face (Alg 3.4 steps 9-10): thread
+// (face K, row r) forms s_r = (C v_u)[3K + r]; the three s of a face meet in
+// LDS and each thread writes its row of v_t.  A block holds 64 faces.
+__global__ __launch_bounds__(192) void k_tface(const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ vu,
+                                               const double* __restrict__ t_t,
+                                               const double* __restrict__ hinv,
+                                               double* __restrict__ v_t,
+                                               int64_t n_p, int trans) {
+  __shared__ double sh[192];
+  const int64_t K = (int64_t)blockIdx.x * 64 + threadIdx.x / 3;
+  const int r = threadIdx.x % 3;
+  const bool act = K < n_p;
+  double a = 0.0;
+  if (act) {
     const int64_t row = 3 * K + r;
     for (int64_t e = rp[row]; e < rp[row + 1]; ++e) a += val[e] * vu[col[e]];
-    s[r] = a;
   }
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  if (!act) return;
+  const double* s3 = sh + (threadIdx.x - r);
   const double* h = hinv + K * 9;
-  for (int r = 0; r < 3; ++r) {
-    double hv = trans ? h[0 * 3 + r] * s[0] + h[1 * 3 + r] * s[1] + h[2 * 3 + r] * s[2]
-                      : h[r * 3 + 0] * s[0] + h[r * 3 + 1] * s[1] + h[r * 3 + 2] * s[2];
-    v_t[3 * K + r] = -t_t[3 * K + r] + hv;
-  }
+  const double hv = trans ? h[0 * 3 + r] * s3[0] + h[1 * 3 + r] * s3[1] + h[2 * 3 + r] * s3[2]
+                          : h[r * 3 + 0] * s3[0] + h[r * 3 + 1] * s3[1] + h[r * 3 + 2] * s3[2];
+  v_t[3 * K + r] = -t_t[3 * K + r] + hv;
 }
 
 // Exact pressure-block solve with the symmetric dense inverse of every
@@ -773,14 +778,16 @@ __global__ __launch_bounds__(256) void k_psym_tile(
 }
 
 // Block row K of component c: the row parts of tiles (K, J), J <= K, then the
-// transposed parts of tiles (I, K), I > K; wavefront w takes every fourth
-// term and the four sums are added in a fixed order.
-__global__ __launch_bounds__(256) void k_psym_reduce(
+// transposed parts of tiles (I, K), I > K; wavefront w of the 16 takes every
+// 16th term and the 16 sums are added in a fixed order.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void k_psym_reduce(
     const int32_t* __restrict__ rowblk, const int64_t* __restrict__ tile_base,
     const int32_t* __restrict__ n_tiles_c, const int64_t* __restrict__ comp_off,
     const int32_t* __restrict__ members, const double* __restrict__ part,
     double* __restrict__ out) {
-  __shared__ double sh[4][64];
+  __shared__ double sh[kRedWaves][64];
   const int64_t rb = blockIdx.x;
   const int c = rowblk[2 * rb], K = rowblk[2 * rb + 1];
   const int64_t base = tile_base[c];
@@ -788,7 +795,7 @@ __global__ __launch_bounds__(256) void k_psym_reduce(
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double acc = 0.0;
 #pragma unroll 4
-  for (int e = w; e < nt; e += 4) {
+  for (int e = w; e < nt; e += kRedWaves) {
     const int64_t off =
         e <= K ? (base + (int64_t)K * (K + 1) / 2 + e) * 128 + lane
                : (base + (int64_t)e * (e + 1) / 2 + K) * 128 + 64 + lane;
@@ -799,8 +806,10 @@ __global__ __launch_bounds__(256) void k_psym_reduce(
   if (w == 0) {
     const int64_t o = comp_off[c], n = comp_off[c + 1] - o;
     const int64_t idx = (int64_t)K * 64 + lane;
-    if (idx < n)
-      out[members[o + idx]] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRedWaves; ++q) t += sh[q][lane];
+    if (idx < n) out[members[o + idx]] = t;
   }
 }
 
@@ -1253,8 +1262,9 @@ void tface(const Csr& C, const double* vu, const double* t_t,
            const double* hinv, double* v_t, int64_t n_p, int trans,
            hipStream_t s) {
   if (n_p == 0) return;
-  k_tface<<<grid_for(n_p, 128), 128, 0, s>>>(C.rowptr.p, C.col.p, C.val.p, vu,
-                                             t_t, hinv, v_t, n_p, trans);
+  k_tface<<<(unsigned)((n_p + 63) / 64), 192, 0, s>>>(C.rowptr.p, C.col.p,
+                                                     C.val.p, vu, t_t, hinv,
+                                                     v_t, n_p, trans);
   FPC_LAUNCH_CHECK();
 }
 
@@ -1272,7 +1282,7 @@ void psolve_apply(const PSolve& ps, const double* in, double* out,
     k_psym_tile<double><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
         ps.packed.p, ps.tile_info.p, ps.comp_off.p, ps.xperm.p, ps.part.p);
   FPC_LAUNCH_CHECK();
-  k_psym_reduce<<<(unsigned)ps.n_rowblk, 256, 0, s>>>(
+  k_psym_reduce<<<(unsigned)ps.n_rowblk, 64 * kRedWaves, 0, s>>>(
       ps.rowblk.p, ps.tile_base.p, ps.n_tiles_c.p, ps.comp_off.p, ps.members.p,
       ps.part.p, out);
   FPC_LAUNCH_CHECK();
