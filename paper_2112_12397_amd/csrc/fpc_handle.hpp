@@ -170,7 +170,9 @@ struct Krylov {
   DevBuf<double> h1, h2, scal, partials;
   DevBuf<int> ctrl;
   double* host = nullptr;     // pinned mirror for scalars read each step
+  hipEvent_t ev = nullptr;    // marks the arrival of those scalars
   ~Krylov() {
+    if (ev) (void)hipEventDestroy(ev);
     if (host) (void)hipHostFree(host);
   }
 };

@@ -881,6 +881,7 @@ void ensure_krylov(fpc_handle* h, Krylov& K, int k) {
   K.partials.alloc(mdot_partials(h->N, m + 1));
   K.ctrl.alloc(4 * k);
   if (!K.host) FPC_HIP(hipHostMalloc((void**)&K.host, 64 * sizeof(double)));
+  if (!K.ev) FPC_HIP(hipEventCreateWithFlags(&K.ev, hipEventDisableTiming));
 }
 
 double dev_norm(fpc_handle* h, Krylov& K, const double* x, double* slot) {
@@ -975,17 +976,21 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
       }
       gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
                  nrm_before, j, sc, K.ctrl.p, s);
+      // the convergence scalars go to the host ahead of the next vector and
+      // its lead stage, and the host waits for them only: the stage-2 work
+      // of step j + 1 is queued while the device still runs the lead stage
+      FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+      FPC_HIP(hipEventRecord(K.ev, s));
       scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
       if (lead && j + 1 < m) {
         apply(h, trans, K.V.p + (int64_t)(j + 1) * N,
               K.Z.p + (int64_t)(j + 1) * N, 1);
         lead_done = true;
       }
-      FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-      FPC_HIP(hipStreamSynchronize(s));
+      FPC_HIP(hipEventSynchronize(K.ev));
       ++its;
       k = j + 1;
       est = K.host[1] / bnorm;
