@@ -311,7 +311,7 @@ def main():
                     help="skip the batch / precision / adjoint / t-p-u runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; multi-GPU runs "
+        print("bench.py: the library runs on exactly one GPU; multi-GPU runs "
               "are not supported (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

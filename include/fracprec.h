@@ -53,7 +53,7 @@ typedef enum {
   FPC_ERR_HIP = -7,            /* HIP runtime error                          */
   FPC_ERR_OOM = -8,            /* device allocation failed                   */
   FPC_ERR_STATE = -9,          /* call before fpc_setup                      */
-  FPC_ERR_UNSUPPORTED = -10    /* case outside this build (see message)      */
+  FPC_ERR_UNSUPPORTED = -10    /* case the library does not handle (message) */
 } fpc_status;
 
 enum { FPC_HOST = 0, FPC_DEVICE = 1 };
