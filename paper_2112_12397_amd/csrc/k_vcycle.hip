@@ -376,37 +376,49 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
 }
 
 // Many columns (interleaved right-hand sides): one thread per (block row,
-// column); a wavefront covers 64/NV consecutive block rows of one slice, so
-// the columns of one x row are read as one contiguous segment and every
-// matrix block is broadcast to the NV lanes of its row.
+// CPL consecutive columns); a wavefront covers 64 CPL / NV consecutive block
+// rows of one slice, so the columns of one x row are read as one contiguous
+// segment and every matrix block is broadcast to the NV / CPL lanes of its
+// row.  For 3x3 blocks from 16 columns on a lane takes two columns, which
+// halves the matrix loads per column (larger blocks keep one column per
+// lane: their registers would not hold two).
+template <int BR, int BC, int NV>
+constexpr int sell_cols_cpl() { return (NV >= 16 && BR * BC <= 9) ? 2 : 1; }
+
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
                                                    Epi epi) {
+  constexpr int CPL = sell_cols_cpl<BR, BC, NV>();
+  constexpr int LPR = NV / CPL;  // lanes per block row
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t gw = blk * 4 + wave;
-  const int64_t slice = gw / NV;
+  const int64_t slice = gw / LPR;
   if (slice >= A.nslices) return;
-  const int sub = (int)(gw % NV);
-  const int rloc = sub * (64 / NV) + lane / NV;
-  const int v = lane % NV;
+  const int sub = (int)(gw % LPR);
+  const int rloc = sub * (64 / LPR) + lane / LPR;
+  const int v0 = (lane % LPR) * CPL;
   const int64_t row = slice * kSliceH + rloc;
   if (row >= A.nrows) return;
   const int len = A.row_len[row];
   const int64_t base = A.slice_ptr[slice];
   const int32_t* __restrict__ cp = A.col + base + rloc;
   const T* __restrict__ vp = A.val + base * (BR * BC) + rloc;
-  T acc[BR];
+  T acc[CPL][BR];
 #pragma unroll
-  for (int i = 0; i < BR; ++i) acc[i] = T(0);
+  for (int u = 0; u < CPL; ++u)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[u][i] = T(0);
 #pragma unroll 2
   for (int k = 0; k < len; ++k) {
     const int32_t raw = cp[(int64_t)k * kSliceH];
     const int64_t c = (BR == 3 && BC == 3) ? slot_col(raw) : raw;
     const T* __restrict__ vb = vp + (int64_t)k * kSliceH * (BR * BC);
-    T xv[BC];
+    T xv[BC][CPL];
 #pragma unroll
-    for (int j = 0; j < BC; ++j) xv[j] = ld(c * BC + j, v);
+    for (int j = 0; j < BC; ++j)
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) xv[j][u] = ld(c * BC + j, v0 + u);
     T m[BR * BC];
     if constexpr (BR == 3 && BC == 3) {
       load33(vb, slot_class(raw), m);
@@ -415,11 +427,14 @@ __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
       for (int q = 0; q < BR * BC; ++q) m[q] = vb[q * kSliceH];
     }
 #pragma unroll
-    for (int i = 0; i < BR; ++i)
+    for (int u = 0; u < CPL; ++u)
 #pragma unroll
-      for (int j = 0; j < BC; ++j) acc[i] += m[i * BC + j] * xv[j];
+      for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int j = 0; j < BC; ++j) acc[u][i] += m[i * BC + j] * xv[j][u];
   }
-  epi_col<T, BR, NV>(epi, row, v, acc);
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) epi_col<T, BR, NV>(epi, row, v0 + u, acc[u]);
 }
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
@@ -430,7 +445,7 @@ void launch_sell(const Sell<T>& A, Load ld, Epi epi, hipStream_t s) {
         (unsigned)((A.nslices + 4 / kSliceSplit - 1) / (4 / kSliceSplit));
     k_sell_rows<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   } else {
-    const int64_t waves = A.nslices * NV;
+    const int64_t waves = A.nslices * (NV / sell_cols_cpl<BR, BC, NV>());
     const unsigned grid = (unsigned)((waves + 3) / 4);
     k_sell_cols<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   }
