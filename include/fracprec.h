@@ -107,7 +107,8 @@ typedef struct {
   int restart;             /* FGMRES restart length (50; 1 to 63)           */
   int maxit;               /* total iteration cap (1000)                    */
   double rtol;             /* default relative tolerance (1e-8)             */
-  int max_batch;           /* right-hand sides per fpc_solve_batch (32)     */
+  int max_batch;           /* right-hand sides per fpc_solve_batch (32;   */
+                           /* 1 to 32, larger values are rejected)          */
   int graphs;              /* 1: the batched V-cycle is captured once into  */
                            /* a HIP graph and replayed (default); 0: eager  */
   int ortho;               /* FPC_CGS2 (default) or FPC_MGS; batched solves */
@@ -167,10 +168,14 @@ fpc_status fpc_create(fpc_handle** h, const fpc_options* opt, void* stream);
  * S~2 = T - FS(Q2, S1, Q1) (eq. FS_algebraic; zero when Q2 is empty) with
  * its exact inverse, and the smoothed-aggregation hierarchy of S1 with the
  * Galerkin products P^T A P.  Every array of *J is copied; the caller may
- * free them afterwards.  Errors: FPC_ERR_DIM / _PATTERN / _NAN on bad input,
- * FPC_ERR_SINGULAR_BLOCK for a singular face block of H, FPC_ERR_NOT_SPD for
- * a nonpositive pivot of S~2, FPC_ERR_UNSUPPORTED for a non-empty Q2 (open
- * faces), FPC_ERR_OOM.  A second call replaces the previous setup. */
+ * free them afterwards.  Open faces (a non-empty Q2, eq. Q2def) are handled
+ * in every mode.  Errors: FPC_ERR_DIM / _PATTERN / _NAN on bad input,
+ * FPC_ERR_SINGULAR_BLOCK for a singular face block of H, a singular pivot of
+ * the pressure block or of the coarsest AMG level, FPC_ERR_NOT_SPD for a
+ * nonpositive pivot of an SPD pressure block (Q2 empty, or t-p-u),
+ * FPC_ERR_UNSUPPORTED when a face's fixed-stress index set K^(k) of
+ * eq. Ak exceeds 64 scalar dofs, FPC_ERR_OOM.  A second call replaces the
+ * previous setup. */
 fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J);
 
 /* Numeric re-setup for the next Newton or active-set iteration (Sec. 2.2:
@@ -207,7 +212,7 @@ fpc_status fpc_vcycle(fpc_handle* h, const double* b, double* x);
 
 /* The pressure-block solve of the preconditioner by itself (device vectors
  * of length n_p): v = S~2^{-1} w (Alg 3.4 step 5; S~2 = T - FS(Q2, S1, Q1),
- * eq. S2approx, = T when Q2 = 0) in t-u-p and M2*, v = T^{-1} w (Alg 3.2
+ * eq. app_Schur2_2, = T when Q2 = 0) in t-u-p and M2*, v = T^{-1} w (Alg 3.2
  * steps 1 and 7) in t-p-u; trans = 1 applies the transpose (the stored
  * inverse is symmetric, so the result is the same).  Runs on the handle's
  * stream in the precision of the hierarchy's pressure inverse. */
@@ -242,7 +247,12 @@ fpc_status fpc_solve_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
 /* dL/d(log Upsilon_K) = -lam_p^T (dT/d log Upsilon_K) p for a loss L(x)
  * whose adjoint pressure is lam_p (from fpc_solve_T): TPFA harmonic
  * averages and Dirichlet terms of eq. FV_inner_product.  lam_p, p, grad:
- * device, length n_p. */
+ * device, length n_p.  Every face pair is checked before use: an index
+ * outside [0, n_p) or a pair (K, K) gives FPC_ERR_PATTERN and no output;
+ * more than (2^31 - 2 n_p - 2) / 2 pairs give FPC_ERR_ARG.  Requires Q2 = 0
+ * (FPC_ERR_UNSUPPORTED otherwise).  Each face sums its terms in ascending
+ * pair order (deterministic).  Allocates a work area of 2 n_p + 1 + 2 n_pairs
+ * int32 for the call. */
 fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
                               const double* lam_p, const double* p,
                               double* grad);

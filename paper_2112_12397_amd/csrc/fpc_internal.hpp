@@ -279,5 +279,22 @@ void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s);
 
 // ---------------------------------------------------------------- k_krylov
 constexpr int kMaxKrylov = 64;
+// right-hand sides of one batched solve (the widest interleaved cycle)
+constexpr int kMaxBatch = 32;
+
+// ---------------------------------------------------------------- k_grad
+// int32 words of work area the transmissibility gradient needs.
+int64_t grad_scratch_words(int64_t n_p, int64_t n_pairs);
+// Counts of every face's pairs into work[0, n_p); flags[FLAG_PATTERN] for a
+// pair with an index outside [0, n_p) or K == L (skipped).
+void grad_validate(int64_t n_p, int64_t n_pairs, const int32_t* pair_k,
+                   const int32_t* pair_l, int32_t* work, int* flags,
+                   hipStream_t s);
+// After grad_validate (and a clean flag check): offsets, pair lists and the
+// gradient of every face.
+void grad_finish(int64_t n_p, int64_t n_pairs, const int32_t* pair_k,
+                 const int32_t* pair_l, const int32_t* ndir,
+                 const double* upsilon, const double* lam_p, const double* p,
+                 double* grad, int32_t* work, hipStream_t s);
 
 }  // namespace fpc

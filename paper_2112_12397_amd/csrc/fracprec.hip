@@ -194,40 +194,6 @@ __global__ void k_cast_dinv(const double* a, float* b, int64_t n) {
   if (i < n) b[i] = (float)a[i];
 }
 
-// pairs -> incidence rows (pair e has entries K (side 0) and L (side 1))
-__global__ void k_pair_rows(const int32_t* pk, const int32_t* pl, int64_t m,
-                            int64_t* rp, int32_t* col, double* val) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e > m) return;
-  rp[e] = 2 * e;
-  if (e == m) return;
-  int32_t a = pk[e], b = pl[e];
-  col[2 * e] = min(a, b);
-  col[2 * e + 1] = max(a, b);
-  val[2 * e] = (double)e;
-  val[2 * e + 1] = (double)e;
-}
-
-__global__ void k_grad(const int64_t* rp, const int32_t* pair,
-                       const int32_t* pk, const int32_t* pl,
-                       const int32_t* ndir, const double* ups,
-                       const double* lam, const double* p, double* grad,
-                       int64_t n_p) {
-  int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (K >= n_p) return;
-  double g = 0.0;
-  for (int64_t q = rp[K]; q < rp[K + 1]; ++q) {
-    const int32_t e = pair[q];
-    const int32_t L = (pk[e] == K) ? pl[e] : pk[e];
-    const double uK = ups[K], uL = ups[L];
-    const double s = uK + uL;
-    const double dK = 2.0 * uK * uL * uL / (s * s);
-    g -= dK * (lam[K] - lam[L]) * (p[K] - p[L]);
-  }
-  g -= (double)ndir[K] * ups[K] * lam[K] * p[K];
-  grad[K] = g;
-}
-
 // ------------------------------------------------------------- helpers
 void check_flags(fpc_handle* h, const char* where) {
   int f[FLAG_COUNT];
@@ -1124,7 +1090,9 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
   if (h->has_q2)
     throw Error(FPC_ERR_UNSUPPORTED,
                 "batched solve needs Q2 = 0 (its two AMG calls share one cycle)");
-  const int KB = k <= 8 ? 8 : 32;
+  if (k < 1 || k > kMaxBatch)
+    throw Error(FPC_ERR_ARG, "batched solve: 1 to 32 right-hand sides");
+  const int KB = k <= 8 ? 8 : kMaxBatch;
   ensure_batch_ops(h);
   BatchWork& w = batch_work(h, KB);
   const int m = h->opt.restart;
@@ -1406,7 +1374,7 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
       (o.precision != FPC_FP64 && o.precision != FPC_FP32_PREC) ||
       o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
-      o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 ||
+      o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 || o.max_batch > kMaxBatch ||
       (o.graphs != 0 && o.graphs != 1) ||
       (o.ortho != FPC_CGS2 && o.ortho != FPC_MGS)) {
     delete h;
@@ -1569,33 +1537,25 @@ fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
                               const double* lam_p, const double* p,
                               double* grad) {
   FPC_REQUIRE_READY(h);
-  if (!g || !lam_p || !p || !grad || g->n_p != h->n_p || g->n_pairs < 0)
+  if (!g || !lam_p || !p || !grad || g->n_p != h->n_p || g->n_pairs < 0 ||
+      (g->n_pairs > 0 && (!g->pair_k || !g->pair_l)) ||
+      (g->n_p > 0 && (!g->ndir || !g->upsilon)))
     return FPC_ERR_ARG;
   return guard(h, [&] {
     if (h->has_q2)
       throw Error(FPC_ERR_UNSUPPORTED,
                   "transmissibility gradient assumes Q2 = 0 (Q2 depends on "
                   "the transmissibility on open faces)");
+    if (g->n_pairs > (INT32_MAX - 2 * g->n_p - 1) / 2)
+      throw Error(FPC_ERR_ARG, "too many face pairs for int32 pair lists");
     hipStream_t s = h->stream;
     const int64_t m = g->n_pairs, n = g->n_p;
-    Csr inc;
-    inc.nrows = m;
-    inc.ncols = n;
-    inc.nnz = 2 * m;
-    inc.rowptr.alloc(m + 1);
-    inc.col.alloc(std::max<int64_t>(2 * m, 1));
-    inc.val.alloc(std::max<int64_t>(2 * m, 1));
-    k_pair_rows<<<grid_for(m + 1, 256), 256, 0, s>>>(g->pair_k, g->pair_l, m,
-                                                     inc.rowptr.p, inc.col.p,
-                                                     inc.val.p);
-    FPC_LAUNCH_CHECK();
-    Csr incT;
-    csr_transpose(inc, incT, s);
-    // incT rows are faces; columns are pair ids (sorted)
-    k_grad<<<grid_for(n, 256), 256, 0, s>>>(incT.rowptr.p, incT.col.p,
-                                            g->pair_k, g->pair_l, g->ndir,
-                                            g->upsilon, lam_p, p, grad, n);
-    FPC_LAUNCH_CHECK();
+    DevBuf<int32_t> work(grad_scratch_words(n, m));
+    fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+    grad_validate(n, m, g->pair_k, g->pair_l, work.p, h->flags.p, s);
+    check_flags(h, "face pairs");
+    grad_finish(n, m, g->pair_k, g->pair_l, g->ndir, g->upsilon, lam_p, p,
+                grad, work.p, s);
     FPC_HIP(hipStreamSynchronize(s));
   });
 }

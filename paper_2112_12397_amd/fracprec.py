@@ -366,7 +366,7 @@ class Solver:
             float(rtol), infos), "solve_batch")
         return X, [i.as_dict() for i in infos], STATUS[st]
 
-    def grad_log_trans(self, pairs, ndir, upsilon, lam_p, p):
+    def grad_log_trans(self, pairs, ndir, upsilon, lam_p, p, out=None):
         """dL/d log Upsilon from the adjoint pressure (device tensors)."""
         t = self.torch
         pk = pairs[:, 0].to(device=self.device, dtype=t.int32).contiguous()
@@ -375,7 +375,7 @@ class Solver:
         up = upsilon.to(device=self.device, dtype=t.float64).contiguous()
         g = FpcFlowGraph(self.n_p, pk.numel(), pk.data_ptr(), pl.data_ptr(),
                          nd.data_ptr(), up.data_ptr())
-        out = self._vec(self.n_p)
+        out = self._vec(self.n_p) if out is None else out
         self._check(self.lib.fpc_grad_log_trans(
             self.h, C.byref(g), self._ptr(lam_p.contiguous()),
             self._ptr(p.contiguous()), self._ptr(out)), "grad_log_trans")

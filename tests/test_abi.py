@@ -48,6 +48,10 @@ def test_default_options_and_status_strings():
     h = ctypes.c_void_p()
     bad = fracprec.default_options(restart=0)
     assert lib.fpc_create(ctypes.byref(h), ctypes.byref(bad), None) == -1
+    # a batch wider than the widest interleaved cycle (32 columns)
+    bad = fracprec.default_options(max_batch=33)
+    assert lib.fpc_create(ctypes.byref(h), ctypes.byref(bad), None) == -1
+    assert not h.value
     # calls on a null handle fail cleanly
     assert lib.fpc_apply_prec(None, None, None) == -1
     assert lib.fpc_num_levels(None) == 0

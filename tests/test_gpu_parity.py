@@ -320,6 +320,33 @@ def test_adjoint_and_gradient(torch):
     assert np.abs(grad[faces] - fd).max() <= 1e-6 * np.abs(fd).max()
 
 
+def test_grad_rejects_bad_pairs(torch):
+    """Face pairs are validated before any of their indices addresses a face
+    array: an index outside [0, n_p) or a pair (K, K) gives FPC_ERR_PATTERN
+    and leaves the output untouched; valid pairs in any order and with
+    repeated faces give the oracle's gradient (terms summed per face in
+    ascending pair order)."""
+    from paper_2112_12397_amd.fracprec import FpcError
+    s, pc, sol = _get("tiny_plane")
+    rng = np.random.default_rng(4)
+    lam = torch.tensor(rng.standard_normal(s.n_p), device="cuda")
+    p = torch.tensor(rng.standard_normal(s.n_p), device="cuda")
+    nd = torch.tensor(s.flow_ndir)
+    up = torch.tensor(s.upsilon)
+    for bad in ([[0, s.n_p]], [[-1, 2]], [[3, 3]]):
+        pairs = torch.tensor(np.vstack([s.flow_pairs, bad]))
+        out = torch.full((s.n_p,), 7.0, dtype=torch.float64, device="cuda")
+        with pytest.raises(FpcError, match="FPC_ERR_PATTERN"):
+            sol.grad_log_trans(pairs, nd, up, lam, p, out=out)
+        assert torch.all(out == 7.0)
+    perm = rng.permutation(len(s.flow_pairs))
+    pairs = s.flow_pairs[perm][:, ::-1].copy()
+    g = sol.grad_log_trans(torch.tensor(pairs), nd, up, lam, p).cpu().numpy()
+    ref = oracle.adjoint.grad_log_trans(s.flow_pairs, s.flow_ndir, s.upsilon,
+                                        lam.cpu().numpy(), p.cpu().numpy())
+    assert _rel(g, ref) <= 1e-13
+
+
 def test_hash_matches_oracle(torch):
     _, _, sol = _get("tiny_plane")
     for first in (0, 12345, 2 ** 32 - 100):
