@@ -114,11 +114,12 @@ def _max_nbr(G, vals):
     return np.maximum.reduceat(vals[G.indices], G.indptr[:-1])
 
 
-def mis2_aggregate(pattern):
+def mis2_aggregate(pattern, return_roots=False):
     """Distance-2 MIS aggregation on the structural node graph.
 
     Returns ``(agg, n_agg)``; ``agg[i] = -1`` marks isolated nodes (no
     off-diagonal block, e.g. Dirichlet nodes), which are not aggregated.
+    With ``return_roots`` also the root node of every aggregate.
 
     Priority of node i: ``(hash32(i) << 28) | i`` (unique).  State 0 = out,
     1 = undecided, 2 = in; key = (state << 61) | priority.  Each synchronous
@@ -170,6 +171,8 @@ def mis2_aggregate(pattern):
             raise RuntimeError("aggregation left unreachable nodes")
         agg[sel] = agg[m[sel] & IDX_MASK]
         root_of[sel] = roots[agg[sel]]
+    if return_roots:
+        return agg, n_agg, roots
     return agg, n_agg
 
 

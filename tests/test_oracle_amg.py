@@ -61,6 +61,46 @@ def test_mis2_aggregation_properties():
     assert np.array_equal(agg, agg3)
 
 
+@pytest.mark.parametrize("shape,slip", [((5, 5, 5), 0.0), ((6, 5, 4), 0.4)])
+def test_mis2_is_a_distance2_maximal_independent_set(shape, slip):
+    """Distance-2 MIS (Bell, Dalton & Olson 2012): the roots are pairwise at
+    graph distance >= 3 (independent in the square of the node graph); every
+    non-isolated node is within distance 2 of a root (maximal); every node
+    adjacent to a root lies in the aggregate of one of its adjacent roots;
+    every aggregated node is within distance 2 of its aggregate's root."""
+    s, S1, pat, h = _setup(shape, slip=slip, seed=4)
+    agg, n_agg, roots = oracle.mis2_aggregate(pat, return_roots=True)
+    G = sp.csr_matrix(pat)
+    G.setdiag(0)
+    G.eliminate_zeros()
+    D = shortest_path(G, unweighted=True, directed=False)
+    iso = np.diff(G.indptr) == 0
+    assert roots.size == n_agg and np.array_equal(agg[roots], np.arange(n_agg))
+    Dr = D[np.ix_(roots, roots)]
+    np.fill_diagonal(Dr, np.inf)
+    assert Dr.min() >= 3
+    near = D[:, roots].min(axis=1)
+    assert (near[~iso] <= 2).all()
+    adj_root = (D[:, roots] == 1)
+    for i in np.flatnonzero(adj_root.any(axis=1) & ~np.isin(np.arange(len(agg)),
+                                                            roots)):
+        assert roots[agg[i]] in roots[adj_root[i]]
+    own = D[np.arange(len(agg))[~iso], roots[agg[~iso]]]
+    assert (own <= 2).all()
+
+
+def test_mis2_rejects_distance1_sets():
+    """The root-distance pin separates MIS-2 from a plain (distance-1) MIS on
+    the same graph: on a path 0-1-2-3-4 a distance-1 MIS may take {0, 2, 4},
+    whose roots are 2 apart; the oracle's roots are >= 3 apart."""
+    n = 5
+    P = sp.diags([np.ones(n - 1), np.ones(n), np.ones(n - 1)], [-1, 0, 1],
+                 format="csr").astype(np.int8)
+    agg, n_agg, roots = oracle.mis2_aggregate(P, return_roots=True)
+    assert np.diff(np.sort(roots)).min(initial=9) >= 3
+    assert 1 <= n_agg <= 2 and (agg >= 0).all()
+
+
 def test_tentative_prolongator():
     s, S1, pat, h = _setup((5, 5, 5))
     L = h.levels[0]
