@@ -257,6 +257,19 @@ fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
                               const double* lam_p, const double* p,
                               double* grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result
+ * as fpc_grad_log_trans, with the work area of 2 n_p + 1 + 2 n_pairs int32
+ * taken from a static array of 2^20 int32 (4 MiB) that the library holds on
+ * every device until the process ends; the call allocates and frees nothing.
+ * A larger work area gives FPC_ERR_ARG and no output.  Every call on one GPU
+ * shares that array (the parts that must start at zero are cleared by each
+ * call): calls that overlap on one GPU, from several handles or threads,
+ * race and must be serialized by the caller.  Errors as fpc_grad_log_trans. */
+fpc_status fpc_grad_log_trans_noalloc(fpc_handle* h, const fpc_flow_graph* g,
+                                      const double* lam_p, const double* p,
+                                      double* grad);
+
 /* Hierarchy introspection (host outputs). */
 int fpc_num_levels(const fpc_handle* h);
 fpc_status fpc_level_info(const fpc_handle* h, int level, fpc_level_desc* d);

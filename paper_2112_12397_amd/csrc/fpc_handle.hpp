@@ -192,6 +192,7 @@ struct BatchWork {
 struct fpc_handle {
   fpc_options opt{};
   hipStream_t stream = nullptr;
+  int device = 0;              // current device at fpc_create
   bool ready = false;
   int64_t n_u = 0, n_t = 0, n_p = 0, N = 0;
   fpc::Csr A, C1, Q1, C2, H, Q2, T;

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
+#include <string>
 
 #include "fpc_apply.hpp"
 
@@ -1332,6 +1334,67 @@ void construct(fpc_handle* h, Hierarchy* prev, double t0) {
   h->setup_times[4] = t4 - t3;
 }
 
+// Transmissibility gradient on a caller-chosen int32 work area of at least
+// grad_scratch_words(n_p, n_pairs) words: pairs validated first, then the
+// per-face lists and the sums.
+void grad_run(fpc_handle* h, const fpc_flow_graph* g, const double* lam_p,
+              const double* p, double* grad, int32_t* work) {
+  hipStream_t s = h->stream;
+  const int64_t m = g->n_pairs, n = g->n_p;
+  fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+  grad_validate(n, m, g->pair_k, g->pair_l, work, h->flags.p, s);
+  check_flags(h, "face pairs");
+  grad_finish(n, m, g->pair_k, g->pair_l, g->ndir, g->upsilon, lam_p, p, grad,
+              work, s);
+  FPC_HIP(hipStreamSynchronize(s));
+}
+
+void grad_precheck(const fpc_handle* h, const fpc_flow_graph* g) {
+  if (h->has_q2)
+    throw Error(FPC_ERR_UNSUPPORTED,
+                "transmissibility gradient assumes Q2 = 0 (Q2 depends on "
+                "the transmissibility on open faces)");
+  if (g->n_pairs > (INT32_MAX - 2 * g->n_p - 1) / 2)
+    throw Error(FPC_ERR_ARG, "too many face pairs for int32 pair lists");
+}
+
+}  // namespace
+
+// ------------------------------------------- allocation-free work area
+// fpc_grad_log_trans_noalloc takes its work area from this file-scope device
+// array instead of allocating one per call.  Every GPU holds its own copy
+// until the process ends.  In host code the name `scratch` is only a host
+// stand-in: the device address is looked up once per device
+// (hipGetSymbolAddress, with that device current, in fpc_create) and kept in
+// g_scratch_dev, which is what kernels receive.
+constexpr int64_t kStaticScratchWords = int64_t(1) << 20;  // 4 MiB of int32
+static __device__ __align__(256) int32_t scratch[kStaticScratchWords];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[kMaxDevices] = {};
+
+// Records the device address of `scratch` on `dev`, the current device.
+void scratch_locate(int dev) {
+  if (dev < 0 || dev >= kMaxDevices)
+    throw Error(FPC_ERR_UNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return;
+  void* ptr = nullptr;
+  FPC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw Error(FPC_ERR_HIP, "hipGetSymbolAddress returned NULL");
+  g_scratch_dev[dev] = static_cast<int32_t*>(ptr);
+}
+
+int32_t* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  int32_t* ptr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_dev[dev] : nullptr;
+  if (!ptr) throw Error(FPC_ERR_STATE, "static work area not located");
+  return ptr;
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -1385,6 +1448,8 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
     // keep freed device memory in the default pool of this device for reuse
     int dev = 0;
     FPC_HIP(hipGetDevice(&dev));
+    h->device = dev;
+    scratch_locate(dev);
     hipMemPool_t pool;
     FPC_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
     uint64_t keep = UINT64_MAX;
@@ -1542,21 +1607,30 @@ fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
       (g->n_p > 0 && (!g->ndir || !g->upsilon)))
     return FPC_ERR_ARG;
   return guard(h, [&] {
-    if (h->has_q2)
-      throw Error(FPC_ERR_UNSUPPORTED,
-                  "transmissibility gradient assumes Q2 = 0 (Q2 depends on "
-                  "the transmissibility on open faces)");
-    if (g->n_pairs > (INT32_MAX - 2 * g->n_p - 1) / 2)
-      throw Error(FPC_ERR_ARG, "too many face pairs for int32 pair lists");
-    hipStream_t s = h->stream;
-    const int64_t m = g->n_pairs, n = g->n_p;
-    DevBuf<int32_t> work(grad_scratch_words(n, m));
-    fill_i32(h->flags.p, 0, FLAG_COUNT, s);
-    grad_validate(n, m, g->pair_k, g->pair_l, work.p, h->flags.p, s);
-    check_flags(h, "face pairs");
-    grad_finish(n, m, g->pair_k, g->pair_l, g->ndir, g->upsilon, lam_p, p,
-                grad, work.p, s);
-    FPC_HIP(hipStreamSynchronize(s));
+    grad_precheck(h, g);
+    DevBuf<int32_t> work(grad_scratch_words(g->n_p, g->n_pairs));
+    grad_run(h, g, lam_p, p, grad, work.p);
+  });
+}
+
+fpc_status fpc_grad_log_trans_noalloc(fpc_handle* h, const fpc_flow_graph* g,
+                                      const double* lam_p, const double* p,
+                                      double* grad) {
+  FPC_REQUIRE_READY(h);
+  if (!g || !lam_p || !p || !grad || g->n_p != h->n_p || g->n_pairs < 0 ||
+      (g->n_pairs > 0 && (!g->pair_k || !g->pair_l)) ||
+      (g->n_p > 0 && (!g->ndir || !g->upsilon)))
+    return FPC_ERR_ARG;
+  return guard(h, [&] {
+    grad_precheck(h, g);
+    const int64_t words = grad_scratch_words(g->n_p, g->n_pairs);
+    if (words > kStaticScratchWords)
+      throw Error(FPC_ERR_ARG,
+                  "work area of 2 n_p + 1 + 2 n_pairs = " +
+                      std::to_string(words) +
+                      " int32 exceeds the static maximum of " +
+                      std::to_string(kStaticScratchWords));
+    grad_run(h, g, lam_p, p, grad, scratch_on(h->device));
   });
 }
 

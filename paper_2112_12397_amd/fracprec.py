@@ -93,7 +93,8 @@ EXPORTS = ("fpc_default_options", "fpc_create", "fpc_setup", "fpc_apply_prec",
            "fpc_export_level_matrix", "fpc_setup_times", "fpc_destroy",
            "fpc_status_string", "fpc_last_error", "fpc_hash32_device",
            "fpc_kernel_timer", "fpc_psolve", "fpc_stream_triad",
-           "fpc_update_values", "fpc_hierarchy_reused")
+           "fpc_update_values", "fpc_hierarchy_reused",
+           "fpc_grad_log_trans_noalloc")
 
 _lib = None
 
@@ -127,6 +128,8 @@ def load_library(path: str = LIB_PATH):
         "fpc_solve_batch": (i32, [H, i32, vp, i64, vp, i64, dbl,
                                   C.POINTER(FpcInfo)]),
         "fpc_grad_log_trans": (i32, [H, C.POINTER(FpcFlowGraph), vp, vp, vp]),
+        "fpc_grad_log_trans_noalloc": (i32, [H, C.POINTER(FpcFlowGraph), vp,
+                                             vp, vp]),
         "fpc_num_levels": (i32, [H]),
         "fpc_level_info": (i32, [H, i32, C.POINTER(FpcLevelDesc)]),
         "fpc_export_aggregates": (i32, [H, i32, vp, vp]),
@@ -366,8 +369,9 @@ class Solver:
             float(rtol), infos), "solve_batch")
         return X, [i.as_dict() for i in infos], STATUS[st]
 
-    def grad_log_trans(self, pairs, ndir, upsilon, lam_p, p, out=None):
-        """dL/d log Upsilon from the adjoint pressure (device tensors)."""
+    def flow_graph(self, pairs, ndir, upsilon):
+        """Device arrays of a fracture flow graph for the gradient calls:
+        (FpcFlowGraph, tensors that must stay alive while it is used)."""
         t = self.torch
         pk = pairs[:, 0].to(device=self.device, dtype=t.int32).contiguous()
         pl = pairs[:, 1].to(device=self.device, dtype=t.int32).contiguous()
@@ -375,10 +379,25 @@ class Solver:
         up = upsilon.to(device=self.device, dtype=t.float64).contiguous()
         g = FpcFlowGraph(self.n_p, pk.numel(), pk.data_ptr(), pl.data_ptr(),
                          nd.data_ptr(), up.data_ptr())
+        return g, (pk, pl, nd, up)
+
+    def grad_log_trans(self, pairs, ndir, upsilon, lam_p, p, out=None):
+        """dL/d log Upsilon from the adjoint pressure (device tensors)."""
+        g, keep = self.flow_graph(pairs, ndir, upsilon)
         out = self._vec(self.n_p) if out is None else out
         self._check(self.lib.fpc_grad_log_trans(
             self.h, C.byref(g), self._ptr(lam_p.contiguous()),
             self._ptr(p.contiguous()), self._ptr(out)), "grad_log_trans")
+        del keep
+        return out
+
+    def grad_log_trans_noalloc(self, graph, lam_p, p, out):
+        """fpc_grad_log_trans_noalloc: every argument already on the device
+        (graph from flow_graph, contiguous float64 tensors); the library
+        allocates nothing."""
+        self._check(self.lib.fpc_grad_log_trans_noalloc(
+            self.h, C.byref(graph), self._ptr(lam_p), self._ptr(p),
+            self._ptr(out)), "grad_log_trans_noalloc")
         return out
 
     # -- introspection ----------------------------------------------------
