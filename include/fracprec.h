@@ -141,6 +141,20 @@ typedef struct {
   double tune_us[3];       /* the winner's measured time per product (us)   */
 } fpc_level_desc;
 
+/* The pressure-block factorization (nested dissection, multifrontal; for
+ * tests and reporting). */
+typedef struct {
+  int n_levels;            /* levels of the front tree (leaves = level 0)   */
+  int64_t n_fronts;        /* fronts: leaves and non-empty separators        */
+  int64_t factor_entries;  /* stored [F11^-1 | F11^-1 F12] entries, sum of   */
+                           /* m (m + k) over fronts (m pivots, k boundary)  */
+  int64_t solve_bytes;     /* algorithmic bytes of one single-column solve: */
+                           /* factor read forward (m (m + k)) and backward  */
+                           /* (m k) in FP64, plus vectors and index lists   */
+  int64_t max_pivots;      /* largest m                                     */
+  int64_t max_boundary;    /* largest k                                     */
+} fpc_pressure_desc;
+
 /* Fracture flow graph for the transmissibility gradient: TPFA face pairs
  * (K, L) (eq. FV_inner_product), Dirichlet edge counts and one-sided
  * transmissibilities.  Device pointers. */
@@ -215,7 +229,8 @@ fpc_status fpc_vcycle(fpc_handle* h, const double* b, double* x);
  * eq. app_Schur2_2, = T when Q2 = 0) in t-u-p and M2*, v = T^{-1} w (Alg 3.2
  * steps 1 and 7) in t-p-u; trans = 1 applies the transpose (the stored
  * inverse is symmetric, so the result is the same).  Runs on the handle's
- * stream in the precision of the hierarchy's pressure inverse. */
+ * stream, in FP64 with either precision of the hierarchy: forward and
+ * backward sweeps over the levels of the nested-dissection factorization. */
 fpc_status fpc_psolve(fpc_handle* h, int trans, const double* w, double* v);
 
 /* Measurement aid, not a step of the method: a = b + scalar * c over n
@@ -269,6 +284,19 @@ fpc_status fpc_grad_log_trans(fpc_handle* h, const fpc_flow_graph* g,
 fpc_status fpc_grad_log_trans_noalloc(fpc_handle* h, const fpc_flow_graph* g,
                                       const double* lam_p, const double* p,
                                       double* grad);
+
+/* The dense inverse of the coarsest AMG level (G17 of the smoothed-
+ * aggregation setup: Gauss-Jordan with partial pivoting in 256-wide panels,
+ * FP64 MFMA panel products) applied to a caller's matrix, for tests: D is a
+ * device n x n row-major matrix (n <= 16384), replaced by its inverse.
+ * FPC_ERR_SINGULAR_BLOCK (D unspecified) when a column has no nonzero pivot.
+ * Any handle (set up or not) supplies the stream; allocates n^2 doubles
+ * (n rounded up to a multiple of 64) for the call. */
+fpc_status fpc_dense_inverse(fpc_handle* h, int64_t n, double* D);
+
+/* Description of the pressure-block factorization (host output); zeros when
+ * n_p = 0.  FPC_ERR_STATE before a successful setup. */
+fpc_status fpc_pressure_info(const fpc_handle* h, fpc_pressure_desc* d);
 
 /* Hierarchy introspection (host outputs). */
 int fpc_num_levels(const fpc_handle* h);

@@ -39,10 +39,24 @@ void from_level(const T* xo, int nv, int64_t n, double* vu, int diff,
 void tface(const Csr& C, const double* vu, const double* t_t,
            const double* hinv, double* v_t, int64_t n_p, int trans,
            hipStream_t s);
+// ---------------------------------------------------------------- k_pnd
+// Ordering (nested dissection) and symbolic analysis of the pressure block's
+// pattern; flags[FLAG_PATTERN] for an unsymmetric matrix,
+// flags[FLAG_OVERFLOW] for a front boundary beyond 4096 faces.
+void psolve_analyse(PSolve& ps, const Csr& T, int* flags, hipStream_t s);
+// Numeric factorization of T - diag(sk) (sk nullable) on the analysis.
+void psolve_factor(PSolve& ps, const Csr& T, const double* sk, bool spd,
+                   int* flags, hipStream_t s);
+int64_t psolve_factor_entries(const PSolve& ps);
+// Algorithmic bytes of one single-column solve: factor entries read by the
+// forward (m (m + k)) and backward (m k) sweeps, FP64; input gathered and
+// output scattered through perm (8 + 4 bytes per face each); c_S written and
+// read back (16 per face); contributions written and gathered (16 + 4 per
+// slot); boundary indices of the backward sweep (4 per slot).
+int64_t psolve_solve_bytes(const PSolve& ps);
 void psolve_apply(const PSolve& ps, const double* in, double* out,
                   int64_t n_p, int trans, hipStream_t s);
-void pack_sym_tiles(const double* D, int64_t ld, int nt, double* out64,
-                    float* out32, hipStream_t s);
+void psolve_batch_buffers(PSolve& ps, int KB);
 
 // ---------------------------------------------------------------- batches
 void sell_mv_b(const Sell<double>& A, const double* x, double* y, int KB,

@@ -135,29 +135,40 @@ struct Hierarchy {
   bool have_transpose = false;
 };
 
-// Exact pressure-block solve: dense inverse of every connected component of
-// the face graph of S~2 (T when Q2 is empty).
+// Exact pressure-block solve: nested-dissection multifrontal factorization
+// of S~2 (T when Q2 is empty).  Fronts are numbered level by level (leaves
+// first); front f eliminates positions [f_slo, f_slo + f_m) of the order and
+// couples to the f_k boundary positions bnd[f_bnd[f] ..]; its dense matrix
+// (ld = m + k, row-major) starts at F + f_F[f], rows 0..m-1 holding
+// [F11^-1 | F11^-1 F12] after the factorization.
 struct PSolve {
-  int64_t n_comp = 0;
-  std::vector<int64_t> comp_n, comp_pad, comp_off_h, dense_off_h;
-  DevBuf<int64_t> comp_off, dense_off, comp_pad_d;
-  DevBuf<int32_t> members, comp_of_row;
-  DevBuf<double> dense;
-  DevBuf<float> dense32;      // FP32 copy (FP32 preconditioner); dense freed
-  int64_t dense_elems = 0;
-  // the same symmetric inverses as packed lower-triangular 64 x 64 tiles:
-  // tile (I, J), J <= I, of component c is tile tile_base[c] + I(I+1)/2 + J,
-  // row-major; diagonal tiles are stored full and exactly symmetric
-  int64_t n_tiles = 0, n_rowblk = 0;
-  std::vector<int64_t> tile_base_h;
-  DevBuf<int64_t> tile_base;
-  DevBuf<int32_t> tile_info;  // (c, I, J) per tile
-  DevBuf<int32_t> rowblk;     // (c, K) per 64-row block
-  DevBuf<int32_t> n_tiles_c;  // tiles per side, per component
-  DevBuf<double> packed;
-  DevBuf<float> packed32;
-  DevBuf<double> part;        // 128 partial sums per tile
-  DevBuf<double> xperm;       // the input in component (members) order
+  int64_t n = 0;
+  int n_levels = 0;
+  int64_t n_fronts = 0, n_slots = 0, F_words = 0;
+  bool spd = true;
+  std::vector<int64_t> lev_off;          // fronts of level l
+  std::vector<int32_t> hm, hk;           // host copies of f_m, f_k
+  DevBuf<int32_t> perm, pos;             // order: perm[position] = face
+  DevBuf<int32_t> f_slo, f_m, f_k;
+  DevBuf<int64_t> f_bnd, f_F;
+  DevBuf<int32_t> bnd;                   // boundary positions, ascending
+  DevBuf<int64_t> ch_off;                // children of f: ch[ch_off[f+1] ..
+  DevBuf<int32_t> ch;                    //   ch_off[f+2])
+  DevBuf<int64_t> g_off;                 // per position: contribution slots
+  DevBuf<int32_t> g_slot;                //   (f_bnd[f] + a) to subtract
+  DevBuf<double> F;
+  // solve work lists per level: (front, first output) forward,
+  // (front, first row) backward
+  std::vector<int64_t> fwd_off, bwd_off;
+  DevBuf<int2> fwd_items, bwd_items;
+  DevBuf<double> xp, contrib;            // single column
+  int KB = 0;                            // batch columns of the buffers below
+  DevBuf<double> bpB, xpB, contribB;
+  // the matrix the factor was computed from, for reuse on unchanged input
+  DevBuf<int64_t> in_rp;
+  DevBuf<int32_t> in_col;
+  DevBuf<double> in_val, in_sk;
+  bool has_sk = false;
 };
 
 // Per right-hand-side block of Krylov work space.

@@ -201,6 +201,8 @@ void cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
 bool same_pattern(const int64_t* rp_a, const int32_t* col_a,
                   const int64_t* rp_b, const int32_t* col_b, int64_t nrows,
                   int64_t nnz, hipStream_t s);
+// True if the two device arrays of n doubles are bitwise equal.
+bool same_values(const double* a, const double* b, int64_t n, hipStream_t s);
 void stream_triad(const double* b, const double* c, double scalar, double* a,
                   int64_t n, hipStream_t s);
 double read_f64(const double* p, hipStream_t s);
@@ -270,12 +272,13 @@ void dummy_diag(Bsr& Ac, const int32_t* rank, hipStream_t s);
 void power_start(int64_t n_nodes, int bs, int key_stride,
                  const int32_t* node_rank, double* x, hipStream_t s);
 void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s);
-// In-place Gauss-Jordan inverse of an n x n (n multiple of 64) row-major
-// matrix without pivoting; flags[FLAG_SINGULAR] / [FLAG_NOT_SPD] if a pivot
-// is not positive when spd != 0 or is tiny.
-// inverse of a symmetric matrix (lower-triangle block sweeps, no pivoting)
-void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s);
-void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s);
+// In-place inverse of an n x n (n multiple of 64) row-major matrix by
+// Gauss-Jordan with partial pivoting; flags[FLAG_SINGULAR] for a column
+// without a nonzero pivot candidate.
+void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s);
+// D (npad x npad) = [A 0; 0 I] for a row-major n x n A (device)
+void dense_pad(const double* A, int64_t n, int64_t npad, double* D,
+               hipStream_t s);
 
 // ---------------------------------------------------------------- k_krylov
 constexpr int kMaxKrylov = 64;

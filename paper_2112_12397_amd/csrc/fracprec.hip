@@ -23,155 +23,6 @@ double now_s() {
 }
 
 // ------------------------------------------------------------- kernels
-__global__ void k_label_init(int32_t* lab, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) lab[i] = (int32_t)i;
-}
-
-__global__ void k_label_prop(const int64_t* rp, const int32_t* col,
-                             const int32_t* in, int32_t* out, int64_t n,
-                             int* changed) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t m = in[i];
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = min(m, in[col[e]]);
-  out[i] = m;
-  if (m != in[i]) atomicOr(changed, 1);
-}
-
-__global__ void k_root_flag(const int32_t* lab, int64_t n, int64_t* f) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) f[i] = lab[i] == i ? 1 : 0;
-}
-
-__global__ void k_comp_of(const int32_t* lab, const int64_t* rscan, int64_t n,
-                          int32_t* comp) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) comp[i] = (int32_t)rscan[lab[i]];
-}
-
-__global__ void k_eq_flag(const int32_t* comp, int32_t c, int64_t n,
-                          int64_t* f) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) f[i] = comp[i] == c ? 1 : 0;
-}
-
-__global__ void k_place(const int32_t* comp, int32_t c, const int64_t* scan,
-                        int64_t off, int64_t n, int32_t* pos, int32_t* members,
-                        int32_t* comp_of_row) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || comp[i] != c) return;
-  const int32_t local = (int32_t)scan[i];
-  pos[i] = local;
-  members[off + local] = (int32_t)i;
-  comp_of_row[off + local] = c;
-}
-
-// Breadth-first levels of every component from its smallest face (level 0):
-// step `cur` gives level cur + 1 to the unvisited neighbours of level cur.
-__global__ void k_bfs_init(const int32_t* lab, int64_t n, int32_t* level) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) level[i] = lab[i] == i ? 0 : -1;
-}
-
-__global__ void k_bfs_step(const int64_t* rp, const int32_t* col, int64_t n,
-                           int32_t cur, int32_t* level, int* changed) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || level[i] != -1) return;
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-    if (level[col[e]] == cur) {
-      level[i] = cur + 1;
-      atomicOr(changed, 1);
-      return;
-    }
-}
-
-// Reorder the members of every component by (BFS level, face index): the
-// rank of each member among its component's members gives its new local
-// position.
-// Rank of a face inside its component by (level, face index).  Block
-// (x, y) takes rows [256 x, 256 x + 256) and the y-th of gridDim.y slices of
-// the positions those rows' components cover; the slice's keys pass through
-// LDS 256 at a time and every thread counts those of its own component that
-// order before its key, adding the count to rank[e] (zeroed before).
-__global__ __launch_bounds__(256) void k_level_count(
-    const int32_t* members, const int64_t* comp_off, const int32_t* comp_of_row,
-    const int32_t* level, int64_t n, int32_t* rank) {
-  __shared__ int64_t keys[256];
-  const int64_t e0 = (int64_t)blockIdx.x * 256;
-  const int64_t e = e0 + threadIdx.x;
-  const bool act = e < n;
-  int64_t a = 0, b = 0, mykey = 0;
-  if (act) {
-    const int32_t c = comp_of_row[e];
-    a = comp_off[c];
-    b = comp_off[c + 1];
-    const int32_t m = members[e];
-    mykey = ((int64_t)level[m] << 32) | (uint32_t)m;
-  }
-  const int64_t elast = e0 + 255 < n ? e0 + 255 : n - 1;
-  const int64_t lo0 = comp_off[comp_of_row[e0]];
-  const int64_t hi0 = comp_off[comp_of_row[elast] + 1];
-  const int64_t chunk = ((hi0 - lo0 + gridDim.y - 1) / gridDim.y + 255) / 256 * 256;
-  const int64_t lo = lo0 + (int64_t)blockIdx.y * chunk;
-  const int64_t hi = lo + chunk < hi0 ? lo + chunk : hi0;
-  int32_t cnt_total = 0;
-  for (int64_t f0 = lo; f0 < hi; f0 += 256) {
-    __syncthreads();
-    const int64_t f = f0 + threadIdx.x;
-    if (f < hi) {
-      const int32_t mf = members[f];
-      keys[threadIdx.x] = ((int64_t)level[mf] << 32) | (uint32_t)mf;
-    }
-    __syncthreads();
-    const int cnt = hi - f0 < 256 ? (int)(hi - f0) : 256;
-    for (int q = 0; q < cnt; ++q) {
-      const int64_t ff = f0 + q;
-      cnt_total += (ff >= a && ff < b && keys[q] < mykey) ? 1 : 0;
-    }
-  }
-  if (act && cnt_total) atomicAdd(&rank[e], cnt_total);
-}
-
-// Position of every face inside its component from its rank.
-__global__ void k_level_place(const int32_t* members, const int64_t* comp_off,
-                              const int32_t* comp_of_row, const int32_t* rank,
-                              int64_t n, int32_t* pos, int32_t* members2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int32_t m = members[e];
-  pos[m] = rank[e];
-  members2[comp_off[comp_of_row[e]] + rank[e]] = m;
-}
-
-__global__ void k_scatter_T(const int64_t* rp, const int32_t* col,
-                            const double* val, int64_t n, const int32_t* comp,
-                            const int32_t* pos, const int64_t* dense_off,
-                            const int64_t* pad, double* dense) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = comp[i];
-  double* D = dense + dense_off[c];
-  const int64_t ld = pad[c];
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-    D[(int64_t)pos[i] * ld + pos[col[e]]] = val[e];
-}
-
-// S~2 = T - S_K: subtract the fixed-stress diagonal in the dense blocks
-__global__ void k_sub_diag(const double* sk, int64_t n, const int32_t* comp,
-                           const int32_t* pos, const int64_t* dense_off,
-                           const int64_t* pad, double* dense) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = comp[i];
-  dense[dense_off[c] + (int64_t)pos[i] * pad[c] + pos[i]] -= sk[i];
-}
-
-__global__ void k_pad_diag(double* D, int64_t n, int64_t ld) {
-  int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ld) D[i * ld + i] = 1.0;
-}
-
 __global__ void k_dense_transpose(const double* A, double* T, int64_t n) {
   __shared__ double t[32][33];
   int64_t bx = blockIdx.x * 32, by = blockIdx.y * 32;
@@ -249,174 +100,56 @@ fpc_status guard(fpc_handle* h, F&& f) {
 int64_t round64(int64_t n) { return ((n + 63) / 64) * 64; }
 
 // ------------------------------------------------------------- p-block
+// Exact solve of S~2 = T - FS(Q2, S1, Q1) (T - diag(S_K) in t-u-p and M2*
+// with open faces, T otherwise): nested-dissection ordering and symbolic
+// analysis of T's pattern, then the multifrontal factorization.  A call on
+// the pattern of the previous factorization keeps its analysis; on the same
+// values too, it keeps the factor.
 void build_psolve(fpc_handle* h) {
   PSolve& ps = h->ps;
   const int64_t n = h->n_p;
   hipStream_t s = h->stream;
-  ps = PSolve();
-  if (n == 0) return;
   const Csr& T = h->T;
-  DevBuf<int32_t> la(n), lb(n);
-  DevBuf<int> changed(1);
-  const unsigned g = grid_for(n, 256);
-  k_label_init<<<g, 256, 0, s>>>(la.p, n);
-  FPC_LAUNCH_CHECK();
-  // eight propagation steps per check of the change flag (steps after
-  // convergence change nothing)
-  for (int it = 0;; it += 8) {
-    FPC_HIP(hipMemsetAsync(changed.p, 0, sizeof(int), s));
-    for (int k = 0; k < 8; ++k) {
-      k_label_prop<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, la.p, lb.p, n,
-                                     changed.p);
-      std::swap(la, lb);
-    }
-    FPC_LAUNCH_CHECK();
-    if (read_i32(changed.p, s) == 0) break;
-    if (it > 4 * n + 8) throw Error(FPC_ERR_HIP, "component labelling stalled");
-  }
-  DevBuf<int64_t> f(n), sc(n + 1);
-  k_root_flag<<<g, 256, 0, s>>>(la.p, n, f.p);
-  FPC_LAUNCH_CHECK();
-  ps.n_comp = scan_counts_total(f.p, sc.p, n, s);
-  DevBuf<int32_t> comp(n), pos(n);
-  k_comp_of<<<g, 256, 0, s>>>(la.p, sc.p, n, comp.p);
-  FPC_LAUNCH_CHECK();
-  ps.members.alloc(n);
-  ps.comp_of_row.alloc(n);
-  ps.comp_n.resize(ps.n_comp);
-  ps.comp_off_h.assign(ps.n_comp + 1, 0);
-  for (int64_t c = 0; c < ps.n_comp; ++c) {
-    k_eq_flag<<<g, 256, 0, s>>>(comp.p, (int32_t)c, n, f.p);
-    FPC_LAUNCH_CHECK();
-    const int64_t cnt = scan_counts_total(f.p, sc.p, n, s);
-    k_place<<<g, 256, 0, s>>>(comp.p, (int32_t)c, sc.p, ps.comp_off_h[c], n,
-                              pos.p, ps.members.p, ps.comp_of_row.p);
-    FPC_LAUNCH_CHECK();
-    ps.comp_n[c] = cnt;
-    ps.comp_off_h[c + 1] = ps.comp_off_h[c] + cnt;
-  }
-  ps.comp_pad.resize(ps.n_comp);
-  ps.dense_off_h.assign(ps.n_comp + 1, 0);
-  for (int64_t c = 0; c < ps.n_comp; ++c) {
-    ps.comp_pad[c] = round64(ps.comp_n[c]);
-    ps.dense_off_h[c + 1] = ps.dense_off_h[c] + ps.comp_pad[c] * ps.comp_pad[c];
-  }
-  ps.dense_elems = ps.dense_off_h[ps.n_comp];
-  if (ps.dense_elems > (int64_t)6 * 1024 * 1024 * 1024)
-    throw Error(FPC_ERR_UNSUPPORTED,
-                "pressure block: connected component too large for the dense "
-                "exact solve");
-  ps.comp_off.alloc(ps.n_comp + 1);
-  ps.dense_off.alloc(ps.n_comp + 1);
-  ps.comp_pad_d.alloc(ps.n_comp);
-  FPC_HIP(hipMemcpyAsync(ps.comp_off.p, ps.comp_off_h.data(),
-                         (ps.n_comp + 1) * sizeof(int64_t),
-                         hipMemcpyHostToDevice, s));
-  FPC_HIP(hipMemcpyAsync(ps.dense_off.p, ps.dense_off_h.data(),
-                         (ps.n_comp + 1) * sizeof(int64_t),
-                         hipMemcpyHostToDevice, s));
-  FPC_HIP(hipMemcpyAsync(ps.comp_pad_d.p, ps.comp_pad.data(),
-                         ps.n_comp * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  // local order inside each component: breadth-first levels from its smallest
-  // face, so that the dense block is banded and the sweeps of the inverse
-  // skip the tiles that stay zero (the inverse itself does not depend on the
-  // order; the apply gathers and scatters through `members`)
-  {
-    DevBuf<int32_t> level(n), members2(n);
-    k_bfs_init<<<g, 256, 0, s>>>(la.p, n, level.p);
-    FPC_LAUNCH_CHECK();
-    for (int32_t cur = 0;; cur += 8) {
-      FPC_HIP(hipMemsetAsync(changed.p, 0, sizeof(int), s));
-      for (int32_t k = 0; k < 8; ++k)
-        k_bfs_step<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, n, cur + k, level.p,
-                                     changed.p);
-      FPC_LAUNCH_CHECK();
-      if (read_i32(changed.p, s) == 0) break;
-      if (cur > n + 8) throw Error(FPC_ERR_HIP, "level ordering stalled");
-    }
-    DevBuf<int32_t> rank(n);
-    FPC_HIP(hipMemsetAsync(rank.p, 0, n * sizeof(int32_t), s));
-    k_level_count<<<dim3(g, 16), 256, 0, s>>>(ps.members.p, ps.comp_off.p,
-                                              ps.comp_of_row.p, level.p, n,
-                                              rank.p);
-    k_level_place<<<g, 256, 0, s>>>(ps.members.p, ps.comp_off.p,
-                                    ps.comp_of_row.p, rank.p, n, pos.p,
-                                    members2.p);
-    FPC_LAUNCH_CHECK();
-    FPC_HIP(hipMemcpyAsync(ps.members.p, members2.p, n * sizeof(int32_t),
-                           hipMemcpyDeviceToDevice, s));
-  }
-  ps.dense.alloc(ps.dense_elems);
-  FPC_HIP(hipMemsetAsync(ps.dense.p, 0, ps.dense.bytes(), s));
-  k_scatter_T<<<g, 256, 0, s>>>(T.rowptr.p, T.col.p, T.val.p, n, comp.p, pos.p,
-                                ps.dense_off.p, ps.comp_pad_d.p, ps.dense.p);
-  FPC_LAUNCH_CHECK();
-  // t-u-p with open faces: S~2 = T - FS(Q2, S1, Q1) (Alg 3.3), symmetric but
-  // possibly indefinite, so its elimination only checks for zero pivots
   const bool fs = h->opt.mode != FPC_TPU && h->has_q2;
+  const double* sk = fs ? h->S_K.p : nullptr;
+  if (n == 0) {
+    ps = PSolve();
+    return;
+  }
+  const bool same_pat =
+      ps.n == n && ps.in_col.n == (size_t)std::max<int64_t>(T.nnz, 1) &&
+      same_pattern(ps.in_rp.p, ps.in_col.p, T.rowptr.p, T.col.p, n, T.nnz, s);
+  if (same_pat && ps.in_val.p && ps.has_sk == fs &&
+      same_values(ps.in_val.p, T.val.p, T.nnz, s) &&
+      (!fs || (ps.in_sk.p && same_values(ps.in_sk.p, sk, n, s))))
+    return;  // the factor of this matrix is in place
+  ps.in_val.release();  // no factor is valid until this one completes
+  if (!same_pat) {
+    fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+    psolve_analyse(ps, T, h->flags.p, s);
+    check_flags(h, "pressure block (nested dissection of a symmetric S~2)");
+    ps.in_rp.alloc(n + 1);
+    ps.in_col.alloc(std::max<int64_t>(T.nnz, 1));
+    FPC_HIP(hipMemcpyAsync(ps.in_rp.p, T.rowptr.p, (n + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, s));
+    if (T.nnz)
+      FPC_HIP(hipMemcpyAsync(ps.in_col.p, T.col.p, T.nnz * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, s));
+  }
+  fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+  psolve_factor(ps, T, sk, /*spd=*/!fs, h->flags.p, s);
+  check_flags(h, "pressure block factorization");
+  ps.in_val.alloc(std::max<int64_t>(T.nnz, 1));
+  if (T.nnz)
+    FPC_HIP(hipMemcpyAsync(ps.in_val.p, T.val.p, T.nnz * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  ps.has_sk = fs;
   if (fs) {
-    k_sub_diag<<<g, 256, 0, s>>>(h->S_K.p, n, comp.p, pos.p, ps.dense_off.p,
-                                 ps.comp_pad_d.p, ps.dense.p);
-    FPC_LAUNCH_CHECK();
-  }
-  for (int64_t c = 0; c < ps.n_comp; ++c) {
-    double* D = ps.dense.p + ps.dense_off_h[c];
-    const int64_t pad = ps.comp_pad[c];
-    if (pad > ps.comp_n[c])
-      k_pad_diag<<<grid_for(pad - ps.comp_n[c], 64), 64, 0, s>>>(D, ps.comp_n[c], pad);
-    FPC_LAUNCH_CHECK();
-    sym_inverse(D, pad, /*spd=*/fs ? 0 : 1, h->flags.p, s);
-  }
-  check_flags(h, "pressure block");
-  // packed symmetric tiles for the single-vector apply
-  {
-    std::vector<int32_t> info, rb, ntc(ps.n_comp);
-    ps.tile_base_h.assign(ps.n_comp + 1, 0);
-    for (int64_t c = 0; c < ps.n_comp; ++c) {
-      const int nt = (int)(ps.comp_pad[c] / 64);
-      ntc[c] = nt;
-      ps.tile_base_h[c + 1] = ps.tile_base_h[c] + (int64_t)nt * (nt + 1) / 2;
-      for (int I = 0; I < nt; ++I) {
-        rb.push_back((int32_t)c);
-        rb.push_back(I);
-        for (int J = 0; J <= I; ++J) {
-          info.push_back((int32_t)c);
-          info.push_back(I);
-          info.push_back(J);
-        }
-      }
-    }
-    ps.n_tiles = ps.tile_base_h[ps.n_comp];
-    ps.n_rowblk = (int64_t)rb.size() / 2;
-    ps.tile_base.alloc(ps.n_comp + 1);
-    ps.tile_info.alloc(info.size());
-    ps.rowblk.alloc(rb.size());
-    ps.n_tiles_c.alloc(ps.n_comp);
-    FPC_HIP(hipMemcpyAsync(ps.tile_base.p, ps.tile_base_h.data(),
-                           (ps.n_comp + 1) * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s));
-    FPC_HIP(hipMemcpyAsync(ps.tile_info.p, info.data(),
-                           info.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    FPC_HIP(hipMemcpyAsync(ps.rowblk.p, rb.data(), rb.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s));
-    FPC_HIP(hipMemcpyAsync(ps.n_tiles_c.p, ntc.data(), ntc.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s));
-    const bool f32 = h->opt.precision == FPC_FP32_PREC;
-    if (f32) ps.packed32.alloc(ps.n_tiles * 4096);
-    else ps.packed.alloc(ps.n_tiles * 4096);
-    ps.part.alloc(ps.n_tiles * 128);
-    ps.xperm.alloc(std::max<int64_t>(n, 1));
-    for (int64_t c = 0; c < ps.n_comp; ++c)
-      pack_sym_tiles(ps.dense.p + ps.dense_off_h[c], ps.comp_pad[c], ntc[c],
-                     f32 ? nullptr : ps.packed.p + ps.tile_base_h[c] * 4096,
-                     f32 ? ps.packed32.p + ps.tile_base_h[c] * 4096 : nullptr, s);
-    FPC_HIP(hipStreamSynchronize(s));
-  }
-  if (h->opt.precision == FPC_FP32_PREC) {
-    ps.dense32.alloc(ps.dense_elems);
-    cast_f64_f32(ps.dense.p, ps.dense32.p, ps.dense_elems, s);
-    FPC_HIP(hipStreamSynchronize(s));
-    ps.dense.release();
+    ps.in_sk.alloc(n);
+    FPC_HIP(hipMemcpyAsync(ps.in_sk.p, sk, n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  } else {
+    ps.in_sk.release();
   }
   FPC_HIP(hipStreamSynchronize(s));
 }
@@ -558,7 +291,7 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
   H.ncpad = round64(std::max<int64_t>(H.nc, 1));
   H.Ainv.alloc(H.ncpad * H.ncpad);
   dense_from_bsr(C.A, H.ncpad, H.Ainv.p, s);
-  gj_inverse(H.Ainv.p, H.ncpad, /*spd=*/0, h->flags.p, s);
+  gj_inverse(H.Ainv.p, H.ncpad, h->flags.p, s);
   check_flags(h, "coarsest level");
   // apply layouts, tuned for the column count of the preconditioner
   const int nv = 1;
@@ -1035,6 +768,7 @@ BatchWork& batch_work(fpc_handle* h, int KB) {
   w->active.alloc(KB);
   w->kc.alloc(KB);
   w->brk.alloc(KB);
+  psolve_batch_buffers(h->ps, KB);
   return *w;
 }
 
@@ -1648,6 +1382,41 @@ fpc_status fpc_stream_triad(fpc_handle* h, int64_t n, const double* b,
 
 int fpc_hierarchy_reused(const fpc_handle* h) {
   return h ? (h->reused_hierarchy ? 1 : 0) : -1;
+}
+
+fpc_status fpc_dense_inverse(fpc_handle* h, int64_t n, double* D) {
+  if (!h || n < 0 || (n > 0 && !D)) return FPC_ERR_ARG;
+  if (n > 16384) return FPC_ERR_ARG;
+  if (n == 0) return FPC_OK;
+  return guard(h, [&] {
+    hipStream_t s = h->stream;
+    const int64_t npad = round64(n);
+    DevBuf<double> P(npad * npad);
+    dense_pad(D, n, npad, P.p, s);
+    fill_i32(h->flags.p, 0, FLAG_COUNT, s);
+    gj_inverse(P.p, npad, h->flags.p, s);
+    check_flags(h, "dense inverse");
+    FPC_HIP(hipMemcpy2DAsync(D, n * sizeof(double), P.p, npad * sizeof(double),
+                             n * sizeof(double), n, hipMemcpyDeviceToDevice,
+                             s));
+    FPC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+fpc_status fpc_pressure_info(const fpc_handle* h, fpc_pressure_desc* d) {
+  if (!h || !d) return FPC_ERR_ARG;
+  if (!h->ready) return FPC_ERR_STATE;
+  *d = fpc_pressure_desc{};
+  const PSolve& ps = h->ps;
+  d->n_levels = ps.n_levels;
+  d->n_fronts = ps.n_fronts;
+  d->factor_entries = psolve_factor_entries(ps);
+  d->solve_bytes = psolve_solve_bytes(ps);
+  for (int64_t f = 0; f < ps.n_fronts; ++f) {
+    d->max_pivots = std::max<int64_t>(d->max_pivots, ps.hm[f]);
+    d->max_boundary = std::max<int64_t>(d->max_boundary, ps.hk[f]);
+  }
+  return FPC_OK;
 }
 
 int fpc_num_levels(const fpc_handle* h) {

@@ -589,13 +589,13 @@ __global__ void k_pad_identity(double* D, int64_t n, int64_t npad) {
 }
 
 // ------------------------------------------------------------- dense GJ
-// Dense inverses in place, without pivoting.  Panels of 64 columns are
-// handled by the tile kernels below.  gj_inverse (the coarsest Galerkin
-// operator) uses 256-wide Gauss-Jordan panels whose diagonal block is
-// inverted with the 64-wide kernels and whose row panel, trailing update and
-// column panel are FP64 MFMA products (k_gemm_f64); sym_inverse (the
-// symmetric pressure blocks) uses 1024-wide symmetric sweeps on the lower
-// triangle.  `ld` is the row pitch, `n` the order.
+// Dense inverse of the coarsest Galerkin operator in place: Gauss-Jordan
+// with partial pivoting in 256-wide panels.  Each panel's pivot rows come
+// from an LU with partial pivoting of the panel's columns and are exchanged
+// first; the diagonal block is then inverted without further exchanges by
+// the 64-wide tile kernels, and the row panel, trailing update and column
+// panel are FP64 MFMA products (k_gemm_f64).  `ld` is the row pitch, `n` the
+// order.
 constexpr int GT = 64;  // tile
 
 // Gauss-Jordan inverse of the diagonal tile, in place.  Thread (tr, tc)
@@ -884,57 +884,6 @@ void gemm_f64(int64_t M, int64_t N, int K, double alpha, double beta,
 }
 
 // dst[c * ldd + r] = src[r * lds + c] for r < rows, c < cols (32 x 32 tiles)
-__global__ void k_tr_copy(const double* __restrict__ src, int64_t lds,
-                          int64_t rows, int64_t cols, double* __restrict__ dst,
-                          int64_t ldd) {
-  __shared__ double t[32][33];
-  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
-  for (int k = threadIdx.y; k < 32; k += 8) {
-    const int64_t r = r0 + k, c = c0 + threadIdx.x;
-    if (r < rows && c < cols) t[k][threadIdx.x] = src[r * lds + c];
-  }
-  __syncthreads();
-  for (int k = threadIdx.y; k < 32; k += 8) {
-    const int64_t c = c0 + k, r = r0 + threadIdx.x;
-    if (r < rows && c < cols) dst[c * ldd + r] = t[threadIdx.x][k];
-  }
-}
-
-void tr_copy(const double* src, int64_t lds, int64_t rows, int64_t cols,
-             double* dst, int64_t ldd, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return;
-  dim3 g((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
-  k_tr_copy<<<g, dim3(32, 8), 0, s>>>(src, lds, rows, cols, dst, ldd);
-  FPC_LAUNCH_CHECK();
-}
-
-// nb x nb block at D (pitch ld): upper triangle <- lower triangle
-__global__ void k_mirror_lower(double* D, int64_t ld, int64_t nb) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nb * nb) return;
-  const int64_t i = e / nb, j = e % nb;
-  if (j > i) D[i * ld + j] = D[j * ld + i];
-}
-
-// nb x nb block at D (pitch ld) <- -itself
-__global__ void k_negate_block(double* D, int64_t ld, int64_t nb) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nb * nb) return;
-  D[(e / nb) * ld + e % nb] = -D[(e / nb) * ld + e % nb];
-}
-
-// full symmetric matrix from the lower triangle, negated: D[i][j] = D[j][i]
-// = -D[max][min]
-__global__ void k_sym_negate(double* D, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.y * 16 + threadIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * 16 + threadIdx.x;
-  if (i >= n || j > i) return;
-  const double v = -D[i * n + j];
-  D[i * n + j] = v;
-  if (j != i) D[j * n + i] = v;
-}
-
-// 64-wide Gauss-Jordan on the n x n block at D (pitch ld).
 void gj_inverse64(double* D, int64_t n, int64_t ld, int spd, int* flags,
                   hipStream_t s) {
   const int64_t nt = n / GT;
@@ -1271,6 +1220,19 @@ void power_start(int64_t n_nodes, int bs, int key_stride,
   FPC_LAUNCH_CHECK();
 }
 
+// D (npad x npad) = [A 0; 0 I] for a row-major n x n A
+void dense_pad(const double* A, int64_t n, int64_t npad, double* D,
+               hipStream_t s) {
+  FPC_HIP(hipMemsetAsync(D, 0, (size_t)npad * npad * sizeof(double), s));
+  if (n)
+    FPC_HIP(hipMemcpy2DAsync(D, npad * sizeof(double), A, n * sizeof(double),
+                             n * sizeof(double), n, hipMemcpyDeviceToDevice,
+                             s));
+  if (npad > n)
+    k_pad_identity<<<grid_for(npad - n, 256), 256, 0, s>>>(D, n, npad);
+  FPC_LAUNCH_CHECK();
+}
+
 void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
   FPC_HIP(hipMemsetAsync(D, 0, (size_t)npad * npad * sizeof(double), s));
   if (a.nbr)
@@ -1282,144 +1244,134 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
   FPC_LAUNCH_CHECK();
 }
 
-// flag[t] = 1 if rows 64t .. 64t+63 of the n x w row-major panel P hold a
-// nonzero (tiles inside [skip_at, skip_at + skip_len) are left 0).
-__global__ __launch_bounds__(256) void k_tile_nonzero(const double* P, int64_t w,
-                                                      int64_t skip_at,
-                                                      int64_t skip_len,
-                                                      int32_t* flag) {
-  __shared__ int any;
-  const int64_t t = blockIdx.x;
-  const int64_t r0 = t * 64;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  const bool skipped = r0 >= skip_at && r0 < skip_at + skip_len;
-  if (!skipped) {
-    // the tile's 64 rows are one contiguous range of 64 w values
-    const double* __restrict__ base = P + r0 * w;
-    const int64_t len = 64 * w;
-    int nz = 0;
-#pragma unroll 8
-    for (int64_t q = threadIdx.x; q < len; q += 256) nz |= base[q] != 0.0;
-    if (nz) any = 1;
+// Pivot rows of the panel [o, o + nb) of the n x n matrix D for Gauss-Jordan
+// with partial pivoting: LU with partial pivoting of the tall block
+// D[o.., o .. o + nb) on a copy (P, (n - o) x nb).  In the elimination the
+// rows below the diagonal receive the same updates as in Gauss-Jordan, so
+// these are the pivots Gauss-Jordan meets on the swapped matrix.  piv[k] =
+// the row of D to exchange with row o + k (LAPACK convention, in order).  A
+// column without a nonzero flags FLAG_SINGULAR.
+__global__ __launch_bounds__(1024) void k_panel_pivots(
+    const double* __restrict__ D, int64_t n, int64_t o, int nb,
+    double* __restrict__ P, int32_t* __restrict__ piv, int* flags) {
+  __shared__ double s_v[16];
+  __shared__ int s_i[16];
+  __shared__ double s_piv_row[256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t m = n - o;
+  for (int64_t idx = t; idx < m * nb; idx += 1024) {
+    const int64_t r = idx / nb, c = idx - r * nb;
+    P[idx] = D[(o + r) * n + o + c];
   }
   __syncthreads();
-  if (threadIdx.x == 0) flag[t] = skipped ? 0 : any;
-}
-
-// list = indices t with flag[t] = 1, ascending; count[0] = their number
-// (one workgroup; nt <= 65536).
-__global__ __launch_bounds__(256) void k_tile_compact(const int32_t* flag,
-                                                      int64_t nt, int32_t* list,
-                                                      int32_t* count) {
-  __shared__ int32_t part[256];
-  const int tid = threadIdx.x;
-  const int64_t per = (nt + 255) / 256;
-  const int64_t a = tid * per, b = a + per < nt ? a + per : nt;
-  int32_t c = 0;
-  for (int64_t t = a; t < b; ++t) c += flag[t];
-  part[tid] = c;
-  __syncthreads();
-  if (tid == 0) {
-    int32_t run = 0;
-    for (int i = 0; i < 256; ++i) {
-      const int32_t v = part[i];
-      part[i] = run;
-      run += v;
+  for (int k = 0; k < nb; ++k) {
+    double bv = -1.0;
+    int bi = k;
+    for (int64_t r = k + t; r < m; r += 1024) {
+      const double a = fabs(P[r * nb + k]);
+      if (a > bv) {
+        bv = a;
+        bi = (int)r;
+      }
     }
-    count[0] = run;
-  }
-  __syncthreads();
-  int32_t o = part[tid];
-  for (int64_t t = a; t < b; ++t)
-    if (flag[t]) list[o++] = (int32_t)t;
-}
-
-// Inverse of a symmetric matrix by block sweeps (Goodnight's sweep operator
-// in 1024-wide panels), in place, touching only the lower triangle: sweeping
-// block k with panel P (the off-diagonal part of block column k) and
-// D_kk^-1 gives D_ij -= P_i D_kk^-1 P_j^T, new panel P D_kk^-1 and
-// D_kk <- -D_kk^-1; after all blocks the lower triangle holds -A^{-1}, which
-// the last pass mirrors and negates.  Half the flops of Gauss-Jordan (the
-// trailing products cover the lower triangle only); no pivoting (a zero
-// pivot of a diagonal block is reported).  The trailing product only visits
-// the 64-row tiles where the panel P has a nonzero: Z_i P_j^T is exactly zero
-// when P_i or P_j is, so the skipped tiles are exactly the unchanged ones.
-// For a sparse matrix swept in a banded order the unswept part away from the
-// band keeps its zeros, and the product shrinks to the swept rows and the
-// band (about a third of the dense flops for a 2D face graph).
-void sym_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
-  if (n % GT) throw Error(FPC_ERR_ARG, "sym_inverse: size not a multiple of 64");
-  constexpr int64_t NB = 1024;
-  if (n <= NB) return gj_inverse64(D, n, n, spd, flags, s);
-  const int64_t nt = n / GT;
-  if (nt > 65536) throw Error(FPC_ERR_UNSUPPORTED, "sym_inverse: order too large");
-  DevBuf<double> prow(NB * n), pcol(n * NB), z(n * NB);
-  DevBuf<int32_t> tflag(nt), tlist(nt), tcount(1);
-  const SkipMap none{INT64_MAX, 0};
-  for (int64_t o = 0; o < n; o += NB) {
-    const int64_t nb = std::min<int64_t>(NB, n - o), e = o + nb;
-    double* Dkk = D + o * n + o;
-    k_mirror_lower<<<grid_for(nb * nb, 256), 256, 0, s>>>(Dkk, n, nb);
-    FPC_LAUNCH_CHECK();
-    gj_inverse64(Dkk, nb, n, spd, flags, s);           // Dkk <- Dkk^-1
-    // P (n x nb, rows outside the panel): lower tiles (i, k) for i >= e,
-    // transposed lower tiles (k, i) for i < o; P^T likewise (nb x n)
-    if (e < n)
-      FPC_HIP(hipMemcpy2DAsync(pcol.p + e * nb, nb * sizeof(double),
-                               D + e * n + o, n * sizeof(double),
-                               nb * sizeof(double), n - e,
-                               hipMemcpyDeviceToDevice, s));
-    tr_copy(D + o * n, n, nb, o, pcol.p, nb, s);
-    if (o > 0)
-      FPC_HIP(hipMemcpy2DAsync(prow.p, n * sizeof(double), D + o * n,
-                               n * sizeof(double), o * sizeof(double), nb,
-                               hipMemcpyDeviceToDevice, s));
-    tr_copy(D + e * n + o, n, n - e, nb, prow.p + e, n, s);
-    // the 64-row tiles where P has a nonzero; elsewhere Z = P Dkk^-1 and the
-    // trailing update are exactly zero
-    k_tile_nonzero<<<(unsigned)nt, 256, 0, s>>>(pcol.p, nb, o, nb, tflag.p);
-    k_tile_compact<<<1, 256, 0, s>>>(tflag.p, nt, tlist.p, tcount.p);
-    FPC_LAUNCH_CHECK();
-    const int64_t mt = read_i32(tcount.p, s);
-    FPC_HIP(hipMemsetAsync(z.p, 0, (size_t)n * nb * sizeof(double), s));
-    if (mt > 0) {
-      const SkipMap sel{0, 0, tlist.p};
-      // Z = P Dkk^-1 on those tiles
-      gemm_f64(mt * GT, nb, (int)nb, 1.0, 0.0, pcol.p, nb, Dkk, n, z.p, nb, sel,
-               none, s);
-      // lower trailing update D_ij -= Z_i P_j^T
-      gemm_f64(mt * GT, mt * GT, (int)nb, -1.0, 1.0, z.p, nb, prow.p, n, D, n,
-               sel, sel, s, /*lower=*/1);
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
     }
-    // new panel Z into the lower tiles; Dkk <- -Dkk^-1
-    if (e < n)
-      FPC_HIP(hipMemcpy2DAsync(D + e * n + o, n * sizeof(double), z.p + e * nb,
-                               nb * sizeof(double), nb * sizeof(double), n - e,
-                               hipMemcpyDeviceToDevice, s));
-    tr_copy(z.p, nb, o, nb, D + o * n, n, s);
-    k_negate_block<<<grid_for(nb * nb, 256), 256, 0, s>>>(Dkk, n, nb);
-    FPC_LAUNCH_CHECK();
+    if (lane == 0) {
+      s_v[w] = bv;
+      s_i[w] = bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      for (int q = 1; q < 16; ++q)
+        if (s_v[q] > s_v[0] || (s_v[q] == s_v[0] && s_i[q] < s_i[0])) {
+          s_v[0] = s_v[q];
+          s_i[0] = s_i[q];
+        }
+      piv[k] = (int32_t)(o + s_i[0]);
+      if (!(s_v[0] > 0.0) || !isfinite(s_v[0]))
+        atomicOr(&flags[FLAG_SINGULAR], 1);
+    }
+    __syncthreads();
+    const int p = s_i[0];
+    const bool bad = !(s_v[0] > 0.0) || !isfinite(s_v[0]);
+    if (p != k)
+      for (int c = t; c < nb; c += 1024) {
+        const double x = P[(int64_t)k * nb + c];
+        P[(int64_t)k * nb + c] = P[(int64_t)p * nb + c];
+        P[(int64_t)p * nb + c] = x;
+      }
+    __syncthreads();
+    for (int c = t; c < nb; c += 1024) s_piv_row[c] = P[(int64_t)k * nb + c];
+    __syncthreads();
+    const double inv = bad ? 0.0 : 1.0 / s_piv_row[k];
+    // rows below the pivot: l = a_rk / a_kk, a_rc -= l a_kc (c > k)
+    for (int64_t r = k + 1 + w; r < m; r += 16) {
+      double* __restrict__ row = P + r * nb;
+      const double l = row[k] * inv;
+      if (l == 0.0) continue;
+      for (int c = k + 1 + lane; c < nb; c += 64) row[c] -= l * s_piv_row[c];
+    }
+    __syncthreads();
   }
-  dim3 g((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16));
-  k_sym_negate<<<g, dim3(16, 16), 0, s>>>(D, n);
-  FPC_LAUNCH_CHECK();
-  FPC_HIP(hipStreamSynchronize(s));
 }
 
-void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
+// Row exchanges of one panel applied in order to whole rows (thread per
+// column).
+__global__ void k_swap_rows(double* D, int64_t n, int64_t o, int nb,
+                            const int32_t* __restrict__ piv) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int k = 0; k < nb; ++k) {
+    const int64_t r = piv[k];
+    if (r == o + k) continue;
+    const double x = D[(o + k) * n + j];
+    D[(o + k) * n + j] = D[r * n + j];
+    D[r * n + j] = x;
+  }
+}
+
+// inv(A) = inv(P A) P: the exchanges applied to the columns in reverse order
+// (thread per row).
+__global__ void k_unswap_cols(double* D, int64_t n,
+                              const int32_t* __restrict__ piv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* row = D + i * n;
+  for (int64_t k = n - 1; k >= 0; --k) {
+    const int64_t c = piv[k];
+    if (c == k) continue;
+    const double x = row[k];
+    row[k] = row[c];
+    row[c] = x;
+  }
+}
+
+void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s) {
   if (n % GT) throw Error(FPC_ERR_ARG, "gj_inverse: size not a multiple of 64");
   constexpr int64_t NB = 256;
-  if (n <= NB) return gj_inverse64(D, n, n, spd, flags, s);
+  DevBuf<int32_t> piv(n);
+  DevBuf<double> panel(n * std::min<int64_t>(NB, n));
   // 256-wide panels: copies of the panel row / column feed the panel
   // products, which may not read what they write
   DevBuf<double> prow(NB * n), pcol(n * NB);
   const SkipMap none{INT64_MAX, 0};
   for (int64_t o = 0; o < n; o += NB) {
     const int64_t nb = std::min<int64_t>(NB, n - o);
-    const SkipMap skip{o, nb};
+    // partial pivoting: choose the panel's pivot rows, exchange them
+    k_panel_pivots<<<1, 1024, 0, s>>>(D, n, o, (int)nb, panel.p, piv.p + o,
+                                      flags);
+    k_swap_rows<<<grid_for(n, 256), 256, 0, s>>>(D, n, o, (int)nb, piv.p + o);
+    FPC_LAUNCH_CHECK();
     double* Dkk = D + o * n + o;
-    gj_inverse64(Dkk, nb, n, spd, flags, s);        // Dkk <- Dkk^-1
+    gj_inverse64(Dkk, nb, n, /*spd=*/0, flags, s);  // Dkk <- Dkk^-1
+    if (nb == n) break;
+    const SkipMap skip{o, nb};
     FPC_HIP(hipMemcpyAsync(prow.p, D + o * n, nb * n * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
     FPC_HIP(hipMemcpy2DAsync(pcol.p, nb * sizeof(double), D + o,
@@ -1435,6 +1387,8 @@ void gj_inverse(double* D, int64_t n, int spd, int* flags, hipStream_t s) {
     gemm_f64(n - nb, nb, (int)nb, -1.0, 0.0, pcol.p, nb, Dkk, n, D + o, n,
              skip, none, s);
   }
+  k_unswap_cols<<<grid_for(n, 256), 256, 0, s>>>(D, n, piv.p);
+  FPC_LAUNCH_CHECK();
   FPC_HIP(hipStreamSynchronize(s));
 }
 

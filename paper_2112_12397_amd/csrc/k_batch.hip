@@ -128,35 +128,6 @@ __global__ void k_tface_b(const int64_t* __restrict__ rp,
                                 h[r * 3 + 2] * s[2];
 }
 
-// dense pressure-block inverse applied to KB columns: one thread per
-// (row, column); the matrix row is read once per wavefront (broadcast)
-template <typename M>
-__global__ __launch_bounds__(256) void k_psolve_b(
-    const M* __restrict__ dense, const int64_t* __restrict__ dense_off,
-    const int64_t* __restrict__ comp_off, const int64_t* __restrict__ comp_pad,
-    const int32_t* __restrict__ comp_of_row, const int32_t* __restrict__ members,
-    const double* __restrict__ in, double* __restrict__ out, int64_t n_p,
-    int KB) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t g = t / KB;
-  const int c = (int)(t % KB);
-  if (g >= n_p) return;
-  const int cc = comp_of_row[g];
-  const int64_t o = comp_off[cc];
-  const int64_t n = comp_off[cc + 1] - o;
-  const int64_t ld = comp_pad[cc];
-  const M* __restrict__ row = dense + dense_off[cc] + (g - o) * ld;
-  const int32_t* __restrict__ mem = members + o;
-  double a0 = 0.0, a1 = 0.0;
-  int64_t k = 0;
-  for (; k + 1 < n; k += 2) {
-    a0 += (double)row[k] * in[(int64_t)mem[k] * KB + c];
-    a1 += (double)row[k + 1] * in[(int64_t)mem[k + 1] * KB + c];
-  }
-  if (k < n) a0 += (double)row[k] * in[(int64_t)mem[k] * KB + c];
-  out[(int64_t)members[g] * KB + c] = a0 + a1;
-}
-
 // ------------------------------------------------------------- Krylov
 constexpr int BT = 256;
 
@@ -505,23 +476,6 @@ void tface_b(const Csr& C, const double* vu, const double* t_t,
   if (!n_p) return;
   k_tface_b<<<grid_for(n_p * KB, 128), 128, 0, s>>>(
       C.rowptr.p, C.col.p, C.val.p, vu, t_t, hinv, v_t, n_p, KB);
-  FPC_LAUNCH_CHECK();
-}
-
-void psolve_apply_b(const PSolve& ps, const double* in, double* out,
-                    int64_t n_p, int KB, hipStream_t s) {
-  if (!n_p) return;
-  const unsigned g = grid_for(n_p * KB, 256);
-  if (ps.dense32.p)
-    k_psolve_b<float><<<g, 256, 0, s>>>(ps.dense32.p, ps.dense_off.p,
-                                        ps.comp_off.p, ps.comp_pad_d.p,
-                                        ps.comp_of_row.p, ps.members.p, in,
-                                        out, n_p, KB);
-  else
-    k_psolve_b<double><<<g, 256, 0, s>>>(ps.dense.p, ps.dense_off.p,
-                                         ps.comp_off.p, ps.comp_pad_d.p,
-                                         ps.comp_of_row.p, ps.members.p, in,
-                                         out, n_p, KB);
   FPC_LAUNCH_CHECK();
 }
 

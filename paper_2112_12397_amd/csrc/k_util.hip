@@ -284,6 +284,17 @@ bool same_pattern(const int64_t* rp_a, const int32_t* col_a,
   return read_i32(f.p, s) == 0;
 }
 
+bool same_values(const double* a, const double* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return true;
+  DevBuf<int> f(1);
+  fill_i32(f.p, 0, 1, s);
+  k_neq<uint64_t><<<grid_for(n, 256), 256, 0, s>>>(
+      reinterpret_cast<const uint64_t*>(a), reinterpret_cast<const uint64_t*>(b),
+      n, f.p);
+  FPC_LAUNCH_CHECK();
+  return read_i32(f.p, s) == 0;
+}
+
 hipStream_t& alloc_stream() {
   static thread_local hipStream_t s = nullptr;
   return s;

@@ -702,154 +702,6 @@ __global__ __launch_bounds__(192) void k_tface(const int64_t* __restrict__ rp,
   v_t[3 * K + r] = -t_t[3 * K + r] + hv;
 }
 
-// Exact pressure-block solve with the symmetric dense inverse of every
-// connected component, stored as packed lower-triangular 64 x 64 tiles.  A
-// tile (I, J) is read once and yields both its row-block product A_IJ x_J
-// (for block row I) and, off the diagonal, its transposed product
-// A_IJ^T x_I (for block row J).  The 128 partial sums per tile are combined
-// per block row by k_psym_reduce in a fixed order.
-// xperm[e] = in[members[e]]: the pressure input in component order, so that
-// a tile reads its two x segments with one dependent load each.
-__global__ void k_psym_gather(const int32_t* __restrict__ members,
-                              const double* __restrict__ in, int64_t n,
-                              double* __restrict__ xperm) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) xperm[e] = in[members[e]];
-}
-
-template <typename M>
-__global__ __launch_bounds__(256) void k_psym_tile(
-    const M* __restrict__ packed, const int32_t* __restrict__ tile_info,
-    const int64_t* __restrict__ comp_off, const double* __restrict__ xperm,
-    double* __restrict__ part) {
-  __shared__ double xs[2][64];
-  __shared__ double cs[4][64];
-  const int64_t t = blockIdx.x;
-  const int c = tile_info[3 * t], I = tile_info[3 * t + 1], J = tile_info[3 * t + 2];
-  const int64_t o = comp_off[c], n = comp_off[c + 1] - o;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  // the x segments first: waiting for them then leaves the tile loads,
-  // issued after them, in flight
-  double xv = 0.0;
-  if (tid < 128) {
-    const int64_t idx = (int64_t)(tid < 64 ? J : I) * 64 + lane;
-    if (idx < n) xv = xperm[o + idx];
-  }
-  const M* __restrict__ tp = packed + t * 4096 + (int64_t)(w * 16) * 64 + lane;
-  M a[16];
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) a[rr] = ld_stream(tp + rr * 64);
-  if (tid < 128) xs[tid >> 6][lane] = xv;
-  __syncthreads();
-  const double xj = xs[0][lane];
-  double v[16];
-  double col = 0.0;
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    const double av = (double)a[rr];
-    v[rr] = av * xj;
-    col += av * xs[1][w * 16 + rr];
-  }
-  cs[w][lane] = col;
-  // row sums of the wavefront's 16 rows over its 64 lanes by a transposing
-  // butterfly: at lane bit 5, 4, 3, 2 a lane keeps the half of its values
-  // selected by that bit and adds the partner's copy of it, so lane l ends
-  // with row (l >> 2) & 15 summed over 16 lanes; bits 1 and 0 finish it
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const bool hi = (lane >> 5) & 1;
-    const double send = hi ? v[k] : v[k + 8];
-    const double recv = __shfl_xor(send, 32, 64);
-    v[k] = (hi ? v[k + 8] : v[k]) + recv;
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const bool hi = (lane >> 4) & 1;
-    const double send = hi ? v[k] : v[k + 4];
-    const double recv = __shfl_xor(send, 16, 64);
-    v[k] = (hi ? v[k + 4] : v[k]) + recv;
-  }
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const bool hi = (lane >> 3) & 1;
-    const double send = hi ? v[k] : v[k + 2];
-    const double recv = __shfl_xor(send, 8, 64);
-    v[k] = (hi ? v[k + 2] : v[k]) + recv;
-  }
-  {
-    const bool hi = (lane >> 2) & 1;
-    const double send = hi ? v[0] : v[1];
-    const double recv = __shfl_xor(send, 4, 64);
-    v[0] = (hi ? v[1] : v[0]) + recv;
-  }
-  double sum = v[0];
-  sum += __shfl_xor(sum, 1, 64);
-  sum += __shfl_xor(sum, 2, 64);
-  if ((lane & 3) == 0) part[t * 128 + w * 16 + (lane >> 2)] = sum;
-  __syncthreads();
-  if (tid < 64)
-    part[t * 128 + 64 + tid] =
-        I != J ? (cs[0][tid] + cs[1][tid]) + (cs[2][tid] + cs[3][tid]) : 0.0;
-}
-
-// Block row K of component c: the row parts of tiles (K, J), J <= K, then the
-// transposed parts of tiles (I, K), I > K; wavefront w of the 16 takes every
-// 16th term and the 16 sums are added in a fixed order.
-constexpr int kRedWaves = 16;
-
-__global__ __launch_bounds__(64 * kRedWaves) void k_psym_reduce(
-    const int32_t* __restrict__ rowblk, const int64_t* __restrict__ tile_base,
-    const int32_t* __restrict__ n_tiles_c, const int64_t* __restrict__ comp_off,
-    const int32_t* __restrict__ members, const double* __restrict__ part,
-    double* __restrict__ out) {
-  __shared__ double sh[kRedWaves][64];
-  const int64_t rb = blockIdx.x;
-  const int c = rowblk[2 * rb], K = rowblk[2 * rb + 1];
-  const int64_t base = tile_base[c];
-  const int nt = n_tiles_c[c];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double acc = 0.0;
-#pragma unroll 4
-  for (int e = w; e < nt; e += kRedWaves) {
-    const int64_t off =
-        e <= K ? (base + (int64_t)K * (K + 1) / 2 + e) * 128 + lane
-               : (base + (int64_t)e * (e + 1) / 2 + K) * 128 + 64 + lane;
-    acc += part[off];
-  }
-  sh[w][lane] = acc;
-  __syncthreads();
-  if (w == 0) {
-    const int64_t o = comp_off[c], n = comp_off[c + 1] - o;
-    const int64_t idx = (int64_t)K * 64 + lane;
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < kRedWaves; ++q) t += sh[q][lane];
-    if (idx < n) out[members[o + idx]] = t;
-  }
-}
-
-// One tile per block: tile index tt of the component -> (I, J), then the
-// 64 x 64 copy; the upper half of a diagonal tile mirrors its lower half.
-template <typename M>
-__global__ __launch_bounds__(256) void k_pack_sym(const double* __restrict__ D,
-                                                  int64_t ld, M* __restrict__ out) {
-  const int64_t tt = blockIdx.x;
-  int I = (int)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(I + 1) * (I + 2) / 2 <= tt) ++I;
-  while ((int64_t)I * (I + 1) / 2 > tt) --I;
-  const int J = (int)(tt - (int64_t)I * (I + 1) / 2);
-  M* __restrict__ dst = out + tt * 4096;
-  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
-    const int r = e >> 6, cc = e & 63;
-    int64_t gr = (int64_t)I * 64 + r, gc = (int64_t)J * 64 + cc;
-    if (I == J && cc > r) {
-      gr = (int64_t)I * 64 + cc;
-      gc = (int64_t)I * 64 + r;
-    }
-    dst[e] = (M)D[gr * ld + gc];
-  }
-}
-
 template <typename T, int NV>
 __global__ void k_zero(T* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1280,35 +1132,6 @@ void tface(const Csr& C, const double* vu, const double* t_t,
   k_tface<<<(unsigned)((n_p + 63) / 64), 192, 0, s>>>(C.rowptr.p, C.col.p,
                                                      C.val.p, vu, t_t, hinv,
                                                      v_t, n_p, trans);
-  FPC_LAUNCH_CHECK();
-}
-
-void psolve_apply(const PSolve& ps, const double* in, double* out,
-                  int64_t n_p, int trans, hipStream_t s) {
-  // the stored inverse is exactly symmetric: the transposed solve is the same
-  (void)trans;
-  if (n_p == 0) return;
-  k_psym_gather<<<grid_for(n_p, 256), 256, 0, s>>>(ps.members.p, in, n_p,
-                                                   ps.xperm.p);
-  if (ps.packed32.p)
-    k_psym_tile<float><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
-        ps.packed32.p, ps.tile_info.p, ps.comp_off.p, ps.xperm.p, ps.part.p);
-  else
-    k_psym_tile<double><<<(unsigned)ps.n_tiles, 256, 0, s>>>(
-        ps.packed.p, ps.tile_info.p, ps.comp_off.p, ps.xperm.p, ps.part.p);
-  FPC_LAUNCH_CHECK();
-  k_psym_reduce<<<(unsigned)ps.n_rowblk, 64 * kRedWaves, 0, s>>>(
-      ps.rowblk.p, ps.tile_base.p, ps.n_tiles_c.p, ps.comp_off.p, ps.members.p,
-      ps.part.p, out);
-  FPC_LAUNCH_CHECK();
-}
-
-void pack_sym_tiles(const double* D, int64_t ld, int nt, double* out64,
-                    float* out32, hipStream_t s) {
-  const unsigned g = (unsigned)((int64_t)nt * (nt + 1) / 2);
-  if (!g) return;
-  if (out64) k_pack_sym<double><<<g, 256, 0, s>>>(D, ld, out64);
-  else k_pack_sym<float><<<g, 256, 0, s>>>(D, ld, out32);
   FPC_LAUNCH_CHECK();
 }
 

@@ -80,6 +80,15 @@ class FpcLevelDesc(C.Structure):
         return out
 
 
+class FpcPressureDesc(C.Structure):
+    _fields_ = [("n_levels", C.c_int), ("n_fronts", C.c_int64),
+                ("factor_entries", C.c_int64), ("solve_bytes", C.c_int64),
+                ("max_pivots", C.c_int64), ("max_boundary", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FpcFlowGraph(C.Structure):
     _fields_ = [("n_p", C.c_int64), ("n_pairs", C.c_int64),
                 ("pair_k", C.c_void_p), ("pair_l", C.c_void_p),
@@ -94,7 +103,8 @@ EXPORTS = ("fpc_default_options", "fpc_create", "fpc_setup", "fpc_apply_prec",
            "fpc_status_string", "fpc_last_error", "fpc_hash32_device",
            "fpc_kernel_timer", "fpc_psolve", "fpc_stream_triad",
            "fpc_update_values", "fpc_hierarchy_reused",
-           "fpc_grad_log_trans_noalloc")
+           "fpc_grad_log_trans_noalloc", "fpc_pressure_info",
+           "fpc_dense_inverse")
 
 _lib = None
 
@@ -130,6 +140,8 @@ def load_library(path: str = LIB_PATH):
         "fpc_grad_log_trans": (i32, [H, C.POINTER(FpcFlowGraph), vp, vp, vp]),
         "fpc_grad_log_trans_noalloc": (i32, [H, C.POINTER(FpcFlowGraph), vp,
                                              vp, vp]),
+        "fpc_pressure_info": (i32, [H, C.POINTER(FpcPressureDesc)]),
+        "fpc_dense_inverse": (i32, [H, i64, vp]),
         "fpc_num_levels": (i32, [H]),
         "fpc_level_info": (i32, [H, i32, C.POINTER(FpcLevelDesc)]),
         "fpc_export_aggregates": (i32, [H, i32, vp, vp]),
@@ -327,6 +339,13 @@ class Solver:
                                         self._ptr(v)), "psolve")
         return v
 
+    def dense_inverse(self, D):
+        """In-place inverse of a square contiguous float64 CUDA tensor by the
+        coarsest-level Gauss-Jordan with partial pivoting."""
+        self._check(self.lib.fpc_dense_inverse(self.h, D.shape[0],
+                                               self._ptr(D)), "dense_inverse")
+        return D
+
     def stream_triad(self, b, c, scalar, out):
         """a = b + scalar c (HBM bandwidth reference)."""
         self._check(self.lib.fpc_stream_triad(self.h, b.numel(), self._ptr(b),
@@ -401,6 +420,12 @@ class Solver:
         return out
 
     # -- introspection ----------------------------------------------------
+    def pressure_info(self):
+        d = FpcPressureDesc()
+        self._check(self.lib.fpc_pressure_info(self.h, C.byref(d)),
+                    "pressure_info")
+        return d.as_dict()
+
     def num_levels(self):
         return self.lib.fpc_num_levels(self.h)
 

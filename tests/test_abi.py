@@ -69,7 +69,8 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"fpc_csr": F.FpcCsr, "fpc_block_system": F.FpcBlockSystem,
                "fpc_amg_options": F.FpcAmgOptions, "fpc_options": F.FpcOptions,
                "fpc_info": F.FpcInfo, "fpc_level_desc": F.FpcLevelDesc,
-               "fpc_flow_graph": F.FpcFlowGraph}
+               "fpc_flow_graph": F.FpcFlowGraph,
+               "fpc_pressure_desc": F.FpcPressureDesc}
     lines = ['#include <stdio.h>', '#include <stddef.h>',
              '#include "fracprec.h"', 'int main(void) {']
     for cname, py in structs.items():

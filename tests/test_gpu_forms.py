@@ -27,11 +27,27 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+_PC = {}
+
+
+def _c1_oracle(s):
+    if "c1" not in _PC:
+        _PC["c1"] = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p,
+                                        coords=s.coords)
+    return _PC["c1"]
+
+
 @pytest.mark.parametrize("k", [3, 12])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_matches_single(torch, c1, k, precision):
+def test_batch_matches_oracle_and_single(torch, c1, k, precision):
+    """Every column of a batched solve (norms 1e-2 .. 1e2) against the FP64
+    oracle's FGMRES(50) with CGS2 on that column: iterations within 2 of the
+    oracle's, solution within 1e-5 relative (both precisions of the
+    hierarchy; the observed errors are printed), true residual <= 1e-8
+    recomputed on the host; and against the GPU's own single solve."""
     from paper_2112_12397_amd import solver_from_system
     s = c1
+    pc = _c1_oracle(s)
     sol = solver_from_system(s, precision=precision)
     B = rhs_batch(s, k=k)                      # norms 1e-2 .. 1e2
     Bt = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
@@ -39,38 +55,55 @@ def test_batch_matches_single(torch, c1, k, precision):
     assert status == "FPC_OK"
     J = s.jacobian()
     Xn = X.cpu().numpy()
+    errs = []
     for c in range(k):
+        xo, io = oracle.fgmres(pc.matvec, pc.apply, B[:, c], rtol=1e-8,
+                               ortho="cgs2")
         x1, i1 = sol.solve(Bt[c].contiguous())
         r = np.linalg.norm(B[:, c] - J @ Xn[c]) / np.linalg.norm(B[:, c])
         assert infos[c]["converged"] == 1 and r <= 1e-8, (c, r, infos[c])
+        assert abs(infos[c]["iterations"] - io.iterations) <= 2, \
+            (c, infos[c]["iterations"], io.iterations)
+        errs.append(_rel(Xn[c], xo))
+        assert errs[-1] <= 1e-5, (c, errs[-1])
         assert abs(infos[c]["iterations"] - i1["iterations"]) <= 2
         assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-5
+    print(f"batch {precision} k={k}: max |x - x_oracle| / |x_oracle| = "
+          f"{max(errs):.2e}")
 
 
 def test_batch_long_cycle(torch):
-    """Batched FGMRES(63) to 1e-10 on the long-row system with random
-    right-hand sides: the first cycle runs all 63 steps, so the batched
-    Gram-Schmidt passes go up to 63 basis vectors per column (past 48 the
-    axpy and dot passes run separately); every column against its single
-    solve.  (These right-hand sides stall near 5e-12 in the oracle too.)"""
+    """Batched FGMRES(63) to 1e-9 on the long-row system with random
+    right-hand sides: the oracle needs 56-57 steps in one cycle, so the
+    batched Gram-Schmidt passes go past 48 basis vectors per column (where
+    the axpy and dot passes run separately); every column against the
+    oracle (CGS2) and its single solve.  (Closer to this system's attainable
+    accuracy, about 5e-12, counts become rounding-sensitive: at 1e-10 the
+    oracle's CGS2 and MGS counts already differ by up to 5.)"""
     from paper_2112_12397_amd import solver_from_system
     from systems_extra import wide_system
     s = wide_system()
     sol = solver_from_system(s, restart=63, amg={"max_coarse": 90})
+    pc = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p, coords=s.coords,
+                             amg_opts=oracle.AMGOptions(max_coarse=90))
     rng = np.random.default_rng(21)
     B = rng.standard_normal((s.N, 4)) * np.array([1e-2, 1.0, 1e2, 3.0])
     Bt = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
-    X, infos, status = sol.solve_batch(Bt, rtol=1e-10)
+    X, infos, status = sol.solve_batch(Bt, rtol=1e-9)
     assert status == "FPC_OK"
     J = s.jacobian()
     Xn = X.cpu().numpy()
     for c in range(4):
-        x1, i1 = sol.solve(Bt[c].contiguous(), rtol=1e-10)
+        xo, io = oracle.fgmres(pc.matvec, pc.apply, B[:, c], rtol=1e-9,
+                               restart=63, ortho="cgs2")
+        x1, i1 = sol.solve(Bt[c].contiguous(), rtol=1e-9)
         r = np.linalg.norm(B[:, c] - J @ Xn[c]) / np.linalg.norm(B[:, c])
-        assert infos[c]["converged"] == 1 and r <= 1e-10, (c, r, infos[c])
-        assert i1["iterations"] >= 63           # a full first cycle
+        assert infos[c]["converged"] == 1 and r <= 1e-9, (c, r, infos[c])
+        assert i1["iterations"] > 48            # past 48 basis vectors
+        assert abs(infos[c]["iterations"] - io.iterations) <= 2
         assert abs(infos[c]["iterations"] - i1["iterations"]) <= 2
-        assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-7
+        assert _rel(Xn[c], xo) <= 1e-6
+        assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-6
 
 
 def test_batch_zero_column_and_mask(torch, c1):
@@ -91,7 +124,9 @@ def test_adjoint_gradients_c5(torch):
     """48^3 with 4 full fractures: gradients of 0.5 |p - p_obs|^2 with respect
     to log transmissibility on 20 seeded faces against central differences
     (h = 1e-6, 80-bit) and against the oracle's adjoint gradient; the
-    gradient with respect to b is the adjoint solution."""
+    gradient with respect to b is the adjoint solution.  The forward solve
+    to 1e-8 also matches the oracle's FGMRES (iterations within 2, solution
+    within 1e-5)."""
     from paper_2112_12397_amd import solver_from_system
     from paper_2112_12397_amd.autograd import SolveFn
     s = fracgen.make_config("c5")
@@ -117,6 +152,12 @@ def test_adjoint_gradients_c5(torch):
         (err / np.abs(fd)).max()
     # oracle adjoint (its own forward and adjoint FGMRES)
     pc = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p, coords=s.coords)
+    # the forward solve at the workload tolerance against the oracle's
+    x8, i8 = sol.solve(torch.tensor(s.b, device="cuda"))
+    xo8, io8 = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8, ortho="cgs2")
+    print(f"c5: GPU {i8['iterations']} iterations, oracle {io8.iterations}")
+    assert abs(i8["iterations"] - io8.iterations) <= 2
+    assert _rel(x8.cpu().numpy(), xo8) <= 1e-5
     xo, _ = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-11)
     L, gx = oracle.adjoint.loss_and_grad_x(xo, s.n_u, s.n_t, p_obs)
     lam, _ = oracle.fgmres(pc.matvec_T, pc.apply_T, gx, rtol=1e-11)

@@ -465,3 +465,41 @@ def test_no_fracture_faces(torch):
     assert info["converged"] == 1 and info["true_rel_residual"] <= 1e-8
     assert abs(info["iterations"] - io.iterations) <= 2
     assert _rel(x.cpu().numpy(), xo) <= 1e-5
+
+
+def test_dense_inverse_pivoting(torch):
+    """The coarsest-level inverse (Gauss-Jordan with partial pivoting in
+    256-wide panels) on matrices that need row exchanges: a tiny but nonzero
+    leading pivot, a row permutation of a diagonally dominant matrix (zero
+    diagonal entries), a random non-symmetric matrix over three panels;
+    against LAPACK's LU (scipy.linalg.lu_factor / lu_solve).  A singular
+    matrix is reported."""
+    import scipy.linalg as sl
+    from paper_2112_12397_amd.fracprec import FpcError
+    s, pc, sol = _get("tiny_plane")
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((300, 300))
+    A[0, 0] = 1e-13
+    Pm = np.eye(130)[rng.permutation(130)] @ (
+        4.0 * np.eye(130) + 0.1 * rng.standard_normal((130, 130)))
+    B = rng.standard_normal((600, 600)) + 10.0 * np.eye(600)
+    for M in (A, Pm, B):
+        ref = sl.lu_solve(sl.lu_factor(M), np.eye(len(M)))
+        inv = sol.dense_inverse(torch.tensor(M, device="cuda")).cpu().numpy()
+        assert _rel(inv, ref) <= 1e-10
+    with pytest.raises(FpcError, match="FPC_ERR_SINGULAR_BLOCK"):
+        sol.dense_inverse(torch.tensor(np.ones((70, 70)), device="cuda"))
+
+
+@pytest.mark.parametrize("name", ["tiny_slip_cross", "c1", "tiny_open_cross"])
+def test_pressure_factor_description(torch, name):
+    """The reported nested-dissection factorization is consistent with the
+    matrix: at least one front and level, no front with more pivots than
+    faces, at least one factor entry per face, and the solve reads the
+    factor at least once."""
+    s, pc, sol = _get(name)
+    d = sol.pressure_info()
+    assert d["n_fronts"] >= 1 and d["n_levels"] >= 1
+    assert 1 <= d["max_pivots"] <= s.n_p
+    assert d["factor_entries"] >= s.n_p
+    assert d["solve_bytes"] >= 8 * d["factor_entries"]
