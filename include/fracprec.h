@@ -202,7 +202,10 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J);
  * aggregates, tentative prolongators and apply layouts of the previous
  * hierarchy are reused (they depend on patterns and coordinates only) and
  * everything else is recomputed, so the result equals fpc_setup on the new
- * system; otherwise the hierarchy is rebuilt from scratch.  Errors as
+ * system; otherwise the hierarchy is rebuilt from scratch.  Likewise the
+ * nested-dissection analysis of the pressure block is kept when its pattern
+ * is unchanged, and its factor too when its values are bitwise unchanged
+ * (with Q2 empty and the same T: always).  fpc_setup reuses nothing.  Errors as
  * fpc_setup; on error the handle is left not set up (FPC_ERR_STATE). */
 fpc_status fpc_update_values(fpc_handle* h, const fpc_block_system* J);
 

@@ -102,10 +102,11 @@ int64_t round64(int64_t n) { return ((n + 63) / 64) * 64; }
 // ------------------------------------------------------------- p-block
 // Exact solve of S~2 = T - FS(Q2, S1, Q1) (T - diag(S_K) in t-u-p and M2*
 // with open faces, T otherwise): nested-dissection ordering and symbolic
-// analysis of T's pattern, then the multifrontal factorization.  A call on
-// the pattern of the previous factorization keeps its analysis; on the same
-// values too, it keeps the factor.
-void build_psolve(fpc_handle* h) {
+// analysis of T's pattern, then the multifrontal factorization.  With
+// `reuse` (numeric re-setup), a matrix with the pattern of the previous
+// factorization keeps its analysis, and one with the same values too keeps
+// the factor; without it everything is built.
+void build_psolve(fpc_handle* h, bool reuse) {
   PSolve& ps = h->ps;
   const int64_t n = h->n_p;
   hipStream_t s = h->stream;
@@ -117,7 +118,8 @@ void build_psolve(fpc_handle* h) {
     return;
   }
   const bool same_pat =
-      ps.n == n && ps.in_col.n == (size_t)std::max<int64_t>(T.nnz, 1) &&
+      reuse && ps.n == n &&
+      ps.in_col.n == (size_t)std::max<int64_t>(T.nnz, 1) &&
       same_pattern(ps.in_rp.p, ps.in_col.p, T.rowptr.p, T.col.p, n, T.nnz, s);
   if (same_pat && ps.in_val.p && ps.has_sk == fs &&
       same_values(ps.in_val.p, T.val.p, T.nnz, s) &&
@@ -995,7 +997,9 @@ void upload_blocks(fpc_handle* h, const fpc_block_system* J) {
 // Alg 3.3 cpt_tup / Alg 3.1 cpt_tpu on the uploaded blocks.  `prev`: the
 // previous hierarchy, whose pattern-only parts are reused when the level-0
 // block pattern is unchanged.
-void construct(fpc_handle* h, Hierarchy* prev, double t0) {
+// update != 0: a numeric re-setup (fpc_update_values), which may keep the
+// pattern-only parts of the previous construction; a setup builds everything.
+void construct(fpc_handle* h, Hierarchy* prev, double t0, bool update) {
   hipStream_t s = h->stream;
   const int64_t nu = h->n_u, nt = h->n_t, np = h->n_p;
   h->has_q2 = h->Q2.nnz > 0;
@@ -1044,7 +1048,7 @@ void construct(fpc_handle* h, Hierarchy* prev, double t0) {
   }
   h->reused_hierarchy = prev != nullptr;
   const double t2 = now_s();
-  build_psolve(h);
+  build_psolve(h, update);
   const double t3 = now_s();
   build_hierarchy(h, std::move(S1), prev);
   const double t4 = now_s();
@@ -1227,7 +1231,7 @@ fpc_status fpc_setup(fpc_handle* h, const fpc_block_system* J) {
       check_finite(h->coords.p, nu, h->flags.p, s);
     }
     check_flags(h, "input");
-    construct(h, nullptr, t0);
+    construct(h, nullptr, t0, false);
   });
 }
 
@@ -1257,7 +1261,7 @@ fpc_status fpc_update_values(fpc_handle* h, const fpc_block_system* J) {
     check_flags(h, "input");
     Hierarchy prev = std::move(h->amg);
     h->amg = Hierarchy();
-    construct(h, &prev, t0);
+    construct(h, &prev, t0, true);
   });
 }
 

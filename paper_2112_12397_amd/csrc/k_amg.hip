@@ -1250,13 +1250,18 @@ void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
 // rows below the diagonal receive the same updates as in Gauss-Jordan, so
 // these are the pivots Gauss-Jordan meets on the swapped matrix.  piv[k] =
 // the row of D to exchange with row o + k (LAPACK convention, in order).  A
-// column without a nonzero flags FLAG_SINGULAR.
+// column without a nonzero flags FLAG_SINGULAR.  Right-looking and blocked:
+// slabs of kLuSlab columns are eliminated column by column (exchanges over
+// the whole panel width), then the rows of the slab are solved with its unit
+// lower triangle and the rest of the panel takes one rank-kLuSlab update, so
+// the panel is read and written once per slab rather than once per column.
+constexpr int kLuSlab = 8;
 __global__ __launch_bounds__(1024) void k_panel_pivots(
     const double* __restrict__ D, int64_t n, int64_t o, int nb,
     double* __restrict__ P, int32_t* __restrict__ piv, int* flags) {
   __shared__ double s_v[16];
   __shared__ int s_i[16];
-  __shared__ double s_piv_row[256];
+  __shared__ double s_l[kLuSlab][kLuSlab];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t m = n - o;
   for (int64_t idx = t; idx < m * nb; idx += 1024) {
@@ -1264,14 +1269,133 @@ __global__ __launch_bounds__(1024) void k_panel_pivots(
     P[idx] = D[(o + r) * n + o + c];
   }
   __syncthreads();
-  for (int k = 0; k < nb; ++k) {
+  for (int s0 = 0; s0 < nb; s0 += kLuSlab) {
+    const int s1 = min(s0 + kLuSlab, nb);
+    for (int k = s0; k < s1; ++k) {
+      double bv = -1.0;
+      int bi = k;
+      for (int64_t r = k + t; r < m; r += 1024) {
+        const double a = fabs(P[r * nb + k]);
+        if (a > bv) {
+          bv = a;
+          bi = (int)r;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_v[w] = bv;
+        s_i[w] = bi;
+      }
+      __syncthreads();
+      if (t == 0) {
+        for (int q = 1; q < 16; ++q)
+          if (s_v[q] > s_v[0] || (s_v[q] == s_v[0] && s_i[q] < s_i[0])) {
+            s_v[0] = s_v[q];
+            s_i[0] = s_i[q];
+          }
+        piv[k] = (int32_t)(o + s_i[0]);
+        if (!(s_v[0] > 0.0) || !isfinite(s_v[0]))
+          atomicOr(&flags[FLAG_SINGULAR], 1);
+      }
+      __syncthreads();
+      const int p = s_i[0];
+      const bool bad = !(s_v[0] > 0.0) || !isfinite(s_v[0]);
+      if (p != k)
+        for (int c = t; c < nb; c += 1024) {
+          const double x = P[(int64_t)k * nb + c];
+          P[(int64_t)k * nb + c] = P[(int64_t)p * nb + c];
+          P[(int64_t)p * nb + c] = x;
+        }
+      __syncthreads();
+      // column k of L below the pivot, rank-1 update inside the slab
+      const double inv = bad ? 0.0 : 1.0 / P[(int64_t)k * nb + k];
+      for (int64_t r = k + 1 + t; r < m; r += 1024) {
+        double* __restrict__ row = P + r * nb;
+        const double l = row[k] * inv;
+        row[k] = l;
+        for (int c = k + 1; c < s1; ++c) row[c] -= l * P[(int64_t)k * nb + c];
+      }
+      __syncthreads();
+    }
+    if (s1 >= nb) break;
+    // rows s0 .. s1 - 1 of U right of the slab: unit lower solve
+    if (t < kLuSlab * kLuSlab) {
+      const int i = t / kLuSlab, q = t % kLuSlab;
+      s_l[i][q] = (s0 + i < s1 && q < i) ? P[(int64_t)(s0 + i) * nb + s0 + q]
+                                         : 0.0;
+    }
+    __syncthreads();
+    for (int c = s1 + t; c < nb; c += 1024) {
+      double u[kLuSlab];
+#pragma unroll
+      for (int i = 0; i < kLuSlab; ++i) {
+        double v = s0 + i < s1 ? P[(int64_t)(s0 + i) * nb + c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) v -= s_l[i][q] * u[q];
+        u[i] = v;
+        if (s0 + i < s1) P[(int64_t)(s0 + i) * nb + c] = v;
+      }
+    }
+    __syncthreads();
+    // rank-(s1 - s0) update of the rows below the slab
+    const int wr = nb - s1;
+    for (int64_t idx = t; idx < (m - s1) * wr; idx += 1024) {
+      const int64_t r = s1 + idx / wr;
+      const int c = s1 + (int)(idx % wr);
+      double* __restrict__ row = P + r * nb;
+      double v = row[c];
+      for (int q = s0; q < s1; ++q) v -= row[q] * P[(int64_t)q * nb + c];
+      row[c] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// The same pivots from three kernels per slab when the panel has at most
+// kLuRows rows below the slab's first column: the slab's columns are
+// eliminated in LDS by one workgroup (k_lu_slab), then its exchanges and the
+// unit lower solve reach the columns to its right (k_lu_swap_u12, thread per
+// column) and the rows below take the rank-kLuSlab update across the whole
+// grid (k_lu_trail).  The column-by-column steps then cost LDS latency only.
+constexpr int kLuRows = 2048;
+__global__ void k_copy_panel(const double* __restrict__ D, int64_t n,
+                             int64_t o, int nb, double* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (n - o) * nb) return;
+  const int64_t r = idx / nb, c = idx - r * nb;
+  P[idx] = D[(o + r) * n + o + c];
+}
+
+__global__ __launch_bounds__(1024) void k_lu_slab(double* __restrict__ P,
+                                                  int64_t m, int nb, int s0,
+                                                  int s1, int64_t o,
+                                                  int32_t* __restrict__ piv,
+                                                  int* flags) {
+  __shared__ double S[kLuRows][kLuSlab];
+  __shared__ double s_v[16];
+  __shared__ int s_i[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rows = (int)(m - s0), ws = s1 - s0;
+  for (int idx = t; idx < rows * kLuSlab; idx += 1024) {
+    const int r = idx / kLuSlab, q = idx % kLuSlab;
+    S[r][q] = q < ws ? P[(int64_t)(s0 + r) * nb + s0 + q] : 0.0;
+  }
+  __syncthreads();
+  for (int q = 0; q < ws; ++q) {
     double bv = -1.0;
-    int bi = k;
-    for (int64_t r = k + t; r < m; r += 1024) {
-      const double a = fabs(P[r * nb + k]);
+    int bi = q;
+    for (int r = q + t; r < rows; r += 1024) {
+      const double a = fabs(S[r][q]);
       if (a > bv) {
         bv = a;
-        bi = (int)r;
+        bi = r;
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -1288,37 +1412,76 @@ __global__ __launch_bounds__(1024) void k_panel_pivots(
     }
     __syncthreads();
     if (t == 0) {
-      for (int q = 1; q < 16; ++q)
-        if (s_v[q] > s_v[0] || (s_v[q] == s_v[0] && s_i[q] < s_i[0])) {
-          s_v[0] = s_v[q];
-          s_i[0] = s_i[q];
+      for (int u = 1; u < 16; ++u)
+        if (s_v[u] > s_v[0] || (s_v[u] == s_v[0] && s_i[u] < s_i[0])) {
+          s_v[0] = s_v[u];
+          s_i[0] = s_i[u];
         }
-      piv[k] = (int32_t)(o + s_i[0]);
+      piv[s0 + q] = (int32_t)(o + s0 + s_i[0]);
       if (!(s_v[0] > 0.0) || !isfinite(s_v[0]))
         atomicOr(&flags[FLAG_SINGULAR], 1);
     }
     __syncthreads();
     const int p = s_i[0];
     const bool bad = !(s_v[0] > 0.0) || !isfinite(s_v[0]);
-    if (p != k)
-      for (int c = t; c < nb; c += 1024) {
-        const double x = P[(int64_t)k * nb + c];
-        P[(int64_t)k * nb + c] = P[(int64_t)p * nb + c];
-        P[(int64_t)p * nb + c] = x;
-      }
+    if (p != q && t < kLuSlab) {
+      const double x = S[q][t];
+      S[q][t] = S[p][t];
+      S[p][t] = x;
+    }
     __syncthreads();
-    for (int c = t; c < nb; c += 1024) s_piv_row[c] = P[(int64_t)k * nb + c];
-    __syncthreads();
-    const double inv = bad ? 0.0 : 1.0 / s_piv_row[k];
-    // rows below the pivot: l = a_rk / a_kk, a_rc -= l a_kc (c > k)
-    for (int64_t r = k + 1 + w; r < m; r += 16) {
-      double* __restrict__ row = P + r * nb;
-      const double l = row[k] * inv;
-      if (l == 0.0) continue;
-      for (int c = k + 1 + lane; c < nb; c += 64) row[c] -= l * s_piv_row[c];
+    const double inv = bad ? 0.0 : 1.0 / S[q][q];
+    for (int r = q + 1 + t; r < rows; r += 1024) {
+      const double l = S[r][q] * inv;
+      S[r][q] = l;
+#pragma unroll
+      for (int c = 0; c < kLuSlab; ++c)
+        if (c > q && c < ws) S[r][c] -= l * S[q][c];
     }
     __syncthreads();
   }
+  for (int idx = t; idx < rows * ws; idx += 1024) {
+    const int r = idx / ws, q = idx % ws;
+    P[(int64_t)(s0 + r) * nb + s0 + q] = S[r][q];
+  }
+}
+
+// columns c >= s1 of the panel: the slab's exchanges in order, then the
+// unit lower solve of its rows
+__global__ void k_lu_swap_u12(double* __restrict__ P, int64_t m, int nb,
+                              int s0, int s1, int64_t o,
+                              const int32_t* __restrict__ piv) {
+  const int c = s1 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= nb) return;
+  for (int k = s0; k < s1; ++k) {
+    const int64_t p = piv[k] - o;
+    if (p == k) continue;
+    const double x = P[(int64_t)k * nb + c];
+    P[(int64_t)k * nb + c] = P[p * nb + c];
+    P[p * nb + c] = x;
+  }
+  double u[kLuSlab];
+#pragma unroll
+  for (int i = 0; i < kLuSlab; ++i) {
+    if (s0 + i >= s1) break;
+    double v = P[(int64_t)(s0 + i) * nb + c];
+    for (int q = 0; q < i; ++q) v -= P[(int64_t)(s0 + i) * nb + s0 + q] * u[q];
+    u[i] = v;
+    P[(int64_t)(s0 + i) * nb + c] = v;
+  }
+  (void)m;
+}
+
+// rows r >= s1, columns c >= s1: P[r][c] -= sum_q L[r][q] U[q][c]
+__global__ void k_lu_trail(double* __restrict__ P, int64_t m, int nb, int s0,
+                           int s1) {
+  const int c = s1 + (int)(blockIdx.x * 64 + (threadIdx.x & 63));
+  const int64_t r = s1 + (int64_t)blockIdx.y * 16 + (threadIdx.x >> 6);
+  if (c >= nb || r >= m) return;
+  double* __restrict__ row = P + r * nb;
+  double v = row[c];
+  for (int q = s0; q < s1; ++q) v -= row[q] * P[(int64_t)q * nb + c];
+  row[c] = v;
 }
 
 // Row exchanges of one panel applied in order to whole rows (thread per
@@ -1364,8 +1527,26 @@ void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s) {
   for (int64_t o = 0; o < n; o += NB) {
     const int64_t nb = std::min<int64_t>(NB, n - o);
     // partial pivoting: choose the panel's pivot rows, exchange them
-    k_panel_pivots<<<1, 1024, 0, s>>>(D, n, o, (int)nb, panel.p, piv.p + o,
-                                      flags);
+    const int64_t m = n - o;
+    if (m <= kLuRows) {
+      k_copy_panel<<<grid_for(m * nb, 256), 256, 0, s>>>(D, n, o, (int)nb,
+                                                         panel.p);
+      for (int s0 = 0; s0 < nb; s0 += kLuSlab) {
+        const int s1 = (int)std::min<int64_t>(s0 + kLuSlab, nb);
+        k_lu_slab<<<1, 1024, 0, s>>>(panel.p, m, (int)nb, s0, s1, o,
+                                     piv.p + o, flags);
+        if (s1 < nb) {
+          k_lu_swap_u12<<<grid_for(nb - s1, 64), 64, 0, s>>>(
+              panel.p, m, (int)nb, s0, s1, o, piv.p + o);
+          const dim3 tg((unsigned)((nb - s1 + 63) / 64),
+                        (unsigned)((m - s1 + 15) / 16));
+          k_lu_trail<<<tg, 1024, 0, s>>>(panel.p, m, (int)nb, s0, s1);
+        }
+      }
+    } else {
+      k_panel_pivots<<<1, 1024, 0, s>>>(D, n, o, (int)nb, panel.p, piv.p + o,
+                                        flags);
+    }
     k_swap_rows<<<grid_for(n, 256), 256, 0, s>>>(D, n, o, (int)nb, piv.p + o);
     FPC_LAUNCH_CHECK();
     double* Dkk = D + o * n + o;

@@ -200,6 +200,32 @@ __device__ inline void epi_row(const Epi& e, int64_t row, const T (&acc)[NV][BR]
     }
 }
 
+// The loads and the stores of epi_row as two steps, so that a kernel can
+// issue the loads before its product and keep the inputs in registers.
+template <typename T, int BR, int NV, class Epi>
+__device__ inline void epi_load_row(const Epi& e, int64_t row,
+                                    T (&in)[NV][BR][Epi::NIN]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+      const int64_t dof = row * BR + i;
+      e.load(dof, dof * NV + v, in[v][i]);
+    }
+}
+template <typename T, int BR, int NV, class Epi>
+__device__ inline void epi_store_row(const Epi& e, int64_t row,
+                                     const T (&acc)[NV][BR],
+                                     const T (&in)[NV][BR][Epi::NIN]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+      const int64_t dof = row * BR + i;
+      e.store(dof, dof * NV + v, acc[v][i], in[v][i]);
+    }
+}
+
 // One column v of one block row.
 template <typename T, int BR, int NV, class Epi>
 __device__ inline void epi_col(const Epi& e, int64_t row, int v, const T (&acc)[BR]) {
@@ -301,6 +327,11 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int i = 0; i < BR; ++i) acc[v][i] = T(0);
+  // the epilogue's inputs do not depend on the product: wavefront 0 fetches
+  // them first, so they arrive while the slice streams in
+  const bool epi_lane = half == 0 && valid && row < A.nrows;
+  T pre[NV][BR][Epi::NIN];
+  if (epi_lane) epi_load_row<T, BR, NV>(epi, row, pre);
   if (valid) {
     const int64_t base = A.slice_ptr[slice];
     const int maxlen = (int)((A.slice_ptr[slice + 1] - base) / kSliceH);
@@ -365,30 +396,39 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
       for (int i = 0; i < BR; ++i) red[pair][half - 1][lane][v * BR + i] = acc[v][i];
   }
   __syncthreads();
-  if (half > 0 || !valid || row >= A.nrows) return;
+  if (!epi_lane) return;
 #pragma unroll
   for (int h = 0; h < SP - 1; ++h)
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int i = 0; i < BR; ++i) acc[v][i] += red[pair][h][lane][v * BR + i];
-  epi_row<T, BR, NV>(epi, row, acc);
+  epi_store_row<T, BR, NV>(epi, row, acc, pre);
 }
 
 // Many columns (interleaved right-hand sides): one thread per (block row,
 // CPL consecutive columns); a wavefront covers 64 CPL / NV consecutive block
 // rows of one slice, so the columns of one x row are read as one contiguous
 // segment and every matrix block is broadcast to the NV / CPL lanes of its
-// row.  For 3x3 blocks from 16 columns on a lane takes two columns, which
-// halves the matrix loads per column (larger blocks keep one column per
-// lane: their registers would not hold two).
-template <int BR, int BC, int NV>
-constexpr int sell_cols_cpl() { return (NV >= 16 && BR * BC <= 9) ? 2 : 1; }
+// row.  For 3x3 blocks from 16 columns on a lane takes 16 bytes of columns
+// (four FP32 or two FP64), fetched as one load per x row, which also cuts
+// the matrix loads per column (larger blocks keep one column per lane:
+// their registers would not hold more).
+template <typename T, int BR, int BC, int NV>
+constexpr int sell_cols_cpl() {
+  return (NV >= 16 && BR * BC <= 9) ? (int)(16 / sizeof(T)) : 1;
+}
+
+// CPL consecutive elements of one x row as a single (16-byte) load
+template <typename T, int CPL>
+struct alignas(sizeof(T) * CPL) XPack {
+  T v[CPL];
+};
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
                                                    Epi epi) {
-  constexpr int CPL = sell_cols_cpl<BR, BC, NV>();
+  constexpr int CPL = sell_cols_cpl<T, BR, BC, NV>();
   constexpr int LPR = NV / CPL;  // lanes per block row
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -415,10 +455,18 @@ __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
     const int64_t c = (BR == 3 && BC == 3) ? slot_col(raw) : raw;
     const T* __restrict__ vb = vp + (int64_t)k * kSliceH * (BR * BC);
     T xv[BC][CPL];
+    if constexpr (CPL > 1) {
 #pragma unroll
-    for (int j = 0; j < BC; ++j)
+      for (int j = 0; j < BC; ++j) {
+        const XPack<T, CPL> q = *reinterpret_cast<const XPack<T, CPL>*>(
+            ld.x + (c * BC + j) * NV + v0);
 #pragma unroll
-      for (int u = 0; u < CPL; ++u) xv[j][u] = ld(c * BC + j, v0 + u);
+        for (int u = 0; u < CPL; ++u) xv[j][u] = q.v[u];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < BC; ++j) xv[j][0] = ld(c * BC + j, v0);
+    }
     T m[BR * BC];
     if constexpr (BR == 3 && BC == 3) {
       load33(vb, slot_class(raw), m);
@@ -445,7 +493,7 @@ void launch_sell(const Sell<T>& A, Load ld, Epi epi, hipStream_t s) {
         (unsigned)((A.nslices + 4 / kSliceSplit - 1) / (4 / kSliceSplit));
     k_sell_rows<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   } else {
-    const int64_t waves = A.nslices * (NV / sell_cols_cpl<BR, BC, NV>());
+    const int64_t waves = A.nslices * (NV / sell_cols_cpl<T, BR, BC, NV>());
     const unsigned grid = (unsigned)((waves + 3) / 4);
     k_sell_cols<T, BR, BC, NV, Load, Epi><<<grid, 256, 0, s>>>(view(A), ld, epi);
   }

@@ -118,6 +118,11 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError(
             f"{path} is missing: build it with __graft_entry__.build() "
             "(hipcc, gfx950)")
+    # torch ships its own HIP runtime (soname libamdhip64.so.7, opened by
+    # torch under another name): loaded first, it is the one this library
+    # binds to, so both share one runtime, its streams and allocations.
+    # Loading this library first would bring in a second runtime.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
     H = C.c_void_p
