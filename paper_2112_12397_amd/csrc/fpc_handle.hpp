@@ -164,6 +164,13 @@ struct PSolve {
   DevBuf<double> xp, contrib;            // single column
   int KB = 0;                            // batch columns of the buffers below
   DevBuf<double> bpB, xpB, contribB;
+  // numeric phase per level: fronts inverted in LDS (small), larger fronts
+  // (big, host list), 64 x 64 tiles (front, ti, tj) of W and of the Schur
+  // complements; host offsets of the front matrices
+  std::vector<int64_t> small_off, w_off, s_off, hF;
+  std::vector<std::vector<int32_t>> big;
+  DevBuf<int32_t> small;
+  DevBuf<int4> w_items, s_items;
   // the matrix the factor was computed from, for reuse on unchanged input
   DevBuf<int64_t> in_rp;
   DevBuf<int32_t> in_col;

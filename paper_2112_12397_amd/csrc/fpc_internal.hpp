@@ -273,9 +273,11 @@ void power_start(int64_t n_nodes, int bs, int key_stride,
                  const int32_t* node_rank, double* x, hipStream_t s);
 void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s);
 // In-place inverse of an n x n (n multiple of 64) row-major matrix by
-// Gauss-Jordan with partial pivoting; flags[FLAG_SINGULAR] for a column
-// without a nonzero pivot candidate.
-void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s);
+// Gauss-Jordan with partial pivoting (flags[FLAG_SINGULAR] for a column
+// without a nonzero pivot candidate), or with pivot = false on the diagonal
+// of an SPD matrix (flags[FLAG_NOT_SPD] for a nonpositive pivot).
+void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s,
+                bool pivot = true);
 // D (npad x npad) = [A 0; 0 I] for a row-major n x n A (device)
 void dense_pad(const double* A, int64_t n, int64_t npad, double* D,
                hipStream_t s);

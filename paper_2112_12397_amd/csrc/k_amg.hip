@@ -1515,7 +1515,7 @@ __global__ void k_unswap_cols(double* D, int64_t n,
   }
 }
 
-void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s) {
+void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s, bool pivot) {
   if (n % GT) throw Error(FPC_ERR_ARG, "gj_inverse: size not a multiple of 64");
   constexpr int64_t NB = 256;
   DevBuf<int32_t> piv(n);
@@ -1528,7 +1528,9 @@ void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s) {
     const int64_t nb = std::min<int64_t>(NB, n - o);
     // partial pivoting: choose the panel's pivot rows, exchange them
     const int64_t m = n - o;
-    if (m <= kLuRows) {
+    if (!pivot) {
+      // SPD: diagonal pivots, nonpositive ones flagged by the tile kernel
+    } else if (m <= kLuRows) {
       k_copy_panel<<<grid_for(m * nb, 256), 256, 0, s>>>(D, n, o, (int)nb,
                                                          panel.p);
       for (int s0 = 0; s0 < nb; s0 += kLuSlab) {
@@ -1547,10 +1549,12 @@ void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s) {
       k_panel_pivots<<<1, 1024, 0, s>>>(D, n, o, (int)nb, panel.p, piv.p + o,
                                         flags);
     }
-    k_swap_rows<<<grid_for(n, 256), 256, 0, s>>>(D, n, o, (int)nb, piv.p + o);
+    if (pivot)
+      k_swap_rows<<<grid_for(n, 256), 256, 0, s>>>(D, n, o, (int)nb,
+                                                  piv.p + o);
     FPC_LAUNCH_CHECK();
     double* Dkk = D + o * n + o;
-    gj_inverse64(Dkk, nb, n, /*spd=*/0, flags, s);  // Dkk <- Dkk^-1
+    gj_inverse64(Dkk, nb, n, /*spd=*/pivot ? 0 : 1, flags, s);  // Dkk^-1
     if (nb == n) break;
     const SkipMap skip{o, nb};
     FPC_HIP(hipMemcpyAsync(prow.p, D + o * n, nb * n * sizeof(double),
@@ -1568,7 +1572,8 @@ void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s) {
     gemm_f64(n - nb, nb, (int)nb, -1.0, 0.0, pcol.p, nb, Dkk, n, D + o, n,
              skip, none, s);
   }
-  k_unswap_cols<<<grid_for(n, 256), 256, 0, s>>>(D, n, piv.p);
+  if (pivot)
+    k_unswap_cols<<<grid_for(n, 256), 256, 0, s>>>(D, n, piv.p);
   FPC_LAUNCH_CHECK();
   FPC_HIP(hipStreamSynchronize(s));
 }

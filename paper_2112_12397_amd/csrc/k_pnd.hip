@@ -16,9 +16,11 @@
 // its own m faces (pivots) and the k faces of its domain's boundary (faces of
 // ancestor separators adjacent to the domain).  The front is assembled from
 // the separator's rows of the matrix and the children's Schur complements;
-// Gauss-Jordan on [F11 | F12] (partial pivoting unless the block is SPD)
-// leaves [F11^-1 | F11^-1 F12] in the first m rows, and
-// F22 - F21 F11^-1 F12 in the last k rows goes to the parent.
+// F11 is inverted by Gauss-Jordan (in LDS up to 128 pivots, else by the
+// tiled dense inverse of the coarsest AMG level; partial pivoting unless the
+// block is SPD), W = F11^-1 F12 replaces F12, and F22 - F21 W (exactly
+// symmetric) goes to the parent.  The first m rows then hold
+// [F11^-1 | F11^-1 F12].
 //
 // Solve (levels of the front tree: leaves first).  Forward: b^ = b_S minus
 // the contributions of descendant fronts, c_S = F11^-1 b^, contribution
@@ -507,13 +509,11 @@ __device__ void nd_argmax(double v, int idx, double* s_v, int* s_i,
   __syncthreads();
 }
 
-// Fronts [f0, f0 + gridDim.x) of one level: assembly, Gauss-Jordan on
-// [F11 | F12], Schur complement into the F22 block.  sk (nullable) is
-// subtracted from the diagonal of the matrix (S~2 = T - S_K).  spd: pivots
-// taken on the diagonal, a nonpositive one flags FLAG_NOT_SPD; otherwise
-// partial pivoting, a pivot at or below 1e-14 of the block's largest
-// entry flags FLAG_SINGULAR.
-__global__ __launch_bounds__(kNdT) void k_nd_factor(
+// Assembly of the fronts [f0, f0 + gridDim.x) of one level: the separator's
+// rows of the matrix (sk, nullable, subtracted from the diagonal: S~2 = T -
+// S_K) with their mirror into F21, then the children's Schur complements,
+// one child after the other (deterministic).
+__global__ __launch_bounds__(kNdT) void k_nd_assemble(
     int32_t f0, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ sk,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ pos,
@@ -521,12 +521,8 @@ __global__ __launch_bounds__(kNdT) void k_nd_factor(
     const int32_t* __restrict__ f_k, const int64_t* __restrict__ f_F,
     const int64_t* __restrict__ f_bnd, const int32_t* __restrict__ bnd,
     const int64_t* __restrict__ ch_off, const int32_t* __restrict__ ch,
-    double* F, int spd, int* flags) {
-  __shared__ double s_col[kMaxPiv];
-  __shared__ int s_piv[kMaxPiv];
+    double* F, int* flags) {
   __shared__ int s_map[kMaxBnd];
-  __shared__ double s_rv[kNdT / 64];
-  __shared__ int s_ri[kNdT / 64];
   const int f = f0 + blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = kNdT / 64;
   const int m = f_m[f], k = f_k[f], ld = m + k, slo = f_slo[f], hi = slo + m;
@@ -586,40 +582,60 @@ __global__ __launch_bounds__(kNdT) void k_nd_factor(
     }
     __syncthreads();
   }
-  // scale for the singularity test: largest entry of F11
-  double amax, dummy_v;
-  int dummy_i;
-  {
-    double v = 0.0;
-    for (int64_t i = t; i < (int64_t)m * m; i += kNdT)
-      v = fmax(v, fabs(A[(i / m) * ld + (i % m)]));
-    nd_argmax(v, 0, s_rv, s_ri, &amax, &dummy_i);
-  }
-  // Gauss-Jordan on the first m rows, in place
+}
+
+// F11 <- F11^-1 in LDS for fronts with at most kLdsPiv pivots (list fl):
+// Gauss-Jordan, pivots on the diagonal when spd (a nonpositive one flags
+// FLAG_NOT_SPD), partial pivoting otherwise (a pivot at or below 1e-14 of
+// the block's largest entry flags FLAG_SINGULAR).
+constexpr int kLdsPiv = 128;
+__global__ __launch_bounds__(kNdT) void k_nd_inv_lds(
+    const int32_t* __restrict__ fl, const int32_t* __restrict__ f_m,
+    const int32_t* __restrict__ f_k, const int64_t* __restrict__ f_F,
+    double* F, int spd, int* flags) {
+  __shared__ double S[kLdsPiv * kLdsPiv];
+  __shared__ double s_col[kLdsPiv];
+  __shared__ int s_piv[kLdsPiv];
+  __shared__ double s_rv[kNdT / 64];
+  __shared__ int s_ri[kNdT / 64];
+  const int f = fl[blockIdx.x];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = kNdT / 64;
+  const int m = f_m[f], ld = m + f_k[f];
+  double* __restrict__ A = F + f_F[f];
+  double vmax = 0.0;
+  for (int i = wv; i < m; i += nw)
+    for (int j = lane; j < m; j += 64) {
+      const double x = A[(int64_t)i * ld + j];
+      S[i * m + j] = x;
+      vmax = fmax(vmax, fabs(x));
+    }
+  double amax, dv;
+  int di;
+  nd_argmax(vmax, 0, s_rv, s_ri, &amax, &di);
   for (int kk = 0; kk < m; ++kk) {
     int p = kk;
     if (!spd) {
       double bv = -1.0;
       int bi = kk;
       for (int i = kk + t; i < m; i += kNdT) {
-        const double a = fabs(A[(int64_t)i * ld + kk]);
-        if (a > bv) {
-          bv = a;
+        const double x = fabs(S[i * m + kk]);
+        if (x > bv) {
+          bv = x;
           bi = i;
         }
       }
-      nd_argmax(bv, bi, s_rv, s_ri, &dummy_v, &p);
+      nd_argmax(bv, bi, s_rv, s_ri, &dv, &p);
       if (p != kk) {
-        for (int j = t; j < ld; j += kNdT) {
-          const double x = A[(int64_t)kk * ld + j];
-          A[(int64_t)kk * ld + j] = A[(int64_t)p * ld + j];
-          A[(int64_t)p * ld + j] = x;
+        for (int j = t; j < m; j += kNdT) {
+          const double x = S[kk * m + j];
+          S[kk * m + j] = S[p * m + j];
+          S[p * m + j] = x;
         }
         __syncthreads();
       }
     }
     if (t == 0) s_piv[kk] = p;
-    for (int i = t; i < m; i += kNdT) s_col[i] = A[(int64_t)i * ld + kk];
+    for (int i = t; i < m; i += kNdT) s_col[i] = S[i * m + kk];
     __syncthreads();
     const double d = s_col[kk];
     const bool bad = spd ? !(d > 0.0) || !isfinite(d)
@@ -629,40 +645,123 @@ __global__ __launch_bounds__(kNdT) void k_nd_factor(
       return;  // uniform: every thread read the same pivot
     }
     const double inv = 1.0 / d;
-    for (int j = t; j < ld; j += kNdT)
-      A[(int64_t)kk * ld + j] = (j == kk ? 1.0 : A[(int64_t)kk * ld + j]) * inv;
+    for (int j = t; j < m; j += kNdT)
+      S[kk * m + j] = (j == kk ? 1.0 : S[kk * m + j]) * inv;
     __syncthreads();
     for (int i = wv; i < m; i += nw) {
       const double fi = s_col[i];
       if (i == kk || fi == 0.0) continue;
-      double* __restrict__ row = A + (int64_t)i * ld;
-      const double* __restrict__ prow = A + (int64_t)kk * ld;
-      for (int j = lane; j < ld; j += 64)
-        row[j] = (j == kk ? 0.0 : row[j]) - fi * prow[j];
+      for (int j = lane; j < m; j += 64)
+        S[i * m + j] = (j == kk ? 0.0 : S[i * m + j]) - fi * S[kk * m + j];
     }
     __syncthreads();
   }
-  // undo the row interchanges on the columns of F11^-1
   if (!spd)
     for (int kk = m - 1; kk >= 0; --kk) {
       const int p = s_piv[kk];
       if (p == kk) continue;
       for (int i = t; i < m; i += kNdT) {
-        const double x = A[(int64_t)i * ld + kk];
-        A[(int64_t)i * ld + kk] = A[(int64_t)i * ld + p];
-        A[(int64_t)i * ld + p] = x;
+        const double x = S[i * m + kk];
+        S[i * m + kk] = S[i * m + p];
+        S[i * m + p] = x;
       }
       __syncthreads();
     }
-  // Schur complement F22 - F21 (F11^-1 F12) in place
-  for (int64_t idx = t; idx < (int64_t)k * k; idx += kNdT) {
-    const int a = (int)(idx / k), b = (int)(idx % k);
-    const double* __restrict__ f21 = A + (int64_t)(m + a) * ld;
-    const double* __restrict__ w = A + m + b;
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += f21[j] * w[(int64_t)j * ld];
-    A[(int64_t)(m + a) * ld + m + b] -= acc;
+  for (int i = wv; i < m; i += nw)
+    for (int j = lane; j < m; j += 64) A[(int64_t)i * ld + j] = S[i * m + j];
+}
+
+// [F11 0; 0 I] (npad x npad) from a front, and F11^-1 back
+__global__ void k_nd_pad(const double* __restrict__ A, int ld, int m,
+                         int npad, double* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)npad * npad) return;
+  const int i = (int)(idx / npad), j = (int)(idx % npad);
+  P[idx] = (i < m && j < m) ? A[(int64_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+}
+__global__ void k_nd_unpad(const double* __restrict__ P, int npad, int m,
+                           double* __restrict__ A, int ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int i = (int)(idx / m), j = (int)(idx % m);
+  A[(int64_t)i * ld + j] = P[(int64_t)i * npad + j];
+}
+
+// 64 x 64 output tiles of the two front products, 256 threads with 4 x 4
+// outputs each, the inner dimension (the m pivots) in chunks of 16 through
+// LDS.  Item (f, ti, tj):
+//   kind 0: W = F11^-1 F12 into the F12 block, F12 read as the transpose of
+//           F21 (the two are assembled as exact mirrors);
+//   kind 1: F22 <- F22 - F21 W, tiles with ti <= tj only, each value written
+//           to both (a, b) and (b, a), so the complement passed to the parent
+//           is exactly symmetric.
+constexpr int kTile = 64, kTk = 16;
+template <int KIND>
+__global__ __launch_bounds__(256) void k_nd_tile(
+    const int4* __restrict__ items, const int32_t* __restrict__ f_m,
+    const int32_t* __restrict__ f_k, const int64_t* __restrict__ f_F,
+    double* F) {
+  __shared__ double As[kTk][kTile + 1];
+  __shared__ double Bs[kTk][kTile + 1];
+  const int4 it = items[blockIdx.x];
+  const int f = it.x, ti = it.y, tj = it.z;
+  const int m = f_m[f], k = f_k[f], ld = m + k;
+  double* __restrict__ A = F + f_F[f];
+  const int rows = KIND == 0 ? m : k;   // output rows
+  const int cols = k;                   // output columns
+  const int r0 = ti * kTile, c0 = tj * kTile;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int j0 = 0; j0 < m; j0 += kTk) {
+    // A tile: rows r0.., inner j0..; B tile: inner j0.., columns c0..
+    for (int e = t; e < kTile * kTk; e += 256) {
+      const int r = e / kTk, q = e % kTk;
+      const int gr = r0 + r, gj = j0 + q;
+      double av = 0.0, bv = 0.0;
+      if (gr < rows && gj < m)
+        av = KIND == 0 ? A[(int64_t)gr * ld + gj]            // F11^-1
+                       : A[(int64_t)(m + gr) * ld + gj];     // F21
+      const int gc = c0 + r;
+      if (gc < cols && gj < m)
+        bv = KIND == 0 ? A[(int64_t)(m + gc) * ld + gj]      // F12^T = F21
+                       : A[(int64_t)gj * ld + m + gc];       // W
+      As[q][r] = av;
+      Bs[q][r] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kTk; ++q) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[q][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[q][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gr = r0 + ty + 16 * i, gc = c0 + tx + 16 * j;
+      if (gr >= rows || gc >= cols) continue;
+      if (KIND == 0) {
+        A[(int64_t)gr * ld + m + gc] = acc[i][j];
+      } else {
+        if (ti == tj && gr > gc) continue;
+        const double u = A[(int64_t)(m + gr) * ld + m + gc] - acc[i][j];
+        A[(int64_t)(m + gr) * ld + m + gc] = u;
+        A[(int64_t)(m + gc) * ld + m + gr] = u;
+      }
+    }
 }
 
 // ------------------------------------------------------------------ solve
@@ -1020,6 +1119,38 @@ void nd_analyse(PSolve& ps, const Csr& T, int* flags, hipStream_t s) {
   }
   to_device(ps.fwd_items, fw, s);
   to_device(ps.bwd_items, bw, s);
+  // numeric phase: fronts whose F11 is inverted in LDS, the larger ones (by
+  // the tiled dense Gauss-Jordan), the 64 x 64 tiles of W and of the Schur
+  // complements; host offsets of the front matrices
+  std::vector<int32_t> sm;
+  std::vector<int4> wt, st;
+  ps.small_off.assign(1, 0);
+  ps.w_off.assign(1, 0);
+  ps.s_off.assign(1, 0);
+  ps.big.assign(ps.n_levels, {});
+  ps.hF.assign(nf + 1, 0);
+  for (int32_t f = 0; f < nf; ++f) {
+    const int64_t ld = (int64_t)ps.hm[f] + ps.hk[f];
+    ps.hF[f + 1] = ps.hF[f] + ld * ld;
+  }
+  for (int l = 0; l < ps.n_levels; ++l) {
+    for (int64_t f = ps.lev_off[l]; f < ps.lev_off[l + 1]; ++f) {
+      const int m = ps.hm[f], k = ps.hk[f];
+      if (m <= kLdsPiv) sm.push_back((int32_t)f);
+      else ps.big[l].push_back((int32_t)f);
+      const int tm = (m + kTile - 1) / kTile, tk = (k + kTile - 1) / kTile;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tk; ++b) wt.push_back(make_int4((int)f, a, b, 0));
+      for (int a = 0; a < tk; ++a)
+        for (int b = a; b < tk; ++b) st.push_back(make_int4((int)f, a, b, 0));
+    }
+    ps.small_off.push_back((int64_t)sm.size());
+    ps.w_off.push_back((int64_t)wt.size());
+    ps.s_off.push_back((int64_t)st.size());
+  }
+  to_device(ps.small, sm, s);
+  to_device(ps.w_items, wt, s);
+  to_device(ps.s_items, st, s);
   ps.xp.alloc(n);
   ps.contrib.alloc(std::max<int64_t>(ps.n_slots, 1));
   ps.n = n;
@@ -1028,18 +1159,48 @@ void nd_analyse(PSolve& ps, const Csr& T, int* flags, hipStream_t s) {
 
 }  // namespace
 
-// Factor (values) for the current analysis: fronts level by level.
+// Factor (values) for the current analysis, level by level: assembly,
+// F11^-1, W = F11^-1 F12, Schur complements for the parents.
 void psolve_factor(PSolve& ps, const Csr& T, const double* sk, bool spd,
                    int* flags, hipStream_t s) {
   ps.spd = spd;
   ps.F.alloc(std::max<int64_t>(ps.F_words, 1));
+  DevBuf<double> pad;
   for (int l = 0; l < ps.n_levels; ++l) {
     const int64_t a = ps.lev_off[l], b = ps.lev_off[l + 1];
-    if (b > a)
-      k_nd_factor<<<(unsigned)(b - a), kNdT, 0, s>>>(
-          (int32_t)a, T.rowptr.p, T.col.p, T.val.p, sk, ps.perm.p, ps.pos.p,
-          ps.f_slo.p, ps.f_m.p, ps.f_k.p, ps.f_F.p, ps.f_bnd.p, ps.bnd.p,
-          ps.ch_off.p, ps.ch.p, ps.F.p, spd ? 1 : 0, flags);
+    if (b == a) continue;
+    k_nd_assemble<<<(unsigned)(b - a), kNdT, 0, s>>>(
+        (int32_t)a, T.rowptr.p, T.col.p, T.val.p, sk, ps.perm.p, ps.pos.p,
+        ps.f_slo.p, ps.f_m.p, ps.f_k.p, ps.f_F.p, ps.f_bnd.p, ps.bnd.p,
+        ps.ch_off.p, ps.ch.p, ps.F.p, flags);
+    FPC_LAUNCH_CHECK();
+    const int64_t sa = ps.small_off[l], sb = ps.small_off[l + 1];
+    if (sb > sa)
+      k_nd_inv_lds<<<(unsigned)(sb - sa), kNdT, 0, s>>>(
+          ps.small.p + sa, ps.f_m.p, ps.f_k.p, ps.f_F.p, ps.F.p, spd ? 1 : 0,
+          flags);
+    FPC_LAUNCH_CHECK();
+    for (int32_t f : ps.big[l]) {
+      const int m = ps.hm[f], ld = m + ps.hk[f];
+      const int npad = (int)((m + 63) / 64 * 64);
+      pad.ensure((size_t)npad * npad);
+      double* A = ps.F.p + ps.hF[f];
+      k_nd_pad<<<grid_for((int64_t)npad * npad, 256), 256, 0, s>>>(A, ld, m,
+                                                                  npad, pad.p);
+      FPC_LAUNCH_CHECK();
+      gj_inverse(pad.p, npad, flags, s, /*pivot=*/!spd);
+      k_nd_unpad<<<grid_for((int64_t)m * m, 256), 256, 0, s>>>(pad.p, npad, m,
+                                                              A, ld);
+      FPC_LAUNCH_CHECK();
+    }
+    const int64_t wa = ps.w_off[l], wb = ps.w_off[l + 1];
+    if (wb > wa)
+      k_nd_tile<0><<<(unsigned)(wb - wa), 256, 0, s>>>(
+          ps.w_items.p + wa, ps.f_m.p, ps.f_k.p, ps.f_F.p, ps.F.p);
+    const int64_t ta = ps.s_off[l], tb = ps.s_off[l + 1];
+    if (tb > ta)
+      k_nd_tile<1><<<(unsigned)(tb - ta), 256, 0, s>>>(
+          ps.s_items.p + ta, ps.f_m.p, ps.f_k.p, ps.f_F.p, ps.F.p);
     FPC_LAUNCH_CHECK();
   }
 }
