@@ -39,10 +39,17 @@ struct Error : std::runtime_error {
 #define FPC_LAUNCH_CHECK() FPC_HIP(hipGetLastError())
 
 // Device buffers come from the stream-ordered allocator (hipMallocAsync on
-// the stream of the library call in progress, see StreamScope) and go back
-// to it on the same stream, so allocation and release queue behind the work
-// that uses them instead of synchronizing the device; the default memory
-// pool keeps freed blocks for reuse (set up by fpc_create).
+// the stream of the library call in progress, see StreamScope) through a
+// block cache: a released block is kept on its (device, stream) under its
+// size class and handed to the next request of that class on the same
+// stream, which is safe because work on one stream runs in order.  Setups
+// make hundreds of short-lived buffers; each hipFreeAsync costs tens of
+// microseconds of host time, the cache none.  The cache holds at most
+// kDevCacheLimit bytes (beyond that blocks go back to the pool) and is
+// emptied when the last handle is destroyed or an allocation fails.
+void* dev_alloc(size_t bytes, hipStream_t s, size_t* cap);
+void dev_free(void* p, size_t cap, hipStream_t s);
+void dev_cache_trim();
 hipStream_t& alloc_stream();
 
 struct StreamScope {
@@ -62,34 +69,31 @@ struct DevBuf {
   hipStream_t st = nullptr;  // stream the allocation is ordered on
   DevBuf() = default;
   explicit DevBuf(size_t n_) { alloc(n_); }
+  size_t cap = 0;             // bytes of the cached block
   void alloc(size_t n_) {
     release();
-    n = n_;
-    if (n) {
+    if (n_) {
       st = alloc_stream();
-      hipError_t e = hipMallocAsync((void**)&p, n * sizeof(T), st);
-      if (e != hipSuccess) {
-        p = nullptr;
-        n = 0;
-        throw Error(e == hipErrorOutOfMemory ? FPC_ERR_OOM : FPC_ERR_HIP,
-                    std::string("hipMallocAsync: ") + hipGetErrorString(e));
-      }
+      p = static_cast<T*>(dev_alloc(n_ * sizeof(T), st, &cap));
+      n = n_;
     }
   }
   void ensure(size_t n_) {
     if (n < n_) alloc(n_);
   }
   void release() {
-    if (p) (void)hipFreeAsync(p, st);
+    if (p) dev_free(p, cap, st);
     p = nullptr;
     n = 0;
+    cap = 0;
   }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), st(o.st) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), st(o.st), cap(o.cap) {
     o.p = nullptr;
     o.n = 0;
+    o.cap = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
@@ -97,8 +101,10 @@ struct DevBuf {
       p = o.p;
       n = o.n;
       st = o.st;
+      cap = o.cap;
       o.p = nullptr;
       o.n = 0;
+      o.cap = 0;
     }
     return *this;
   }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <atomic>
 #include <mutex>
 #include <string>
 
@@ -1111,6 +1112,7 @@ static __device__ __align__(256) int32_t scratch[kStaticScratchWords];
 namespace {
 
 constexpr int kMaxDevices = 64;
+std::atomic<int> g_live_handles{0};  // handles created and not destroyed
 std::mutex g_scratch_mu;
 int32_t* g_scratch_dev[kMaxDevices] = {};
 
@@ -1200,6 +1202,7 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
     return st;
   }
   *hp = h;
+  g_live_handles.fetch_add(1);
   return FPC_OK;
 }
 
@@ -1524,12 +1527,14 @@ fpc_status fpc_hash32_device(fpc_handle* h, uint32_t first, int64_t n,
 
 void fpc_destroy(fpc_handle* h) {
   if (!h) return;
-  // finish the handle's work, release (buffers go back to the pool on
-  // their stream), then wait for the releases
+  // finish the handle's work, release (buffers go to the block cache on
+  // their stream; the last handle returns the cache to the pool), then wait
+  // for the releases
   hipStream_t s = h->stream;
   if (s) (void)hipStreamSynchronize(s);
   else (void)hipDeviceSynchronize();
   delete h;
+  if (g_live_handles.fetch_sub(1) == 1) dev_cache_trim();
   if (s) (void)hipStreamSynchronize(s);
   else (void)hipDeviceSynchronize();
 }

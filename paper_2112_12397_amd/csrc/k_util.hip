@@ -1,4 +1,7 @@
 // Utility kernels: fills, prefix sums, deterministic reductions, hashing.
+#include <map>
+#include <mutex>
+
 #include "fpc_internal.hpp"
 
 namespace fpc {
@@ -293,6 +296,102 @@ bool same_values(const double* a, const double* b, int64_t n, hipStream_t s) {
       n, f.p);
   FPC_LAUNCH_CHECK();
   return read_i32(f.p, s) == 0;
+}
+
+// ------------------------------------------------------- block cache
+namespace {
+
+constexpr size_t kDevCacheLimit = size_t(8) << 30;
+struct CacheKey {
+  int dev;
+  hipStream_t s;
+  size_t cap;
+  bool operator<(const CacheKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (s != o.s) return s < o.s;
+    return cap < o.cap;
+  }
+};
+std::mutex g_cache_mu;
+std::map<CacheKey, std::vector<void*>> g_cache;
+size_t g_cached = 0;
+
+// size classes: 256 B, then eight steps per power of two (at most 1/8
+// rounded up)
+size_t size_class(size_t b) {
+  if (b <= 256) return 256;
+  int e = 63 - __builtin_clzll((unsigned long long)(b - 1));
+  const size_t base = size_t(1) << e, step = base / 8;
+  return base + ((b - base + step - 1) / step) * step;
+}
+
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s, size_t* cap) {
+  const size_t c = size_class(bytes);
+  const CacheKey key{current_device(), s, c};
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      g_cached -= c;
+      *cap = c;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMallocAsync(&p, c, s);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    dev_cache_trim();
+    e = hipMallocAsync(&p, c, s);
+  }
+  if (e != hipSuccess)
+    throw Error(e == hipErrorOutOfMemory ? FPC_ERR_OOM : FPC_ERR_HIP,
+                std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  *cap = c;
+  return p;
+}
+
+void dev_free(void* p, size_t cap, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (g_cached + cap <= kDevCacheLimit) {
+      g_cache[CacheKey{current_device(), s, cap}].push_back(p);
+      g_cached += cap;
+      return;
+    }
+  }
+  (void)hipFreeAsync(p, s);
+}
+
+// Every cached block back to the pool, on the stream it was last used on
+// (the device current for each is the one it belongs to).
+void dev_cache_trim() {
+  std::map<CacheKey, std::vector<void*>> all;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    all.swap(g_cache);
+    g_cached = 0;
+  }
+  const int home = current_device();
+  int cur = home;
+  for (auto& kv : all) {
+    if (kv.first.dev != cur) {
+      (void)hipSetDevice(kv.first.dev);
+      cur = kv.first.dev;
+    }
+    for (void* p : kv.second) (void)hipFreeAsync(p, kv.first.s);
+  }
+  if (cur != home) (void)hipSetDevice(home);
 }
 
 hipStream_t& alloc_stream() {
