@@ -62,10 +62,15 @@ enum { FPC_HOST = 0, FPC_DEVICE = 1 };
  * remark after Prop 3.2: one AMG call per application). */
 enum { FPC_TUP = 0, FPC_TPU = 1, FPC_TUP_STAR = 2 };
 enum { FPC_FP64 = 0, FPC_FP32_PREC = 1 };
-/* Arnoldi orthogonalization of the single-right-hand-side FGMRES: classical
- * Gram-Schmidt applied twice (two multi-dot passes per iteration) or the
- * textbook modified Gram-Schmidt (j + 1 dependent dot products). */
-enum { FPC_CGS2 = 0, FPC_MGS = 1 };
+/* Arnoldi orthogonalization of the single-right-hand-side FGMRES (the
+ * paper does not fix it; Sec. 4 names GMRES only): classical Gram-Schmidt
+ * applied twice (three passes over the basis per iteration), the textbook
+ * modified Gram-Schmidt (j + 1 dependent dot products), or classical
+ * Gram-Schmidt twice with the second projection delayed to the next step
+ * (DCGS2 of Swirydowicz et al., Numer. Linear Algebra Appl. 2021: two passes
+ * per iteration, the same Arnoldi relation in exact arithmetic; the last
+ * column of a cycle takes one more pass). */
+enum { FPC_CGS2 = 0, FPC_MGS = 1, FPC_DCGS2 = 2 };
 
 /* Compressed sparse rows, 0-based, column indices strictly increasing in
  * every row.  Arrays live in host or device memory (fpc_block_system.ptr_space)
@@ -111,8 +116,8 @@ typedef struct {
                            /* 1 to 32, larger values are rejected)          */
   int graphs;              /* 1: the batched V-cycle is captured once into  */
                            /* a HIP graph and replayed (default); 0: eager  */
-  int ortho;               /* FPC_CGS2 (default) or FPC_MGS; batched solves */
-                           /* always use CGS2                               */
+  int ortho;               /* FPC_DCGS2 (default), FPC_CGS2 or FPC_MGS;     */
+                           /* batched solves always use CGS2                */
   fpc_amg_options amg;
 } fpc_options;
 

@@ -127,6 +127,32 @@ void cgs_axpy_dot(const double* V, int64_t ldv, int nv, const double* h,
 void cgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
                    double* w, int64_t n, double* partials, double* out,
                    hipStream_t s);
+// Gram-Schmidt twice with the second projection delayed by one step
+// (partials sized by mdot_partials for 2 kMaxKrylov + 1 vectors).  Slot j
+// of V holds u_j (unnormalized remainder of step j-1), V_0 .. V_{j-1} are
+// final.
+//   dcgs_dot:    D[i] = <V_i, u>, and with w: D[nv + i] = <V_i, w>,
+//                D[2 nv] = <w, w> (i < nv; the last vector may be u itself)
+//   dcgs_finish: rho_j into scal[0]; fin: column j-1 of H final (P + a,
+//                subdiagonal rho_j) and committed, estimate in scal[5],
+//                ctrl[0] = 2 if rho_j = 0; fresh: first projection of
+//                column j into P, <w, w> into scal[6]
+//   dcgs_update: slot j <- v_j, slot j+1 <- u_{j+1}, partials of |u_{j+1}|^2
+//   dcgs_peek:   provisional estimate of column j into scal[1]; on
+//                breakdown the column is committed, scal[5] set, ctrl[0] = 1
+bool dcgs_supported(int64_t n);
+void dcgs_dot(const double* V, int64_t ldv, int nv, const double* u,
+              const double* w, int64_t n, double* partials, double* D,
+              hipStream_t s);
+void dcgs_finish(const double* D, int nv, bool fin, bool fresh, double* H,
+                 int ldh, double* cs, double* sn, double* g, double* P,
+                 double* scal, int* ctrl, hipStream_t s);
+void dcgs_update(double* V, int64_t ldv, int j, const double* D,
+                 const double* P, const double* scal, const double* w,
+                 int64_t n, double* partials, hipStream_t s);
+void dcgs_peek(const double* partials, int64_t n, double* H, int ldh,
+               double* cs, double* sn, double* g, const double* P, int j,
+               double* scal, int* ctrl, hipStream_t s);
 // w -= sum_i h_i V_i
 void maxpy(const double* V, int64_t ldv, int nv, const double* h, double* w,
            int64_t n, hipStream_t s);

@@ -186,6 +186,7 @@ struct Krylov {
   DevBuf<double> w, r, tmp;   // N x k
   DevBuf<double> H, cs, sn, g, y;  // small arrays (device)
   DevBuf<double> h1, h2, scal, partials;
+  DevBuf<double> D, P;        // delayed Gram-Schmidt: dot outputs, column
   DevBuf<int> ctrl;
   double* host = nullptr;     // pinned mirror for scalars read each step
   hipEvent_t ev = nullptr;    // marks the arrival of those scalars

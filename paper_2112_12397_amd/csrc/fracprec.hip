@@ -582,7 +582,9 @@ void ensure_krylov(fpc_handle* h, Krylov& K, int k) {
   K.h1.alloc((int64_t)(m + 1) * k);
   K.h2.alloc((int64_t)(m + 1) * k);
   K.scal.alloc(8 * k);
-  K.partials.alloc(mdot_partials(h->N, m + 1));
+  K.D.alloc(2 * (m + 1) + 1);
+  K.P.alloc(m + 1);
+  K.partials.alloc(mdot_partials(h->N, 2 * (m + 1) + 1));
   K.ctrl.alloc(4 * k);
   if (!K.host) FPC_HIP(hipHostMalloc((void**)&K.host, 64 * sizeof(double)));
   if (!K.ev) FPC_HIP(hipEventCreateWithFlags(&K.ev, hipEventDisableTiming));
@@ -591,6 +593,166 @@ void ensure_krylov(fpc_handle* h, Krylov& K, int k) {
 double dev_norm(fpc_handle* h, Krylov& K, const double* x, double* slot) {
   mdot(x, 0, 1, x, h->N, K.partials.p, slot, h->stream);
   return std::sqrt(std::max(read_f64(slot, h->stream), 0.0));
+}
+
+// One restart cycle of FGMRES with classical Gram-Schmidt twice in three
+// passes or modified Gram-Schmidt (u_0 = v_0 = r / beta in slot 0, g = beta
+// e_1); returns the number of columns of H.
+int cgs_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
+              double& est) {
+  hipStream_t s = h->stream;
+  const int64_t N = h->N;
+  const int m = h->opt.restart;
+  double* sc = K.scal.p;
+  // The leading steps of M^-1 v_{j+1} (which need v_{j+1} only) are queued
+  // before the host waits for the convergence test of step j, so the
+  // device has work during that round trip; after the last step of a
+  // cycle they are unused.
+  const bool lead = !trans && fwd_has_lead(h);
+  bool lead_done = false;
+  int k = 0;
+  for (int j = 0; j < m; ++j) {
+    double* vj = K.V.p + (int64_t)j * N;
+    double* zj = K.Z.p + (int64_t)j * N;
+    if (lead) {
+      if (!lead_done) apply(h, trans, vj, zj, 1);
+      apply(h, trans, vj, zj, 2);
+      lead_done = false;
+    } else {
+      apply(h, trans, vj, zj);
+    }
+    matvec(h, trans, zj, K.w.p);
+    // |w|^2 before the projections (breakdown test) at nrm_before
+    const double* nrm_before = sc + 4;
+    if (h->opt.ortho == FPC_MGS) {
+      // modified Gram-Schmidt: h_ij = v_i^T w with the w of step i
+      mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
+      for (int i = 0; i <= j; ++i) {
+        const double* vi = K.V.p + (int64_t)i * N;
+        mdot(vi, N, 1, K.w.p, N, K.partials.p, K.h1.p + i, s);
+        maxpy(vi, N, 1, K.h1.p + i, K.w.p, N, s);
+      }
+      FPC_HIP(hipMemsetAsync(K.h2.p, 0, (j + 1) * sizeof(double), s));
+      mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 5, s);
+    } else {
+      // classical Gram-Schmidt, twice, in three passes over the basis:
+      // h1 = V^T w (and |w|^2); w -= V h1 with h2 = V^T w from the same
+      // rows; w -= V h2 with |w|^2
+      cgs_dot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
+      nrm_before = K.h1.p + j + 1;
+      cgs_axpy_dot(K.V.p, N, j + 1, K.h1.p, K.w.p, N, K.partials.p, K.h2.p,
+                   s);
+      cgs_axpy_norm(K.V.p, N, j + 1, K.h2.p, K.w.p, N, K.partials.p, sc + 5,
+                    s);
+    }
+    gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
+               nrm_before, j, sc, K.ctrl.p, s);
+    // the convergence scalars go to the host ahead of the next vector and
+    // its lead stage, and the host waits for them only: the stage-2 work
+    // of step j + 1 is queued while the device still runs the lead stage
+    FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipEventRecord(K.ev, s));
+    scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
+    if (lead && j + 1 < m) {
+      apply(h, trans, K.V.p + (int64_t)(j + 1) * N,
+            K.Z.p + (int64_t)(j + 1) * N, 1);
+      lead_done = true;
+    }
+    FPC_HIP(hipEventSynchronize(K.ev));
+    ++its;
+    k = j + 1;
+    est = K.host[1];
+    const int breakdown = *(int*)(K.host + 2);
+    if (K.host[1] <= tol || breakdown || its >= h->opt.maxit) break;
+  }
+  return k;
+}
+
+// One restart cycle of FGMRES with the delayed Gram-Schmidt (two passes
+// over the basis per step; u_0 = r / beta already in slot 0 and g = beta
+// e_1).  Column j of H is made final at step j + 1; the host decides from
+// the provisional estimate of column j and, when that one meets the
+// tolerance (or the cycle or the iteration budget ends), makes the column
+// final with one more dot pass over V_0 .. V_j, u_{j+1} before it stops.
+// Returns the number of final columns.
+int dcgs2_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
+                double& est) {
+  hipStream_t s = h->stream;
+  const int64_t N = h->N;
+  const int m = h->opt.restart;
+  double* sc = K.scal.p;
+  // scal: [0] rho_j, [1] provisional estimate, [5] estimate of the last
+  // final column, [6] |w|^2 before the projections; leading stage of
+  // M^-1 u_{j+1} queued before the host waits, as in cgs_cycle
+  const bool lead = !trans && fwd_has_lead(h);
+  bool lead_done = false;
+  bool prev_final = true;  // column j - 1 already final (none for j = 0)
+  auto fetch = [&]() {
+    FPC_HIP(hipMemcpyAsync(K.host, sc, 8 * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipMemcpyAsync((int*)(K.host + 8), K.ctrl.p, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipEventRecord(K.ev, s));
+  };
+  for (int j = 0; j < m; ++j) {
+    double* uj = K.V.p + (int64_t)j * N;
+    double* zj = K.Z.p + (int64_t)j * N;
+    if (lead) {
+      if (!lead_done) apply(h, trans, uj, zj, 1);
+      apply(h, trans, uj, zj, 2);
+      lead_done = false;
+    } else {
+      apply(h, trans, uj, zj);
+    }
+    matvec(h, trans, zj, K.w.p);
+    dcgs_dot(K.V.p, N, j + 1, uj, K.w.p, N, K.partials.p, K.D.p, s);
+    dcgs_finish(K.D.p, j + 1, !prev_final, true, K.H.p, m, K.cs.p, K.sn.p,
+                K.g.p, K.P.p, sc, K.ctrl.p, s);
+    dcgs_update(K.V.p, N, j, K.D.p, K.P.p, sc, K.w.p, N, K.partials.p, s);
+    dcgs_peek(K.partials.p, N, K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.P.p, j, sc,
+              K.ctrl.p, s);
+    fetch();
+    if (lead && j + 1 < m) {
+      apply(h, trans, K.V.p + (int64_t)(j + 1) * N,
+            K.Z.p + (int64_t)(j + 1) * N, 1);
+      lead_done = true;
+    }
+    FPC_HIP(hipEventSynchronize(K.ev));
+    ++its;
+    const int ctrl = *(int*)(K.host + 8);
+    if (ctrl == 2) {  // u_j inside span(V_0 .. V_{j-1}): column j - 1 final
+      est = K.host[5];
+      return j;
+    }
+    if (ctrl == 1) {  // breakdown at step j: column j committed as it is
+      est = K.host[5];
+      return j + 1;
+    }
+    prev_final = false;
+    const bool last = j + 1 == m || its >= h->opt.maxit;
+    if (j > 0 && K.host[5] <= tol) {
+      // column j - 1 (final) already meets the tolerance
+      est = K.host[5];
+      return j;
+    }
+    if (K.host[1] <= tol || last) {
+      dcgs_dot(K.V.p, N, j + 2, K.V.p + (int64_t)(j + 1) * N, nullptr, N,
+               K.partials.p, K.D.p, s);
+      dcgs_finish(K.D.p, j + 2, true, false, K.H.p, m, K.cs.p, K.sn.p, K.g.p,
+                  K.P.p, sc, K.ctrl.p, s);
+      fetch();
+      FPC_HIP(hipEventSynchronize(K.ev));
+      prev_final = true;
+      est = K.host[5];
+      if (K.host[5] <= tol || last || *(int*)(K.host + 8) == 2) return j + 1;
+    } else {
+      est = K.host[1];
+    }
+  }
+  return m;
 }
 
 fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
@@ -618,6 +780,7 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
   }
   if (!use_x0) FPC_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
   const double tol = rtol * bnorm;
+  const bool dcgs = h->opt.ortho == FPC_DCGS2 && dcgs_supported(N);
   int its = 0, cycles = 0;
   bool converged = false;
   double est = 1.0, truer = 1.0;
@@ -637,70 +800,9 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
     }
     if (its >= h->opt.maxit) break;
     scale_by_inv(K.r.p, sc, K.V.p, N, s);
-    int k = 0;
-    // The leading steps of M^-1 v_{j+1} (which need v_{j+1} only) are queued
-    // before the host waits for the convergence test of step j, so the
-    // device has work during that round trip; after the last step of a
-    // cycle they are unused.
-    const bool lead = !trans && fwd_has_lead(h);
-    bool lead_done = false;
-    for (int j = 0; j < m; ++j) {
-      double* vj = K.V.p + (int64_t)j * N;
-      double* zj = K.Z.p + (int64_t)j * N;
-      if (lead) {
-        if (!lead_done) apply(h, trans, vj, zj, 1);
-        apply(h, trans, vj, zj, 2);
-        lead_done = false;
-      } else {
-        apply(h, trans, vj, zj);
-      }
-      matvec(h, trans, zj, K.w.p);
-      // |w|^2 before the projections (breakdown test) at nrm_before
-      const double* nrm_before = sc + 4;
-      if (h->opt.ortho == FPC_MGS) {
-        // modified Gram-Schmidt: h_ij = v_i^T w with the w of step i
-        mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 4, s);
-        for (int i = 0; i <= j; ++i) {
-          const double* vi = K.V.p + (int64_t)i * N;
-          mdot(vi, N, 1, K.w.p, N, K.partials.p, K.h1.p + i, s);
-          maxpy(vi, N, 1, K.h1.p + i, K.w.p, N, s);
-        }
-        FPC_HIP(hipMemsetAsync(K.h2.p, 0, (j + 1) * sizeof(double), s));
-        mdot(K.w.p, 0, 1, K.w.p, N, K.partials.p, sc + 5, s);
-      } else {
-        // classical Gram-Schmidt, twice, in three passes over the basis:
-        // h1 = V^T w (and |w|^2); w -= V h1 with h2 = V^T w from the same
-        // rows; w -= V h2 with |w|^2
-        cgs_dot(K.V.p, N, j + 1, K.w.p, N, K.partials.p, K.h1.p, s);
-        nrm_before = K.h1.p + j + 1;
-        cgs_axpy_dot(K.V.p, N, j + 1, K.h1.p, K.w.p, N, K.partials.p, K.h2.p,
-                     s);
-        cgs_axpy_norm(K.V.p, N, j + 1, K.h2.p, K.w.p, N, K.partials.p, sc + 5,
-                      s);
-      }
-      gmres_step(K.H.p, m, K.cs.p, K.sn.p, K.g.p, K.h1.p, K.h2.p, sc + 5,
-                 nrm_before, j, sc, K.ctrl.p, s);
-      // the convergence scalars go to the host ahead of the next vector and
-      // its lead stage, and the host waits for them only: the stage-2 work
-      // of step j + 1 is queued while the device still runs the lead stage
-      FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-      FPC_HIP(hipEventRecord(K.ev, s));
-      scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
-      if (lead && j + 1 < m) {
-        apply(h, trans, K.V.p + (int64_t)(j + 1) * N,
-              K.Z.p + (int64_t)(j + 1) * N, 1);
-        lead_done = true;
-      }
-      FPC_HIP(hipEventSynchronize(K.ev));
-      ++its;
-      k = j + 1;
-      est = K.host[1] / bnorm;
-      const int breakdown = *(int*)(K.host + 2);
-      if (K.host[1] <= tol || breakdown || its >= h->opt.maxit) break;
-    }
+    const int k = dcgs ? dcgs2_cycle(h, K, trans, tol, its, est)
+                       : cgs_cycle(h, K, trans, tol, its, est);
+    est /= bnorm;
     gmres_trisolve(K.H.p, m, K.g.p, K.y.p, k, s);
     // x += Z y  (maxpy subtracts, so negate y on the device)
     axpby(-1.0, K.y.p, 0.0, K.h1.p, k, s);
@@ -1150,7 +1252,7 @@ void fpc_default_options(fpc_options* o) {
   o->rtol = 1e-8;
   o->max_batch = 32;
   o->graphs = 1;
-  o->ortho = FPC_CGS2;
+  o->ortho = FPC_DCGS2;
   o->amg.max_coarse = 2000;
   o->amg.max_levels = 12;
   o->amg.cheb_degree = 2;
@@ -1179,7 +1281,7 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
       o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 || o.max_batch > kMaxBatch ||
       (o.graphs != 0 && o.graphs != 1) ||
-      (o.ortho != FPC_CGS2 && o.ortho != FPC_MGS)) {
+      (o.ortho != FPC_CGS2 && o.ortho != FPC_MGS && o.ortho != FPC_DCGS2)) {
     delete h;
     return FPC_ERR_ARG;
   }

@@ -215,6 +215,251 @@ __global__ __launch_bounds__(DT) void k_cgs_axpy_norm(
   block_partials<1>(acc, 1, part);
 }
 
+// ---- Gram-Schmidt twice with the second pass delayed by one step (DCGS2,
+// Swirydowicz, Langou, Ananthan, Yang and Thomas, Numer. Linear Algebra
+// Appl. 2021; Bielich et al., Parallel Comput. 2022).  Step j holds the
+// final orthonormal V_0 .. V_{j-1} and, in slot j, u_j: the remainder of
+// step j-1's first projection, not normalized.  One pass gives
+// <V_i, u_j> and <V_i, w> for i <= j (slot j included, so <u, u> and
+// <u, w> come with them); a second pass writes v_j = (u_j - sum a_i V_i) /
+// rho_j and u_{j+1} = w - sum b_i V_i - h_j v_j.  The correction a of u_j is
+// the second projection of step j-1, so Hessenberg column j-1 is final one
+// step late.
+
+// Block partials of two per-vector sums (outputs ou + i and ow + i, i <
+// cnt) and optionally one extra (output oe), wavefronts added in order.
+template <int NV, bool TWO>
+__device__ inline void block_partials2(const double (&au)[NV],
+                                       const double (&aw)[NV], int cnt,
+                                       double* __restrict__ part, int ou,
+                                       int ow, bool has_extra, double extra,
+                                       int oe) {
+  __shared__ double red[DT / 64][2 * NV + 1];
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    if (i < cnt) {
+      const double t = wsum(au[i]);
+      if ((threadIdx.x & 63) == 0) red[wave][i] = t;
+      if (TWO) {
+        const double t2 = wsum(aw[i]);
+        if ((threadIdx.x & 63) == 0) red[wave][NV + i] = t2;
+      }
+    }
+  if (has_extra) {
+    const double t = wsum(extra);
+    if ((threadIdx.x & 63) == 0) red[wave][2 * NV] = t;
+  }
+  __syncthreads();
+  const int G = gridDim.x;
+  const int t = threadIdx.x;
+  auto sum4 = [&](int q) {
+    return (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+  };
+  if (t < cnt) part[(int64_t)(ou + t) * G + blockIdx.x] = sum4(t);
+  if (TWO && t >= NV && t < NV + cnt)
+    part[(int64_t)(ow + t - NV) * G + blockIdx.x] = sum4(t);
+  if (has_extra && t == 2 * NV) part[(int64_t)oe * G + blockIdx.x] = sum4(t);
+}
+
+// Partials of <V_{i0+i}, u> (output i0 + i) and, with W, <V_{i0+i}, w>
+// (output nv + i0 + i) for i < cnt; with EXTRA also <w, w> (output 2 nv).
+template <int NV, bool W>
+__global__ __launch_bounds__(DT) void k_dcgs_dot(
+    const double* __restrict__ V, int64_t ldv, int i0, int cnt, int nv,
+    const double* __restrict__ u, const double* __restrict__ w, int64_t n,
+    bool extra, double* __restrict__ part) {
+  double au[NV], aw[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) au[i] = aw[i] = 0.0;
+  double ww = 0.0;
+  const double* Vc = V + (int64_t)i0 * ldv;
+  const uint64_t stride = (uint64_t)ldv * sizeof(double);
+  for (uint32_t k = blockIdx.x * DT + threadIdx.x; k < (uint64_t)n;
+       k += gridDim.x * DT) {
+    const uint32_t off = k * (uint32_t)sizeof(double);
+    const double uk = u[k];
+    const double wk = W ? w[k] : 0.0;
+    uint64_t st = stride;
+    asm volatile("" : "+s"(st));
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = cgs_load(cgs_base(Vc, st, i, cnt), off);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      au[i] += v[i] * uk;
+      if (W) aw[i] += v[i] * wk;
+    }
+    ww += wk * wk;
+  }
+  block_partials2<NV, W>(au, aw, cnt, part, i0, nv + i0, W && extra, ww,
+                         2 * nv);
+}
+
+// v_j = (u_j - sum_{i<j} a_i V_i) / rho into slot j and u_{j+1} = w -
+// sum_{i<j} b_i V_i - h_j v_j into slot j + 1, with the partials of
+// <u_{j+1}, u_{j+1}>.  a = D[0 .. j-1], b = P[0 .. j-1], h_j = P[j], rho =
+// scal[0] (v_j = 0 when rho = 0).  For j = 0 the sums are empty.
+template <int NV>
+__global__ __launch_bounds__(DT) void k_dcgs_update(
+    double* V, int64_t ldv, int j, const double* __restrict__ D,
+    const double* __restrict__ P, const double* __restrict__ scal,
+    const double* __restrict__ w, int64_t n, double* __restrict__ part) {
+  __shared__ double2 ab[NV];
+  if ((int)threadIdx.x < NV)
+    ab[threadIdx.x] = (int)threadIdx.x < j
+                          ? make_double2(D[threadIdx.x], P[threadIdx.x])
+                          : make_double2(0.0, 0.0);
+  __syncthreads();
+  const double rho = scal[0];
+  const double hj = P[j];
+  double* uj = V + (int64_t)j * ldv;
+  double* un = V + (int64_t)(j + 1) * ldv;
+  const int cnt = j > 0 ? j : 1;  // j = 0: slot 0 loaded with weight 0
+  const uint64_t stride = (uint64_t)ldv * sizeof(double);
+  double acc[1] = {0.0};
+  for (uint32_t k = blockIdx.x * DT + threadIdx.x; k < (uint64_t)n;
+       k += gridDim.x * DT) {
+    const uint32_t off = k * (uint32_t)sizeof(double);
+    uint64_t st = stride;
+    asm volatile("" : "+s"(st)::"memory");
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = cgs_load(cgs_base(V, st, i, cnt), off);
+    double t = uj[k];
+    double s = w[k];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double2 c = ab[i];
+      t -= c.x * v[i];
+      s -= c.y * v[i];
+    }
+    const double vj = rho != 0.0 ? t / rho : 0.0;
+    s -= hj * vj;
+    uj[k] = vj;
+    un[k] = s;
+    acc[0] += s * s;
+  }
+  block_partials<1>(acc, 1, part);
+}
+
+// Applies the rotations 0 .. c-1 (staged in LDS: rc, rs) to col[0 .. c+1]
+// (LDS), forms rotation c and returns the residual estimate |g_{c+1}| it
+// gives; with commit, also stores the rotation, column c of H and the
+// updated g.  Caller: one thread.
+__device__ inline double givens_col(double* col, const double* rc,
+                                    const double* rs, int c, double* H,
+                                    int ldh, double* cs, double* sn, double* g,
+                                    bool commit) {
+  for (int i = 0; i < c; ++i) {
+    const double t = rc[i] * col[i] + rs[i] * col[i + 1];
+    col[i + 1] = -rs[i] * col[i] + rc[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double rho = hypot(col[c], col[c + 1]);
+  const double cc = rho != 0.0 ? col[c] / rho : 1.0;
+  const double ss = rho != 0.0 ? col[c + 1] / rho : 0.0;
+  const double gc = g[c];
+  if (commit) {
+    cs[c] = cc;
+    sn[c] = ss;
+    col[c] = rho;
+    col[c + 1] = 0.0;
+    g[c + 1] = -ss * gc;
+    g[c] = cc * gc;
+    for (int i = 0; i <= c + 1; ++i) H[(int64_t)i * ldh + c] = col[i];
+  }
+  return fabs(ss * gc);
+}
+
+// After the dot pass over nv = j + 1 vectors (slot j = u_j included):
+// rho_j = sqrt(<u,u> - |a|^2) (1 for j = 0, whose u_0 is normalized) into
+// scal[0]; with fin, Hessenberg column j - 1 made final (P + a, subdiagonal
+// rho_j), rotated and committed, its estimate in scal[5], ctrl[0] = 2 if
+// rho_j = 0; with fresh, the first projection of column j into P (b, then
+// h_j = (<u,w> - a.b) / rho_j) and <w, w> into scal[6].
+__global__ __launch_bounds__(64) void k_dcgs_finish(
+    const double* __restrict__ D, int nv, int fin, int fresh, double* H,
+    int ldh, double* cs, double* sn, double* g, double* P, double* scal,
+    int* ctrl) {
+  __shared__ double col[kMaxKrylov + 2], rc[kMaxKrylov], rs[kMaxKrylov];
+  const int j = nv - 1;
+  const int lane = threadIdx.x;
+  fin = fin && j > 0;
+  double aa = 0.0, ab = 0.0;
+  for (int i = lane; i < j; i += 64) {
+    const double a = D[i];
+    aa += a * a;
+    if (fresh) ab += a * D[nv + i];
+    if (fin) col[i] = P[i] + a;
+  }
+  if (fin)
+    for (int i = lane; i < j - 1; i += 64) {
+      rc[i] = cs[i];
+      rs[i] = sn[i];
+    }
+  aa = wsum(aa);
+  ab = wsum(ab);
+  __syncthreads();
+  if (lane == 0) {
+    const double r2 = D[j] - aa;
+    const double rho = j == 0 ? 1.0 : (r2 > 0.0 ? sqrt(r2) : 0.0);
+    scal[0] = rho;
+    ctrl[0] = 0;
+    if (fin) {
+      col[j] = rho;
+      scal[5] = givens_col(col, rc, rs, j - 1, H, ldh, cs, sn, g, true);
+      if (rho == 0.0) ctrl[0] = 2;
+    }
+    if (fresh) {
+      P[j] = rho != 0.0 ? (D[nv + j] - ab) / rho : 0.0;
+      scal[6] = D[2 * nv];
+    }
+  }
+  __syncthreads();
+  if (fresh)
+    for (int i = lane; i < j; i += 64) P[i] = D[nv + i];
+}
+
+// After the update pass: <u_{j+1}, u_{j+1}> reduced from the partials
+// (nu_j = its root), the provisional column j (P, subdiagonal nu_j) rotated
+// for an estimate of the residual into scal[1].  If nu_j <= 1e-14 |w| (w
+// before the projections) the step breaks down: the column is committed as
+// it is and ctrl[0] = 1.  Nothing is done if the finish step flagged a
+// breakdown.
+__global__ __launch_bounds__(DT) void k_dcgs_peek(
+    const double* __restrict__ part, int np, double* H, int ldh, double* cs,
+    double* sn, double* g, const double* __restrict__ P, int j, double* scal,
+    int* ctrl) {
+  __shared__ double sh[DT / 64];
+  __shared__ double col[kMaxKrylov + 2], rc[kMaxKrylov], rs[kMaxKrylov];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < np; k += DT) acc += part[k];
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  for (int i = threadIdx.x; i <= j; i += DT) col[i] = P[i];
+  for (int i = threadIdx.x; i < j; i += DT) {
+    rc[i] = cs[i];
+    rs[i] = sn[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double nu2 = 0.0;
+    for (int q = 0; q < DT / 64; ++q) nu2 += sh[q];
+    if (ctrl[0] == 2) return;
+    const double nu = sqrt(fmax(nu2, 0.0));
+    const double w0 = sqrt(fmax(scal[6], 0.0));
+    const bool bd = !(nu > 1e-14 * w0);
+    col[j + 1] = nu;
+    const double est = givens_col(col, rc, rs, j, H, ldh, cs, sn, g, bd);
+    scal[1] = est;
+    if (bd) {
+      scal[5] = est;
+      ctrl[0] = 1;
+    }
+  }
+}
+
 __global__ void k_scale_inv(const double* __restrict__ x,
                             const double* __restrict__ scal,
                             double* __restrict__ y, int64_t n) {
@@ -388,6 +633,77 @@ void cgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
   k_cgs_axpy_norm<<<(unsigned)G, DT, 0, s>>>(V, ldv, nv, h, w, n, partials);
   FPC_LAUNCH_CHECK();
   k_mdot_reduce<<<1, DT, 0, s>>>(partials, (int)G, out);
+  FPC_LAUNCH_CHECK();
+}
+
+bool dcgs_supported(int64_t n) { return n < kCgsMaxRows; }
+
+// Largest vector count of one dot-pass launch (two sums per vector held in
+// registers); more vectors take a second launch that reads u and w again.
+constexpr int kDcgsChunk = 32;
+
+void dcgs_dot(const double* V, int64_t ldv, int nv, const double* u,
+              const double* w, int64_t n, double* partials, double* D,
+              hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov || !dcgs_supported(n))
+    throw Error(FPC_ERR_ARG, "dcgs_dot: vector count or length");
+  const int64_t G = cgs_blocks(n);
+  for (int i0 = 0; i0 < nv; i0 += kDcgsChunk) {
+    const int cnt = std::min(kDcgsChunk, nv - i0);
+    const bool extra = i0 == 0;
+    switch ((cnt + 7) / 8) {
+#define FPC_CASE(B)                                                          \
+  case B / 8:                                                                \
+    if constexpr (B <= kDcgsChunk) {                                         \
+      if (w)                                                                 \
+        k_dcgs_dot<B, true><<<(unsigned)G, DT, 0, s>>>(                      \
+            V, ldv, i0, cnt, nv, u, w, n, extra, partials);                  \
+      else                                                                   \
+        k_dcgs_dot<B, false><<<(unsigned)G, DT, 0, s>>>(                     \
+            V, ldv, i0, cnt, nv, u, w, n, extra, partials);                  \
+    }                                                                        \
+    break;
+      FPC_CGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+    }
+    FPC_LAUNCH_CHECK();
+  }
+  k_mdot_reduce<<<w ? 2 * nv + 1 : nv, DT, 0, s>>>(partials, (int)G, D);
+  FPC_LAUNCH_CHECK();
+}
+
+void dcgs_finish(const double* D, int nv, bool fin, bool fresh, double* H,
+                 int ldh, double* cs, double* sn, double* g, double* P,
+                 double* scal, int* ctrl, hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov) throw Error(FPC_ERR_ARG, "dcgs_finish: j");
+  k_dcgs_finish<<<1, 64, 0, s>>>(D, nv, fin ? 1 : 0, fresh ? 1 : 0, H, ldh,
+                                 cs, sn, g, P, scal, ctrl);
+  FPC_LAUNCH_CHECK();
+}
+
+void dcgs_update(double* V, int64_t ldv, int j, const double* D,
+                 const double* P, const double* scal, const double* w,
+                 int64_t n, double* partials, hipStream_t s) {
+  if (j < 0 || j + 1 > kMaxKrylov || !dcgs_supported(n))
+    throw Error(FPC_ERR_ARG, "dcgs_update: j or length");
+  const int64_t G = cgs_blocks(n);
+  switch ((std::max(j, 1) + 7) / 8) {
+#define FPC_CASE(B)                                                          \
+  case B / 8:                                                                \
+    k_dcgs_update<B><<<(unsigned)G, DT, 0, s>>>(V, ldv, j, D, P, scal, w, n, \
+                                                partials);                   \
+    break;
+    FPC_CGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+  }
+  FPC_LAUNCH_CHECK();
+}
+
+void dcgs_peek(const double* partials, int64_t n, double* H, int ldh,
+               double* cs, double* sn, double* g, const double* P, int j,
+               double* scal, int* ctrl, hipStream_t s) {
+  k_dcgs_peek<<<1, DT, 0, s>>>(partials, (int)cgs_blocks(n), H, ldh, cs, sn,
+                               g, P, j, scal, ctrl);
   FPC_LAUNCH_CHECK();
 }
 

@@ -183,7 +183,7 @@ def default_options(**kw) -> FpcOptions:
             v = {"tup": FPC_TUP, "tpu": FPC_TPU,
                  "tup_star": FPC_TUP_STAR}.get(v, v)
         if k == "ortho":
-            v = {"cgs2": 0, "mgs": 1}.get(v, v)
+            v = {"cgs2": 0, "mgs": 1, "dcgs2": 2}.get(v, v)
         if k == "precision":
             v = {"fp64": FPC_FP64, "fp32": FPC_FP32_PREC,
                  "fp32prec": FPC_FP32_PREC}.get(v, v)

@@ -253,14 +253,48 @@ def test_solve_mgs(torch, name):
     assert _rel(x.cpu().numpy(), xo) <= 1e-5
 
 
-def test_solve_long_cycle(torch):
+@pytest.mark.parametrize("name", ["tiny_slip_cross", "c1"])
+def test_solve_cgs2(torch, name):
+    """FGMRES with Gram-Schmidt twice in three passes per step (not the
+    default) against the oracle's CGS2 FGMRES."""
+    from paper_2112_12397_amd import solver_from_system
+    s, pc, _ = _get(name)
+    mc = _cases()[name][1]
+    sol = solver_from_system(s, ortho="cgs2", amg={"max_coarse": mc})
+    _check_solve(torch, s, pc, sol)
+
+
+@pytest.mark.parametrize("restart", [3, 7])
+def test_solve_dcgs2_short_cycles(torch, restart):
+    """The delayed Gram-Schmidt (default) with short restart cycles, so the
+    last column of every cycle is made final by the extra dot pass: the
+    oracle's CGS2 FGMRES has the same Arnoldi relation in exact arithmetic,
+    so the iteration and restart counts agree within 1."""
+    from paper_2112_12397_amd import solver_from_system
+    s, pc, _ = _get("c1")
+    sol = solver_from_system(s, ortho="dcgs2", restart=restart,
+                             amg={"max_coarse": 2000})
+    x, info = sol.solve(torch.tensor(s.b, device="cuda"))
+    xo, io = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-8,
+                           restart=restart, ortho="cgs2")
+    assert info["converged"] == 1 and info["true_rel_residual"] <= 1e-8
+    assert abs(info["iterations"] - io.iterations) <= 1
+    assert abs(info["restarts"] - io.restarts) <= 1
+    assert _rel(x.cpu().numpy(), xo) <= 1e-5
+
+
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
+def test_solve_long_cycle(torch, ortho):
     """FGMRES(63) to 1e-12 on the long-row case: one restart cycle of about
     60 steps, so the Gram-Schmidt passes run with up to 60 basis vectors
-    (the widest register buckets and, past 48 vectors, the separate axpy and
-    dot passes); same iteration count as the oracle within 2, same solution."""
+    (the widest register buckets; for CGS2, past 48 vectors, the separate
+    axpy and dot passes; for the delayed variant, past 32 vectors, the dot
+    pass in two launches, and the final pass over 64 vectors); same
+    iteration count as the oracle within 2, same solution."""
     from paper_2112_12397_amd import solver_from_system
     s, pc, _ = _get("tiny_wide")
-    sol = solver_from_system(s, restart=63, amg={"max_coarse": 90})
+    sol = solver_from_system(s, restart=63, ortho=ortho,
+                             amg={"max_coarse": 90})
     x, info = sol.solve(torch.tensor(s.b, device="cuda"), rtol=1e-12)
     xo, io = oracle.fgmres(pc.matvec, pc.apply, s.b, rtol=1e-12, restart=63,
                            ortho="cgs2")
