@@ -58,9 +58,10 @@ def spmv_bytes(nnz, nrows, ncols, sv=8, si=4, nv=1, extra_vec=0):
 
 def vcycle_bytes(levels, nv=1, sv=8):
     """Algorithmic bytes of one V-cycle: per level the four fused smoother /
-    residual products with A_l (their vector streams beyond one read and
-    one write: 3 + 1 + 4 + 3), restriction, prolongation; the coarsest level
-    reads its dense FP64 inverse once."""
+    residual products with A_l (their vector streams beyond the gathered
+    input and one output, D^-1 included: pre 4 (b, D^-1, d, R), residual 1
+    (R), post 2 + 2 (b, D^-1; D^-1, x)), restriction, prolongation; the
+    coarsest level reads its dense FP64 inverse once."""
     total = 0
     for i, d in enumerate(levels):
         n = d["n_nodes"] * d["block"]
@@ -71,7 +72,7 @@ def vcycle_bytes(levels, nv=1, sv=8):
         nc = nxt["n_nodes"] * nxt["block"]
         nnzP = d["p_nnzb"] * d["block"] * nxt["block"]
         total += 4 * spmv_bytes(d["nnz_scalar"], n, n, sv, nv=nv)
-        total += nv * 11 * n * sv
+        total += nv * 9 * n * sv
         total += spmv_bytes(nnzP, nc, n, sv, nv=nv)          # R = P^T
         total += spmv_bytes(nnzP, n, nc, sv, nv=nv)          # P
     return total

@@ -42,54 +42,64 @@ struct LoadX {
 // ---------------------------------------------------------------- epilogues
 // Every epilogue works element-wise on (dof, column): element (dof, v) of an
 // NV-column vector sits at k = dof * NV + v.  `load` fetches the element's
-// inputs into registers, `store` combines them with the product value `a`
-// and writes the outputs.  Callers issue all loads of a row before any store,
-// so the loads are in flight together (the compiler cannot reorder them past
-// stores through other pointers on its own).
+// inputs into registers, `eval` combines them with the product value `a`
+// into NOUT outputs and `put(o, k, value)` writes output o.  Callers issue
+// all loads of a row before any store, and write the outputs array by array
+// in increasing k: the compiler may not move a store past a store through
+// another pointer, so interleaved outputs would be written one element per
+// instruction, while one array's consecutive elements merge into one wide
+// store.
 template <typename T, int NV>
 struct EpiStore {
-  static constexpr int NIN = 1;
+  static constexpr int NIN = 1, NOUT = 1;
   T* __restrict__ y;
   __device__ void load(int64_t, int64_t, T*) const {}
-  __device__ void store(int64_t, int64_t k, T a, const T*) const { y[k] = a; }
+  __device__ void eval(int64_t, T a, const T*, T* out) const { out[0] = a; }
+  __device__ void put(int, int64_t k, T val) const { y[k] = val; }
 };
 
 template <typename T, int NV>
 struct EpiAdd {
-  static constexpr int NIN = 1;
+  static constexpr int NIN = 1, NOUT = 1;
   T* __restrict__ y;
   __device__ void load(int64_t, int64_t k, T* in) const { in[0] = y[k]; }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
-    y[k] = in[0] + a;
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
+    out[0] = in[0] + a;
   }
+  __device__ void put(int, int64_t k, T val) const { y[k] = val; }
 };
 
 // restriction onto a smoothed level: b = R res and the first Chebyshev
 // direction d0 = D^{-1} b / theta of that level
 template <typename T, int NV>
 struct EpiRestrict {
-  static constexpr int NIN = 1;
+  static constexpr int NIN = 1, NOUT = 2;
   T* __restrict__ b;
   T* __restrict__ d0;
   const T* __restrict__ dinv;
   T inv_theta;
   __device__ void load(int64_t dof, int64_t, T* in) const { in[0] = dinv[dof]; }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
-    b[k] = a;
-    d0[k] = in[0] * a * inv_theta;
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
+    out[0] = a;
+    out[1] = in[0] * a * inv_theta;
+  }
+  __device__ void put(int o, int64_t k, T val) const {
+    if (o == 0) b[k] = val;
+    else d0[k] = val;
   }
 };
 
 // y = D^{-1} (A x), one column
 template <typename T, int NV>
 struct EpiDinv {
-  static constexpr int NIN = 1;
+  static constexpr int NIN = 1, NOUT = 1;
   const T* __restrict__ dinv;
   T* __restrict__ y;
   __device__ void load(int64_t dof, int64_t, T* in) const { in[0] = dinv[dof]; }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
-    y[k] = in[0] * a;
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
+    out[0] = in[0] * a;
   }
+  __device__ void put(int, int64_t k, T val) const { y[k] = val; }
 };
 
 // Pre-smoothing from x = 0, two Chebyshev steps fused around q = A d0 (d0
@@ -97,7 +107,7 @@ struct EpiDinv {
 //   R1 = b - q, r1 = D^-1 R1, d1 = c1 d0 + c2 r1, x = d0 + d1.
 template <typename T, int NV>
 struct EpiPre1 {
-  static constexpr int NIN = 2;
+  static constexpr int NIN = 2, NOUT = 3;
   const T* __restrict__ b;
   const T* __restrict__ dinv;
   T* __restrict__ x;
@@ -108,100 +118,82 @@ struct EpiPre1 {
     in[0] = b[k];
     in[1] = dinv[dof];
   }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
     const T bi = in[0], di = in[1];
     const T d0 = di * bi * inv_theta;
     const T R1 = bi - a;
     const T r1 = di * R1;
     const T d1 = c1 * d0 + c2 * r1;
-    x[k] = d0 + d1;
-    d[k] = d1;
-    R[k] = R1;
+    out[0] = d0 + d1;
+    out[1] = d1;
+    out[2] = R1;
+  }
+  __device__ void put(int o, int64_t k, T val) const {
+    if (o == 0) x[k] = val;
+    else if (o == 1) d[k] = val;
+    else R[k] = val;
   }
 };
 
 // residual after pre-smoothing: res = R1 - A d1 = b - A x
 template <typename T, int NV>
 struct EpiRes {
-  static constexpr int NIN = 1;
+  static constexpr int NIN = 1, NOUT = 1;
   const T* __restrict__ R;
   T* __restrict__ res;
   __device__ void load(int64_t, int64_t k, T* in) const { in[0] = R[k]; }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
-    res[k] = in[0] - a;
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
+    out[0] = in[0] - a;
   }
+  __device__ void put(int, int64_t k, T val) const { res[k] = val; }
 };
 
-// post-smoothing step 1 around q = A x: r0 = D^-1 (b - q), d0 = r0 / theta,
-// xo = x + d0
+// post-smoothing step 1 around q = A x: r0 = D^-1 (b - q) and d0 = r0 /
+// theta; only d0 is stored (r0 = theta d0 is formed again in step 2, and
+// step 2 adds d0 to x itself)
 template <typename T, int NV>
 struct EpiPost1 {
-  static constexpr int NIN = 3;
+  static constexpr int NIN = 2, NOUT = 1;
   const T* __restrict__ b;
   const T* __restrict__ dinv;
-  const T* __restrict__ xin;
-  T* __restrict__ xo;
   T* __restrict__ d;
-  T* __restrict__ r;
   T inv_theta;
   __device__ void load(int64_t dof, int64_t k, T* in) const {
     in[0] = b[k];
     in[1] = dinv[dof];
-    in[2] = xin[k];
   }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
-    const T r0 = in[1] * (in[0] - a);
-    const T d0 = r0 * inv_theta;
-    xo[k] = in[2] + d0;
-    d[k] = d0;
-    r[k] = r0;
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
+    out[0] = in[1] * (in[0] - a) * inv_theta;
   }
+  __device__ void put(int, int64_t k, T val) const { d[k] = val; }
 };
 
-// post-smoothing step 2 around q = A d0: r1 = r0 - D^-1 q,
-// d1 = c1 d0 + c2 r1, xo += d1
+// post-smoothing step 2 around q = A d0: r1 = theta d0 - D^-1 q,
+// d1 = c1 d0 + c2 r1, xo = (x + d0) + d1
 template <typename T, int NV>
 struct EpiPost2 {
-  static constexpr int NIN = 4;
+  static constexpr int NIN = 3, NOUT = 1;
   const T* __restrict__ dinv;
-  const T* __restrict__ r;
   const T* __restrict__ din;
+  const T* __restrict__ x;
   T* __restrict__ xo;
-  T c1, c2;
+  T theta, c1, c2;
   __device__ void load(int64_t dof, int64_t k, T* in) const {
     in[0] = dinv[dof];
-    in[1] = r[k];
-    in[2] = din[k];
-    in[3] = xo[k];
+    in[1] = din[k];
+    in[2] = x[k];
   }
-  __device__ void store(int64_t, int64_t k, T a, const T* in) const {
-    const T r1 = in[1] - in[0] * a;
-    xo[k] = in[3] + (c1 * in[2] + c2 * r1);
+  __device__ void eval(int64_t, T a, const T* in, T* out) const {
+    const T d0 = in[1];
+    const T r1 = theta * d0 - in[0] * a;
+    out[0] = (in[2] + d0) + (c1 * d0 + c2 * r1);
   }
+  __device__ void put(int, int64_t k, T val) const { xo[k] = val; }
 };
 
-// All NV columns of one block row: loads first, then stores.
-template <typename T, int BR, int NV, class Epi>
-__device__ inline void epi_row(const Epi& e, int64_t row, const T (&acc)[NV][BR]) {
-  T in[NV][BR][Epi::NIN];
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t dof = row * BR + i;
-      e.load(dof, dof * NV + v, in[v][i]);
-    }
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t dof = row * BR + i;
-      e.store(dof, dof * NV + v, acc[v][i], in[v][i]);
-    }
-}
-
-// The loads and the stores of epi_row as two steps, so that a kernel can
-// issue the loads before its product and keep the inputs in registers.
+// The loads and the stores of one block row (all NV columns) as two steps,
+// so that a kernel can issue the loads before its product and keep the
+// inputs in registers.
 template <typename T, int BR, int NV, class Epi>
 __device__ inline void epi_load_row(const Epi& e, int64_t row,
                                     T (&in)[NV][BR][Epi::NIN]) {
@@ -217,38 +209,58 @@ template <typename T, int BR, int NV, class Epi>
 __device__ inline void epi_store_row(const Epi& e, int64_t row,
                                      const T (&acc)[NV][BR],
                                      const T (&in)[NV][BR][Epi::NIN]) {
+  T out[NV][BR][Epi::NOUT];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int i = 0; i < BR; ++i) {
-      const int64_t dof = row * BR + i;
-      e.store(dof, dof * NV + v, acc[v][i], in[v][i]);
-    }
+    for (int i = 0; i < BR; ++i)
+      e.eval(row * BR + i, acc[v][i], in[v][i], out[v][i]);
+#pragma unroll
+  for (int o = 0; o < Epi::NOUT; ++o)
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        e.put(o, (row * BR + i) * NV + v, out[v][i][o]);
 }
 
-// One column v of one block row.
-template <typename T, int BR, int NV, class Epi>
-__device__ inline void epi_col(const Epi& e, int64_t row, int v, const T (&acc)[BR]) {
-  T in[BR][Epi::NIN];
+// Columns v0 .. v0 + CPL - 1 of one block row.
+template <typename T, int BR, int NV, int CPL, class Epi>
+__device__ inline void epi_cols(const Epi& e, int64_t row, int v0,
+                                const T (&acc)[CPL][BR]) {
+  T in[CPL][BR][Epi::NIN];
+  T out[CPL][BR][Epi::NOUT];
 #pragma unroll
-  for (int i = 0; i < BR; ++i) {
-    const int64_t dof = row * BR + i;
-    e.load(dof, dof * NV + v, in[i]);
-  }
+  for (int i = 0; i < BR; ++i)
 #pragma unroll
-  for (int i = 0; i < BR; ++i) {
-    const int64_t dof = row * BR + i;
-    e.store(dof, dof * NV + v, acc[i], in[i]);
-  }
+    for (int u = 0; u < CPL; ++u) {
+      const int64_t dof = row * BR + i;
+      e.load(dof, dof * NV + v0 + u, in[u][i]);
+    }
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      e.eval(row * BR + i, acc[u][i], in[u][i], out[u][i]);
+#pragma unroll
+  for (int o = 0; o < Epi::NOUT; ++o)
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        e.put(o, (row * BR + i) * NV + v0 + u, out[u][i][o]);
 }
 
 // One element (component i, column v) of one block row.
 template <typename T, int BR, int NV, class Epi>
 __device__ inline void epi_one(const Epi& e, int64_t row, int i, int v, T a) {
   T in[Epi::NIN];
+  T out[Epi::NOUT];
   const int64_t dof = row * BR + i;
   e.load(dof, dof * NV + v, in);
-  e.store(dof, dof * NV + v, a, in);
+  e.eval(dof, a, in, out);
+#pragma unroll
+  for (int o = 0; o < Epi::NOUT; ++o) e.put(o, dof * NV + v, out[o]);
 }
 
 // ---------------------------------------------------------------- SpMV
@@ -481,8 +493,7 @@ __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
 #pragma unroll
         for (int j = 0; j < BC; ++j) acc[u][i] += m[i * BC + j] * xv[j][u];
   }
-#pragma unroll
-  for (int u = 0; u < CPL; ++u) epi_col<T, BR, NV>(epi, row, v0 + u, acc[u]);
+  epi_cols<T, BR, NV, CPL>(epi, row, v0, acc);
 }
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
@@ -811,12 +822,10 @@ void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
     if (timer) timer->end(s);
   } else {
     launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.x.p},
-                               EpiPost1<T, NV>{v.b.p, dinv, v.x.p, v.xo.p,
-                                                   v.d.p, v.r.p, it},
-                               s);
+                               EpiPost1<T, NV>{v.b.p, dinv, v.d.p, it}, s);
     launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
-                               EpiPost2<T, NV>{dinv, v.r.p, v.d.p, v.xo.p,
-                                                   c1, c2},
+                               EpiPost2<T, NV>{dinv, v.d.p, v.x.p, v.xo.p,
+                                                   T(L.theta), c1, c2},
                                s);
   }
 }
