@@ -140,6 +140,8 @@ void cgs_axpy_norm(const double* V, int64_t ldv, int nv, const double* h,
 //   dcgs_update: slot j <- v_j, slot j+1 <- u_{j+1}, partials of |u_{j+1}|^2
 //   dcgs_peek:   provisional estimate of column j into scal[1]; on
 //                breakdown the column is committed, scal[5] set, ctrl[0] = 1
+// (dcgs_finish and dcgs_peek also leave ctrl[0] in scal[7], as a double, so
+// that one copy of scal brings every scalar the host tests)
 bool dcgs_supported(int64_t n);
 void dcgs_dot(const double* V, int64_t ldv, int nv, const double* u,
               const double* w, int64_t n, double* partials, double* D,
@@ -164,7 +166,8 @@ void axpby(double a, const double* x, double b, double* y, int64_t n,
            hipStream_t s);
 // FGMRES step j on device: H[:, j] = h1 + h2 (j+1 entries), H[j+1, j] =
 // sqrt(nrm2); Givens update of H, cs, sn, g; scal[0] = H[j+1,j] before
-// rotation (0 on breakdown), scal[1] = |g_{j+1}|, ctrl[0] = breakdown.
+// rotation (0 on breakdown), scal[1] = |g_{j+1}|, ctrl[0] = scal[7] =
+// breakdown.
 void gmres_step(double* H, int ldh, double* cs, double* sn, double* g,
                 const double* h1, const double* h2, const double* nrm2,
                 const double* nrm2_before, int j, double* scal, int* ctrl,

@@ -12,6 +12,7 @@
 //            wavefront loads each block component as 64 consecutive words.
 #pragma once
 
+#include <initializer_list>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -236,6 +237,19 @@ void csr_validate(const Csr& m, int* flags, hipStream_t s);
 void csr_spmv2(const Csr* m1, const double* x1, double a1, const Csr* m2,
                const double* x2, double a2, double* y, double beta,
                hipStream_t s);
+// Several csr_spmv2 products (independent outputs, or outputs in different
+// rows) in one launch, with the arithmetic of csr_spmv2 per row.
+struct Spmv2Call {
+  const Csr* m1;
+  const double* x1;
+  double a1;
+  const Csr* m2;
+  const double* x2;
+  double a2;
+  double* y;
+  double beta;
+};
+void csr_spmv2_many(std::initializer_list<Spmv2Call> calls, hipStream_t s);
 void csr_transpose(const Csr& a, Csr& t, hipStream_t s);
 void csr_to_bsr(const Csr& a, int br, int bc, Bsr& out, hipStream_t s);
 void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s);

@@ -384,17 +384,21 @@ void matvec(fpc_handle* h, int trans, const double* x, double* y) {
   hipStream_t s = h->stream;
   const double *xu = x, *xt = x + h->n_u, *xp = x + h->n_u + h->n_t;
   double *yu = y, *yt = y + h->n_u, *yp = y + h->n_u + h->n_t;
+  // the A block, then the coupling rows of y_u and the t and p rows in one
+  // launch
   if (!trans) {
     sell_mv(h->sAJ, xu, yu, s);
-    csr_spmv2(&h->C1, xt, 1.0, &h->Q1, xp, 1.0, yu, 1.0, s);
-    csr_spmv2(&h->C2, xu, 1.0, &h->H, xt, -1.0, yt, 0.0, s);
-    csr_spmv2(&h->Q2, xu, 1.0, &h->T, xp, 1.0, yp, 0.0, s);
+    csr_spmv2_many({{&h->C1, xt, 1.0, &h->Q1, xp, 1.0, yu, 1.0},
+                    {&h->C2, xu, 1.0, &h->H, xt, -1.0, yt, 0.0},
+                    {&h->Q2, xu, 1.0, &h->T, xp, 1.0, yp, 0.0}},
+                   s);
   } else {
     ensure_transposes(h);
     sell_mv(h->sAJT, xu, yu, s);
-    csr_spmv2(&h->C2T, xt, 1.0, &h->Q2T, xp, 1.0, yu, 1.0, s);
-    csr_spmv2(&h->C1T, xu, 1.0, &h->HT, xt, -1.0, yt, 0.0, s);
-    csr_spmv2(&h->Q1T, xu, 1.0, &h->TT, xp, 1.0, yp, 0.0, s);
+    csr_spmv2_many({{&h->C2T, xt, 1.0, &h->Q2T, xp, 1.0, yu, 1.0},
+                    {&h->C1T, xu, 1.0, &h->HT, xt, -1.0, yt, 0.0},
+                    {&h->Q1T, xu, 1.0, &h->TT, xp, 1.0, yp, 0.0}},
+                   s);
   }
 }
 
@@ -650,9 +654,7 @@ int cgs_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
     // the convergence scalars go to the host ahead of the next vector and
     // its lead stage, and the host waits for them only: the stage-2 work
     // of step j + 1 is queued while the device still runs the lead stage
-    FPC_HIP(hipMemcpyAsync(K.host, sc, 2 * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    FPC_HIP(hipMemcpyAsync((int*)(K.host + 2), K.ctrl.p, sizeof(int),
+    FPC_HIP(hipMemcpyAsync(K.host, sc, 8 * sizeof(double),
                            hipMemcpyDeviceToHost, s));
     FPC_HIP(hipEventRecord(K.ev, s));
     scale_by_inv(K.w.p, sc, K.V.p + (int64_t)(j + 1) * N, N, s);
@@ -665,7 +667,7 @@ int cgs_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
     ++its;
     k = j + 1;
     est = K.host[1];
-    const int breakdown = *(int*)(K.host + 2);
+    const int breakdown = K.host[7] != 0.0;
     if (K.host[1] <= tol || breakdown || its >= h->opt.maxit) break;
   }
   return k;
@@ -685,15 +687,14 @@ int dcgs2_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
   const int m = h->opt.restart;
   double* sc = K.scal.p;
   // scal: [0] rho_j, [1] provisional estimate, [5] estimate of the last
-  // final column, [6] |w|^2 before the projections; leading stage of
+  // final column, [6] |w|^2 before the projections, [7] the step's code
+  // (1: breakdown at step j, 2: rho_j = 0); leading stage of
   // M^-1 u_{j+1} queued before the host waits, as in cgs_cycle
   const bool lead = !trans && fwd_has_lead(h);
   bool lead_done = false;
   bool prev_final = true;  // column j - 1 already final (none for j = 0)
   auto fetch = [&]() {
     FPC_HIP(hipMemcpyAsync(K.host, sc, 8 * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    FPC_HIP(hipMemcpyAsync((int*)(K.host + 8), K.ctrl.p, sizeof(int),
                            hipMemcpyDeviceToHost, s));
     FPC_HIP(hipEventRecord(K.ev, s));
   };
@@ -722,7 +723,7 @@ int dcgs2_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
     }
     FPC_HIP(hipEventSynchronize(K.ev));
     ++its;
-    const int ctrl = *(int*)(K.host + 8);
+    const int ctrl = (int)K.host[7];
     if (ctrl == 2) {  // u_j inside span(V_0 .. V_{j-1}): column j - 1 final
       est = K.host[5];
       return j;
@@ -747,7 +748,7 @@ int dcgs2_cycle(fpc_handle* h, Krylov& K, int trans, double tol, int& its,
       FPC_HIP(hipEventSynchronize(K.ev));
       prev_final = true;
       est = K.host[5];
-      if (K.host[5] <= tol || last || *(int*)(K.host + 8) == 2) return j + 1;
+      if (K.host[5] <= tol || last || K.host[7] == 2.0) return j + 1;
     } else {
       est = K.host[1];
     }

@@ -405,12 +405,14 @@ __global__ __launch_bounds__(64) void k_dcgs_finish(
     const double r2 = D[j] - aa;
     const double rho = j == 0 ? 1.0 : (r2 > 0.0 ? sqrt(r2) : 0.0);
     scal[0] = rho;
-    ctrl[0] = 0;
+    int code = 0;
     if (fin) {
       col[j] = rho;
       scal[5] = givens_col(col, rc, rs, j - 1, H, ldh, cs, sn, g, true);
-      if (rho == 0.0) ctrl[0] = 2;
+      if (rho == 0.0) code = 2;
     }
+    ctrl[0] = code;
+    scal[7] = code;
     if (fresh) {
       P[j] = rho != 0.0 ? (D[nv + j] - ab) / rho : 0.0;
       scal[6] = D[2 * nv];
@@ -456,6 +458,7 @@ __global__ __launch_bounds__(DT) void k_dcgs_peek(
     if (bd) {
       scal[5] = est;
       ctrl[0] = 1;
+      scal[7] = 1.0;
     }
   }
 }
@@ -516,6 +519,7 @@ __global__ __launch_bounds__(64) void k_gmres_step(
     g[j] = c * gj;
     scal[1] = fabs(sgn * gj);
     ctrl[0] = breakdown;
+    scal[7] = breakdown;
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j + 1; i += 64) H[(int64_t)i * ldh + j] = col[i];

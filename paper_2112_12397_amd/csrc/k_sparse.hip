@@ -78,6 +78,53 @@ __global__ void k_csr_spmv2_rows(const int32_t* rows, int64_t nr, int skip1,
   y[i] = (beta == 0.0) ? r : beta * y[i] + r;
 }
 
+// Several row sets of csr_spmv2 in one launch: job q covers threads
+// [start[q], start[q + 1]) and does, per row, the arithmetic of
+// k_csr_spmv2 (rows == nullptr: thread t is row t) or of k_csr_spmv2_rows.
+struct Spmv2Job {
+  const int32_t* rows;
+  int skip1;
+  const int64_t* rp1;
+  const int32_t* c1;
+  const double* v1;
+  const double* x1;
+  double a1;
+  const int64_t* rp2;
+  const int32_t* c2;
+  const double* v2;
+  const double* x2;
+  double a2;
+  double* y;
+  double beta;
+};
+constexpr int kSpmv2Jobs = 8;
+struct Spmv2Jobs {
+  Spmv2Job j[kSpmv2Jobs];
+  int64_t start[kSpmv2Jobs + 1];
+  int n;
+};
+
+__global__ void k_csr_spmv2_multi(const Spmv2Jobs jobs) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= jobs.start[jobs.n]) return;
+  int q = 0;
+  while (t >= jobs.start[q + 1]) ++q;
+  const Spmv2Job& J = jobs.j[q];
+  const int64_t r = t - jobs.start[q];
+  const int64_t i = J.rows ? J.rows[r] : r;
+  if (J.skip1 && J.rp1 && J.rp1[i] < J.rp1[i + 1]) return;
+  double s1 = 0.0;
+  if (J.rp1)
+    for (int64_t e = J.rp1[i]; e < J.rp1[i + 1]; ++e) s1 += J.v1[e] * J.x1[J.c1[e]];
+  double res = J.a1 * s1;
+  if (J.rp2) {
+    double s2 = 0.0;
+    for (int64_t e = J.rp2[i]; e < J.rp2[i + 1]; ++e) s2 += J.v2[e] * J.x2[J.c2[e]];
+    res += J.a2 * s2;
+  }
+  J.y[i] = (J.beta == 0.0) ? res : J.beta * J.y[i] + res;
+}
+
 __global__ void k_row_nonempty(const int64_t* rp, int64_t n, int64_t* f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) f[i] = rp[i] < rp[i + 1] ? 1 : 0;
@@ -1071,6 +1118,45 @@ void csr_spmv2(const Csr* m1, const double* x1, double a1, const Csr* m2,
       m1->rowptr.p, m1->col.p, m1->val.p, x1, a1,
       m2 ? m2->rowptr.p : nullptr, m2 ? m2->col.p : nullptr,
       m2 ? m2->val.p : nullptr, x2, a2, y, beta, m1->nrows);
+  FPC_LAUNCH_CHECK();
+}
+
+void csr_spmv2_many(std::initializer_list<Spmv2Call> calls, hipStream_t s) {
+  Spmv2Jobs J{};
+  auto add = [&](const Spmv2Call& c, const int32_t* rows, int64_t nr,
+                 int skip1) {
+    if (nr <= 0) return;
+    if (J.n == kSpmv2Jobs) throw Error(FPC_ERR_ARG, "csr_spmv2_many: jobs");
+    Spmv2Job& j = J.j[J.n];
+    j.rows = rows;
+    j.skip1 = skip1;
+    j.rp1 = c.m1->rowptr.p;
+    j.c1 = c.m1->col.p;
+    j.v1 = c.m1->val.p;
+    j.x1 = c.x1;
+    j.a1 = c.a1;
+    j.rp2 = c.m2 ? c.m2->rowptr.p : nullptr;
+    j.c2 = c.m2 ? c.m2->col.p : nullptr;
+    j.v2 = c.m2 ? c.m2->val.p : nullptr;
+    j.x2 = c.x2;
+    j.a2 = c.a2;
+    j.y = c.y;
+    j.beta = c.beta;
+    J.start[J.n + 1] = J.start[J.n] + nr;
+    ++J.n;
+  };
+  for (const Spmv2Call& c : calls) {
+    if (c.m1->nrows == 0) continue;
+    if (c.beta == 1.0 && c.m1->nact >= 0 && (!c.m2 || c.m2->nact >= 0)) {
+      add(c, c.m1->act.p, c.m1->nact, 0);
+      if (c.m2) add(c, c.m2->act.p, c.m2->nact, 1);
+    } else {
+      add(c, nullptr, c.m1->nrows, 0);
+    }
+  }
+  if (J.n == 0) return;
+  const int64_t total = J.start[J.n];
+  k_csr_spmv2_multi<<<grid_for(total, 256), 256, 0, s>>>(J);
   FPC_LAUNCH_CHECK();
 }
 

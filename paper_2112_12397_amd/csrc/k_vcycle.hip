@@ -613,34 +613,48 @@ void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- coarsest
-// x = Ainv b on the coarsest level (FP64 arithmetic), one wavefront per row.
+// x = Ainv b on the coarsest level (FP64 arithmetic), one workgroup per row
+// (the level has at most a few thousand rows: a wavefront per row left too
+// few loads in flight).  Thread t adds the elements k = t, t + 256, ... in
+// order, fetched CU at a time; the four wavefronts' sums are added in order.
 template <typename T, int NV>
 __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ Ai,
                                                 int64_t ld, int64_t n,
                                                 const T* __restrict__ b,
                                                 T* __restrict__ x) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+  constexpr int CU = NV >= 8 ? 1 : 8;
+  __shared__ double red[4][NV];
+  const int64_t row = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const double* __restrict__ a = Ai + row * ld;
-  for (int64_t k = lane; k < n; k += 64) {
-    const double m = a[k];
+  for (int64_t k0 = t; k0 < n; k0 += 256 * CU) {
+    double m[CU];
+    T bv[CU][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += m * (double)b[k * NV + v];
+    for (int u = 0; u < CU; ++u) {
+      const int64_t k = k0 + 256 * u;
+      const bool in = k < n;
+      m[u] = in ? a[k] : 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bv[u][v] = in ? b[k * NV + v] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CU; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += m[u] * (double)bv[u][v];
   }
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
-    for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off, 64);
-  if (lane < NV) {
-    double out = 0.0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (v == lane) out = acc[v];
-    x[row * NV + lane] = (T)out;
+  for (int v = 0; v < NV; ++v) {
+    double r = acc[v];
+    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+    if (lane == 0) red[wave][v] = r;
   }
+  __syncthreads();
+  if (t < NV)
+    x[row * NV + t] = (T)((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
 }
 
 // ---------------------------------------------------------------- interface
@@ -695,20 +709,23 @@ __global__ void k_base_copy(T* __restrict__ out, int nv, int colv,
   out[i * nv + colv] = (T)(base ? base[i] : 0.0);
 }
 
-// k_to_level on the rows of a list only (rows where m1 is nonempty, or with
-// skip1 the listed rows of m2 where m1 is empty); same arithmetic per row.
+// k_to_level on the rows of two lists only: threads [0, nr1) take the rows
+// where m1 is nonempty, threads [nr1, nr1 + nr2) the listed rows of m2
+// where m1 is empty; same arithmetic per row.
 template <typename T>
 __global__ void k_to_level_rows(T* __restrict__ out, int nv, int colv,
                                 const double* __restrict__ base,
-                                const int32_t* rows, int64_t nr, int skip1,
+                                const int32_t* rows1, int64_t nr1,
+                                const int32_t* rows2, int64_t nr2,
                                 const int64_t* rp1, const int32_t* c1,
                                 const double* v1, const double* x1, double a1,
                                 const int64_t* rp2, const int32_t* c2,
                                 const double* v2, const double* x2, double a2) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nr) return;
-  const int64_t i = rows[t];
-  if (skip1 && rp1 && rp1[i] < rp1[i + 1]) return;
+  if (t >= nr1 + nr2) return;
+  const bool second = t >= nr1;
+  const int64_t i = second ? rows2[t - nr1] : rows1[t];
+  if (second && rp1 && rp1[i] < rp1[i + 1]) return;
   double r = base ? base[i] : 0.0;
   if (rp1) {
     double s = 0.0;
@@ -889,8 +906,9 @@ void vcycle_rec(Hierarchy& H, CycleVecs<T>& cv, size_t l, bool tr,
   LevelVecs<T>& v = cv.lv[l];
   if (L.coarsest) {
     const double* Ai = tr ? H.AinvT.p : H.Ainv.p;
-    const unsigned g = (unsigned)((H.nc + 3) / 4);
-    k_coarse<T, NV><<<g, 256, 0, s>>>(Ai, H.ncpad, H.nc, v.b.p, v.xo.p);
+    if (H.nc > 0)
+      k_coarse<T, NV><<<(unsigned)H.nc, 256, 0, s>>>(Ai, H.ncpad, H.nc,
+                                                     v.b.p, v.xo.p);
     FPC_LAUNCH_CHECK();
     return;
   }
@@ -1144,15 +1162,13 @@ void to_level(T* out, int nv, int colv, int64_t n, const double* base,
     // base everywhere, then the rows the coupling blocks touch
     k_base_copy<T><<<grid_for(n, 256), 256, 0, s>>>(out, nv, colv, base, n);
     const int64_t* rp2 = m2 ? m2->rowptr.p : nullptr;
-    if (m1->nact)
-      k_to_level_rows<T><<<grid_for(m1->nact, 256), 256, 0, s>>>(
-          out, nv, colv, base, m1->act.p, m1->nact, 0, m1->rowptr.p,
-          m1->col.p, m1->val.p, x1, a1, rp2, m2 ? m2->col.p : nullptr,
-          m2 ? m2->val.p : nullptr, x2, a2);
-    if (m2 && m2->nact)
-      k_to_level_rows<T><<<grid_for(m2->nact, 256), 256, 0, s>>>(
-          out, nv, colv, base, m2->act.p, m2->nact, 1, m1->rowptr.p,
-          m1->col.p, m1->val.p, x1, a1, rp2, m2->col.p, m2->val.p, x2, a2);
+    const int64_t nr2 = m2 ? m2->nact : 0;
+    if (m1->nact + nr2 > 0)
+      k_to_level_rows<T><<<grid_for(m1->nact + nr2, 256), 256, 0, s>>>(
+          out, nv, colv, base, m1->act.p, m1->nact,
+          m2 ? m2->act.p : nullptr, nr2, m1->rowptr.p, m1->col.p, m1->val.p,
+          x1, a1, rp2, m2 ? m2->col.p : nullptr, m2 ? m2->val.p : nullptr,
+          x2, a2);
     FPC_LAUNCH_CHECK();
     return;
   }
