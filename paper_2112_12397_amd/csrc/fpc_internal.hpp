@@ -166,7 +166,8 @@ struct Vrow {
 };
 
 // An apply-path operator in the layout the setup autotuner chose:
-// fmt 0 = sliced ELL (one thread per block row), fmt 1 = row groups.
+// fmt 0 = sliced ELL (one thread per block row), fmt 1 = row groups; the
+// batched operators use fmt 1 for one wavefront per row and fmt 2 for four.
 template <typename T>
 struct Op {
   int fmt = 0;
@@ -306,6 +307,10 @@ void dense_pad(const double* A, int64_t n, int64_t npad, double* D,
 constexpr int kMaxKrylov = 64;
 // right-hand sides of one batched solve (the widest interleaved cycle)
 constexpr int kMaxBatch = 32;
+// Chunk width of the row-group layout of batched operators with long rows
+// (lanes per row splitting its blocks; the other 64 / 8 lanes of a
+// wavefront split the columns).
+constexpr int kBatchRowGroup = 8;
 
 // ---------------------------------------------------------------- k_grad
 // int32 words of work area the transmissibility gradient needs.

@@ -821,22 +821,36 @@ fpc_status fgmres(fpc_handle* h, int trans, const double* b, double* x,
 }
 
 // ------------------------------------------------------------- batches
+// Operators of the batched V-cycle: sliced ELL, or for rows of 32 blocks
+// and more on average (the restrictions, coarse operators) the row-group
+// layout read by one wavefront per row, by four from 256 blocks on (the
+// restriction onto the coarsest level has a few hundred rows of about a
+// thousand blocks).
+template <typename T>
+void batch_op(const Bsr& a, Op<T>& op, hipStream_t s) {
+  if (a.nbr > 0 && a.nnzb >= 32 * a.nbr) {
+    op.fmt = a.nnzb >= 256 * a.nbr ? 2 : 1;
+    bsr_to_vrow(a, kBatchRowGroup, op.v, s);
+  } else {
+    op.fmt = 0;
+    bsr_to_sell(a, op.s, s);
+  }
+}
+
 void ensure_batch_ops(fpc_handle* h) {
   hipStream_t s = h->stream;
   const bool fp32 = h->opt.precision == FPC_FP32_PREC;
   for (Level& L : h->amg.L) {
     if (L.coarsest) continue;
-    if (fp32 ? L.gA.s.nrows != 0 : L.bA.s.nrows != 0) continue;
+    if (fp32 ? L.gA.rows() != 0 : L.bA.rows() != 0) continue;
     if (fp32) {
-      L.gA.fmt = L.gP.fmt = L.gR.fmt = 0;
-      bsr_to_sell(L.A, L.gA.s, s);
-      bsr_to_sell(L.P, L.gP.s, s);
-      bsr_to_sell(L.R, L.gR.s, s);
+      batch_op(L.A, L.gA, s);
+      batch_op(L.P, L.gP, s);
+      batch_op(L.R, L.gR, s);
     } else {
-      L.bA.fmt = L.bP.fmt = L.bR.fmt = 0;
-      bsr_to_sell(L.A, L.bA.s, s);
-      bsr_to_sell(L.P, L.bP.s, s);
-      bsr_to_sell(L.R, L.bR.s, s);
+      batch_op(L.A, L.bA, s);
+      batch_op(L.P, L.bP, s);
+      batch_op(L.R, L.bR, s);
     }
   }
   FPC_HIP(hipStreamSynchronize(s));

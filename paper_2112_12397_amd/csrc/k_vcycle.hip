@@ -586,6 +586,115 @@ __global__ __launch_bounds__(256) void k_vrow(VrowView<T> A, Load ld, Epi epi) {
   }
 }
 
+// Many columns on the row-group layout (operators with long rows, such as
+// the restrictions): one wavefront per block row; lane = g + G cg with G =
+// kBatchRowGroup, the G lanes g split the row's blocks (chunks of G,
+// component-major, so the G lanes of a column group read G consecutive
+// words and the 8 column groups share them) and column group cg takes the
+// NV / 8 consecutive columns from v0 = cg NV / 8 (16- or 32-byte x loads
+// for 32 columns); the G partial sums are combined by shuffles and lane
+// g = 0 of each group runs the epilogue.
+template <typename T, int BR, int BC, int NV, int WPR, class Load, class Epi>
+__global__ __launch_bounds__(256) void k_vrow_cols(VrowView<T> A, Load ld,
+                                                   Epi epi) {
+  constexpr int G = kBatchRowGroup;
+  constexpr int CPL = NV / (64 / G);
+  static_assert(CPL >= 1 && CPL * (64 / G) == NV, "one wavefront per row");
+  // WPR wavefronts per row (rows of hundreds of blocks): wavefront h takes
+  // chunks h, h + WPR, ...; their sums are added in order through LDS
+  __shared__ T red[WPR > 1 ? 4 : 1][64 / G][CPL * BR];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int wave = threadIdx.x >> 6;
+  const int64_t row = blk * (4 / WPR) + wave / WPR;
+  const int h = wave % WPR;
+  const bool live = row < A.nrows;
+  if (WPR == 1 && !live) return;
+  const int lane = threadIdx.x & 63;
+  const int g = lane % G, cg = lane / G;
+  const int v0 = cg * CPL;
+  T acc[CPL][BR];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u)
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[u][i] = T(0);
+  if (live) {
+    const int len = A.row_len[row];
+    const int64_t c0 = A.chunk_ptr[row];
+    for (int k0 = h * G; k0 < len; k0 += G * WPR) {
+      if (k0 + g < len) {
+        const int64_t grp = (c0 + k0 / G) * (int64_t)G;
+        const int64_t c = A.col[grp + g];
+        const T* __restrict__ vb = A.val + grp * (BR * BC) + g;
+        T m[BR * BC];
+#pragma unroll
+        for (int q = 0; q < BR * BC; ++q) m[q] = vb[(int64_t)q * G];
+        T xv[BC][CPL];
+        if constexpr (CPL > 1) {
+#pragma unroll
+          for (int j = 0; j < BC; ++j) {
+            const XPack<T, CPL> xp = *reinterpret_cast<const XPack<T, CPL>*>(
+                ld.x + (c * BC + j) * NV + v0);
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) xv[j][u] = xp.v[u];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < BC; ++j) xv[j][0] = ld(c * BC + j, v0);
+        }
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+#pragma unroll
+          for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) acc[u][i] += m[i * BC + j] * xv[j][u];
+      }
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+#pragma unroll
+      for (int i = 0; i < BR; ++i) acc[u][i] += __shfl_xor(acc[u][i], off, 64);
+  if constexpr (WPR > 1) {
+    if (g == 0)
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+#pragma unroll
+        for (int i = 0; i < BR; ++i) red[wave][cg][u * BR + i] = acc[u][i];
+    __syncthreads();
+    if (h != 0 || !live) return;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+#pragma unroll
+      for (int i = 0; i < BR; ++i) {
+        T t = red[wave][cg][u * BR + i];
+#pragma unroll
+        for (int q = 1; q < WPR; ++q) t += red[wave + q][cg][u * BR + i];
+        acc[u][i] = t;
+      }
+  }
+  if (g == 0) epi_cols<T, BR, NV, CPL>(epi, row, v0, acc);
+}
+
+template <typename T, int BR, int BC, int NV, class Load, class Epi>
+void launch_vrow_cols(const Vrow<T>& A, int wpr, Load ld, Epi epi,
+                      hipStream_t s) {
+  if (A.nrows == 0) return;
+  if (A.G != kBatchRowGroup)
+    throw Error(FPC_ERR_ARG, "launch_vrow_cols: row-group width");
+  if (wpr == 4) {
+    const unsigned grid = (unsigned)A.nrows;
+    k_vrow_cols<T, BR, BC, NV, 4, Load, Epi><<<grid, 256, 0, s>>>(vview(A), ld,
+                                                                  epi);
+  } else {
+    const unsigned grid = (unsigned)((A.nrows + 3) / 4);
+    k_vrow_cols<T, BR, BC, NV, 1, Load, Epi><<<grid, 256, 0, s>>>(vview(A), ld,
+                                                                  epi);
+  }
+  FPC_LAUNCH_CHECK();
+}
+
 template <typename T, int BR, int BC, int NV, int G, class Load, class Epi>
 void launch_vrow(const Vrow<T>& A, Load ld, Epi epi, hipStream_t s) {
   if (A.nrows == 0) return;
@@ -598,9 +707,11 @@ void launch_vrow(const Vrow<T>& A, Load ld, Epi epi, hipStream_t s) {
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
 void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
   if constexpr (NV > 2) {
-    // many columns: one thread per (row, column), sliced ELL only
-    if (op.fmt != 0) throw Error(FPC_ERR_ARG, "batched operator layout");
-    return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
+    // many columns: sliced ELL (one thread per row and column group), or
+    // one (fmt 1) or four (fmt 2) wavefronts per row on the row-group layout
+    if (op.fmt == 0) return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
+    return launch_vrow_cols<T, BR, BC, NV>(op.v, op.fmt == 2 ? 4 : 1, ld, epi,
+                                           s);
   } else {
   if (op.fmt == 0) return launch_sell<T, BR, BC, NV>(op.s, ld, epi, s);
   switch (op.v.G) {
