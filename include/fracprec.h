@@ -117,7 +117,8 @@ typedef struct {
   int graphs;              /* 1: the batched V-cycle is captured once into  */
                            /* a HIP graph and replayed (default); 0: eager  */
   int ortho;               /* FPC_DCGS2 (default), FPC_CGS2 or FPC_MGS;     */
-                           /* batched solves always use CGS2                */
+                           /* batched solves use DCGS2, or CGS2 for either  */
+                           /* of the other two                              */
   fpc_amg_options amg;
 } fpc_options;
 

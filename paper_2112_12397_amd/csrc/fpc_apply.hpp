@@ -103,6 +103,25 @@ void bgmres_step(double* H, double* cs, double* sn, double* g,
                  const double* h1, const double* h2, const double* nrm2,
                  const double* nrm0, int j, int m, int KB, const int* active,
                  double* scal, double* est, int* brk, hipStream_t s);
+// Batched delayed Gram-Schmidt (the dcgs_* steps per column of the
+// interleaved block; D and P hold column c of output o at [o * KB + c], sc
+// holds the provisional estimates [0, KB), the final ones [KB, 2 KB) and
+// the step codes [2 KB, 3 KB) as doubles).
+bool bdcgs_supported(int64_t n, int KB);
+void bdcgs_dot(const double* V, int64_t ldv, int nv, const double* U,
+               const double* W, int64_t n, int KB, double* part, double* D,
+               hipStream_t s);
+void bdcgs_finish(const double* D, int nv, bool fresh, const int* needfin,
+                  double* H, int m, double* cs, double* sn, double* g,
+                  double* P, double* rho, double* ww, double* sc, int* pf,
+                  const int* active, int KB, hipStream_t s);
+void bdcgs_update(double* V, int64_t ldv, int j, const double* D,
+                  const double* P, const double* rho, const double* W,
+                  int64_t n, int KB, double* part, hipStream_t s);
+void bdcgs_peek(const double* part, int64_t n, double* H, int m, double* cs,
+                double* sn, double* g, const double* P, int j,
+                const double* ww, double* sc, int* pf, const int* active,
+                int KB, hipStream_t s);
 void bgmres_init(double* g, int m, int KB, const double* beta2,
                  const int* active, double* scal, hipStream_t s);
 void btrisolve(const double* H, const double* g, double* y, const int* kc,

@@ -203,7 +203,8 @@ struct BatchWork {
   DevBuf<double> V, Z, W, R, Bi, Xi, tt;
   DevBuf<double> H, cs, sn, g, y, yneg, h1, h2, nrm2, beta2, scal, est,
       bnorm2, partials;
-  DevBuf<int> active, kc, brk;
+  DevBuf<double> D, P, rho, ww, sc;  // delayed Gram-Schmidt
+  DevBuf<int> active, kc, brk, pf, needfin;
 };
 
 }  // namespace fpc

@@ -884,10 +884,17 @@ BatchWork& batch_work(fpc_handle* h, int KB) {
   w->scal.alloc(KB);
   w->est.alloc(KB);
   w->bnorm2.alloc(KB);
-  w->partials.alloc(bdot_partials(m + 1, KB));
+  w->partials.alloc(bdot_partials(2 * (m + 1) + 1, KB));
+  w->D.alloc((int64_t)(2 * (m + 1) + 1) * KB);
+  w->P.alloc((int64_t)(m + 1) * KB);
+  w->rho.alloc(KB);
+  w->ww.alloc(KB);
+  w->sc.alloc(3 * KB);
   w->active.alloc(KB);
   w->kc.alloc(KB);
   w->brk.alloc(KB);
+  w->pf.alloc(KB);
+  w->needfin.alloc(KB);
   psolve_batch_buffers(h->ps, KB);
   return *w;
 }
@@ -962,7 +969,9 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
   std::vector<double> bn(KB), hbuf(KB);
   std::vector<int> act(KB, 0), kc(KB, 0), brk(KB, 0), done(KB, 0),
       conv(KB, 0), its(KB, 0), cycles(KB, 0);
-  std::vector<double> truer(KB, 0.0), estv(KB, 0.0);
+  std::vector<double> truer(KB, 0.0), estv(KB, 0.0), hs(3 * KB, 0.0);
+  std::vector<int> pfh(KB, 1), nf(KB, 0);
+  const bool dcgs = h->opt.ortho == FPC_DCGS2 && bdcgs_supported(N, KB);
   FPC_HIP(hipMemcpyAsync(bn.data(), w.bnorm2.p, KB * sizeof(double),
                          hipMemcpyDeviceToHost, s));
   FPC_HIP(hipStreamSynchronize(s));
@@ -1007,46 +1016,137 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
     for (int c = 0; c < KB; ++c)
       if (act[c]) ++cycles[c];
     int jlast = 0;
-    for (int j = 0; j < m; ++j) {
+    if (dcgs) {
+      // delayed Gram-Schmidt per column, as dcgs2_cycle: the decision on the
+      // provisional estimate, a finalizing pass for the columns that stop
+      fill_i32(w.pf.p, 1, KB, s);
+      std::fill(pfh.begin(), pfh.end(), 1);
       const int64_t stride = N * KB;
-      double* Vj = w.V.p + (int64_t)j * stride;
-      double* Zj = w.Z.p + (int64_t)j * stride;
-      apply_b(h, w, Vj, Zj);
-      matvec_b(h, Zj, w.W.p, KB);
-      // classical Gram-Schmidt twice in three passes, per column: h1 with
-      // |w|^2 (in h1 row j + 1), w -= V h1 with h2, w -= V h2 with |w|^2
-      bcgs_dot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h1.p, s);
-      bcgs_axpy_dot(w.V.p, stride, j + 1, w.h1.p, w.W.p, N, KB, w.partials.p,
-                    w.h2.p, s);
-      bcgs_axpy_norm(w.V.p, stride, j + 1, w.h2.p, w.W.p, N, KB, w.partials.p,
-                     w.nrm2.p, s);
-      bgmres_step(w.H.p, w.cs.p, w.sn.p, w.g.p, w.h1.p, w.h2.p, w.nrm2.p,
-                  w.h1.p + (int64_t)(j + 1) * KB, j, m, KB, w.active.p,
-                  w.scal.p, w.est.p, w.brk.p, s);
-      bscale(w.W.p, w.scal.p, w.V.p + (int64_t)(j + 1) * stride, N, KB, s);
-      FPC_HIP(hipMemcpyAsync(estv.data(), w.est.p, KB * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      FPC_HIP(hipMemcpyAsync(brk.data(), w.brk.p, KB * sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-      FPC_HIP(hipStreamSynchronize(s));
-      ++total;
-      jlast = j;
-      bool changed = false, still = false;
-      for (int c = 0; c < KB; ++c) {
-        if (!act[c]) continue;
-        ++its[c];
-        if (estv[c] <= rtol * bn[c] || brk[c] || its[c] >= h->opt.maxit) {
+      auto fetch = [&]() {
+        FPC_HIP(hipMemcpyAsync(hs.data(), w.sc.p, 3 * KB * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        FPC_HIP(hipStreamSynchronize(s));
+      };
+      for (int j = 0; j < m; ++j) {
+        double* Uj = w.V.p + (int64_t)j * stride;
+        double* Zj = w.Z.p + (int64_t)j * stride;
+        apply_b(h, w, Uj, Zj);
+        matvec_b(h, Zj, w.W.p, KB);
+        bdcgs_dot(w.V.p, stride, j + 1, Uj, w.W.p, N, KB, w.partials.p, w.D.p,
+                  s);
+        bdcgs_finish(w.D.p, j + 1, true, nullptr, w.H.p, m, w.cs.p, w.sn.p,
+                     w.g.p, w.P.p, w.rho.p, w.ww.p, w.sc.p, w.pf.p,
+                     w.active.p, KB, s);
+        bdcgs_update(w.V.p, stride, j, w.D.p, w.P.p, w.rho.p, w.W.p, N, KB,
+                     w.partials.p, s);
+        bdcgs_peek(w.partials.p, N, w.H.p, m, w.cs.p, w.sn.p, w.g.p, w.P.p, j,
+                   w.ww.p, w.sc.p, w.pf.p, w.active.p, KB, s);
+        fetch();
+        ++total;
+        jlast = j;
+        bool changed = false, any_nf = false;
+        auto stop = [&](int c, int kcol) {
           act[c] = 0;
-          kc[c] = j + 1;
+          kc[c] = kcol;
           changed = true;
-        } else {
-          still = true;
+        };
+        for (int c = 0; c < KB; ++c) {
+          nf[c] = 0;
+          if (!act[c]) continue;
+          ++its[c];
+          const double tol = rtol * bn[c];
+          const int code = (int)hs[2 * KB + c];
+          const bool was_fin = j > 0 && !pfh[c];  // column j - 1 made final now
+          pfh[c] = 0;
+          if (code == 2) {  // u_j inside the basis: column j - 1 is the last
+            estv[c] = hs[KB + c];
+            pfh[c] = 1;
+            stop(c, j);
+          } else if (code == 1) {  // breakdown: column j committed as it is
+            estv[c] = hs[KB + c];
+            pfh[c] = 1;
+            stop(c, j + 1);
+          } else if (was_fin && hs[KB + c] <= tol) {
+            estv[c] = hs[KB + c];
+            stop(c, j);
+          } else {
+            estv[c] = hs[c];
+            const bool last = j + 1 == m || its[c] >= h->opt.maxit ||
+                              total >= h->opt.maxit;
+            if (hs[c] <= tol || last) {
+              nf[c] = 1;
+              any_nf = true;
+            }
+          }
         }
+        if (any_nf) {
+          FPC_HIP(hipMemcpyAsync(w.needfin.p, nf.data(), KB * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+          bdcgs_dot(w.V.p, stride, j + 2, w.V.p + (int64_t)(j + 1) * stride,
+                    nullptr, N, KB, w.partials.p, w.D.p, s);
+          bdcgs_finish(w.D.p, j + 2, false, w.needfin.p, w.H.p, m, w.cs.p,
+                       w.sn.p, w.g.p, w.P.p, w.rho.p, w.ww.p, w.sc.p, w.pf.p,
+                       w.active.p, KB, s);
+          fetch();
+          for (int c = 0; c < KB; ++c) {
+            if (!nf[c]) continue;
+            pfh[c] = 1;
+            estv[c] = hs[KB + c];
+            const bool last = j + 1 == m || its[c] >= h->opt.maxit ||
+                              total >= h->opt.maxit;
+            if (hs[KB + c] <= rtol * bn[c] || last || (int)hs[2 * KB + c] == 2)
+              stop(c, j + 1);
+          }
+        }
+        bool still = false;
+        for (int c = 0; c < KB; ++c) still = still || act[c];
+        if (!still || total >= h->opt.maxit) break;
+        if (changed)
+          FPC_HIP(hipMemcpyAsync(w.active.p, act.data(), KB * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
       }
-      if (!still || total >= h->opt.maxit) break;
-      if (changed)
-        FPC_HIP(hipMemcpyAsync(w.active.p, act.data(), KB * sizeof(int),
-                               hipMemcpyHostToDevice, s));
+    } else {
+      for (int j = 0; j < m; ++j) {
+        const int64_t stride = N * KB;
+        double* Vj = w.V.p + (int64_t)j * stride;
+        double* Zj = w.Z.p + (int64_t)j * stride;
+        apply_b(h, w, Vj, Zj);
+        matvec_b(h, Zj, w.W.p, KB);
+        // classical Gram-Schmidt twice in three passes, per column: h1 with
+        // |w|^2 (in h1 row j + 1), w -= V h1 with h2, w -= V h2 with |w|^2
+        bcgs_dot(w.V.p, stride, j + 1, w.W.p, N, KB, w.partials.p, w.h1.p, s);
+        bcgs_axpy_dot(w.V.p, stride, j + 1, w.h1.p, w.W.p, N, KB, w.partials.p,
+                      w.h2.p, s);
+        bcgs_axpy_norm(w.V.p, stride, j + 1, w.h2.p, w.W.p, N, KB, w.partials.p,
+                       w.nrm2.p, s);
+        bgmres_step(w.H.p, w.cs.p, w.sn.p, w.g.p, w.h1.p, w.h2.p, w.nrm2.p,
+                    w.h1.p + (int64_t)(j + 1) * KB, j, m, KB, w.active.p,
+                    w.scal.p, w.est.p, w.brk.p, s);
+        bscale(w.W.p, w.scal.p, w.V.p + (int64_t)(j + 1) * stride, N, KB, s);
+        FPC_HIP(hipMemcpyAsync(estv.data(), w.est.p, KB * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        FPC_HIP(hipMemcpyAsync(brk.data(), w.brk.p, KB * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+        FPC_HIP(hipStreamSynchronize(s));
+        ++total;
+        jlast = j;
+        bool changed = false, still = false;
+        for (int c = 0; c < KB; ++c) {
+          if (!act[c]) continue;
+          ++its[c];
+          if (estv[c] <= rtol * bn[c] || brk[c] || its[c] >= h->opt.maxit) {
+            act[c] = 0;
+            kc[c] = j + 1;
+            changed = true;
+          } else {
+            still = true;
+          }
+        }
+        if (!still || total >= h->opt.maxit) break;
+        if (changed)
+          FPC_HIP(hipMemcpyAsync(w.active.p, act.data(), KB * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+      }
     }
     for (int c = 0; c < KB; ++c)
       if (act[c]) kc[c] = jlast + 1;

@@ -321,6 +321,256 @@ __global__ __launch_bounds__(BT) void k_bcgs_axpy_norm(
   bblock_partials<1>(acc, 1, false, 0.0, KB, part);
 }
 
+// ---- Batched delayed Gram-Schmidt: the dcgs_* steps of the single solve,
+// per column of the interleaved block (element t = r * KB + c), with
+// per-column masks: active (column still iterating), pf (its last Hessenberg
+// column is final) and, for the finalizing pass, needfin.
+
+// Per-column block partials of two per-vector sums, outputs ou + i and
+// ow + i (i < cnt), and optionally an extra one (output oe):
+// part[(o * G + b) * KB + c].
+template <int NV, bool TWO>
+__device__ inline void bblock_partials2(const double (&au)[NV],
+                                        const double (&aw)[NV], int cnt,
+                                        int ou, int ow, bool has_extra,
+                                        double extra, int oe, int KB,
+                                        double* __restrict__ part) {
+  __shared__ double sh[BT];
+  const int rl = threadIdx.x / KB, nrl = BT / KB;
+  const bool lane_ok = rl < nrl;
+  const int64_t G = gridDim.x;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    if (i < cnt) {
+      double t = bwsum_cols(sh, lane_ok ? au[i] : 0.0, KB, nrl);
+      if ((int)threadIdx.x < KB)
+        part[((int64_t)(ou + i) * G + blockIdx.x) * KB + threadIdx.x] = t;
+      if (TWO) {
+        t = bwsum_cols(sh, lane_ok ? aw[i] : 0.0, KB, nrl);
+        if ((int)threadIdx.x < KB)
+          part[((int64_t)(ow + i) * G + blockIdx.x) * KB + threadIdx.x] = t;
+      }
+    }
+  }
+  if (has_extra) {
+    const double t = bwsum_cols(sh, lane_ok ? extra : 0.0, KB, nrl);
+    if ((int)threadIdx.x < KB)
+      part[((int64_t)oe * G + blockIdx.x) * KB + threadIdx.x] = t;
+  }
+}
+
+// Per column: <V_{i0+i}, U> (output i0 + i) and, with W, <V_{i0+i}, W>
+// (output nv + i0 + i), i < cnt; with extra also <W, W> (output 2 nv).
+template <int NV, bool WW>
+__global__ __launch_bounds__(BT) void k_bdcgs_dot(
+    const double* __restrict__ V, int64_t ldv, int i0, int cnt, int nv,
+    const double* __restrict__ U, const double* __restrict__ W, int64_t n,
+    int KB, bool extra, double* __restrict__ part) {
+  const int rl = threadIdx.x / KB, c = threadIdx.x % KB, nrl = BT / KB;
+  double au[NV], aw[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) au[i] = aw[i] = 0.0;
+  double ww = 0.0;
+  const double* Vc = V + (int64_t)i0 * ldv;
+  if (rl < nrl) {
+    const uint64_t stride = (uint64_t)ldv * sizeof(double);
+    for (int64_t r = (int64_t)blockIdx.x * nrl + rl; r < n;
+         r += (int64_t)gridDim.x * nrl) {
+      const uint32_t t = (uint32_t)(r * KB + c);
+      const uint32_t off = t * (uint32_t)sizeof(double);
+      const double uk = U[t];
+      const double wk = WW ? W[t] : 0.0;
+      uint64_t st = stride;
+      asm volatile("" : "+s"(st));
+      double v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = cgs_load(cgs_base(Vc, st, i, cnt), off);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        au[i] += v[i] * uk;
+        if (WW) aw[i] += v[i] * wk;
+      }
+      ww += wk * wk;
+    }
+  }
+  bblock_partials2<NV, WW>(au, aw, cnt, i0, nv + i0, WW && extra, ww, 2 * nv,
+                           KB, part);
+}
+
+// Per column: v_j = (u_j - sum_{i<j} a_i V_i) / rho into slot j and
+// u_{j+1} = W - sum_{i<j} b_i V_i - h_j v_j into slot j + 1, with the
+// partials of |u_{j+1}|^2; a(i, c) = D[i KB + c], b(i, c) = P[i KB + c],
+// h_j = P[j KB + c] (v_j = 0 where rho = 0).
+template <int NV>
+__global__ __launch_bounds__(BT) void k_bdcgs_update(
+    double* V, int64_t ldv, int j, const double* __restrict__ D,
+    const double* __restrict__ P, const double* __restrict__ rho,
+    const double* __restrict__ W, int64_t n, int KB,
+    double* __restrict__ part) {
+  __shared__ double2 ab[NV * 32];
+  for (int q = threadIdx.x; q < NV * KB; q += BT) {
+    const int i = q / KB;
+    ab[q] = i < j ? make_double2(D[q], P[q]) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int rl = threadIdx.x / KB, c = threadIdx.x % KB, nrl = BT / KB;
+  const double rc = rho[c];
+  const double hj = P[(int64_t)j * KB + c];
+  double* uj = V + (int64_t)j * ldv;
+  double* un = V + (int64_t)(j + 1) * ldv;
+  const int cnt = j > 0 ? j : 1;  // j = 0: slot 0 loaded with weight 0
+  double acc[1] = {0.0};
+  if (rl < nrl) {
+    const uint64_t stride = (uint64_t)ldv * sizeof(double);
+    for (int64_t r = (int64_t)blockIdx.x * nrl + rl; r < n;
+         r += (int64_t)gridDim.x * nrl) {
+      const uint32_t t = (uint32_t)(r * KB + c);
+      const uint32_t off = t * (uint32_t)sizeof(double);
+      uint64_t st = stride;
+      asm volatile("" : "+s"(st)::"memory");
+      double v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = cgs_load(cgs_base(V, st, i, cnt), off);
+      double tu = uj[t];
+      double sw = W[t];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const double2 cf = ab[i * KB + c];
+        tu -= cf.x * v[i];
+        sw -= cf.y * v[i];
+      }
+      const double vj = rc != 0.0 ? tu / rc : 0.0;
+      sw -= hj * vj;
+      uj[t] = vj;
+      un[t] = sw;
+      acc[0] += sw * sw;
+    }
+  }
+  bblock_partials<1>(acc, 1, false, 0.0, KB, part);
+}
+
+// Column c's Givens step on column cc of its Hessenberg matrix (col in
+// private memory, rotations read from cs / sn); returns |g_{cc+1}| and,
+// with commit, stores the rotation, the column and g.
+__device__ inline double bgivens_col(double* col, int cc, double* Hc, int m,
+                                     double* csc, double* snc, double* gc,
+                                     bool commit) {
+  for (int i = 0; i < cc; ++i) {
+    const double t = csc[i] * col[i] + snc[i] * col[i + 1];
+    col[i + 1] = -snc[i] * col[i] + csc[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double r = hypot(col[cc], col[cc + 1]);
+  const double cj = r != 0.0 ? col[cc] / r : 1.0;
+  const double sj = r != 0.0 ? col[cc + 1] / r : 0.0;
+  const double gj = gc[cc];
+  if (commit) {
+    csc[cc] = cj;
+    snc[cc] = sj;
+    col[cc] = r;
+    col[cc + 1] = 0.0;
+    gc[cc + 1] = -sj * gj;
+    gc[cc] = cj * gj;
+    for (int i = 0; i <= cc + 1; ++i) Hc[(int64_t)i * m + cc] = col[i];
+  }
+  return fabs(sj * gj);
+}
+
+// After a dot pass over nv = j + 1 vectors (slot j = u_j included), per
+// active column: rho_j (1 for j = 0); Hessenberg column j - 1 made final
+// when fresh and pf[c] = 0, or when needfin[c] (fresh = 0): estimate in
+// sc[KB + c], code 2 where rho_j = 0, pf[c] = 1; with fresh the first
+// projection of column j into P, <W, W> into ww[c], pf[c] = 0.  sc[2 KB + c]
+// holds the code (0, 1 breakdown at step j, 2).  Inactive columns get rho =
+// 0 and a zero projection.
+__global__ void k_bdcgs_finish(const double* __restrict__ D, int nv, int fresh,
+                               const int* __restrict__ needfin, double* H,
+                               int m, double* cs, double* sn, double* g,
+                               double* P, double* rho, double* ww, double* sc,
+                               int* pf, const int* __restrict__ active,
+                               int KB) {
+  const int c = threadIdx.x;
+  if (c >= KB) return;
+  const int j = nv - 1;
+  if (!active[c]) {
+    if (fresh) {
+      rho[c] = 0.0;
+      for (int i = 0; i <= j; ++i) P[(int64_t)i * KB + c] = 0.0;
+    }
+    sc[2 * KB + c] = 0.0;
+    return;
+  }
+  double aa = 0.0, ab = 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = D[(int64_t)i * KB + c];
+    aa += a * a;
+    if (fresh) ab += a * D[(int64_t)(nv + i) * KB + c];
+  }
+  const double r2 = D[(int64_t)j * KB + c] - aa;
+  const double rh = j == 0 ? 1.0 : (r2 > 0.0 ? sqrt(r2) : 0.0);
+  rho[c] = rh;
+  int code = 0;
+  const bool fin = fresh ? (j > 0 && !pf[c]) : (needfin[c] != 0);
+  if (fin && j > 0) {
+    double col[kMaxKrylov + 2];
+    for (int i = 0; i < j; ++i)
+      col[i] = P[(int64_t)i * KB + c] + D[(int64_t)i * KB + c];
+    col[j] = rh;
+    sc[KB + c] = bgivens_col(col, j - 1, H + (int64_t)c * (m + 1) * m, m,
+                             cs + (int64_t)c * m, sn + (int64_t)c * m,
+                             g + (int64_t)c * (m + 1), true);
+    if (rh == 0.0) code = 2;
+    pf[c] = 1;
+  }
+  if (fresh) {
+    P[(int64_t)j * KB + c] =
+        rh != 0.0 ? (D[(int64_t)(nv + j) * KB + c] - ab) / rh : 0.0;
+    for (int i = 0; i < j; ++i)
+      P[(int64_t)i * KB + c] = D[(int64_t)(nv + i) * KB + c];
+    ww[c] = D[(int64_t)(2 * nv) * KB + c];
+    pf[c] = 0;
+  }
+  sc[2 * KB + c] = code;
+}
+
+// After the update pass: per active column (code != 2) |u_{j+1}|^2 reduced
+// from the partials (in the order of k_bmdot_reduce), the provisional column
+// j (P, subdiagonal nu_j) rotated for the estimate sc[c]; nu_j <= 1e-14 |W|
+// is a breakdown: the column is committed, sc[KB + c] = estimate, code 1,
+// pf[c] = 1.
+__global__ __launch_bounds__(BT) void k_bdcgs_peek(
+    const double* __restrict__ part, int np, double* H, int m, double* cs,
+    double* sn, double* g, const double* __restrict__ P, int j,
+    const double* __restrict__ ww, double* sc, int* pf,
+    const int* __restrict__ active, int KB) {
+  __shared__ double sh[BT];
+  const int ql = threadIdx.x / KB, c0 = threadIdx.x % KB, nql = BT / KB;
+  double t = 0.0;
+  if (ql < nql)
+    for (int q = ql; q < np; q += nql) t += part[(int64_t)q * KB + c0];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c >= KB || !active[c] || sc[2 * KB + c] == 2.0) return;
+  double nu2 = 0.0;
+  for (int q = 0; q < nql; ++q) nu2 += sh[q * KB + c];
+  const double nu = sqrt(fmax(nu2, 0.0));
+  const double w0 = sqrt(fmax(ww[c], 0.0));
+  const bool bd = !(nu > 1e-14 * w0);
+  double col[kMaxKrylov + 2];
+  for (int i = 0; i <= j; ++i) col[i] = P[(int64_t)i * KB + c];
+  col[j + 1] = nu;
+  const double est = bgivens_col(col, j, H + (int64_t)c * (m + 1) * m, m,
+                                 cs + (int64_t)c * m, sn + (int64_t)c * m,
+                                 g + (int64_t)c * (m + 1), bd);
+  sc[c] = est;
+  if (bd) {
+    sc[KB + c] = est;
+    sc[2 * KB + c] = 1.0;
+    pf[c] = 1;
+  }
+}
+
 __global__ void k_bscale(const double* __restrict__ x,
                          const double* __restrict__ scal, double* __restrict__ y,
                          int64_t n, int KB) {
@@ -578,6 +828,80 @@ void bmaxpy(const double* V, int64_t ldv, int nv, const double* h, double* W,
   unsigned g = grid_for(n * KB, BT);
   if (g > 16384) g = 16384;
   k_bmaxpy<<<g, BT, 0, s>>>(V, ldv, nv, h, W, n, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+// Largest vector count of one batched delayed dot launch (two sums per
+// vector in registers).
+constexpr int kBdcgsChunk = 32;
+
+bool bdcgs_supported(int64_t n, int KB) { return n * KB < (int64_t(1) << 29); }
+
+void bdcgs_dot(const double* V, int64_t ldv, int nv, const double* U,
+               const double* W, int64_t n, int KB, double* part, double* D,
+               hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov || KB < 1 || KB > 32 || !bdcgs_supported(n, KB))
+    throw Error(FPC_ERR_ARG, "bdcgs_dot size");
+  const int64_t G = bcgs_blocks(n, KB);
+  for (int i0 = 0; i0 < nv; i0 += kBdcgsChunk) {
+    const int cnt = std::min(kBdcgsChunk, nv - i0);
+    const bool extra = i0 == 0;
+    switch ((cnt + 7) / 8) {
+#define FPC_CASE(B)                                                          \
+  case B / 8:                                                                \
+    if constexpr (B <= kBdcgsChunk) {                                        \
+      if (W)                                                                 \
+        k_bdcgs_dot<B, true><<<(unsigned)G, BT, 0, s>>>(                     \
+            V, ldv, i0, cnt, nv, U, W, n, KB, extra, part);                  \
+      else                                                                   \
+        k_bdcgs_dot<B, false><<<(unsigned)G, BT, 0, s>>>(                    \
+            V, ldv, i0, cnt, nv, U, W, n, KB, extra, part);                  \
+    }                                                                        \
+    break;
+      FPC_BCGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+    }
+    FPC_LAUNCH_CHECK();
+  }
+  k_bmdot_reduce<<<W ? 2 * nv + 1 : nv, BT, 0, s>>>(part, (int)G, KB, D);
+  FPC_LAUNCH_CHECK();
+}
+
+void bdcgs_finish(const double* D, int nv, bool fresh, const int* needfin,
+                  double* H, int m, double* cs, double* sn, double* g,
+                  double* P, double* rho, double* ww, double* sc, int* pf,
+                  const int* active, int KB, hipStream_t s) {
+  if (nv < 1 || nv > kMaxKrylov || KB < 1 || KB > 64)
+    throw Error(FPC_ERR_ARG, "bdcgs_finish size");
+  k_bdcgs_finish<<<1, 64, 0, s>>>(D, nv, fresh ? 1 : 0, needfin, H, m, cs, sn,
+                                  g, P, rho, ww, sc, pf, active, KB);
+  FPC_LAUNCH_CHECK();
+}
+
+void bdcgs_update(double* V, int64_t ldv, int j, const double* D,
+                  const double* P, const double* rho, const double* W,
+                  int64_t n, int KB, double* part, hipStream_t s) {
+  if (j < 0 || j + 1 > kMaxKrylov || KB < 1 || KB > 32 || !bdcgs_supported(n, KB))
+    throw Error(FPC_ERR_ARG, "bdcgs_update size");
+  const int64_t G = bcgs_blocks(n, KB);
+  switch ((std::max(j, 1) + 7) / 8) {
+#define FPC_CASE(B)                                                          \
+  case B / 8:                                                                \
+    k_bdcgs_update<B><<<(unsigned)G, BT, 0, s>>>(V, ldv, j, D, P, rho, W, n, \
+                                                 KB, part);                  \
+    break;
+    FPC_BCGS_BUCKETS(FPC_CASE)
+#undef FPC_CASE
+  }
+  FPC_LAUNCH_CHECK();
+}
+
+void bdcgs_peek(const double* part, int64_t n, double* H, int m, double* cs,
+                double* sn, double* g, const double* P, int j,
+                const double* ww, double* sc, int* pf, const int* active,
+                int KB, hipStream_t s) {
+  k_bdcgs_peek<<<1, BT, 0, s>>>(part, (int)bcgs_blocks(n, KB), H, m, cs, sn,
+                                g, P, j, ww, sc, pf, active, KB);
   FPC_LAUNCH_CHECK();
 }
 

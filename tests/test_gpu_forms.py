@@ -72,18 +72,52 @@ def test_batch_matches_oracle_and_single(torch, c1, k, precision):
           f"{max(errs):.2e}")
 
 
-def test_batch_long_cycle(torch):
+@pytest.mark.parametrize("k", [5])
+def test_batch_short_cycles(torch, c1, k):
+    """Batched FGMRES(7) with the delayed Gram-Schmidt: columns of different
+    norms restart at different steps, every cycle ends with the finalizing
+    pass; each column against the oracle's CGS2 FGMRES(7) (iterations
+    within 2, solution within 1e-5) and its own single solve."""
+    from paper_2112_12397_amd import solver_from_system
+    s = c1
+    pc = _c1_oracle(s)
+    sol = solver_from_system(s, restart=7)
+    B = rhs_batch(s, k=k)
+    Bt = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
+    X, infos, status = sol.solve_batch(Bt)
+    assert status == "FPC_OK"
+    J = s.jacobian()
+    Xn = X.cpu().numpy()
+    for c in range(k):
+        xo, io = oracle.fgmres(pc.matvec, pc.apply, B[:, c], rtol=1e-8,
+                               restart=7, ortho="cgs2")
+        x1, i1 = sol.solve(Bt[c].contiguous())
+        r = np.linalg.norm(B[:, c] - J @ Xn[c]) / np.linalg.norm(B[:, c])
+        assert infos[c]["converged"] == 1 and r <= 1e-8, (c, r, infos[c])
+        assert infos[c]["restarts"] > 2
+        assert abs(infos[c]["iterations"] - io.iterations) <= 2, \
+            (c, infos[c]["iterations"], io.iterations)
+        assert abs(infos[c]["iterations"] - i1["iterations"]) <= 2
+        assert _rel(Xn[c], xo) <= 1e-5
+        assert _rel(Xn[c], x1.cpu().numpy()) <= 1e-5
+
+
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
+def test_batch_long_cycle(torch, ortho):
     """Batched FGMRES(63) to 1e-9 on the long-row system with random
     right-hand sides: the oracle needs 56-57 steps in one cycle, so the
-    batched Gram-Schmidt passes go past 48 basis vectors per column (where
-    the axpy and dot passes run separately); every column against the
-    oracle (CGS2) and its single solve.  (Closer to this system's attainable
-    accuracy, about 5e-12, counts become rounding-sensitive: at 1e-10 the
-    oracle's CGS2 and MGS counts already differ by up to 5.)"""
+    batched Gram-Schmidt passes go past 48 basis vectors per column (CGS2:
+    the axpy and dot passes run separately there; delayed: the dot pass in
+    two launches past 32, the finalizing pass over 57 vectors); every column
+    against the oracle (CGS2) and its single solve.  (Closer to this
+    system's attainable accuracy, about 5e-12, counts become
+    rounding-sensitive: at 1e-10 the oracle's CGS2 and MGS counts already
+    differ by up to 5.)"""
     from paper_2112_12397_amd import solver_from_system
     from systems_extra import wide_system
     s = wide_system()
-    sol = solver_from_system(s, restart=63, amg={"max_coarse": 90})
+    sol = solver_from_system(s, restart=63, ortho=ortho,
+                             amg={"max_coarse": 90})
     pc = oracle.BlockPrecond(s.blocks(), s.n_u, s.n_t, s.n_p, coords=s.coords,
                              amg_opts=oracle.AMGOptions(max_coarse=90))
     rng = np.random.default_rng(21)
