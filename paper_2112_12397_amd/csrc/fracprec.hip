@@ -1044,7 +1044,7 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
         fetch();
         ++total;
         jlast = j;
-        bool changed = false, any_nf = false;
+        bool changed = false, any_nf = false, any_last = false, others = false;
         auto stop = [&](int c, int kcol) {
           act[c] = 0;
           kc[c] = kcol;
@@ -1053,7 +1053,6 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
         for (int c = 0; c < KB; ++c) {
           nf[c] = 0;
           if (!act[c]) continue;
-          ++its[c];
           const double tol = rtol * bn[c];
           const int code = (int)hs[2 * KB + c];
           const bool was_fin = j > 0 && !pfh[c];  // column j - 1 made final now
@@ -1062,23 +1061,38 @@ fpc_status fgmres_batch(fpc_handle* h, int k, const double* B, int64_t ldb,
             estv[c] = hs[KB + c];
             pfh[c] = 1;
             stop(c, j);
-          } else if (code == 1) {  // breakdown: column j committed as it is
+            continue;
+          }
+          if (was_fin && hs[KB + c] <= tol) {
+            // column j - 1 meets the tolerance: the step only made it final
+            estv[c] = hs[KB + c];
+            stop(c, j);
+            continue;
+          }
+          ++its[c];
+          if (code == 1) {  // breakdown: column j committed as it is
             estv[c] = hs[KB + c];
             pfh[c] = 1;
             stop(c, j + 1);
-          } else if (was_fin && hs[KB + c] <= tol) {
-            estv[c] = hs[KB + c];
-            stop(c, j);
+            continue;
+          }
+          estv[c] = hs[c];
+          const bool last = j + 1 == m || its[c] >= h->opt.maxit ||
+                            total >= h->opt.maxit;
+          if (hs[c] <= tol || last) {
+            nf[c] = 1;
+            any_nf = true;
+            any_last = any_last || last;
           } else {
-            estv[c] = hs[c];
-            const bool last = j + 1 == m || its[c] >= h->opt.maxit ||
-                              total >= h->opt.maxit;
-            if (hs[c] <= tol || last) {
-              nf[c] = 1;
-              any_nf = true;
-            }
+            others = true;
           }
         }
+        // A column whose provisional estimate meets the tolerance while
+        // others go on stays one more step, whose first pass makes its
+        // column final at no extra cost (the block is processed whole); the
+        // finalizing pass runs when no active column goes on, or at the end
+        // of the cycle or of the iteration budget.
+        if (any_nf && !any_last && others) any_nf = false;
         if (any_nf) {
           FPC_HIP(hipMemcpyAsync(w.needfin.p, nf.data(), KB * sizeof(int),
                                  hipMemcpyHostToDevice, s));
