@@ -36,7 +36,7 @@ namespace fpc {
 namespace {
 
 constexpr int kNdT = 1024;         // threads of the ordering / factor blocks
-constexpr int kNdLeaf = 64;        // largest leaf part
+constexpr int kNdLeaf = 128;       // largest leaf part (one level fewer than 64)
 constexpr int kBndCap = 8192;      // LDS hash slots for a front's boundary
 constexpr int kMaxBnd = kBndCap / 2;
 constexpr int kMaxPiv = 2048;      // largest separator (pivots of one front)
@@ -589,6 +589,7 @@ __global__ __launch_bounds__(kNdT) void k_nd_assemble(
 // FLAG_NOT_SPD), partial pivoting otherwise (a pivot at or below 1e-14 of
 // the block's largest entry flags FLAG_SINGULAR).
 constexpr int kLdsPiv = 128;
+static_assert(kNdLeaf <= kLdsPiv, "leaf fronts are inverted in LDS");
 __global__ __launch_bounds__(kNdT) void k_nd_inv_lds(
     const int32_t* __restrict__ fl, const int32_t* __restrict__ f_m,
     const int32_t* __restrict__ f_k, const int64_t* __restrict__ f_F,
