@@ -318,8 +318,11 @@ __global__ __launch_bounds__(DT) void k_dcgs_update(
   const int cnt = j > 0 ? j : 1;  // j = 0: slot 0 loaded with weight 0
   const uint64_t stride = (uint64_t)ldv * sizeof(double);
   double acc[1] = {0.0};
-  for (uint32_t k = blockIdx.x * DT + threadIdx.x; k < (uint64_t)n;
-       k += gridDim.x * DT) {
+  // rows from the last one down: the dot pass that precedes this one walked
+  // them upwards, so the rows it read last are still in the last-level cache
+  for (uint32_t kk = blockIdx.x * DT + threadIdx.x; kk < (uint64_t)n;
+       kk += gridDim.x * DT) {
+    const uint32_t k = (uint32_t)n - 1 - kk;
     const uint32_t off = k * (uint32_t)sizeof(double);
     uint64_t st = stride;
     asm volatile("" : "+s"(st)::"memory");
