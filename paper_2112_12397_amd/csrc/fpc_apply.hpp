@@ -11,6 +11,17 @@ CycleVecs<T>& cycle_vecs(Hierarchy& H, int nv);
 // output .lv[0].xo.
 template <typename T, int NV>
 void vcycle(Hierarchy& H, bool transpose, hipStream_t s);
+// Single-column cycle whose input is formed by vcycle_input (as to_level on
+// the finest level's b, plus that level's first Chebyshev direction when the
+// coupling blocks have row lists: the return value) and whose result goes,
+// in FP64, straight to out from the last smoothing product.
+template <typename T>
+bool vcycle_input(Hierarchy& H, const double* base, const Csr* m1,
+                  const double* x1, double a1, const Csr* m2,
+                  const double* x2, double a2, hipStream_t s);
+template <typename T>
+void vcycle_to(Hierarchy& H, bool transpose, bool d0_ready, double* out,
+               hipStream_t s);
 
 // Autotuned apply layout of one operator for `nv` columns; *choice = 1 for
 // sliced ELL, else the row-group width.

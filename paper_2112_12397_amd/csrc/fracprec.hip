@@ -423,11 +423,9 @@ void apply_fwd(fpc_handle* h, const double* w, double* v, int stage = 0) {
       psolve_apply(h->ps, wp, vp, np, 0, s);                // v_p = S~2^-1 w_p
       return;
     }
-    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
-    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, &h->Q1, vp,
-                -1.0, s);
-    vcycle<T, 1>(h->amg, false, s);
-    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    const bool d0 = vcycle_input<T>(h->amg, wu, &h->C1, h->t_t.p, 1.0, &h->Q1,
+                                    vp, -1.0, s);
+    vcycle_to<T>(h->amg, false, d0, vu, s);
     tface(h->C2, vu, h->t_t.p, h->hinv.p, vt, np, 0, s);    // v_t
     return;
   }
@@ -487,11 +485,9 @@ void apply_fwd(fpc_handle* h, const double* w, double* v, int stage = 0) {
     // v_u = AMG(t_u) - AMG(Q1 v_p) = AMG(w_u + C1 t_t - Q1 v_p).
     // Alg 3.2: t_p = T^-1 w_p is also v_p, and v_u is the same cycle.
     psolve_apply(h->ps, wp, vp, np, 0, s);
-    CycleVecs<T>& cv = cycle_vecs<T>(h->amg, 1);
-    to_level<T>(cv.lv[0].b.p, 1, 0, nu, wu, &h->C1, h->t_t.p, 1.0, &h->Q1, vp,
-                -1.0, s);
-    vcycle<T, 1>(h->amg, false, s);
-    from_level<T>(cv.lv[0].xo.p, 1, nu, vu, 0, s);
+    const bool d0 = vcycle_input<T>(h->amg, wu, &h->C1, h->t_t.p, 1.0, &h->Q1,
+                                    vp, -1.0, s);
+    vcycle_to<T>(h->amg, false, d0, vu, s);
   }
   tface(h->C2, vu, h->t_t.p, h->hinv.p, vt, np, 0, s);      // v_t
 }

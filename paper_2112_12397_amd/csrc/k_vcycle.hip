@@ -191,6 +191,30 @@ struct EpiPost2 {
   __device__ void put(int, int64_t k, T val) const { xo[k] = val; }
 };
 
+// EpiPost2 on the finest level with the cycle's result written once, in
+// FP64, to the caller's vector (rounded to T first, as a separate
+// conversion of xo would do)
+template <typename T, int NV>
+struct EpiPost2Out {
+  static constexpr int NIN = 3, NOUT = 1;
+  const T* __restrict__ dinv;
+  const T* __restrict__ din;
+  const T* __restrict__ x;
+  double* __restrict__ out;
+  T theta, c1, c2;
+  __device__ void load(int64_t dof, int64_t k, T* in) const {
+    in[0] = dinv[dof];
+    in[1] = din[k];
+    in[2] = x[k];
+  }
+  __device__ void eval(int64_t, T a, const T* in, T* o) const {
+    const T d0 = in[1];
+    const T r1 = theta * d0 - in[0] * a;
+    o[0] = (in[2] + d0) + (c1 * d0 + c2 * r1);
+  }
+  __device__ void put(int, int64_t k, T val) const { out[k] = (double)val; }
+};
+
 // The loads and the stores of one block row (all NV columns) as two steps,
 // so that a kernel can issue the loads before its product and keep the
 // inputs in registers.
@@ -814,10 +838,15 @@ __global__ void k_to_level(T* __restrict__ out, int nv, int colv,
 
 template <typename T>
 __global__ void k_base_copy(T* __restrict__ out, int nv, int colv,
-                            const double* __restrict__ base, int64_t n) {
+                            const double* __restrict__ base, int64_t n,
+                            T* __restrict__ d0, const T* __restrict__ dinv,
+                            T inv_theta) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i * nv + colv] = (T)(base ? base[i] : 0.0);
+  const T b = (T)(base ? base[i] : 0.0);
+  out[i * nv + colv] = b;
+  // the first Chebyshev direction of the finest level (as k_first_dir)
+  if (d0) d0[i] = dinv[i] * b * inv_theta;
 }
 
 // k_to_level on the rows of two lists only: threads [0, nr1) take the rows
@@ -831,7 +860,9 @@ __global__ void k_to_level_rows(T* __restrict__ out, int nv, int colv,
                                 const int64_t* rp1, const int32_t* c1,
                                 const double* v1, const double* x1, double a1,
                                 const int64_t* rp2, const int32_t* c2,
-                                const double* v2, const double* x2, double a2) {
+                                const double* v2, const double* x2, double a2,
+                                T* __restrict__ d0, const T* __restrict__ dinv,
+                                T inv_theta) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nr1 + nr2) return;
   const bool second = t >= nr1;
@@ -848,7 +879,9 @@ __global__ void k_to_level_rows(T* __restrict__ out, int nv, int colv,
     for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s += v2[e] * x2[c2[e]];
     r += a2 * s;
   }
-  out[i * nv + colv] = (T)r;
+  const T b = (T)r;
+  out[i * nv + colv] = b;
+  if (d0) d0[i] = dinv[i] * b * inv_theta;
 }
 
 template <typename T>
@@ -935,7 +968,7 @@ const float* seldinv<float>(const Level& L) { return L.dinv32.p; }
 
 template <typename T, int BS, int NV>
 void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
-                  int phase, KTimer* timer) {
+                  int phase, KTimer* timer, double* out = nullptr) {
   const Op<T>& A = selA<T>(L, tr, NV > 2);
   const T* dinv = seldinv<T>(L);
   const T it = T(1.0 / L.theta), c1 = T(L.c1), c2 = T(L.c2);
@@ -951,10 +984,16 @@ void smooth_level(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
   } else {
     launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.x.p},
                                EpiPost1<T, NV>{v.b.p, dinv, v.d.p, it}, s);
-    launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
-                               EpiPost2<T, NV>{dinv, v.d.p, v.x.p, v.xo.p,
-                                                   T(L.theta), c1, c2},
-                               s);
+    if (NV == 1 && out)
+      launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
+                                 EpiPost2Out<T, NV>{dinv, v.d.p, v.x.p, out,
+                                                    T(L.theta), c1, c2},
+                                 s);
+    else
+      launch_op<T, BS, BS, NV>(A, LoadX<T, NV>{v.d.p},
+                                 EpiPost2<T, NV>{dinv, v.d.p, v.x.p, v.xo.p,
+                                                     T(L.theta), c1, c2},
+                                 s);
   }
 }
 
@@ -982,9 +1021,9 @@ void prolong_level(const Level& L, LevelVecs<T>& v, LevelVecs<T>& vc,
 
 template <typename T, int NV>
 void dispatch_smooth(const Level& L, LevelVecs<T>& v, bool tr, hipStream_t s,
-                     int phase, KTimer* timer) {
-  if (L.bs == 3) smooth_level<T, 3, NV>(L, v, tr, s, phase, timer);
-  else smooth_level<T, 6, NV>(L, v, tr, s, phase, timer);
+                     int phase, KTimer* timer, double* out = nullptr) {
+  if (L.bs == 3) smooth_level<T, 3, NV>(L, v, tr, s, phase, timer, out);
+  else smooth_level<T, 6, NV>(L, v, tr, s, phase, timer, out);
 }
 
 template <typename T, int NV>
@@ -1010,9 +1049,17 @@ __global__ void k_first_dir(const T* __restrict__ b, const T* __restrict__ dinv,
   if (i < n * NV) d0[i] = dinv[i / NV] * b[i] * inv_theta;
 }
 
+// Options of a single-column cycle: the finest level's first Chebyshev
+// direction already formed (vcycle_input), and the result written in FP64
+// to out by the last smoothing product instead of the finest level's xo.
+struct CycleEnds {
+  bool d0_ready = false;
+  double* out = nullptr;
+};
+
 template <typename T, int NV>
 void vcycle_rec(Hierarchy& H, CycleVecs<T>& cv, size_t l, bool tr,
-                hipStream_t s) {
+                hipStream_t s, const CycleEnds& ends = CycleEnds{}) {
   const Level& L = H.L[l];
   LevelVecs<T>& v = cv.lv[l];
   if (L.coarsest) {
@@ -1024,7 +1071,7 @@ void vcycle_rec(Hierarchy& H, CycleVecs<T>& cv, size_t l, bool tr,
     return;
   }
   KTimer* timer = (l == 0) ? H.timer : nullptr;
-  if (l == 0) {
+  if (l == 0 && !ends.d0_ready) {
     const int64_t n = L.n_nodes * L.bs;
     k_first_dir<T, NV><<<grid_for(n * NV, 256), 256, 0, s>>>(
         v.b.p, seldinv<T>(L), T(1.0 / L.theta), v.d0.p, n);
@@ -1035,7 +1082,7 @@ void vcycle_rec(Hierarchy& H, CycleVecs<T>& cv, size_t l, bool tr,
   dispatch_transfer<T, NV>(L, Lc, v, cv.lv[l + 1], s, true);
   vcycle_rec<T, NV>(H, cv, l + 1, tr, s);
   dispatch_transfer<T, NV>(L, Lc, v, cv.lv[l + 1], s, false);
-  dispatch_smooth<T, NV>(L, v, tr, s, 1, nullptr);
+  dispatch_smooth<T, NV>(L, v, tr, s, 1, nullptr, l == 0 ? ends.out : nullptr);
 }
 
 template <typename T>
@@ -1214,6 +1261,21 @@ void vcycle(Hierarchy& H, bool transpose, hipStream_t s) {
   }
   vcycle_rec<T, NV>(H, cv, 0, transpose, s);
 }
+
+template <typename T>
+void vcycle_to(Hierarchy& H, bool transpose, bool d0_ready, double* out,
+               hipStream_t s) {
+  CycleVecs<T>& cv = cycle_vecs<T>(H, 1);
+  if (H.L.empty() || H.L[0].coarsest) {
+    vcycle_rec<T, 1>(H, cv, 0, transpose, s);
+    from_level<T>(cv.lv[0].xo.p, 1, H.L.empty() ? 0 : H.nc, out, 0, s);
+    return;
+  }
+  vcycle_rec<T, 1>(H, cv, 0, transpose, s, CycleEnds{d0_ready, out});
+}
+template void vcycle_to<double>(Hierarchy&, bool, bool, double*, hipStream_t);
+template void vcycle_to<float>(Hierarchy&, bool, bool, double*, hipStream_t);
+
 template void vcycle<double, 1>(Hierarchy&, bool, hipStream_t);
 template void vcycle<float, 1>(Hierarchy&, bool, hipStream_t);
 template void vcycle<double, 8>(Hierarchy&, bool, hipStream_t);
@@ -1265,13 +1327,25 @@ void face_apply(const double* hinv, const double* in, double* out,
 }
 
 template <typename T>
-void to_level(T* out, int nv, int colv, int64_t n, const double* base,
-              const Csr* m1, const double* x1, double a1, const Csr* m2,
-              const double* x2, double a2, hipStream_t s) {
-  if (n == 0) return;
+struct LevelPrep {
+  T* d0 = nullptr;          // first Chebyshev direction of the finest level
+  const T* dinv = nullptr;
+  T inv_theta = T(0);
+};
+
+// to_level; with prep.d0, also the finest level's first Chebyshev direction
+// (formed only on the row-list path: returns whether it was)
+template <typename T>
+bool to_level_impl(T* out, int nv, int colv, int64_t n, const double* base,
+                   const Csr* m1, const double* x1, double a1, const Csr* m2,
+                   const double* x2, double a2, const LevelPrep<T>& prep,
+                   hipStream_t s) {
+  if (n == 0) return prep.d0 != nullptr;
   if (m1 && m1->nact >= 0 && (!m2 || m2->nact >= 0)) {
     // base everywhere, then the rows the coupling blocks touch
-    k_base_copy<T><<<grid_for(n, 256), 256, 0, s>>>(out, nv, colv, base, n);
+    k_base_copy<T><<<grid_for(n, 256), 256, 0, s>>>(out, nv, colv, base, n,
+                                                     prep.d0, prep.dinv,
+                                                     prep.inv_theta);
     const int64_t* rp2 = m2 ? m2->rowptr.p : nullptr;
     const int64_t nr2 = m2 ? m2->nact : 0;
     if (m1->nact + nr2 > 0)
@@ -1279,9 +1353,9 @@ void to_level(T* out, int nv, int colv, int64_t n, const double* base,
           out, nv, colv, base, m1->act.p, m1->nact,
           m2 ? m2->act.p : nullptr, nr2, m1->rowptr.p, m1->col.p, m1->val.p,
           x1, a1, rp2, m2 ? m2->col.p : nullptr, m2 ? m2->val.p : nullptr,
-          x2, a2);
+          x2, a2, prep.d0, prep.dinv, prep.inv_theta);
     FPC_LAUNCH_CHECK();
-    return;
+    return prep.d0 != nullptr;
   }
   k_to_level<T><<<grid_for(n, 256), 256, 0, s>>>(
       out, nv, colv, base, m1 ? m1->rowptr.p : nullptr,
@@ -1289,7 +1363,38 @@ void to_level(T* out, int nv, int colv, int64_t n, const double* base,
       m2 ? m2->rowptr.p : nullptr, m2 ? m2->col.p : nullptr,
       m2 ? m2->val.p : nullptr, x2, a2, n);
   FPC_LAUNCH_CHECK();
+  return false;
 }
+
+template <typename T>
+void to_level(T* out, int nv, int colv, int64_t n, const double* base,
+              const Csr* m1, const double* x1, double a1, const Csr* m2,
+              const double* x2, double a2, hipStream_t s) {
+  (void)to_level_impl<T>(out, nv, colv, n, base, m1, x1, a1, m2, x2, a2,
+                         LevelPrep<T>{}, s);
+}
+
+template <typename T>
+bool vcycle_input(Hierarchy& H, const double* base, const Csr* m1,
+                  const double* x1, double a1, const Csr* m2,
+                  const double* x2, double a2, hipStream_t s) {
+  CycleVecs<T>& cv = cycle_vecs<T>(H, 1);
+  const Level& L = H.L[0];
+  LevelPrep<T> prep;
+  if (!L.coarsest) {
+    prep.d0 = cv.lv[0].d0.p;
+    prep.dinv = seldinv<T>(L);
+    prep.inv_theta = T(1.0 / L.theta);
+  }
+  return to_level_impl<T>(cv.lv[0].b.p, 1, 0, L.n_nodes * L.bs, base, m1, x1,
+                          a1, m2, x2, a2, prep, s);
+}
+template bool vcycle_input<double>(Hierarchy&, const double*, const Csr*,
+                                   const double*, double, const Csr*,
+                                   const double*, double, hipStream_t);
+template bool vcycle_input<float>(Hierarchy&, const double*, const Csr*,
+                                  const double*, double, const Csr*,
+                                  const double*, double, hipStream_t);
 template void to_level<double>(double*, int, int, int64_t, const double*,
                                const Csr*, const double*, double, const Csr*,
                                const double*, double, hipStream_t);
