@@ -624,17 +624,59 @@ __global__ __launch_bounds__(64) void k_spgemm_sym(
   }
 }
 
-// Numeric phase with the output row accumulated in LDS (cap blocks at most).
-// Lane (e, c) = (lane / BN, lane % BN) takes block column c of B entry e of
-// each group of 64 / BN entries; per output value the terms are added in the
-// same order as in k_spgemm_num below (A entries ascending), one global
-// write per output value.
+// One step of a row of the numeric phase below: the entries eb of B's row
+// k (lane group le takes eb = b0 + le, b0 + le + EPP, ...) times the A
+// block a, added to the row's accumulator blocks in LDS (distinct entries
+// of one B row hit distinct output blocks).
+template <int BM, int BK, int BN>
+__device__ inline void spgemm_step(const double (&a)[BM * BK], int64_t b0,
+                                   int64_t bend, const int32_t* cb,
+                                   const double* vb, const int* scol, int clen,
+                                   double* sacc, int le, int c) {
+  constexpr int EPP = 64 / BN;
+  for (int64_t eb = b0 + le; le < EPP && eb < bend; eb += EPP) {
+    const int32_t j = cb[eb];
+    int lo = 0, hi = clen;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (scol[mid] < j) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= clen || scol[lo] != j) continue;
+    const double* b = vb + eb * (BK * BN) + c;
+    double bt[BK];
+#pragma unroll
+    for (int t = 0; t < BK; ++t) bt[t] = b[t * BN];
+    double* o = sacc + lo * (BM * BN) + c;
+#pragma unroll
+    for (int r = 0; r < BM; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < BK; ++t) acc += a[r * BK + t] * bt[t];
+      o[r * BN] += acc;
+    }
+  }
+}
+
+// Numeric phase with the output row accumulated in LDS (cap blocks at
+// most).  Lane (e, c) = (lane / BN, lane % BN) takes block column c of B
+// entry e of each group of 64 / BN entries; the entries of A's row are taken
+// one after the other (a barrier between them), so per output value the
+// terms are added in the order of k_spgemm_num below (A entries ascending),
+// with one global write per output value.  For 3x3 A blocks (A P_tent
+// and A P on the finest level, short B rows) the entries are taken SA at a
+// time with their B-row bounds and values staged in LDS by parallel loads,
+// so the walk over them waits only for B's entries; for the long rows of
+// R (A P) that staging cost more than it saved.
 template <int BM, int BK, int BN>
 __global__ __launch_bounds__(64) void k_spgemm_num_lds(
     const int64_t* ra, const int32_t* ca, const double* va, const int64_t* rb,
     const int32_t* cb, const double* vb, int64_t nrows, const int64_t* rc,
     const int32_t* cc, double* vc, int cap) {
-  constexpr int EPP = 64 / BN;
+  constexpr bool kStage = BM * BK <= 9;
+  constexpr int SA = kStage ? 16 : 1;
+  __shared__ double s_a[SA][BM * BK];
+  __shared__ int64_t s_b0[SA], s_b1[SA];
   extern __shared__ double sacc[];
   int* scol = (int*)(sacc + (int64_t)cap * BM * BN);
   const int64_t row = blockIdx.x;
@@ -645,37 +687,41 @@ __global__ __launch_bounds__(64) void k_spgemm_num_lds(
   const int clen = (int)(rc[row + 1] - c0);
   for (int q = lane; q < clen * BM * BN; q += 64) sacc[q] = 0.0;
   for (int q = lane; q < clen; q += 64) scol[q] = cc[c0 + q];
-  __syncthreads();
-  for (int64_t ea = ra[row]; ea < ra[row + 1]; ++ea) {
-    const int32_t k = ca[ea];
-    double a[BM * BK];
+  const int64_t a0 = ra[row], a1 = ra[row + 1];
+  if constexpr (!kStage) {
+    __syncthreads();
+    for (int64_t ea = a0; ea < a1; ++ea) {
+      const int32_t k = ca[ea];
+      double a[BM * BK];
 #pragma unroll
-    for (int q = 0; q < BM * BK; ++q) a[q] = va[ea * (BM * BK) + q];
-    const int64_t bend = rb[k + 1];
-    for (int64_t eb = rb[k] + le; le < EPP && eb < bend; eb += EPP) {
-      const int32_t j = cb[eb];
-      int lo = 0, hi = clen;
-      while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (scol[mid] < j) lo = mid + 1;
-        else hi = mid;
+      for (int q = 0; q < BM * BK; ++q) a[q] = va[ea * (BM * BK) + q];
+      spgemm_step<BM, BK, BN>(a, rb[k], rb[k + 1], cb, vb, scol, clen, sacc,
+                              le, c);
+      __syncthreads();
+    }
+  } else {
+    for (int64_t e0 = a0; e0 < a1; e0 += SA) {
+      const int na = (int)(a1 - e0 < SA ? a1 - e0 : SA);
+      __syncthreads();  // the previous chunk is done with the staging arrays
+      if (lane < na) {
+        const int32_t k = ca[e0 + lane];
+        s_b0[lane] = rb[k];
+        s_b1[lane] = rb[k + 1];
       }
-      if (lo >= clen || scol[lo] != j) continue;
-      const double* b = vb + eb * (BK * BN) + c;
-      double bt[BK];
+      for (int q = lane; q < na * BM * BK; q += 64)
+        s_a[q / (BM * BK)][q % (BM * BK)] = va[e0 * (BM * BK) + q];
+      __syncthreads();
+      for (int e = 0; e < na; ++e) {
+        double a[BM * BK];
 #pragma unroll
-      for (int t = 0; t < BK; ++t) bt[t] = b[t * BN];
-      double* o = sacc + lo * (BM * BN) + c;
-#pragma unroll
-      for (int r = 0; r < BM; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < BK; ++t) acc += a[r * BK + t] * bt[t];
-        o[r * BN] += acc;
+        for (int q = 0; q < BM * BK; ++q) a[q] = s_a[e][q];
+        spgemm_step<BM, BK, BN>(a, s_b0[e], s_b1[e], cb, vb, scol, clen, sacc,
+                                le, c);
+        __syncthreads();
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int q = lane; q < clen * BM * BN; q += 64) vc[c0 * BM * BN + q] = sacc[q];
 }
 
@@ -1026,7 +1072,7 @@ void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
   FPC_HIP(hipStreamSynchronize(s));
   const int64_t cap = (int64_t)h[1];
   const size_t abytes = (size_t)cap * (BM * BN * sizeof(double) + sizeof(int));
-  if (abytes <= 60 * 1024) {
+  if (abytes <= 56 * 1024) {  // with the kernel's own staging, under 64 KB
     k_spgemm_num_lds<BM, BK, BN><<<(unsigned)c.nbr, 64, abytes, s>>>(
         a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
         c.rowptr.p, c.col.p, c.val.p, (int)cap);
