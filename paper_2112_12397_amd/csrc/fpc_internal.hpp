@@ -256,7 +256,11 @@ void csr_to_bsr(const Csr& a, int br, int bc, Bsr& out, hipStream_t s);
 void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s);
 void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s);
 // C = A * B (block shapes must chain).  flags[FLAG_OVERFLOW] on hash overflow.
-void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s);
+// C = A B (block CSR); b_single: every row of B holds at most one block (a
+// tentative prolongator), which a faster numeric kernel uses when C's rows
+// are short; a row with more raises FLAG_PATTERN.
+void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s,
+            bool b_single = false);
 template <typename T>
 void bsr_to_sell(const Bsr& a, Sell<T>& out, hipStream_t s);
 template <typename T>

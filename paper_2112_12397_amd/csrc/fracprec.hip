@@ -258,7 +258,7 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
       ptent_bsr(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, ptent.p, L.Pt, s);
     }
     Bsr AP0;
-    spgemm(L.A, L.Pt, AP0, h->flags.p, s);
+    spgemm(L.A, L.Pt, AP0, h->flags.p, s, /*b_single=*/true);
     // P = P_tent - omega D^{-1} (A P_tent)
     smooth_prolongator(AP0, L.dinv.p, o.omega_factor / L.lam_hi, s);
     bsr_add(L.Pt, AP0, L.P, s);

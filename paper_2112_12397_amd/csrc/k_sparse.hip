@@ -725,6 +725,87 @@ __global__ __launch_bounds__(64) void k_spgemm_num_lds(
   for (int q = lane; q < clen * BM * BN; q += 64) vc[c0 * BM * BN + q] = sacc[q];
 }
 
+// Numeric phase when every row of B holds at most one block (A P_tent):
+// each entry of A's row meets one output block, so the products of up to
+// NE entries are formed at once (lane = (entry, block column)) and staged
+// in LDS with their output slots; lane q then adds, for its output values,
+// the staged products in entry order.  Every output value is the sum of its
+// terms in ascending A order, each term summed over t first, as in the
+// kernels above: the results are the same bit for bit.  Output rows of up
+// to 64 QM / (BM BN) blocks (the caller checks).
+template <int BM, int BK, int BN, int QM>
+__global__ __launch_bounds__(64) void k_spgemm_num_b1(
+    const int64_t* ra, const int32_t* ca, const double* va, const int64_t* rb,
+    const int32_t* cb, const double* vb, int64_t nrows, const int64_t* rc,
+    const int32_t* cc, double* vc, int* flags) {
+  constexpr int NE = 32;
+  __shared__ double s_p[NE][BM * BN];
+  __shared__ int s_t[NE];
+  __shared__ int scol[64 * QM / (BM * BN)];
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (row >= nrows) return;
+  const int64_t c0 = rc[row];
+  const int clen = (int)(rc[row + 1] - c0);
+  const int nout = clen * BM * BN;
+  for (int q = lane; q < clen; q += 64) scol[q] = cc[c0 + q];
+  double acc[QM];
+#pragma unroll
+  for (int i = 0; i < QM; ++i) acc[i] = 0.0;
+  const int64_t a0 = ra[row], a1 = ra[row + 1];
+  for (int64_t e0 = a0; e0 < a1; e0 += NE) {
+    const int ne = (int)(a1 - e0 < NE ? a1 - e0 : NE);
+    __syncthreads();  // scol written; the previous chunk's products used
+    for (int w = lane; w < ne * BN; w += 64) {
+      const int e = w / BN, cj = w % BN;
+      const int64_t ea = e0 + e;
+      const int32_t k = ca[ea];
+      const int64_t b0 = rb[k];
+      const int64_t b1 = rb[k + 1];
+      const bool has = b0 < b1;
+      if (b1 - b0 > 1) atomicOr(&flags[FLAG_PATTERN], 1);  // not one block
+      if (cj == 0) {
+        int slot = -1;
+        if (has) {
+          const int32_t j = cb[b0];
+          int lo = 0, hi = clen;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (scol[mid] < j) lo = mid + 1;
+            else hi = mid;
+          }
+          if (lo < clen && scol[lo] == j) slot = lo;
+        }
+        s_t[e] = slot;
+      }
+#pragma unroll
+      for (int r = 0; r < BM; ++r) {
+        double t = 0.0;
+        if (has)
+#pragma unroll
+          for (int u = 0; u < BK; ++u)
+            t += va[ea * (BM * BK) + r * BK + u] * vb[b0 * (BK * BN) + u * BN + cj];
+        s_p[e][r * BN + cj] = t;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < QM; ++i) {
+      const int q = lane + 64 * i;
+      if (q < nout) {
+        const int slot = q / (BM * BN), rq = q % (BM * BN);
+        for (int e = 0; e < ne; ++e)
+          if (s_t[e] == slot) acc[i] += s_p[e][rq];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < QM; ++i) {
+    const int q = lane + 64 * i;
+    if (q < nout) vc[c0 * BM * BN + q] = acc[i];
+  }
+}
+
 // Numeric phase: C row i = sum_k A(i,k) B(k,:).  The loop over the entries
 // of A's row is sequential; within one step the lanes take distinct entries
 // of B's row, hence distinct output blocks, so the accumulation order is
@@ -1033,7 +1114,7 @@ void to_bsr_impl(const Csr& a, Bsr& out, hipStream_t s) {
 
 template <int BM, int BK, int BN>
 void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
-                 hipStream_t s) {
+                 hipStream_t s, bool b_single) {
   c.br = BM;
   c.bc = BN;
   c.nbr = a.nbr;
@@ -1072,7 +1153,12 @@ void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
   FPC_HIP(hipStreamSynchronize(s));
   const int64_t cap = (int64_t)h[1];
   const size_t abytes = (size_t)cap * (BM * BN * sizeof(double) + sizeof(int));
-  if (abytes <= 56 * 1024) {  // with the kernel's own staging, under 64 KB
+  constexpr int QM = 8;
+  if (b_single && cap * BM * BN <= 64 * QM) {
+    k_spgemm_num_b1<BM, BK, BN, QM><<<(unsigned)c.nbr, 64, 0, s>>>(
+        a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
+        c.rowptr.p, c.col.p, c.val.p, flags);
+  } else if (abytes <= 56 * 1024) {  // with the kernel's own staging, under 64 KB
     k_spgemm_num_lds<BM, BK, BN><<<(unsigned)c.nbr, 64, abytes, s>>>(
         a.rowptr.p, a.col.p, a.val.p, b.rowptr.p, b.col.p, b.val.p, c.nbr,
         c.rowptr.p, c.col.p, c.val.p, (int)cap);
@@ -1288,15 +1374,21 @@ void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s) {
   throw Error(FPC_ERR_ARG, "bsr_transpose: unsupported block shape");
 }
 
-void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s) {
+void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s,
+            bool b_single) {
   if (a.bc != b.br || a.nbc != b.nbr)
     throw Error(FPC_ERR_DIM, "spgemm: shapes do not chain");
   const int m = a.br, k = a.bc, n = b.bc;
-  if (m == 3 && k == 3 && n == 3) return spgemm_impl<3, 3, 3>(a, b, c, flags, s);
-  if (m == 3 && k == 3 && n == 6) return spgemm_impl<3, 3, 6>(a, b, c, flags, s);
-  if (m == 6 && k == 3 && n == 6) return spgemm_impl<6, 3, 6>(a, b, c, flags, s);
-  if (m == 6 && k == 6 && n == 6) return spgemm_impl<6, 6, 6>(a, b, c, flags, s);
-  if (m == 3 && k == 1 && n == 3) return spgemm_impl<3, 1, 3>(a, b, c, flags, s);
+  if (m == 3 && k == 3 && n == 3)
+    return spgemm_impl<3, 3, 3>(a, b, c, flags, s, b_single);
+  if (m == 3 && k == 3 && n == 6)
+    return spgemm_impl<3, 3, 6>(a, b, c, flags, s, b_single);
+  if (m == 6 && k == 3 && n == 6)
+    return spgemm_impl<6, 3, 6>(a, b, c, flags, s, b_single);
+  if (m == 6 && k == 6 && n == 6)
+    return spgemm_impl<6, 6, 6>(a, b, c, flags, s, b_single);
+  if (m == 3 && k == 1 && n == 3)
+    return spgemm_impl<3, 1, 3>(a, b, c, flags, s, b_single);
   throw Error(FPC_ERR_ARG, "spgemm: unsupported block shapes");
 }
 
