@@ -1358,13 +1358,15 @@ __global__ __launch_bounds__(1024) void k_panel_pivots(
   }
 }
 
-// The same pivots from three kernels per slab when the panel has at most
-// kLuRows rows below the slab's first column: the slab's columns are
-// eliminated in LDS by one workgroup (k_lu_slab), then its exchanges and the
-// unit lower solve reach the columns to its right (k_lu_swap_u12, thread per
-// column) and the rows below take the rank-kLuSlab update across the whole
-// grid (k_lu_trail).  The column-by-column steps then cost LDS latency only.
+// The same pivots from three kernels per slab of kLuSlabR columns when the
+// panel has at most kLuRows rows below the slab's first column: the slab's
+// columns are eliminated by one workgroup holding the slab in registers (two
+// rows per thread, k_lu_slab), then its exchanges and the unit lower solve
+// reach the columns to its right (k_lu_swap_u12, thread per column) and the
+// rows below take the rank-kLuSlabR update across the whole grid
+// (k_lu_trail).  The column-by-column steps then cost a few barriers each.
 constexpr int kLuRows = 2048;
+constexpr int kLuSlabR = 16;
 __global__ void k_copy_panel(const double* __restrict__ D, int64_t n,
                              int64_t o, int nb, double* __restrict__ P) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1378,25 +1380,36 @@ __global__ __launch_bounds__(1024) void k_lu_slab(double* __restrict__ P,
                                                   int s1, int64_t o,
                                                   int32_t* __restrict__ piv,
                                                   int* flags) {
-  __shared__ double S[kLuRows][kLuSlab];
+  constexpr int W = kLuSlabR;
+  static_assert(kLuRows == 2 * 1024, "two rows per thread");
   __shared__ double s_v[16];
   __shared__ int s_i[16];
+  __shared__ double s_rp[W], s_rq[W];
+  __shared__ int s_p, s_bad;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rows = (int)(m - s0), ws = s1 - s0;
-  for (int idx = t; idx < rows * kLuSlab; idx += 1024) {
-    const int r = idx / kLuSlab, q = idx % kLuSlab;
-    S[r][q] = q < ws ? P[(int64_t)(s0 + r) * nb + s0 + q] : 0.0;
+  const int r0 = t, r1 = t + 1024;
+  // rows r0 and r1 of the slab (two arrays, selected by value, so that they
+  // stay in registers)
+  double A0[W], A1[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    A0[c] = (r0 < rows && c < ws) ? P[(int64_t)(s0 + r0) * nb + s0 + c] : 0.0;
+    A1[c] = (r1 < rows && c < ws) ? P[(int64_t)(s0 + r1) * nb + s0 + c] : 0.0;
   }
-  __syncthreads();
-  for (int q = 0; q < ws; ++q) {
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    if (q >= ws) continue;  // uniform: the slab's last columns may be absent
+    // largest |entry| of column q at or below row q, first row on ties
     double bv = -1.0;
     int bi = q;
-    for (int r = q + t; r < rows; r += 1024) {
-      const double a = fabs(S[r][q]);
-      if (a > bv) {
-        bv = a;
-        bi = r;
-      }
+    if (r0 >= q && r0 < rows && fabs(A0[q]) > bv) {
+      bv = fabs(A0[q]);
+      bi = r0;
+    }
+    if (r1 >= q && r1 < rows && fabs(A1[q]) > bv) {
+      bv = fabs(A1[q]);
+      bi = r1;
     }
     for (int off = 32; off > 0; off >>= 1) {
       const double ov = __shfl_xor(bv, off);
@@ -1411,38 +1424,69 @@ __global__ __launch_bounds__(1024) void k_lu_slab(double* __restrict__ P,
       s_i[w] = bi;
     }
     __syncthreads();
-    if (t == 0) {
-      for (int u = 1; u < 16; ++u)
-        if (s_v[u] > s_v[0] || (s_v[u] == s_v[0] && s_i[u] < s_i[0])) {
-          s_v[0] = s_v[u];
-          s_i[0] = s_i[u];
+    if (w == 0) {
+      double v = lane < 16 ? s_v[lane] : -2.0;
+      int ix = lane < 16 ? s_i[lane] : 0x7fffffff;
+      for (int off = 8; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(ix, off);
+        if (ov > v || (ov == v && oi < ix)) {
+          v = ov;
+          ix = oi;
         }
-      piv[s0 + q] = (int32_t)(o + s0 + s_i[0]);
-      if (!(s_v[0] > 0.0) || !isfinite(s_v[0]))
-        atomicOr(&flags[FLAG_SINGULAR], 1);
+      }
+      if (lane == 0) {
+        const bool bad = !(v > 0.0) || !isfinite(v);
+        piv[s0 + q] = (int32_t)(o + s0 + ix);
+        if (bad) atomicOr(&flags[FLAG_SINGULAR], 1);
+        s_p = ix;
+        s_bad = bad ? 1 : 0;
+      }
     }
     __syncthreads();
-    const int p = s_i[0];
-    const bool bad = !(s_v[0] > 0.0) || !isfinite(s_v[0]);
-    if (p != q && t < kLuSlab) {
-      const double x = S[q][t];
-      S[q][t] = S[p][t];
-      S[p][t] = x;
-    }
-    __syncthreads();
-    const double inv = bad ? 0.0 : 1.0 / S[q][q];
-    for (int r = q + 1 + t; r < rows; r += 1024) {
-      const double l = S[r][q] * inv;
-      S[r][q] = l;
+    const int p = s_p;
+    const bool bad = s_bad != 0;
+    // the pivot row and row q through LDS, then exchanged
+    const bool own_p = t == (p & 1023), p_hi = p >= 1024;
+    const bool own_q = t == (q & 1023), q_hi = q >= 1024;
+    if (own_p)
 #pragma unroll
-      for (int c = 0; c < kLuSlab; ++c)
-        if (c > q && c < ws) S[r][c] -= l * S[q][c];
-    }
+      for (int c = 0; c < W; ++c) s_rp[c] = p_hi ? A1[c] : A0[c];
+    if (own_q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) s_rq[c] = q_hi ? A1[c] : A0[c];
     __syncthreads();
+    if (p != q) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const double vp = s_rp[c], vq = s_rq[c];
+        if (own_q && !q_hi) A0[c] = vp;
+        if (own_q && q_hi) A1[c] = vp;
+        if (own_p && !p_hi) A0[c] = vq;
+        if (own_p && p_hi) A1[c] = vq;
+      }
+    }
+    // column q of L below the pivot, rank-1 update inside the slab
+    const double inv = bad ? 0.0 : 1.0 / s_rp[q];
+    if (r0 > q && r0 < rows) {
+      const double l = A0[q] * inv;
+      A0[q] = l;
+#pragma unroll
+      for (int c = q + 1; c < W; ++c)
+        if (c < ws) A0[c] -= l * s_rp[c];
+    }
+    if (r1 > q && r1 < rows) {
+      const double l = A1[q] * inv;
+      A1[q] = l;
+#pragma unroll
+      for (int c = q + 1; c < W; ++c)
+        if (c < ws) A1[c] -= l * s_rp[c];
+    }
   }
-  for (int idx = t; idx < rows * ws; idx += 1024) {
-    const int r = idx / ws, q = idx % ws;
-    P[(int64_t)(s0 + r) * nb + s0 + q] = S[r][q];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    if (c < ws && r0 < rows) P[(int64_t)(s0 + r0) * nb + s0 + c] = A0[c];
+    if (c < ws && r1 < rows) P[(int64_t)(s0 + r1) * nb + s0 + c] = A1[c];
   }
 }
 
@@ -1460,9 +1504,9 @@ __global__ void k_lu_swap_u12(double* __restrict__ P, int64_t m, int nb,
     P[(int64_t)k * nb + c] = P[p * nb + c];
     P[p * nb + c] = x;
   }
-  double u[kLuSlab];
+  double u[kLuSlabR];
 #pragma unroll
-  for (int i = 0; i < kLuSlab; ++i) {
+  for (int i = 0; i < kLuSlabR; ++i) {
     if (s0 + i >= s1) break;
     double v = P[(int64_t)(s0 + i) * nb + c];
     for (int q = 0; q < i; ++q) v -= P[(int64_t)(s0 + i) * nb + s0 + q] * u[q];
@@ -1533,8 +1577,8 @@ void gj_inverse(double* D, int64_t n, int* flags, hipStream_t s, bool pivot) {
     } else if (m <= kLuRows) {
       k_copy_panel<<<grid_for(m * nb, 256), 256, 0, s>>>(D, n, o, (int)nb,
                                                          panel.p);
-      for (int s0 = 0; s0 < nb; s0 += kLuSlab) {
-        const int s1 = (int)std::min<int64_t>(s0 + kLuSlab, nb);
+      for (int s0 = 0; s0 < nb; s0 += kLuSlabR) {
+        const int s1 = (int)std::min<int64_t>(s0 + kLuSlabR, nb);
         k_lu_slab<<<1, 1024, 0, s>>>(panel.p, m, (int)nb, s0, s1, o,
                                      piv.p + o, flags);
         if (s1 < nb) {
