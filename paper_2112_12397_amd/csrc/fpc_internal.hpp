@@ -217,6 +217,51 @@ double read_f64(const double* p, hipStream_t s);
 int64_t read_i64(const int64_t* p, hipStream_t s);
 int read_i32(const int32_t* p, hipStream_t s);
 
+// sum over e in [b, end) of val[e] x[col[e]], added in order of e; the
+// column, value and gather loads are issued four entries at a time so a
+// row's gathers overlap instead of waiting one after the other.
+__device__ inline double csr_row_sum(const int32_t* __restrict__ col,
+                                     const double* __restrict__ val,
+                                     const double* __restrict__ x, int64_t b,
+                                     int64_t end) {
+  double s = 0.0;
+  int64_t e = b;
+  for (; e + 4 <= end; e += 4) {
+    const int32_t c0 = col[e], c1 = col[e + 1], c2 = col[e + 2], c3 = col[e + 3];
+    const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
+    const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; e < end; ++e) s += val[e] * x[col[e]];
+  return s;
+}
+
+// The same on column c of KB interleaved columns (x element (j, c) at
+// j KB + c).
+__device__ inline double csr_row_sum_col(const int32_t* __restrict__ col,
+                                         const double* __restrict__ val,
+                                         const double* __restrict__ x,
+                                         int64_t b, int64_t end, int KB,
+                                         int c) {
+  double s = 0.0;
+  int64_t e = b;
+  for (; e + 4 <= end; e += 4) {
+    const int64_t c0 = col[e], c1 = col[e + 1], c2 = col[e + 2], c3 = col[e + 3];
+    const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
+    const double x0 = x[c0 * KB + c], x1 = x[c1 * KB + c];
+    const double x2 = x[c2 * KB + c], x3 = x[c3 * KB + c];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; e < end; ++e) s += val[e] * x[(int64_t)col[e] * KB + c];
+  return s;
+}
+
 __host__ __device__ inline uint32_t lowbias32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;

@@ -53,21 +53,17 @@ __global__ void k_csr_spmv2_b(const int64_t* rp1, const int32_t* c1,
   if (t >= nrows * KB) return;
   const int64_t i = t / KB;
   const int c = (int)(t % KB);
-  double s1 = 0.0;
-  for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e)
-    s1 += v1[e] * x1[(int64_t)c1[e] * KB + c];
+  const double s1 = csr_row_sum_col(c1, v1, x1, rp1[i], rp1[i + 1], KB, c);
   double r = a1 * s1;
   if (rp2) {
-    double s2 = 0.0;
-    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e)
-      s2 += v2[e] * x2[(int64_t)c2[e] * KB + c];
+    const double s2 = csr_row_sum_col(c2, v2, x2, rp2[i], rp2[i + 1], KB, c);
     r += a2 * s2;
   }
   y[t] = (beta == 0.0) ? r : beta * y[t] + r;
 }
 
-// level-0 input of the two-column V-cycle per right-hand side:
-// out(i, 2c + sel) = (T)(base(i, c) + a1 (M1 x1)(i, c))
+// level-0 input per right-hand side:
+// out(i, c) = (T)(base(i, c) + a1 (M1 x1)(i, c) + a2 (M2 x2)(i, c))
 template <typename T>
 __global__ void k_to_level_b(T* __restrict__ out, int KB,
                              const double* __restrict__ base,
@@ -81,14 +77,8 @@ __global__ void k_to_level_b(T* __restrict__ out, int KB,
   const int64_t i = t / KB;
   const int c = (int)(t % KB);
   double r = base ? base[t] : 0.0;
-  double s = 0.0;
-  for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e)
-    s += v1[e] * x1[(int64_t)c1[e] * KB + c];
-  r += a1 * s;
-  s = 0.0;
-  for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e)
-    s += v2[e] * x2[(int64_t)c2[e] * KB + c];
-  r += a2 * s;
+  r += a1 * csr_row_sum_col(c1, v1, x1, rp1[i], rp1[i + 1], KB, c);
+  r += a2 * csr_row_sum_col(c2, v2, x2, rp2[i], rp2[i + 1], KB, c);
   out[t] = (T)r;
 }
 
@@ -115,11 +105,8 @@ __global__ void k_tface_b(const int64_t* __restrict__ rp,
   const int c = (int)(t % KB);
   double s[3];
   for (int r = 0; r < 3; ++r) {
-    double a = 0.0;
     const int64_t row = 3 * K + r;
-    for (int64_t e = rp[row]; e < rp[row + 1]; ++e)
-      a += val[e] * vu[(int64_t)col[e] * KB + c];
-    s[r] = a;
+    s[r] = csr_row_sum_col(col, val, vu, rp[row], rp[row + 1], KB, c);
   }
   const double* h = hinv + K * 9;
   for (int r = 0; r < 3; ++r)

@@ -42,12 +42,10 @@ __global__ void k_csr_spmv2(const int64_t* rp1, const int32_t* c1,
                             double* y, double beta, int64_t nrows) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
-  double s1 = 0.0;
-  for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s1 += v1[e] * x1[c1[e]];
+  const double s1 = csr_row_sum(c1, v1, x1, rp1[i], rp1[i + 1]);
   double r = a1 * s1;
   if (rp2) {
-    double s2 = 0.0;
-    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s2 += v2[e] * x2[c2[e]];
+    const double s2 = csr_row_sum(c2, v2, x2, rp2[i], rp2[i + 1]);
     r += a2 * s2;
   }
   y[i] = (beta == 0.0) ? r : beta * y[i] + r;
@@ -68,11 +66,10 @@ __global__ void k_csr_spmv2_rows(const int32_t* rows, int64_t nr, int skip1,
   if (skip1 && rp1 && rp1[i] < rp1[i + 1]) return;
   double s1 = 0.0;
   if (rp1)
-    for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s1 += v1[e] * x1[c1[e]];
+    s1 = csr_row_sum(c1, v1, x1, rp1[i], rp1[i + 1]);
   double r = a1 * s1;
   if (rp2) {
-    double s2 = 0.0;
-    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s2 += v2[e] * x2[c2[e]];
+    const double s2 = csr_row_sum(c2, v2, x2, rp2[i], rp2[i + 1]);
     r += a2 * s2;
   }
   y[i] = (beta == 0.0) ? r : beta * y[i] + r;
@@ -115,11 +112,10 @@ __global__ void k_csr_spmv2_multi(const Spmv2Jobs jobs) {
   if (J.skip1 && J.rp1 && J.rp1[i] < J.rp1[i + 1]) return;
   double s1 = 0.0;
   if (J.rp1)
-    for (int64_t e = J.rp1[i]; e < J.rp1[i + 1]; ++e) s1 += J.v1[e] * J.x1[J.c1[e]];
+    s1 = csr_row_sum(J.c1, J.v1, J.x1, J.rp1[i], J.rp1[i + 1]);
   double res = J.a1 * s1;
   if (J.rp2) {
-    double s2 = 0.0;
-    for (int64_t e = J.rp2[i]; e < J.rp2[i + 1]; ++e) s2 += J.v2[e] * J.x2[J.c2[e]];
+    const double s2 = csr_row_sum(J.c2, J.v2, J.x2, J.rp2[i], J.rp2[i + 1]);
     res += J.a2 * s2;
   }
   J.y[i] = (J.beta == 0.0) ? res : J.beta * J.y[i] + res;

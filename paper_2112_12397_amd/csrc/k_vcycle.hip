@@ -824,13 +824,11 @@ __global__ void k_to_level(T* __restrict__ out, int nv, int colv,
   if (i >= n) return;
   double r = base ? base[i] : 0.0;
   if (rp1) {
-    double s = 0.0;
-    for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s += v1[e] * x1[c1[e]];
+    const double s = csr_row_sum(c1, v1, x1, rp1[i], rp1[i + 1]);
     r += a1 * s;
   }
   if (rp2) {
-    double s = 0.0;
-    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s += v2[e] * x2[c2[e]];
+    const double s = csr_row_sum(c2, v2, x2, rp2[i], rp2[i + 1]);
     r += a2 * s;
   }
   out[i * nv + colv] = (T)r;
@@ -870,13 +868,11 @@ __global__ void k_to_level_rows(T* __restrict__ out, int nv, int colv,
   if (second && rp1 && rp1[i] < rp1[i + 1]) return;
   double r = base ? base[i] : 0.0;
   if (rp1) {
-    double s = 0.0;
-    for (int64_t e = rp1[i]; e < rp1[i + 1]; ++e) s += v1[e] * x1[c1[e]];
+    const double s = csr_row_sum(c1, v1, x1, rp1[i], rp1[i + 1]);
     r += a1 * s;
   }
   if (rp2) {
-    double s = 0.0;
-    for (int64_t e = rp2[i]; e < rp2[i + 1]; ++e) s += v2[e] * x2[c2[e]];
+    const double s = csr_row_sum(c2, v2, x2, rp2[i], rp2[i + 1]);
     r += a2 * s;
   }
   const T b = (T)r;
@@ -910,7 +906,7 @@ __global__ __launch_bounds__(192) void k_tface(const int64_t* __restrict__ rp,
   double a = 0.0;
   if (act) {
     const int64_t row = 3 * K + r;
-    for (int64_t e = rp[row]; e < rp[row + 1]; ++e) a += val[e] * vu[col[e]];
+    a = csr_row_sum(col, val, vu, rp[row], rp[row + 1]);
   }
   sh[threadIdx.x] = a;
   __syncthreads();
