@@ -119,6 +119,11 @@ typedef struct {
   int ortho;               /* FPC_DCGS2 (default), FPC_CGS2 or FPC_MGS;     */
                            /* batched solves use DCGS2, or CGS2 for either  */
                            /* of the other two                              */
+  int tune;                /* 1: each operator's apply layout is picked by  */
+                           /* timing the candidates at setup (default); 0:  */
+                           /* by its average row length alone, so that two  */
+                           /* setups of one system give bitwise equal       */
+                           /* hierarchies, preconditioners and solutions    */
   fpc_amg_options amg;
 } fpc_options;
 

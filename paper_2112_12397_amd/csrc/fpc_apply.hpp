@@ -30,6 +30,11 @@ template <typename T>
 void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
              double* best_us, Sell<T>* sell = nullptr);
 
+// The apply layout chosen from the average row length alone (no timing, so
+// the same for every setup of a pattern): sliced ELL up to 32 blocks per
+// row, row groups of 16 lanes below 64 blocks per row, of 64 lanes above.
+int rule_layout(const Bsr& M);
+
 // The apply layout `choice` (as returned by tune_op) of one operator.
 template <typename T>
 void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s,

@@ -303,12 +303,12 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
     if (L.coarsest) continue;
     // L.sA (built for the power iteration) is handed to the FP64 layout
     // choice and released otherwise
-    if (prev) {
-      // the layouts picked for the same patterns
-      const Level& pv = prev->L[li];
+    if (prev || !h->opt.tune) {
+      // the layouts picked for the same patterns, or by row length alone
+      const Bsr* ops[3] = {&L.A, &L.P, &L.R};
       for (int k = 0; k < 3; ++k) {
-        L.layout[k] = pv.layout[k];
-        L.tune_us[k] = pv.tune_us[k];
+        L.layout[k] = prev ? prev->L[li].layout[k] : rule_layout(*ops[k]);
+        L.tune_us[k] = prev ? prev->L[li].tune_us[k] : 0.0;
       }
       if (h->opt.precision == FPC_FP32_PREC) {
         const int64_t n = L.n_nodes * L.bs;
@@ -368,7 +368,10 @@ void ensure_transposes(fpc_handle* h) {
   for (Level& L : H.L) {
     if (L.coarsest) continue;
     bsr_transpose(L.A, L.AT, s);
-    if (h->opt.precision == FPC_FP32_PREC) tune_op<float>(L.AT, 1, L.fAT, s, nullptr, nullptr);
+    const bool f32 = h->opt.precision == FPC_FP32_PREC;
+    if (!h->opt.tune && f32) build_op<float>(L.AT, rule_layout(L.AT), L.fAT, s);
+    else if (!h->opt.tune) build_op<double>(L.AT, rule_layout(L.AT), L.oAT, s);
+    else if (f32) tune_op<float>(L.AT, 1, L.fAT, s, nullptr, nullptr);
     else tune_op<double>(L.AT, 1, L.oAT, s, nullptr, nullptr);
   }
   H.AinvT.alloc(H.ncpad * H.ncpad);
@@ -1378,6 +1381,7 @@ void fpc_default_options(fpc_options* o) {
   o->max_batch = 32;
   o->graphs = 1;
   o->ortho = FPC_DCGS2;
+  o->tune = 1;
   o->amg.max_coarse = 2000;
   o->amg.max_levels = 12;
   o->amg.cheb_degree = 2;
@@ -1405,7 +1409,7 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
       o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
       o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 || o.max_batch > kMaxBatch ||
-      (o.graphs != 0 && o.graphs != 1) ||
+      (o.graphs != 0 && o.graphs != 1) || (o.tune != 0 && o.tune != 1) ||
       (o.ortho != FPC_CGS2 && o.ortho != FPC_MGS && o.ortho != FPC_DCGS2)) {
     delete h;
     return FPC_ERR_ARG;

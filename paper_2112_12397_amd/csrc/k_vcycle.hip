@@ -1170,6 +1170,10 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
   if (best_us) *best_us = 1e3 * tbest;
   FPC_HIP(hipStreamSynchronize(s));
 }
+int rule_layout(const Bsr& M) {
+  const double avg = M.nbr ? (double)M.nnzb / (double)M.nbr : 0.0;
+  return avg <= 32.0 ? 1 : avg < 64.0 ? 16 : 64;
+}
 template <typename T>
 void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s,
               Sell<T>* sell) {

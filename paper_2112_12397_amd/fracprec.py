@@ -53,7 +53,7 @@ class FpcOptions(C.Structure):
                 ("restart", C.c_int), ("maxit", C.c_int),
                 ("rtol", C.c_double), ("max_batch", C.c_int),
                 ("graphs", C.c_int), ("ortho", C.c_int),
-                ("amg", FpcAmgOptions)]
+                ("tune", C.c_int), ("amg", FpcAmgOptions)]
 
 
 class FpcInfo(C.Structure):

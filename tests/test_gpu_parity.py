@@ -155,9 +155,12 @@ def test_apply_prec_parity(torch, name, mode):
         v = sol.apply_prec(torch.tensor(w, device="cuda")).cpu().numpy()
         vo = pc.apply(w)
         assert _rel(v, vo) <= TOL
-        # every block separately (t and p are much smaller than u)
+        # every block separately (t and p are much smaller than u), in the
+        # 2-norm and entry by entry against the block's largest entry
         for a, b_ in ((0, s.n_u), (s.n_u, s.n_u + s.n_t), (s.n_u + s.n_t, s.N)):
             assert _rel(v[a:b_], vo[a:b_]) <= 1e-9
+            assert np.max(np.abs(v[a:b_] - vo[a:b_])) <= \
+                1e-9 * np.max(np.abs(vo[a:b_]))
 
 
 @pytest.mark.parametrize("name", NAMES)
