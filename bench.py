@@ -188,9 +188,11 @@ def path_report(torch, sol, s, res, sv, nrep=20):
     k_bytes = spmv_bytes(d0["nnz_scalar"], s.n_u, s.n_u, sv=sv, extra_vec=1)
     k_avg_s = kernel_ms / max(launches, 1) / 1e3
     out = {
-        "amg_levels": [{"dofs": d["n_dofs"], "nnz": d["nnz_scalar"],
-                        "layout_A_P_R": d["layout"],
-                        "tuned_us_A_P_R": [round(t, 1) for t in d["tune_us"]]}
+        "amg_levels": [dict({"dofs": d["n_dofs"], "nnz": d["nnz_scalar"],
+                             "layout_A_P_R": d["layout"]},
+                            **({"tuned_us_A_P_R": [round(t, 1)
+                                                   for t in d["tune_us"]]}
+                               if any(d["tune_us"]) else {}))
                        for d in levels],
         "vcycle": {"seconds": vc_s, "vcycles_per_s": 1.0 / vc_s,
                    "algorithmic_bytes": vc_bytes,

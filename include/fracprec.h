@@ -119,11 +119,13 @@ typedef struct {
   int ortho;               /* FPC_DCGS2 (default), FPC_CGS2 or FPC_MGS;     */
                            /* batched solves use DCGS2, or CGS2 for either  */
                            /* of the other two                              */
-  int tune;                /* 1: each operator's apply layout is picked by  */
-                           /* timing the candidates at setup (default); 0:  */
-                           /* by its average row length alone, so that two  */
-                           /* setups of one system give bitwise equal       */
-                           /* hierarchies, preconditioners and solutions    */
+  int tune;                /* 0: each operator's apply layout follows from  */
+                           /* its average row length (default): two setups  */
+                           /* of one system give bitwise equal hierarchies, */
+                           /* preconditioners and solutions; 1: the         */
+                           /* candidates are timed at setup and the fastest */
+                           /* kept (the order of a product's sums may then  */
+                           /* differ from setup to setup)                   */
   fpc_amg_options amg;
 } fpc_options;
 

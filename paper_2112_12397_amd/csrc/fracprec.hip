@@ -1381,7 +1381,7 @@ void fpc_default_options(fpc_options* o) {
   o->max_batch = 32;
   o->graphs = 1;
   o->ortho = FPC_DCGS2;
-  o->tune = 1;
+  o->tune = 0;
   o->amg.max_coarse = 2000;
   o->amg.max_levels = 12;
   o->amg.cheb_degree = 2;

@@ -1375,6 +1375,49 @@ __global__ void k_copy_panel(const double* __restrict__ D, int64_t n,
   P[idx] = D[(o + r) * n + o + c];
 }
 
+// Wavefront maximum of a 64-bit key: DPP exchanges inside each row of 16
+// lanes (the two quad swaps, then the half-row and row mirrors leave the
+// row's maximum in all its lanes), then the four rows read lane by lane.
+// Every lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32),
+                                             CTRL, 0xf, 0xf, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t row16_max_u64(uint64_t k) {
+  uint64_t o = dpp_u64<0xb1>(k);   // quad_perm [1, 0, 3, 2]
+  k = o > k ? o : k;
+  o = dpp_u64<0x4e>(k);            // quad_perm [2, 3, 0, 1]
+  k = o > k ? o : k;
+  o = dpp_u64<0x141>(k);           // row_half_mirror
+  k = o > k ? o : k;
+  o = dpp_u64<0x140>(k);           // row_mirror
+  return o > k ? o : k;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t k) {
+  k = row16_max_u64(k);
+  uint64_t r = 0;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, row * 16);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), row * 16);
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    r = v > r ? v : r;
+  }
+  return r;
+}
+
+__device__ __forceinline__ uint64_t lane0_u64(uint64_t k) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 0)
+          << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, 0);
+}
+
 __global__ __launch_bounds__(1024) void k_lu_slab(double* __restrict__ P,
                                                   int64_t m, int nb, int s0,
                                                   int s1, int64_t o,
@@ -1382,10 +1425,9 @@ __global__ __launch_bounds__(1024) void k_lu_slab(double* __restrict__ P,
                                                   int* flags) {
   constexpr int W = kLuSlabR;
   static_assert(kLuRows == 2 * 1024, "two rows per thread");
-  __shared__ double s_v[16];
-  __shared__ int s_i[16];
+  __shared__ uint64_t s_key[16];
+  __shared__ int s_idx[16];
   __shared__ double s_rp[W], s_rq[W];
-  __shared__ int s_p, s_bad;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rows = (int)(m - s0), ws = s1 - s0;
   const int r0 = t, r1 = t + 1024;
@@ -1400,70 +1442,86 @@ __global__ __launch_bounds__(1024) void k_lu_slab(double* __restrict__ P,
 #pragma unroll
   for (int q = 0; q < W; ++q) {
     if (q >= ws) continue;  // uniform: the slab's last columns may be absent
-    // largest |entry| of column q at or below row q, first row on ties
-    double bv = -1.0;
-    int bi = q;
-    if (r0 >= q && r0 < rows && fabs(A0[q]) > bv) {
-      bv = fabs(A0[q]);
-      bi = r0;
-    }
-    if (r1 >= q && r1 < rows && fabs(A1[q]) > bv) {
-      bv = fabs(A1[q]);
-      bi = r1;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
+    // largest |entry| of column q at or below row q, first row on ties.
+    // Key of a candidate: the bits of |entry| (ordered as integers for
+    // nonnegative doubles) plus one, 0 for rows above q or past the end; a
+    // thread's row r0 comes before its row r1.
+    uint64_t k0 = 0, k1 = 0;
+    if (r0 >= q && r0 < rows)
+      k0 = (uint64_t)__double_as_longlong(fabs(A0[q])) + 1;
+    if (r1 >= q && r1 < rows)
+      k1 = (uint64_t)__double_as_longlong(fabs(A1[q])) + 1;
+    const bool use1 = k1 > k0;
+    const uint64_t key = use1 ? k1 : k0;
+    const uint64_t wmax = wave_max_u64(key);
+    // the wavefront's first row with the maximum: its rows t precede its
+    // rows t + 1024
+    const uint64_t m0 = __ballot(key == wmax && !use1);
+    const uint64_t m1 = __ballot(key == wmax);
     if (lane == 0) {
-      s_v[w] = bv;
-      s_i[w] = bi;
+      s_key[w] = wmax;
+      s_idx[w] = m0 ? 64 * w + __ffsll((unsigned long long)m0) - 1
+                    : 1024 + 64 * w + __ffsll((unsigned long long)m1) - 1;
     }
     __syncthreads();
-    if (w == 0) {
-      double v = lane < 16 ? s_v[lane] : -2.0;
-      int ix = lane < 16 ? s_i[lane] : 0x7fffffff;
-      for (int off = 8; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off);
-        const int oi = __shfl_xor(ix, off);
-        if (ov > v || (ov == v && oi < ix)) {
-          v = ov;
-          ix = oi;
-        }
-      }
-      if (lane == 0) {
-        const bool bad = !(v > 0.0) || !isfinite(v);
-        piv[s0 + q] = (int32_t)(o + s0 + ix);
-        if (bad) atomicOr(&flags[FLAG_SINGULAR], 1);
-        s_p = ix;
-        s_bad = bad ? 1 : 0;
-      }
+    // the 16 wavefront results, lane i of each row of 16 taking wavefront
+    // i's: their maximum, then the first row holding it (rows below 1024
+    // first, each half in wavefront order)
+    const uint64_t kv = s_key[lane & 15];
+    const int iv = s_idx[lane & 15];
+    const uint64_t bk = lane0_u64(row16_max_u64(kv));
+    const uint64_t t0 = __ballot(kv == bk && iv < 1024) & 0xffffull;
+    const uint64_t t1 = __ballot(kv == bk) & 0xffffull;
+    const int src = (t0 ? __ffsll((unsigned long long)t0)
+                        : __ffsll((unsigned long long)t1)) - 1;
+    const int p = __builtin_amdgcn_readlane(iv, src);
+    const double pv = __longlong_as_double((long long)(bk - 1));
+    const bool bad = bk == 0 || !(pv > 0.0) || !isfinite(pv);
+    if (t == 0) {
+      piv[s0 + q] = (int32_t)(o + s0 + p);
+      if (bad) atomicOr(&flags[FLAG_SINGULAR], 1);
     }
-    __syncthreads();
-    const int p = s_p;
-    const bool bad = s_bad != 0;
-    // the pivot row and row q through LDS, then exchanged
+    // the pivot row and row q through LDS, then exchanged (only the
+    // wavefronts of the two owners take these branches)
     const bool own_p = t == (p & 1023), p_hi = p >= 1024;
     const bool own_q = t == (q & 1023), q_hi = q >= 1024;
-    if (own_p)
+    if (own_p) {
+      if (p_hi) {
 #pragma unroll
-      for (int c = 0; c < W; ++c) s_rp[c] = p_hi ? A1[c] : A0[c];
-    if (own_q)
+        for (int c = 0; c < W; ++c) s_rp[c] = A1[c];
+      } else {
 #pragma unroll
-      for (int c = 0; c < W; ++c) s_rq[c] = q_hi ? A1[c] : A0[c];
+        for (int c = 0; c < W; ++c) s_rp[c] = A0[c];
+      }
+    }
+    if (own_q) {
+      if (q_hi) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) s_rq[c] = A1[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < W; ++c) s_rq[c] = A0[c];
+      }
+    }
     __syncthreads();
-    if (p != q) {
+    if (p != q && (own_p || own_q)) {
+      // row q takes the pivot row and the pivot row takes row q; a thread
+      // may own both (p and q 1024 apart)
+      if (own_q && !q_hi) {
 #pragma unroll
-      for (int c = 0; c < W; ++c) {
-        const double vp = s_rp[c], vq = s_rq[c];
-        if (own_q && !q_hi) A0[c] = vp;
-        if (own_q && q_hi) A1[c] = vp;
-        if (own_p && !p_hi) A0[c] = vq;
-        if (own_p && p_hi) A1[c] = vq;
+        for (int c = 0; c < W; ++c) A0[c] = s_rp[c];
+      }
+      if (own_q && q_hi) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) A1[c] = s_rp[c];
+      }
+      if (own_p && !p_hi) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) A0[c] = s_rq[c];
+      }
+      if (own_p && p_hi) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) A1[c] = s_rq[c];
       }
     }
     // column q of L below the pivot, rank-1 update inside the slab

@@ -632,6 +632,12 @@ __device__ inline void spgemm_step(const double (&a)[BM * BK], int64_t b0,
   constexpr int EPP = 64 / BN;
   for (int64_t eb = b0 + le; le < EPP && eb < bend; eb += EPP) {
     const int32_t j = cb[eb];
+    // the B values are loaded before the search for the output slot, so
+    // their latency overlaps it (the entry exists: eb < bend)
+    const double* b = vb + eb * (BK * BN) + c;
+    double bt[BK];
+#pragma unroll
+    for (int t = 0; t < BK; ++t) bt[t] = b[t * BN];
     int lo = 0, hi = clen;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -639,10 +645,6 @@ __device__ inline void spgemm_step(const double (&a)[BM * BK], int64_t b0,
       else hi = mid;
     }
     if (lo >= clen || scol[lo] != j) continue;
-    const double* b = vb + eb * (BK * BN) + c;
-    double bt[BK];
-#pragma unroll
-    for (int t = 0; t < BK; ++t) bt[t] = b[t * BN];
     double* o = sacc + lo * (BM * BN) + c;
 #pragma unroll
     for (int r = 0; r < BM; ++r) {
@@ -891,14 +893,13 @@ __device__ inline void pack33(const double* v, int cls, double* p) {
   p[4] = v[i2 * 3 + i2];
 }
 
-// Sliced-ELL fill, one thread per block row, for blocks other than 3x3
-// (those take k_sell_fill_w33): slot k of row r holds its k-th block.
-template <typename T, int B>
-__global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
-                            const double* val, int64_t nrows,
-                            const int64_t* slice_ptr, int32_t* row_len,
-                            int32_t* scol, T* sval) {
-  static_assert(B != 9, "3x3 blocks use k_sell_fill_w33");
+// Sliced-ELL slots, one thread per block row, for blocks other than 3x3
+// (those take k_sell_slots_w33): slot k of row r takes its k-th block; the
+// slot's column and source entry are written here, its values by
+// k_sell_vals.
+__global__ void k_sell_slots(const int64_t* rowptr, const int32_t* col,
+                             int64_t nrows, const int64_t* slice_ptr,
+                             int32_t* row_len, int32_t* scol, int64_t* sent) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int64_t s = r / kSliceH;
@@ -910,29 +911,40 @@ __global__ void k_sell_fill(const int64_t* rowptr, const int32_t* col,
   for (int k = 0; k < len; ++k) {
     const int64_t grp = base + (int64_t)k * kSliceH;
     scol[grp + l] = col[a + k];
-    T* dst = sval + grp * B + l;
-#pragma unroll
-    for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)val[(a + k) * B + q];
+    sent[grp + l] = a + k;
   }
-  // padding slots up to the slice's longest row keep zero values and repeat
+  // padding slots up to the slice's longest row get zero values and repeat
   // the row's last column (column 0 for an empty row), so a product may read
   // them unguarded: a padded term adds 0 * x[c] for a c the row already uses
   const int maxlen = (int)((slice_ptr[s + 1] - base) / kSliceH);
   const int32_t cpad = len > 0 ? col[a + len - 1] : 0;
-  for (int k = len; k < maxlen; ++k) scol[base + (int64_t)k * kSliceH + l] = cpad;
+  for (int k = len; k < maxlen; ++k) {
+    scol[base + (int64_t)k * kSliceH + l] = cpad;
+    sent[base + (int64_t)k * kSliceH + l] = -1;
+  }
 }
 
-// Sliced-ELL fill for 3x3 blocks with one wavefront per block row: lane e
+// Class of every 3x3 block (one thread per block, a streaming pass).
+__global__ __launch_bounds__(256) void k_block_class33(
+    const double* __restrict__ val, int64_t nnzb, uint8_t* __restrict__ cls) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nnzb) return;
+  double v[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) v[q] = val[e * 9 + q];
+  cls[e] = (uint8_t)class33(v);
+}
+
+// Sliced-ELL slots for 3x3 blocks with one wavefront per block row: lane e
 // takes block e of a 64-block chunk, and the slot of a block (full blocks
 // first, then the packed ones, each group in column order) is its rank
-// among the row's blocks of its kind, counted with ballots.  Same layout as
-// k_sell_fill.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sell_fill_w33(
+// among the row's blocks of its kind, counted with ballots.  Writes the
+// slot's column with its class and its source entry, as k_sell_slots.
+__global__ __launch_bounds__(256) void k_sell_slots_w33(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, int64_t nrows,
+    const uint8_t* __restrict__ bcls, int64_t nrows,
     const int64_t* __restrict__ slice_ptr, int32_t* __restrict__ row_len,
-    int32_t* __restrict__ scol, T* __restrict__ sval) {
+    int32_t* __restrict__ scol, int64_t* __restrict__ sent) {
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= nrows) return;
@@ -943,25 +955,19 @@ __global__ __launch_bounds__(256) void k_sell_fill_w33(
   const int len = (int)(rowptr[r + 1] - a);
   if (lane == 0) row_len[r] = len;
   const uint64_t lt = (uint64_t(1) << lane) - 1;
-  // full blocks of the row (a second pass over the values only for rows
+  // full blocks of the row (a second pass over the classes only for rows
   // longer than one chunk)
   int nfull = 0;
   if (len > 64)
     for (int e0 = 0; e0 < len; e0 += 64) {
       const int e = e0 + lane;
-      const bool full = e < len && class33(val + (a + e) * 9) == 0;
+      const bool full = e < len && bcls[a + e] == 0;
       nfull += __popcll(__ballot(full));
     }
   int before_full = 0, before_packed = 0;
   for (int e0 = 0; e0 < len; e0 += 64) {
     const int e = e0 + lane;
-    double v[9];
-    int cls = 1;
-    if (e < len) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) v[q] = val[(a + e) * 9 + q];
-      cls = class33(v);
-    }
+    const int cls = e < len ? (int)bcls[a + e] : 1;
     const bool full = e < len && cls == 0;
     const bool packed = e < len && cls != 0;
     const uint64_t mf = __ballot(full), mp = __ballot(packed);
@@ -971,16 +977,7 @@ __global__ __launch_bounds__(256) void k_sell_fill_w33(
                          : nfull + before_packed + __popcll(mp & lt);
       const int64_t grp = base + (int64_t)k * kSliceH;
       scol[grp + l] = (int32_t)((uint32_t)col[a + e] | ((uint32_t)cls << 30));
-      T* dst = sval + grp * 9 + l;
-      if (full) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) dst[q * kSliceH] = (T)v[q];
-      } else {
-        double p[5];
-        pack33(v, cls, p);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) dst[q * kSliceH] = (T)p[q];
-      }
+      sent[grp + l] = a + e;
     }
     before_full += __popcll(mf);
     before_packed += __popcll(mp);
@@ -988,8 +985,46 @@ __global__ __launch_bounds__(256) void k_sell_fill_w33(
   // padding slots: packed zeros repeating the row's last column
   const int maxlen = (int)((slice_ptr[sl + 1] - base) / kSliceH);
   const int32_t cpad = (len > 0 ? col[a + len - 1] : 0) | (int32_t)(1u << 30);
-  for (int k = len + lane; k < maxlen; k += 64)
+  for (int k = len + lane; k < maxlen; k += 64) {
     scol[base + (int64_t)k * kSliceH + l] = cpad;
+    sent[base + (int64_t)k * kSliceH + l] = -1;
+  }
+}
+
+// Sliced-ELL values, one thread per slot: the slot's source block (entry
+// index from the slot pass, -1 for padding and for the missing rows of a
+// short last slice) is read whole and written plane by plane, so that
+// consecutive threads write consecutive words of each plane.  Every value
+// of the layout is written once: padding slots and the unused planes of
+// packed 3x3 slots get zeros.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_sell_vals(
+    const int64_t* __restrict__ sent, const int32_t* __restrict__ scol,
+    const double* __restrict__ val, int64_t nslots, T* __restrict__ sval) {
+  static_assert((kSliceH & (kSliceH - 1)) == 0, "slice height: power of 2");
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nslots) return;
+  const int64_t e = sent[i];
+  const int l = (int)(i & (kSliceH - 1));
+  double v[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) v[q] = 0.0;
+  if (e >= 0) {
+#pragma unroll
+    for (int q = 0; q < B; ++q) v[q] = val[e * B + q];
+    if constexpr (B == 9) {
+      const int cls = (int)((uint32_t)scol[i] >> 30);
+      if (cls) {
+        double p[5];
+        pack33(v, cls, p);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] = q < 5 ? p[q] : 0.0;
+      }
+    }
+  }
+  T* dst = sval + (i - l) * B + l;
+#pragma unroll
+  for (int q = 0; q < B; ++q) dst[q * kSliceH] = (T)v[q];
 }
 
 __global__ void k_vrow_count(const int64_t* rowptr, int64_t nrows, int G,
@@ -1185,17 +1220,27 @@ void to_sell_impl(const Bsr& a, Sell<T>& out, hipStream_t s) {
   out.row_len.alloc(std::max<int64_t>(out.nrows, 1));
   out.col.alloc(std::max<int64_t>(out.nslots, 1));
   out.val.alloc(std::max<int64_t>(out.nslots * B, 1));
+  // slots of the rows missing from a short last slice: column 0, no source
+  DevBuf<int64_t> sent(std::max<int64_t>(out.nslots, 1));
   fill_i32(out.col.p, 0, out.nslots, s);
-  FPC_HIP(hipMemsetAsync(out.val.p, 0, out.val.bytes(), s));
+  FPC_HIP(hipMemsetAsync(sent.p, 0xff, sent.bytes(), s));
   if (out.nrows) {
-    if constexpr (B == 9)
-      k_sell_fill_w33<T><<<(unsigned)((out.nrows + 3) / 4), 256, 0, s>>>(
-          a.rowptr.p, a.col.p, a.val.p, a.nbr, out.slice_ptr.p, out.row_len.p,
-          out.col.p, out.val.p);
-    else
-      k_sell_fill<T, B><<<grid_for(out.nrows, 256), 256, 0, s>>>(
-          a.rowptr.p, a.col.p, a.val.p, a.nbr, out.slice_ptr.p, out.row_len.p,
-          out.col.p, out.val.p);
+    if constexpr (B == 9) {
+      DevBuf<uint8_t> bcls(std::max<int64_t>(a.nnzb, 1));
+      if (a.nnzb)
+        k_block_class33<<<grid_for(a.nnzb, 256), 256, 0, s>>>(a.val.p, a.nnzb,
+                                                              bcls.p);
+      FPC_LAUNCH_CHECK();
+      k_sell_slots_w33<<<(unsigned)((out.nrows + 3) / 4), 256, 0, s>>>(
+          a.rowptr.p, a.col.p, bcls.p, a.nbr, out.slice_ptr.p, out.row_len.p,
+          out.col.p, sent.p);
+    } else
+      k_sell_slots<<<grid_for(out.nrows, 256), 256, 0, s>>>(
+          a.rowptr.p, a.col.p, a.nbr, out.slice_ptr.p, out.row_len.p,
+          out.col.p, sent.p);
+    FPC_LAUNCH_CHECK();
+    k_sell_vals<T, B><<<grid_for(out.nslots, 256), 256, 0, s>>>(
+        sent.p, out.col.p, a.val.p, out.nslots, out.val.p);
   }
   FPC_LAUNCH_CHECK();
 }

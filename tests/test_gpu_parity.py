@@ -508,7 +508,8 @@ def test_dense_inverse_pivoting(torch):
     """The coarsest-level inverse (Gauss-Jordan with partial pivoting in
     256-wide panels) on matrices that need row exchanges: a tiny but nonzero
     leading pivot, a row permutation of a diagonally dominant matrix (zero
-    diagonal entries), a random non-symmetric matrix over three panels;
+    diagonal entries), a random non-symmetric matrix over three panels, a
+    noisy scaled permutation that only the largest pivot keeps accurate;
     against LAPACK's LU (scipy.linalg.lu_factor / lu_solve).  A singular
     matrix is reported."""
     import scipy.linalg as sl
@@ -520,7 +521,14 @@ def test_dense_inverse_pivoting(torch):
     Pm = np.eye(130)[rng.permutation(130)] @ (
         4.0 * np.eye(130) + 0.1 * rng.standard_normal((130, 130)))
     B = rng.standard_normal((600, 600)) + 10.0 * np.eye(600)
-    for M in (A, Pm, B):
+    # scaled permutation plus 1e-9 noise over 1,500 rows (six panels, pivot
+    # candidates in both row halves of the search): every column has one
+    # entry of order 1, and any other pivot would bring multipliers near 1e9
+    # and an inverse off by far more than the bound below
+    n = 1500
+    Q = (np.eye(n)[rng.permutation(n)] * (1.0 + rng.random(n))[:, None]
+         + 1e-9 * rng.standard_normal((n, n)))
+    for M in (A, Pm, B, Q):
         ref = sl.lu_solve(sl.lu_factor(M), np.eye(len(M)))
         inv = sol.dense_inverse(torch.tensor(M, device="cuda")).cpu().numpy()
         assert _rel(inv, ref) <= 1e-10
