@@ -30,9 +30,12 @@ template <typename T>
 void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
              double* best_us, Sell<T>* sell = nullptr);
 
-// The apply layout chosen from the average row length alone (no timing, so
-// the same for every setup of a pattern): sliced ELL up to 32 blocks per
-// row, row groups of 16 lanes below 64 blocks per row, of 64 lanes above.
+// The apply layout chosen from the shape alone (no timing, so the same for
+// every setup of a pattern): rows of more than 32 blocks take row groups of
+// 16 lanes below 64 blocks per row and of 64 lanes above; shorter rows take
+// sliced ELL when there are at least 65,536 of them (1,024 slices, enough to
+// fill the GPU with one lane per row), row groups of 16 or 4 lanes (from 16
+// blocks per row) otherwise.
 int rule_layout(const Bsr& M);
 
 // The apply layout `choice` (as returned by tune_op) of one operator.

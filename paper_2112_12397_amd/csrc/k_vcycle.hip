@@ -1172,7 +1172,9 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
 }
 int rule_layout(const Bsr& M) {
   const double avg = M.nbr ? (double)M.nnzb / (double)M.nbr : 0.0;
-  return avg <= 32.0 ? 1 : avg < 64.0 ? 16 : 64;
+  if (avg > 32.0) return avg < 64.0 ? 16 : 64;
+  if (M.nbr >= 65536) return 1;
+  return avg >= 16.0 ? 16 : 4;
 }
 template <typename T>
 void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s,
