@@ -151,7 +151,8 @@ typedef struct {
   int layout[3];           /* apply layout picked for A_l, P_l, R_l: 1 =    */
                            /* sliced ELL, 4/16/64 = row groups of that many */
                            /* lanes, 0 = none (coarsest)                    */
-  double tune_us[3];       /* the winner's measured time per product (us)   */
+  double tune_us[3];       /* with tune = 1, the winner's measured time per */
+                           /* product (us); 0 when the rule picked it       */
 } fpc_level_desc;
 
 /* The pressure-block factorization (nested dissection, multifrontal; for
