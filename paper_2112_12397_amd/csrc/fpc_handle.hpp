@@ -18,14 +18,17 @@ struct Level {
   int64_t n_dofs_real = 0;  // without padding dofs
   Bsr A, P, R;              // FP64 block CSR (setup, export, transposes)
   Bsr Pt;                   // tentative prolongator (kept for re-setups)
+  // patterns of A P_tent, A P and R (A P) (kept for re-setups: the numeric
+  // phase of each product runs on them)
+  BsrPattern pat_ap0, pat_ap, pat_ac;
   Sell<double> sA;          // FP64 A in sliced ELL (power iteration)
-  Op<double> oA, oP, oR;    // apply operators (layout chosen by the tuner)
+  Op<double> oA, oP, oR;    // apply operators (layouts: rule or timing)
   Op<float> fA, fP, fR;
   Bsr AT;                   // A^T for the transposed cycle (lazy)
   Op<double> oAT;
   Op<float> fAT;
-  int layout[3] = {0, 0, 0};   // tuner choice for A, P, R (1 = sliced ELL)
-  double tune_us[3] = {0, 0, 0};  // winning time per product (us)
+  int layout[3] = {0, 0, 0};   // layout of A, P, R (1 = sliced ELL, else lanes)
+  double tune_us[3] = {0, 0, 0};  // timed winner per product (us), 0 by rule
   // multi-right-hand-side operators (sliced ELL, one thread per row and
   // column), built on the first batched solve
   Op<double> bA, bP, bR;

@@ -300,12 +300,23 @@ void csr_transpose(const Csr& a, Csr& t, hipStream_t s);
 void csr_to_bsr(const Csr& a, int br, int bc, Bsr& out, hipStream_t s);
 void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s);
 void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s);
-// C = A * B (block shapes must chain).  flags[FLAG_OVERFLOW] on hash overflow.
-// C = A B (block CSR); b_single: every row of B holds at most one block (a
+// Block pattern of a product kept for a later product of operands with the
+// same patterns (numeric re-setup): row pointers, block columns, and the
+// longest row.
+struct BsrPattern {
+  int64_t nnzb = 0, cap = 0;
+  DevBuf<int64_t> rowptr;
+  DevBuf<int32_t> col;
+};
+// C = A B (block CSR; block shapes must chain).  flags[FLAG_OVERFLOW] on
+// hash overflow.  b_single: every row of B holds at most one block (a
 // tentative prolongator), which a faster numeric kernel uses when C's rows
-// are short; a row with more raises FLAG_PATTERN.
+// are short; a row with more raises FLAG_PATTERN.  reuse: C's pattern from
+// an earlier product of operands with the same patterns (taken over; only
+// the numeric phase runs); keep: receives C's pattern.
 void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s,
-            bool b_single = false);
+            bool b_single = false, BsrPattern* keep = nullptr,
+            BsrPattern* reuse = nullptr);
 template <typename T>
 void bsr_to_sell(const Bsr& a, Sell<T>& out, hipStream_t s);
 template <typename T>

@@ -257,15 +257,20 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
                 ptent.p, Bc.p, L.rank.p, s);
       ptent_bsr(L.agg.p, L.n_nodes, L.n_agg, L.bs, nb, ptent.p, L.Pt, s);
     }
+    // the products' patterns follow from the operands' patterns, which a
+    // re-setup keeps: only their numeric phases run then
     Bsr AP0;
-    spgemm(L.A, L.Pt, AP0, h->flags.p, s, /*b_single=*/true);
+    spgemm(L.A, L.Pt, AP0, h->flags.p, s, /*b_single=*/true, &L.pat_ap0,
+           pv ? &pv->pat_ap0 : nullptr);
     // P = P_tent - omega D^{-1} (A P_tent)
     smooth_prolongator(AP0, L.dinv.p, o.omega_factor / L.lam_hi, s);
     bsr_add(L.Pt, AP0, L.P, s);
     bsr_transpose(L.P, L.R, s);
     Bsr AP, Ac;
-    spgemm(L.A, L.P, AP, h->flags.p, s);
-    spgemm(L.R, AP, Ac, h->flags.p, s);
+    spgemm(L.A, L.P, AP, h->flags.p, s, false, &L.pat_ap,
+           pv ? &pv->pat_ap : nullptr);
+    spgemm(L.R, AP, Ac, h->flags.p, s, false, &L.pat_ac,
+           pv ? &pv->pat_ac : nullptr);
     check_flags(h, "Galerkin product");
     dummy_diag(Ac, L.rank.p, s);
     // next level

@@ -1144,17 +1144,51 @@ void to_bsr_impl(const Csr& a, Bsr& out, hipStream_t s) {
 }
 
 template <int BM, int BK, int BN>
+void spgemm_numeric(const Bsr& a, const Bsr& b, Bsr& c, int64_t cap,
+                    int* flags, hipStream_t s, bool b_single);
+
+template <int BM, int BK, int BN>
 void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
-                 hipStream_t s, bool b_single) {
+                 hipStream_t s, bool b_single, BsrPattern* keep,
+                 BsrPattern* reuse) {
   c.br = BM;
   c.bc = BN;
   c.nbr = a.nbr;
   c.nbc = b.nbc;
+  if (reuse) {
+    if ((int64_t)reuse->rowptr.n != c.nbr + 1)
+      throw Error(FPC_ERR_STATE, "spgemm: kept pattern of another shape");
+    c.nnzb = reuse->nnzb;
+    c.rowptr = std::move(reuse->rowptr);
+    c.col = std::move(reuse->col);
+    const int64_t cap = reuse->cap;
+    if (keep) {
+      keep->nnzb = c.nnzb;
+      keep->cap = cap;
+      keep->rowptr.alloc(c.nbr + 1);
+      FPC_HIP(hipMemcpyAsync(keep->rowptr.p, c.rowptr.p, keep->rowptr.bytes(),
+                             hipMemcpyDeviceToDevice, s));
+      keep->col.alloc(std::max<int64_t>(c.nnzb, 1));
+      FPC_HIP(hipMemcpyAsync(keep->col.p, c.col.p, keep->col.bytes(),
+                             hipMemcpyDeviceToDevice, s));
+    }
+    c.val.alloc(std::max<int64_t>(c.nnzb * BM * BN, 1));
+    if (c.nbr) spgemm_numeric<BM, BK, BN>(a, b, c, cap, flags, s, b_single);
+    return;
+  }
   DevBuf<int64_t> cnt(std::max<int64_t>(c.nbr, 1));
   DevBuf<unsigned long long> mx(2);
   c.rowptr.alloc(c.nbr + 1);
   if (!c.nbr) {
     c.nnzb = scan_counts_total(cnt.p, c.rowptr.p, 0, s);
+    if (keep) {
+      keep->nnzb = 0;
+      keep->cap = 0;
+      keep->rowptr.alloc(1);
+      FPC_HIP(hipMemcpyAsync(keep->rowptr.p, c.rowptr.p, sizeof(int64_t),
+                             hipMemcpyDeviceToDevice, s));
+      keep->col.alloc(1);
+    }
     return;
   }
   FPC_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(unsigned long long), s));
@@ -1183,6 +1217,23 @@ void spgemm_impl(const Bsr& a, const Bsr& b, Bsr& c, int* flags,
   FPC_HIP(hipMemcpyAsync(h, mx.p, sizeof(h), hipMemcpyDeviceToHost, s));
   FPC_HIP(hipStreamSynchronize(s));
   const int64_t cap = (int64_t)h[1];
+  if (keep) {
+    keep->nnzb = c.nnzb;
+    keep->cap = cap;
+    keep->rowptr.alloc(c.nbr + 1);
+    FPC_HIP(hipMemcpyAsync(keep->rowptr.p, c.rowptr.p, keep->rowptr.bytes(),
+                           hipMemcpyDeviceToDevice, s));
+    keep->col.alloc(std::max<int64_t>(c.nnzb, 1));
+    FPC_HIP(hipMemcpyAsync(keep->col.p, c.col.p, keep->col.bytes(),
+                           hipMemcpyDeviceToDevice, s));
+  }
+  spgemm_numeric<BM, BK, BN>(a, b, c, cap, flags, s, b_single);
+}
+
+// The numeric phase of C = A B on C's pattern (rows of at most cap blocks).
+template <int BM, int BK, int BN>
+void spgemm_numeric(const Bsr& a, const Bsr& b, Bsr& c, int64_t cap,
+                    int* flags, hipStream_t s, bool b_single) {
   const size_t abytes = (size_t)cap * (BM * BN * sizeof(double) + sizeof(int));
   constexpr int QM = 8;
   if (b_single && cap * BM * BN <= 64 * QM) {
@@ -1416,20 +1467,20 @@ void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s) {
 }
 
 void spgemm(const Bsr& a, const Bsr& b, Bsr& c, int* flags, hipStream_t s,
-            bool b_single) {
+            bool b_single, BsrPattern* keep, BsrPattern* reuse) {
   if (a.bc != b.br || a.nbc != b.nbr)
     throw Error(FPC_ERR_DIM, "spgemm: shapes do not chain");
   const int m = a.br, k = a.bc, n = b.bc;
   if (m == 3 && k == 3 && n == 3)
-    return spgemm_impl<3, 3, 3>(a, b, c, flags, s, b_single);
+    return spgemm_impl<3, 3, 3>(a, b, c, flags, s, b_single, keep, reuse);
   if (m == 3 && k == 3 && n == 6)
-    return spgemm_impl<3, 3, 6>(a, b, c, flags, s, b_single);
+    return spgemm_impl<3, 3, 6>(a, b, c, flags, s, b_single, keep, reuse);
   if (m == 6 && k == 3 && n == 6)
-    return spgemm_impl<6, 3, 6>(a, b, c, flags, s, b_single);
+    return spgemm_impl<6, 3, 6>(a, b, c, flags, s, b_single, keep, reuse);
   if (m == 6 && k == 6 && n == 6)
-    return spgemm_impl<6, 6, 6>(a, b, c, flags, s, b_single);
+    return spgemm_impl<6, 6, 6>(a, b, c, flags, s, b_single, keep, reuse);
   if (m == 3 && k == 1 && n == 3)
-    return spgemm_impl<3, 1, 3>(a, b, c, flags, s, b_single);
+    return spgemm_impl<3, 1, 3>(a, b, c, flags, s, b_single, keep, reuse);
   throw Error(FPC_ERR_ARG, "spgemm: unsupported block shapes");
 }
 
