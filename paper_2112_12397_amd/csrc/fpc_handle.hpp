@@ -21,6 +21,7 @@ struct Level {
   // patterns of A P_tent, A P and R (A P) (kept for re-setups: the numeric
   // phase of each product runs on them)
   BsrPattern pat_ap0, pat_ap, pat_ac;
+  TransposePlan plan_r;     // R = P^T
   Sell<double> sA;          // FP64 A in sliced ELL (power iteration)
   Op<double> oA, oP, oR;    // apply operators (layouts: rule or timing)
   Op<float> fA, fP, fR;
@@ -39,7 +40,7 @@ struct Level {
   DevBuf<int32_t> rank;     // kept modes per aggregate (n_agg)
   DevBuf<int32_t> node_rank;// real dofs per node (coarse levels)
   int64_t n_agg = 0;
-  int64_t nnz_scalar = 0;
+  int64_t nnz_scalar = -1;  // nonzero scalars of A (counted when queried)
   double lam_hi = 0, theta = 0, delta = 0, c1 = 0, c2 = 0;
   bool coarsest = false;
 };

@@ -299,7 +299,19 @@ void csr_spmv2_many(std::initializer_list<Spmv2Call> calls, hipStream_t s);
 void csr_transpose(const Csr& a, Csr& t, hipStream_t s);
 void csr_to_bsr(const Csr& a, int br, int bc, Bsr& out, hipStream_t s);
 void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s);
-void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s);
+// The pattern of a block transpose and, for each of its blocks, the source
+// block, kept for a later transpose of a matrix with the same pattern.
+struct TransposePlan {
+  int64_t nnzb = 0;
+  DevBuf<int64_t> rowptr;
+  DevBuf<int32_t> col;
+  DevBuf<int64_t> src;
+};
+// t = a^T.  reuse: the plan of an earlier transpose of the same pattern
+// (only the values are gathered); keep: receives the plan.
+void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s,
+                   TransposePlan* keep = nullptr,
+                   TransposePlan* reuse = nullptr);
 // Block pattern of a product kept for a later product of operands with the
 // same patterns (numeric re-setup): row pointers, block columns, and the
 // longest row.

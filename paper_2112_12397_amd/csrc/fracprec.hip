@@ -213,7 +213,6 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
     L.dinv.alloc(L.n_nodes * L.bs);
     bsr_dinv(L.A, L.dinv.p, h->flags.p, s);
     check_flags(h, "AMG diagonal");
-    L.nnz_scalar = bsr_count_nonzeros(L.A, s);
     if (L.n_dofs_real <= o.max_coarse || (int)H.L.size() == o.max_levels) {
       L.coarsest = true;
       break;
@@ -265,7 +264,7 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
     // P = P_tent - omega D^{-1} (A P_tent)
     smooth_prolongator(AP0, L.dinv.p, o.omega_factor / L.lam_hi, s);
     bsr_add(L.Pt, AP0, L.P, s);
-    bsr_transpose(L.P, L.R, s);
+    bsr_transpose(L.P, L.R, s, &L.plan_r, pv ? &pv->plan_r : nullptr);
     Bsr AP, Ac;
     spgemm(L.A, L.P, AP, h->flags.p, s, false, &L.pat_ap,
            pv ? &pv->pat_ap : nullptr);
@@ -1671,6 +1670,14 @@ fpc_status fpc_level_info(const fpc_handle* h, int level, fpc_level_desc* d) {
   if (!h->ready) return FPC_ERR_STATE;
   if (level < 0 || level >= (int)h->amg.L.size()) return FPC_ERR_ARG;
   const Level& L = h->amg.L[level];
+  if (L.nnz_scalar < 0) {
+    // counted on the first query (reporting only, not needed by the setup)
+    fpc_handle* hh = const_cast<fpc_handle*>(h);
+    const fpc_status st = guard(hh, [&] {
+      hh->amg.L[level].nnz_scalar = bsr_count_nonzeros(L.A, h->stream);
+    });
+    if (st != FPC_OK) return st;
+  }
   d->n_nodes = L.n_nodes;
   d->n_dofs = L.n_dofs_real;
   d->block = L.bs;

@@ -571,16 +571,20 @@ __global__ void k_power_start(int64_t n_nodes, int bs, int stride,
   x[i] = (double)h / 4294967296.0 - 0.5;
 }
 
-__global__ void k_dense_from_bsr(const int64_t* rp, const int32_t* col,
-                                 const double* val, int64_t nbr, int br,
-                                 int bc, int64_t npad, double* D) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per block row: its threads stride over the row's values
+// (the coarsest operator's rows hold hundreds of blocks).
+__global__ __launch_bounds__(256) void k_dense_from_bsr(
+    const int64_t* rp, const int32_t* col, const double* val, int64_t nbr,
+    int br, int bc, int64_t npad, double* D) {
+  const int64_t i = blockIdx.x;
   if (i >= nbr) return;
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-    for (int r = 0; r < br; ++r)
-      for (int c = 0; c < bc; ++c)
-        D[(i * br + r) * npad + (int64_t)col[e] * bc + c] =
-            val[e * br * bc + r * bc + c];
+  const int bs = br * bc;
+  const int64_t e0 = rp[i], n = (rp[i + 1] - e0) * bs;
+  for (int64_t idx = threadIdx.x; idx < n; idx += 256) {
+    const int64_t e = e0 + idx / bs;
+    const int q = (int)(idx % bs), r = q / bc, c = q % bc;
+    D[(i * br + r) * npad + (int64_t)col[e] * bc + c] = val[e * bs + q];
+  }
 }
 
 __global__ void k_pad_identity(double* D, int64_t n, int64_t npad) {
@@ -1236,7 +1240,7 @@ void dense_pad(const double* A, int64_t n, int64_t npad, double* D,
 void dense_from_bsr(const Bsr& a, int64_t npad, double* D, hipStream_t s) {
   FPC_HIP(hipMemsetAsync(D, 0, (size_t)npad * npad * sizeof(double), s));
   if (a.nbr)
-    k_dense_from_bsr<<<grid_for(a.nbr, 128), 128, 0, s>>>(
+    k_dense_from_bsr<<<(unsigned)a.nbr, 256, 0, s>>>(
         a.rowptr.p, a.col.p, a.val.p, a.nbr, a.br, a.bc, npad, D);
   const int64_t n = a.nbr * a.br;
   if (npad > n)

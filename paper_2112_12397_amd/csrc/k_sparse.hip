@@ -1073,12 +1073,31 @@ __global__ void k_count_nz(const double* v, int64_t n,
 }
 
 template <int BR, int BC>
-void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s) {
+void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s,
+                          TransposePlan* keep = nullptr,
+                          TransposePlan* reuse = nullptr) {
   t.br = BC;
   t.bc = BR;
   t.nbr = a.nbc;
   t.nbc = a.nbr;
   t.nnzb = a.nnzb;
+  if (reuse) {
+    if ((int64_t)reuse->rowptr.n != t.nbr + 1 || reuse->nnzb != t.nnzb)
+      throw Error(FPC_ERR_STATE, "transpose: kept plan of another shape");
+    t.rowptr.alloc(t.nbr + 1);
+    FPC_HIP(hipMemcpyAsync(t.rowptr.p, reuse->rowptr.p, t.rowptr.bytes(),
+                           hipMemcpyDeviceToDevice, s));
+    t.col.alloc(std::max<int64_t>(t.nnzb, 1));
+    FPC_HIP(hipMemcpyAsync(t.col.p, reuse->col.p, t.col.bytes(),
+                           hipMemcpyDeviceToDevice, s));
+    t.val.alloc(std::max<int64_t>(t.nnzb * BR * BC, 1));
+    if (t.nnzb)
+      k_tr_gather<BR, BC><<<grid_for(t.nnzb * BR * BC, 256), 256, 0, s>>>(
+          a.val.p, reuse->src.p, t.nnzb, t.val.p);
+    FPC_LAUNCH_CHECK();
+    if (keep) *keep = std::move(*reuse);
+    return;
+  }
   DevBuf<unsigned long long> cnt(a.nbc + 1);
   FPC_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
   if (a.nbr)
@@ -1108,6 +1127,16 @@ void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s) {
     k_tr_gather<BR, BC><<<grid_for(t.nnzb * BR * BC, 256), 256, 0, s>>>(
         a.val.p, src.p, t.nnzb, t.val.p);
   FPC_LAUNCH_CHECK();
+  if (keep) {
+    keep->nnzb = t.nnzb;
+    keep->rowptr.alloc(t.nbr + 1);
+    FPC_HIP(hipMemcpyAsync(keep->rowptr.p, t.rowptr.p, keep->rowptr.bytes(),
+                           hipMemcpyDeviceToDevice, s));
+    keep->col.alloc(std::max<int64_t>(t.nnzb, 1));
+    FPC_HIP(hipMemcpyAsync(keep->col.p, t.col.p, keep->col.bytes(),
+                           hipMemcpyDeviceToDevice, s));
+    keep->src = std::move(src);
+  }
   FPC_HIP(hipStreamSynchronize(s));
 }
 
@@ -1458,11 +1487,16 @@ void bsr_add(const Bsr& a, const Bsr& b, Bsr& c, hipStream_t s) {
   FPC_LAUNCH_CHECK();
 }
 
-void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s) {
-  if (a.br == 3 && a.bc == 3) return block_transpose_impl<3, 3>(a, t, s);
-  if (a.br == 3 && a.bc == 6) return block_transpose_impl<3, 6>(a, t, s);
-  if (a.br == 6 && a.bc == 3) return block_transpose_impl<6, 3>(a, t, s);
-  if (a.br == 6 && a.bc == 6) return block_transpose_impl<6, 6>(a, t, s);
+void bsr_transpose(const Bsr& a, Bsr& t, hipStream_t s, TransposePlan* keep,
+                   TransposePlan* reuse) {
+  if (a.br == 3 && a.bc == 3)
+    return block_transpose_impl<3, 3>(a, t, s, keep, reuse);
+  if (a.br == 3 && a.bc == 6)
+    return block_transpose_impl<3, 6>(a, t, s, keep, reuse);
+  if (a.br == 6 && a.bc == 3)
+    return block_transpose_impl<6, 3>(a, t, s, keep, reuse);
+  if (a.br == 6 && a.bc == 6)
+    return block_transpose_impl<6, 6>(a, t, s, keep, reuse);
   throw Error(FPC_ERR_ARG, "bsr_transpose: unsupported block shape");
 }
 
