@@ -1137,7 +1137,6 @@ void block_transpose_impl(const Bsr& a, Bsr& t, hipStream_t s,
                            hipMemcpyDeviceToDevice, s));
     keep->src = std::move(src);
   }
-  FPC_HIP(hipStreamSynchronize(s));
 }
 
 template <int BR, int BC>
