@@ -23,7 +23,8 @@ template <typename T>
 void vcycle_to(Hierarchy& H, bool transpose, bool d0_ready, double* out,
                hipStream_t s);
 
-// Autotuned apply layout of one operator for `nv` columns; *choice = 1 for
+// Apply layout of one operator picked by timing the candidates with `nv`
+// columns (option tune = 1); *choice = 1 for
 // sliced ELL, else the row-group width.
 // `sell`: the operator's sliced-ELL layout if already built (taken over).
 template <typename T>

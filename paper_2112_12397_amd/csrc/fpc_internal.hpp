@@ -165,7 +165,8 @@ struct Vrow {
   }
 };
 
-// An apply-path operator in the layout the setup autotuner chose:
+// An apply-path operator in the layout the setup chose (by row length, or
+// by timing the candidates):
 // fmt 0 = sliced ELL (one thread per block row), fmt 1 = row groups; the
 // batched operators use fmt 1 for one wavefront per row and fmt 2 for four.
 template <typename T>
