@@ -179,9 +179,10 @@ double power_lambda(fpc_handle* h, Level& L, int key_stride) {
 // With `prev` (a hierarchy built on the same level-0 block pattern), the
 // pattern-only parts are taken over instead of recomputed: the aggregates
 // (structure-only MIS-2), the tentative prolongators and coarse ranks (they
-// depend on the aggregates and the coordinates only) and the apply layouts
-// picked by the tuner.  Everything that depends on values is recomputed, so
-// the result equals a fresh build.
+// depend on the aggregates and the coordinates only), the apply layouts, the
+// patterns of the Galerkin products and the transpose plan of R.
+// Everything that depends on values is recomputed, so the result equals a
+// fresh build.
 void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
   Hierarchy& H = h->amg;
   h->graphs.clear();  // captured cycles refer to the old hierarchy
