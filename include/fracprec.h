@@ -120,12 +120,15 @@ typedef struct {
                            /* batched solves use DCGS2, or CGS2 for either  */
                            /* of the other two                              */
   int tune;                /* 0: each operator's apply layout follows from  */
-                           /* its average row length (default): two setups  */
-                           /* of one system give bitwise equal hierarchies, */
+                           /* its shape (default): two setups of one system */
+                           /* give bitwise equal hierarchies,               */
                            /* preconditioners and solutions; 1: the         */
                            /* candidates are timed at setup and the fastest */
                            /* kept (the order of a product's sums may then  */
-                           /* differ from setup to setup)                   */
+                           /* differ from setup to setup); 2: as 0, but     */
+                           /* sliced ELL for rows of up to 32 blocks at any */
+                           /* row count (small systems then take the layout */
+                           /* of large ones)                                */
   fpc_amg_options amg;
 } fpc_options;
 

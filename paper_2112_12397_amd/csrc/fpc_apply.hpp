@@ -35,9 +35,9 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
 // every setup of a pattern): rows of more than 32 blocks take row groups of
 // 16 lanes below 64 blocks per row and of 64 lanes above; shorter rows take
 // sliced ELL when there are at least 65,536 of them (1,024 slices, enough to
-// fill the GPU with one lane per row), row groups of 16 or 4 lanes (from 16
-// blocks per row) otherwise.
-int rule_layout(const Bsr& M);
+// fill the GPU with one lane per row) or when any_rows is set, row groups of
+// 16 or 4 lanes (from 16 blocks per row) otherwise.
+int rule_layout(const Bsr& M, bool any_rows = false);
 
 // The apply layout `choice` (as returned by tune_op) of one operator.
 template <typename T>

@@ -308,11 +308,12 @@ void build_hierarchy(fpc_handle* h, Bsr&& S1, Hierarchy* prev = nullptr) {
     if (L.coarsest) continue;
     // L.sA (built for the power iteration) is handed to the FP64 layout
     // choice and released otherwise
-    if (prev || !h->opt.tune) {
-      // the layouts picked for the same patterns, or by row length alone
+    if (prev || h->opt.tune != 1) {
+      // the layouts picked for the same patterns, or by the shape alone
       const Bsr* ops[3] = {&L.A, &L.P, &L.R};
       for (int k = 0; k < 3; ++k) {
-        L.layout[k] = prev ? prev->L[li].layout[k] : rule_layout(*ops[k]);
+        L.layout[k] = prev ? prev->L[li].layout[k]
+                           : rule_layout(*ops[k], h->opt.tune == 2);
         L.tune_us[k] = prev ? prev->L[li].tune_us[k] : 0.0;
       }
       if (h->opt.precision == FPC_FP32_PREC) {
@@ -374,8 +375,10 @@ void ensure_transposes(fpc_handle* h) {
     if (L.coarsest) continue;
     bsr_transpose(L.A, L.AT, s);
     const bool f32 = h->opt.precision == FPC_FP32_PREC;
-    if (!h->opt.tune && f32) build_op<float>(L.AT, rule_layout(L.AT), L.fAT, s);
-    else if (!h->opt.tune) build_op<double>(L.AT, rule_layout(L.AT), L.oAT, s);
+    const bool timed = h->opt.tune == 1;
+    const int rule = rule_layout(L.AT, h->opt.tune == 2);
+    if (!timed && f32) build_op<float>(L.AT, rule, L.fAT, s);
+    else if (!timed) build_op<double>(L.AT, rule, L.oAT, s);
     else if (f32) tune_op<float>(L.AT, 1, L.fAT, s, nullptr, nullptr);
     else tune_op<double>(L.AT, 1, L.oAT, s, nullptr, nullptr);
   }
@@ -1414,7 +1417,7 @@ fpc_status fpc_create(fpc_handle** hp, const fpc_options* opt, void* stream) {
       o.restart < 1 || o.restart + 1 > kMaxKrylov || o.maxit < 1 ||
       o.amg.cheb_degree != 2 || o.amg.max_levels < 1 || o.amg.power_its < 1 ||
       o.amg.cheb_ratio <= 1.0 || o.max_batch < 1 || o.max_batch > kMaxBatch ||
-      (o.graphs != 0 && o.graphs != 1) || (o.tune != 0 && o.tune != 1) ||
+      (o.graphs != 0 && o.graphs != 1) || o.tune < 0 || o.tune > 2 ||
       (o.ortho != FPC_CGS2 && o.ortho != FPC_MGS && o.ortho != FPC_DCGS2)) {
     delete h;
     return FPC_ERR_ARG;

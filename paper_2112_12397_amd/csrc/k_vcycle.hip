@@ -1170,10 +1170,10 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
   if (best_us) *best_us = 1e3 * tbest;
   FPC_HIP(hipStreamSynchronize(s));
 }
-int rule_layout(const Bsr& M) {
+int rule_layout(const Bsr& M, bool any_rows) {
   const double avg = M.nbr ? (double)M.nnzb / (double)M.nbr : 0.0;
   if (avg > 32.0) return avg < 64.0 ? 16 : 64;
-  if (M.nbr >= 65536) return 1;
+  if (any_rows || M.nbr >= 65536) return 1;
   return avg >= 16.0 ? 16 : 4;
 }
 template <typename T>
