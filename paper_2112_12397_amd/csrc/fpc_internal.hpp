@@ -139,11 +139,15 @@ struct Sell {
   int br = 0, bc = 0;
   int64_t nrows = 0, nslices = 0, nslots = 0, nnzb = 0;
   DevBuf<int64_t> slice_ptr;  // nslices + 1, in slots (multiples of 64)
-  DevBuf<int32_t> row_len;    // nrows
+  DevBuf<int32_t> row_len;    // nrows, by position in the layout
   DevBuf<int32_t> col;        // nslots
   DevBuf<T> val;              // nslots * br * bc
+  // row at each position of the layout when rows are sorted by length
+  // within windows (empty: the identity)
+  DevBuf<int32_t> perm;
   size_t bytes() const {
-    return slice_ptr.bytes() + row_len.bytes() + col.bytes() + val.bytes();
+    return slice_ptr.bytes() + row_len.bytes() + col.bytes() + val.bytes() +
+           perm.bytes();
   }
 };
 

@@ -23,12 +23,20 @@ struct SellView {
   const int32_t* __restrict__ row_len;
   const int32_t* __restrict__ col;
   const T* __restrict__ val;
+  const int32_t* __restrict__ perm;  // null: position = row
 };
 
 template <typename T>
 SellView<T> view(const Sell<T>& a) {
   return SellView<T>{a.nrows, a.nslices, a.slice_ptr.p, a.row_len.p,
-                     a.col.p, a.val.p};
+                     a.col.p, a.val.p, a.perm.n ? a.perm.p : nullptr};
+}
+
+// The row stored at position `pos` of a sliced-ELL layout.
+template <typename T>
+__device__ __forceinline__ int64_t sell_row(const SellView<T>& A,
+                                            int64_t pos) {
+  return A.perm ? (int64_t)A.perm[pos] : pos;
 }
 
 // ---------------------------------------------------------------- loaders
@@ -366,8 +374,9 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
   // the epilogue's inputs do not depend on the product: wavefront 0 fetches
   // them first, so they arrive while the slice streams in
   const bool epi_lane = half == 0 && valid && row < A.nrows;
+  const int64_t orow = epi_lane ? sell_row(A, row) : 0;
   T pre[NV][BR][Epi::NIN];
-  if (epi_lane) epi_load_row<T, BR, NV>(epi, row, pre);
+  if (epi_lane) epi_load_row<T, BR, NV>(epi, orow, pre);
   if (valid) {
     const int64_t base = A.slice_ptr[slice];
     const int maxlen = (int)((A.slice_ptr[slice + 1] - base) / kSliceH);
@@ -439,7 +448,7 @@ __global__ __launch_bounds__(256) void k_sell_rows(SellView<T> A, Load ld,
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int i = 0; i < BR; ++i) acc[v][i] += red[pair][h][lane][v * BR + i];
-  epi_store_row<T, BR, NV>(epi, row, acc, pre);
+  epi_store_row<T, BR, NV>(epi, orow, acc, pre);
 }
 
 // Many columns (interleaved right-hand sides): one thread per (block row,
@@ -517,7 +526,7 @@ __global__ __launch_bounds__(256) void k_sell_cols(SellView<T> A, Load ld,
 #pragma unroll
         for (int j = 0; j < BC; ++j) acc[u][i] += m[i * BC + j] * xv[j][u];
   }
-  epi_cols<T, BR, NV, CPL>(epi, row, v0, acc);
+  epi_cols<T, BR, NV, CPL>(epi, sell_row(A, row), v0, acc);
 }
 
 template <typename T, int BR, int BC, int NV, class Load, class Epi>
