@@ -152,8 +152,8 @@ typedef struct {
   double lam_hi;           /* Chebyshev upper bound                         */
   int64_t n_agg;           /* aggregates formed on this level (0 coarsest)  */
   int layout[3];           /* apply layout picked for A_l, P_l, R_l: 1 =    */
-                           /* sliced ELL, 4/16/64 = row groups of that many */
-                           /* lanes, 0 = none (coarsest)                    */
+                           /* sliced ELL, 4/16/64/256 = row groups of that  */
+                           /* many lanes, 0 = none (coarsest)               */
   double tune_us[3];       /* with tune = 1, the winner's measured time per */
                            /* product (us); 0 when the rule picked it       */
 } fpc_level_desc;

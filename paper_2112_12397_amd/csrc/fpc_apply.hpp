@@ -33,7 +33,8 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
 
 // The apply layout chosen from the shape alone (no timing, so the same for
 // every setup of a pattern): rows of more than 32 blocks take row groups of
-// 16 lanes below 64 blocks per row and of 64 lanes above; shorter rows take
+// 16 lanes below 64 blocks per row and of 64 lanes above (a workgroup of 256
+// lanes for fewer than 4,096 rows of 256 blocks or more); shorter rows take
 // sliced ELL when there are at least 65,536 of them (1,024 slices, enough to
 // fill the GPU with one lane per row) or when any_rows is set, row groups of
 // 16 or 4 lanes (from 16 blocks per row) otherwise.

@@ -561,9 +561,13 @@ VrowView<T> vview(const Vrow<T>& a) {
 
 // G lanes per block row: lane sl takes blocks sl, sl+G, ... of the row
 // (chunk-contiguous, component-major), then the G partial sums are combined
-// with cross-lane shuffles inside the aligned lane group.
+// with cross-lane shuffles inside the aligned lane group; with G = 256 (a
+// workgroup per row, for the few long rows of coarse restrictions) the four
+// wavefronts' sums then meet in LDS and are added in wavefront order.
 template <typename T, int BR, int BC, int NV, int G, class Load, class Epi>
 __global__ __launch_bounds__(256) void k_vrow(VrowView<T> A, Load ld, Epi epi) {
+  static_assert(G <= 64 || G == 256, "row groups: up to 64 lanes, or 256");
+  constexpr int GW = G > 64 ? 64 : G;  // lanes combined by shuffles
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t t = blk * 256 + threadIdx.x;
   const int64_t row = t / G;
@@ -597,11 +601,27 @@ __global__ __launch_bounds__(256) void k_vrow(VrowView<T> A, Load ld, Epi epi) {
     }
   }
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1)
+  for (int off = GW / 2; off > 0; off >>= 1)
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int i = 0; i < BR; ++i) acc[v][i] += __shfl_xor(acc[v][i], off, 64);
+  if constexpr (G == 256) {
+    __shared__ T red[4][BR * NV];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int i = 0; i < BR; ++i) red[w][i * NV + v] = acc[v][i];
+    __syncthreads();
+    if (threadIdx.x < BR * NV) {
+      const int q = threadIdx.x;
+      const T a = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+      epi_one<T, BR, NV>(epi, row, q / NV, q % NV, a);
+    }
+    return;
+  }
   // after the butterfly every lane of the group holds all BR*NV sums; lane
   // sl writes elements sl, sl+G, ...
 #pragma unroll
@@ -751,6 +771,7 @@ void launch_op(const Op<T>& op, Load ld, Epi epi, hipStream_t s) {
     case 4: return launch_vrow<T, BR, BC, NV, 4>(op.v, ld, epi, s);
     case 16: return launch_vrow<T, BR, BC, NV, 16>(op.v, ld, epi, s);
     case 64: return launch_vrow<T, BR, BC, NV, 64>(op.v, ld, epi, s);
+    case 256: return launch_vrow<T, BR, BC, NV, 256>(op.v, ld, epi, s);
   }
   throw Error(FPC_ERR_ARG, "launch_op: unsupported row-group width");
   }
@@ -1181,7 +1202,8 @@ void tune_op(const Bsr& M, int nv, Op<T>& out, hipStream_t s, int* choice,
 }
 int rule_layout(const Bsr& M, bool any_rows) {
   const double avg = M.nbr ? (double)M.nnzb / (double)M.nbr : 0.0;
-  if (avg > 32.0) return avg < 64.0 ? 16 : 64;
+  if (avg > 32.0)
+    return avg < 64.0 ? 16 : (avg >= 256.0 && M.nbr < 4096) ? 256 : 64;
   if (any_rows || M.nbr >= 65536) return 1;
   return avg >= 16.0 ? 16 : 4;
 }
@@ -1193,7 +1215,7 @@ void build_op(const Bsr& M, int choice, Op<T>& out, hipStream_t s,
     out.fmt = 0;
     if (sell && sell->nrows == M.nbr) out.s = std::move(*sell);
     else bsr_to_sell(M, out.s, s);
-  } else if (choice == 4 || choice == 16 || choice == 64) {
+  } else if (choice == 4 || choice == 16 || choice == 64 || choice == 256) {
     out.fmt = 1;
     bsr_to_vrow(M, choice, out.v, s);
   } else {

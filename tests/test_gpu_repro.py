@@ -41,7 +41,7 @@ def test_two_setups_bitwise(torch, c1, precision):
     for l in range(a.num_levels() - 1):
         d = a.level_info(l)
         assert all(t == 0.0 for t in d["tune_us"])
-        assert all(c in (1, 4, 16, 64) for c in d["layout"])
+        assert all(c in (1, 4, 16, 64, 256) for c in d["layout"])
     w = torch.tensor(np.random.default_rng(11).standard_normal(c1.N),
                      device="cuda")
     va = a.apply_prec(w).clone()
