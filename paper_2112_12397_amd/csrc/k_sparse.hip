@@ -8,14 +8,18 @@ namespace fpc {
 namespace {
 
 // ------------------------------------------------------------- validation
-// Four lanes per row: lane q checks entries e = a + q, a + q + 4, ... (column
-// in range, strictly above the previous entry's, finite value).
+// 2^lg lanes per row: lane q checks entries e = a + q, a + q + 2^lg, ...
+// (column in range, strictly above the previous entry's, finite value); the
+// caller picks lg from the average row length, so that the lanes of a row
+// read whole cache lines.
 __global__ void k_csr_validate(const int64_t* rowptr, const int32_t* col,
                                const double* val, int64_t nrows,
-                               int64_t ncols, int64_t nnz, int* flags) {
+                               int64_t ncols, int64_t nnz, int lg,
+                               int* flags) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = t >> 2;
-  const int q = (int)(t & 3);
+  const int64_t i = t >> lg;
+  const int L = 1 << lg;
+  const int q = (int)(t & (L - 1));
   if (t == 0 && (rowptr[0] != 0 || rowptr[nrows] != nnz))
     atomicOr(&flags[FLAG_PATTERN], 1);
   if (i >= nrows) return;
@@ -25,7 +29,7 @@ __global__ void k_csr_validate(const int64_t* rowptr, const int32_t* col,
     return;
   }
   bool bad = false, nan = false;
-  for (int64_t e = a + q; e < b; e += 4) {
+  for (int64_t e = a + q; e < b; e += L) {
     const int32_t c = col[e];
     if (c < 0 || c >= ncols || (e > a && c <= col[e - 1])) bad = true;
     if (!isfinite(val[e])) nan = true;
@@ -1384,8 +1388,11 @@ void to_sell_impl(const Bsr& a, Sell<T>& out, hipStream_t s) {
 }  // namespace
 
 void csr_validate(const Csr& m, int* flags, hipStream_t s) {
-  k_csr_validate<<<grid_for(4 * std::max<int64_t>(m.nrows, 1), 256), 256, 0, s>>>(
-      m.rowptr.p, m.col.p, m.val.p, m.nrows, m.ncols, m.nnz, flags);
+  const double avg = m.nrows > 0 ? (double)m.nnz / (double)m.nrows : 0.0;
+  const int lg = avg >= 32.0 ? 4 : avg >= 12.0 ? 3 : 2;
+  k_csr_validate<<<grid_for(std::max<int64_t>(m.nrows, 1) << lg, 256), 256, 0,
+                   s>>>(m.rowptr.p, m.col.p, m.val.p, m.nrows, m.ncols, m.nnz,
+                        lg, flags);
   FPC_LAUNCH_CHECK();
 }
 
